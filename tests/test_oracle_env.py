@@ -1,0 +1,306 @@
+"""Pins of the oracle's environment step (Sec. 4 steps 1-5, Sec. 4.1 agents, Eq. 1-4).
+
+* Hand-worked scenarios: expected books, trades, fills, rewards and observations were
+  computed by hand from the step definition and written out below.
+* Brute force: a naive pure-Python env (tests/naive_env.py, written independently on
+  the naive book) must agree exactly with the oracle on small synthetic workloads with
+  all three agent kinds, under both the in-kernel random policy and given actions.
+* Closed forms / special cases: the SplitMix64 reference outputs, Lemire's
+  multiply-shift range, Spooner with lambda = 1, no fills -> zero spread PnL.
+* Invariants: inventory and cash equal the running sums of fills; fills equal what
+  the trade records attribute to each agent; the book is never crossed.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OracleEnvs, chain_hash, splitmix64_mix
+from helpers import hand_stream, hand_book, book_lists, msg
+from naive_env import NaiveEnv, hash_chain as naive_hash
+from paper_2511_02136_amd import synth
+
+LIMIT, PARTIAL_CANCEL, DELETE, MARKET = 1, 2, 3, 4
+BUY, SELL = 0, 1
+E0 = 1 << 30                  # oid of agent 0's first order
+M0 = (1 << 30) | (1 << 26)    # oid of agent 1's first order
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def f32(x):
+    return np.float32(x)
+
+
+# ----------------------------------------------------------------------------------
+# counter hash
+# ----------------------------------------------------------------------------------
+def test_splitmix64_reference_outputs():
+    with open(os.path.join(GOLDEN, "splitmix64_seed1234567.json")) as f:
+        g = json.load(f)
+    gamma = 0x9E3779B97F4A7C15
+    state = g["seed"]
+    for want in g["outputs"]:
+        assert splitmix64_mix(state) == want
+        state = (state + gamma) & ((1 << 64) - 1)
+
+
+def test_chain_hash_is_the_mix_chain():
+    # an independent Python implementation of the same chain must agree everywhere
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        s, d, a, b, c = (int(v) for v in rng.integers(0, 2**63, size=5))
+        assert chain_hash(s, d, a, b, c) == naive_hash(s, d, a, b, c)
+
+
+def test_random_policy_range_and_uniformity():
+    # Lemire's multiply-shift maps u32 onto [0, n): floor(u * n / 2^32)
+    n = 9
+    counts = np.zeros(n, dtype=np.int64)
+    for t in range(300):
+        for e in range(30):
+            u = chain_hash(77, oracle.DOM_ACTION, e, t, 0) >> 32
+            a = (u * n) >> 32
+            counts[a] += 1
+    expect = counts.sum() / n
+    chi2 = ((counts - expect) ** 2 / expect).sum()
+    assert chi2 < 30.0  # 8 dof, p ~ 2e-4
+    assert ((0 * n) >> 32) == 0 and (((2**32 - 1) * n) >> 32) == n - 1
+
+
+# ----------------------------------------------------------------------------------
+# hand-worked scenarios
+# ----------------------------------------------------------------------------------
+def two_agent_scenario(second_exec_action):
+    """exec (agent 0) + market maker (agent 1), two steps, cap 10."""
+    snap = hand_book([([[99, 10, 1, 0, 1, 0]], [[101, 10, 2, 0, 1, 5]])], 10)
+    steps = [[[msg(MARKET, BUY, 0, 15, 50, 0, 2, 0)], [msg(LIMIT, BUY, 103, 5, 51, 0, 2, 10)]]]
+    o = OracleEnvs(np.array([10]), 10, [0, 1], episode_len=2, seed=5, exec_task=6, exec_q0=4,
+                   mm_q=10, exec_penalty=0.5)
+    o.reset(snap)
+    acts = np.array([[[4], [1]], [[second_exec_action], [0]]], dtype=np.int32)
+    out = o.step(hand_stream(steps), n_steps=2, actions=acts)
+    return o, out
+
+
+def test_two_agent_scenario_step_by_step():
+    o, out = two_agent_scenario(8)
+    tr = out["trades"]
+    n = out["n_trades"][:, 0]
+    assert list(n) == [3, 1]
+    # step 0: the replayed market buy for 15 takes the snapshot ask (older) at 101, then
+    # the execution agent's 4 at 101, then 1 of the market maker's ask at 103; it is the
+    # 4th message of the step (3 agent orders before it, no cancels)
+    assert tr[:3].tolist() == [[101, 10, 50, 2, 0, 0, 6, 0],
+                               [101, 4, 50, E0, 0, 1, 6, 0],
+                               [103, 1, 50, M0 + 1, 0, 2, 6, 0]]
+    # step 1: the market maker's two cancels, the execution agent's ladder clipped to
+    # its remaining 2 shares at 103, then the replayed buy at 103 (4th message)
+    assert tr[3].tolist() == [103, 2, 51, E0 + 1, 0, 1, 6, 1]
+    # fills [buy_qty, buy_notional, sell_qty, sell_notional]
+    assert out["fills"][0, :, 0].tolist() == [[0, 0, 4, 404], [0, 0, 1, 103]]
+    assert out["fills"][1, :, 0].tolist() == [[0, 0, 2, 206], [0, 0, 0, 0]]
+    # rewards: exec = sold notional - P_init * qty (P_init = 100); market maker:
+    # Mbar = (200*3 + 202) / 8 = 100.25, psi_s = 103 - 100.25, psi_inv = -1 * (101 - 100)
+    assert out["reward"][:, :, 0].tolist() == [[4.0, 1.75], [6.0, -2.0]]
+    assert out["done"][:, 0].tolist() == [0, 1]
+    bids, asks = book_lists(o.books(), 0)
+    assert bids == [[103, 3, 51, 0, 2, 10], [99, 10, 1, 0, 1, 0]]
+    assert asks == []
+    st = o.state()
+    assert st["env"][0].tolist() == [103, 103, 206, 200, 2, 10, 2, 4]
+    assert st["agents"][0].tolist() == [[-6, 610, 0, 2], [-1, 103, 0, 2]]
+    assert st["counters"][0].tolist() == [8, 4, 0, 0, 0, 0, 0, 0, 0, 0]
+    # observations after step 0
+    ob = out["obs"][0, :, 0]
+    exec0 = [4, 2, 2, 10, 0, 10, 0, 0, 0, 0, 0, 0, 0, 9, 0, 0, 0, 0, 0, 0, 0, 0, 0,
+             20, 9, 2, 1, 15, 0, 3, 4, -4, 404, 2, 1, 0, 0, 0, 0, 4]
+    mm0 = exec0[:31] + [-1, 103, 0, 1, 10, 9, 2, 0, 1]
+    assert ob[0].tolist() == exec0
+    assert ob[1].tolist() == mm0
+    # after step 1: the ask side is empty, so its reference price stays 103
+    ob = out["obs"][1, :, 0]
+    exec1 = [0, 4, 6, 3, 0, 0, 0, 10, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0,
+             13, 0, 2, 0, 2, 0, 1, 0, -6, 610, 0, 0, 0, 0, 0, 0, 2]
+    mm1 = exec1[:31] + [-1, 103, 0, 0, 0, 0, 0, 0, 0]
+    assert ob[0].tolist() == exec1
+    assert ob[1].tolist() == mm1
+    # observing again reproduces the last step's observation
+    assert np.array_equal(o.observe(), out["obs"][1])
+
+
+def test_execution_end_penalty():
+    _, out = two_agent_scenario(0)
+    # the agent does nothing in the last step: 2 shares unfilled, penalty 0.5 * 2 * 100
+    assert out["reward"][1, 0, 0] == f32(-100.0)
+    assert out["n_trades"][1, 0] == 0
+
+
+def test_execution_net_to_target_partial_cancels_newest_first():
+    snap = hand_book([([[100, 5, 1, 0, 1, 0]], [[102, 50, 2, 0, 1, 1]])], 10)
+    steps = [[[], [msg(MARKET, BUY, 0, 52, 70, 0, 2, 0)], [], []]]
+    o = OracleEnvs(np.array([10]), 10, [0], episode_len=4, seed=1, exec_task=100, exec_q0=4)
+    o.reset(snap)
+    acts = np.array([7, 4, 6, 4], dtype=np.int32).reshape(4, 1, 1)
+    out = o.step(hand_stream(steps), n_steps=4, actions=acts)
+    # step 0: 5*q0 = 20 at the best ask joins behind the snapshot's order
+    # step 1: desired 4 < resting 20 -> partial cancel of 16 (priority kept), then the
+    # market buy takes the snapshot order (50) and 2 of the agent's remaining 4
+    assert out["trades"][:2].tolist() == [[102, 50, 70, 2, 0, 0, 2, 1],
+                                          [102, 2, 70, E0, 0, 1, 2, 1]]
+    # step 2: desired 8 vs resting 2 -> a new order of 6 behind it at 102
+    # step 3: desired 4 vs resting 8 -> the newest order gives up 4, the older keeps 2
+    bids, asks = book_lists(o.books(), 0)
+    assert [a[:4] for a in asks] == [[102, 2, E0, 1], [102, 2, E0 + 1, 1]]
+    st = o.state()
+    assert st["agents"][0].tolist() == [[-2, 204, 98, 2]]
+    assert st["counters"][0, 2] == 0  # no cancel missed
+    assert out["reward"][1, 0, 0] == f32(204.0 - 101.0 * 2)
+    pen = float(np.float32(0.01))
+    assert out["reward"][3, 0, 0] == f32(0.0 - (pen * 98.0) * 101.0)
+
+
+def test_market_maker_ladder_keep_and_clamp():
+    snap = hand_book([([[100, 5, 1, 0, 1, 0]], [[102, 5, 2, 0, 1, 1]])], 16)
+    steps = [[[msg(MARKET, SELL, 0, 12, 60, 0, 2, 0)], [], [msg(LIMIT, SELL, 101, 3, 61, 0, 3, 0)]]]
+    o = OracleEnvs(np.array([16]), 16, [1], episode_len=3, seed=3, mm_q=10)
+    o.reset(snap)
+    acts = np.array([8, 1, 3], dtype=np.int32).reshape(3, 1, 1)
+    out = o.step(hand_stream(steps), n_steps=3, actions=acts)
+    # step 0: ladder bids 100..97 and asks 102..105 (10 each); the market sell takes the
+    # snapshot bid (5) and 7 of the agent's 100 bid, which is behind it in time
+    assert out["trades"][:2, :4].tolist() == [[100, 5, 60, 1], [100, 7, 60, E0]]
+    assert out["fills"][0, 0, 0].tolist() == [7, 700, 0, 0]
+    # step 1: quotes (2, 2) around 100/102 -> bid 98, ask 104: both already rest with 10,
+    # so they are kept; every other level is deleted
+    bids, asks = book_lists(o.books(), 0)
+    # step 2: (-1, -1) into the spread from bb=98, ba=102 -> bid 99, ask 101; the replayed
+    # sell at 101 joins the agent's ask (later in time)
+    assert [b[:4] for b in bids] == [[99, 10, E0 + 8, 1]]
+    assert [a[:4] for a in asks] == [[101, 10, E0 + 9, 1], [101, 3, 61, 0], [102, 5, 2, 0]]
+    st = o.state()
+    assert st["agents"][0, 0].tolist() == [7, -700, 0, 10]
+
+
+# ----------------------------------------------------------------------------------
+# brute force against the naive env
+# ----------------------------------------------------------------------------------
+def run_naive(stream, w, n_steps, actions=None, **kw):
+    envs = []
+    outs = []
+    kinds = synth.agent_kinds(w.agents)
+    for e in range(w.n_envs):
+        ne = NaiveEnv(e, int(stream.caps[e]), kinds, w.ep_len, w.seed, **kw)
+        bids, asks = book_lists(stream.book, e)
+        ne.reset(bids, asks)
+        envs.append(ne)
+    for t in range(n_steps):
+        row = []
+        for e, ne in enumerate(envs):
+            lo, hi = stream.off[e, t], stream.off[e, t + 1]
+            replay = [[int(f[j]) for f in stream.msg_fields()] for j in range(lo, hi)]
+            a = None if actions is None else actions[t, :, e]
+            row.append(ne.step(replay, a))
+        outs.append(row)
+    return envs, outs
+
+
+def compare(o, out, envs, outs, n_steps, A):
+    N = len(envs)
+    for t in range(n_steps):
+        for e in range(N):
+            ref = outs[t][e]
+            lo = out["trade_off"][e]
+            # trades of env e at step t: the env's records are consecutive over steps
+            before = int(out["n_trades"][:t, e].sum())
+            k = int(out["n_trades"][t, e])
+            got = out["trades"][lo + before: lo + before + k].tolist()
+            assert got == ref["trades"], (t, e)
+            assert out["fills"][t, :, e].tolist() == ref["fills"], (t, e)
+            assert out["reward"][t, :, e].tobytes() == np.array(ref["reward"], np.float32).tobytes(), (t, e)
+            assert out["obs"][t, :, e].tobytes() == np.array(ref["obs"], np.float32).tobytes(), (t, e)
+            assert int(out["done"][t, e]) == ref["done"]
+            assert out["actions"][t, :, e].tolist() == ref["actions"]
+    books = o.books()
+    for e, ne in enumerate(envs):
+        bids, asks = book_lists(books, e)
+        assert bids == ne.book.side(BUY) and asks == ne.book.side(SELL), e
+        assert o.state()["counters"][e].tolist() == ne.book.counters, e
+
+
+@pytest.mark.parametrize("agents,policy", [(("exec", "mm"), "random"), (("exec", "mm", "dir"), "given"),
+                                           (("dir", "mm"), "random"), ((), "random")])
+def test_oracle_matches_naive_env(agents, policy):
+    w = synth.Workload("t", n_envs=5, n_steps=12, msgs_range=(1, 40), cap_choices=(3, 6, 12),
+                       agents=agents, seed=99 + len(agents), mid0=1000, snapshot_fill_pct=50)
+    s = synth.generate(w, threads=2)
+    A = len(agents)
+    kinds = synth.agent_kinds(agents)
+    acts = None
+    if policy == "given":
+        rng = np.random.default_rng(4)
+        acts = np.stack([rng.integers(-1, 10 if k != 2 else 4, size=(12, w.n_envs)) for k in kinds], 1).astype(np.int32)
+    o = OracleEnvs(s.caps, w.max_cap, kinds, w.ep_len, w.seed, exec_task=60, exec_q0=4)
+    o.reset(s.book)
+    out = o.step(s, n_steps=12, actions=acts)
+    envs, outs = run_naive(s, w, 12, acts, exec_task=60, q0=4)
+    compare(o, out, envs, outs, 12, A)
+
+
+def test_oracle_matches_naive_env_rewards_with_weights():
+    w = synth.Workload("t", n_envs=3, n_steps=10, msgs_per_step=30, cap=8, agents=("mm", "exec", "mm"),
+                       seed=5, mid0=500)
+    s = synth.generate(w, threads=1)
+    kinds = synth.agent_kinds(w.agents)
+    kw = dict(exec_penalty=0.07, mm_lambda=0.3, mm_rho=0.02)
+    o = OracleEnvs(s.caps, w.max_cap, kinds, w.ep_len, w.seed, exec_task=40, exec_q0=3, **kw)
+    o.reset(s.book)
+    out = o.step(s, n_steps=10)
+    envs, outs = run_naive(s, w, 10, None, exec_task=40, q0=3, pen=0.07, lam=0.3, rho=0.02)
+    compare(o, out, envs, outs, 10, 3)
+
+
+# ----------------------------------------------------------------------------------
+# reward special cases and invariants over a longer run
+# ----------------------------------------------------------------------------------
+def test_spooner_lambda_one_and_invariants():
+    w = synth.Workload("t", n_envs=16, n_steps=32, msgs_per_step=60, cap=20, agents=("exec", "mm"),
+                       seed=11)
+    s = synth.generate(w, threads=4)
+    kinds = synth.agent_kinds(w.agents)
+    o = OracleEnvs(s.caps, w.max_cap, kinds, w.ep_len, w.seed, mm_lambda=1.0)
+    o.reset(s.book)
+    inv = np.zeros((16, 2), np.int64)
+    cash = np.zeros((16, 2), np.int64)
+    for t in range(32):
+        st0 = o.state()
+        out = o.step(s, n_steps=1)
+        st1 = o.state()
+        fills = out["fills"][0]  # [A, N, 4]
+        inv += (fills[:, :, 0] - fills[:, :, 2]).T
+        cash += (fills[:, :, 3] - fills[:, :, 1]).T
+        assert np.array_equal(st1["agents"][:, :, 0], inv)
+        assert np.array_equal(st1["agents"][:, :, 1], cash)
+        # with lambda = 1 the market maker's reward is psi_b + psi_s + psi_inv; recompute
+        # it from the published state (mid2 before/after) and the fills
+        tr = out["trades"]
+        for e in range(16):
+            lo = out["trade_off"][e]
+            k = int(out["n_trades"][0, e])
+            recs = tr[lo:lo + k]
+            for i in range(2):
+                bq = sum(int(r[1]) for r in recs if (r[4] == i + 1 and r[6] & 1 == 0) or (r[5] == i + 1 and r[6] & 1 == 1))
+                sq = sum(int(r[1]) for r in recs if (r[4] == i + 1 and r[6] & 1 == 1) or (r[5] == i + 1 and r[6] & 1 == 0))
+                assert fills[i, e, 0] == bq and fills[i, e, 2] == sq
+            mprev = st0["env"][e, 2] * 0.5
+            mt = st1["env"][e, 2] * 0.5
+            b = fills[1, e]
+            if b[0] == 0 and b[2] == 0:
+                # no fills: spread PnL is zero, only the inventory term remains
+                expect = float(inv[e, 1]) * (mt - mprev)
+                assert out["reward"][0, 1, e] == f32(0.0 + 0.0 + expect - 0.0 * max(expect, 0.0) - 0.0)
+        books = o.books()
+        for e in range(16):
+            if books["n"][e, 0] and books["n"][e, 1]:
+                assert books["price"][e, 0, 0] < books["price"][e, 1, 0]
