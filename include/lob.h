@@ -1,0 +1,185 @@
+/*
+ * liblob — batched limit-order-book environment step for MI355X (gfx950).
+ *
+ * The hot path of the JaxMARL-HFT environment (arXiv 2511.02136, Sec. 4): for thousands
+ * of parallel environments, one env-step
+ *   1. converts each agent's discrete action into order-book messages, cancelling the
+ *      agent's earlier unmatched orders unless it quotes again at the same price level
+ *      (Sec. 4, step 1; agent types of Sec. 4.1),
+ *   2. shuffles the agents' new orders (Sec. 4, step 2),
+ *   3. concatenates [cancels, shuffled orders, replayed market-by-order messages]
+ *      (Sec. 4, step 3),
+ *   4. processes them in sequence against a fixed-capacity price-time-priority book,
+ *      recording trades (Sec. 4, step 4; Sec. 2.1; capacity from Table 2),
+ *   5. computes fills, rewards (Eq. 2-4), done flags and observations (Sec. 4, step 5).
+ *
+ * Conventions
+ *   - Every pointer named *_d / documented "device" is device memory owned by the caller
+ *     (e.g. a torch tensor's data_ptr()); host pointers are read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls that
+ *     launch work are asynchronous on that stream; arguments are validated on the host
+ *     first and a negative code is returned synchronously on error (nothing launched).
+ *   - Device-side conditions (cancel misses, evictions, drops, unfilled market orders,
+ *     trade records that did not fit) are counted per env, never turned into errors.
+ *   - Integer work (books, trades, fills, counters) is exact.  Rewards are one double
+ *     expression per agent rounded once to float; observations are integers converted
+ *     to float with round-to-nearest-even.
+ *
+ * Message encoding (structure of arrays, int32 each, one entry per message):
+ *   ts    = type | (side << 8); type 1 LIMIT, 2 PARTIAL_CANCEL, 3 DELETE, 4 MARKET
+ *           (immediate-or-cancel, no price limit); side 0 buy, 1 sell; other types are
+ *           counted as bad and ignored.
+ *   price (ticks), qty (> 0), oid (order id; cancels name the order by id on their
+ *   side), tid (trader id; agents are tid 1..n_agents, replay data must not use them),
+ *   tsec, tns (time payload, not used for priority: arrival order is time priority).
+ * Replay message ids must stay below 2^30 (agent order ids have bit 30 set).
+ */
+#ifndef LOB_H
+#define LOB_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LOB_OK = 0,
+    LOB_EINVAL = -1,       /* a bad argument (sizes, NULL pointers, ranges) */
+    LOB_ENOMEM = -2,       /* device allocation failed */
+    LOB_EHIP = -3,         /* a HIP runtime call failed */
+    LOB_ESTATE = -4,       /* call order: no reset yet, or the episode/stream is exhausted */
+    LOB_EUNSUPPORTED = -5  /* a configuration this build does not support */
+};
+
+#define LOB_LIMIT 1
+#define LOB_PARTIAL_CANCEL 2
+#define LOB_DELETE 3
+#define LOB_MARKET 4
+#define LOB_OBS_DIM 40
+#define LOB_TRADE_WORDS 8
+#define LOB_N_COUNTERS 10
+#define LOB_ENV_STATE_WORDS 8
+#define LOB_AGENT_STATE_WORDS 4
+#define LOB_MAX_AGENTS 4
+#define LOB_MAX_CAP 1024
+
+/* agent kinds (Sec. 4.1) */
+#define LOB_AGENT_EXEC 0 /* order execution, sell task; 9 actions */
+#define LOB_AGENT_MM 1   /* market making, fixed-quantity action space; 9 actions */
+#define LOB_AGENT_DIR 2  /* directional trading; 3 actions */
+
+typedef struct lob_ctx lob_ctx;
+
+/* Environment configuration (host struct, copied by lob_init). */
+typedef struct {
+    int32_t n_envs;            /* >= 1 */
+    int32_t n_agents;          /* 0..LOB_MAX_AGENTS; agent i has tid i+1 */
+    int32_t max_cap;           /* 1..LOB_MAX_CAP: stride of book arrays, >= every cap */
+    int32_t episode_len;       /* steps per episode (done on the last) */
+    const int32_t *cap;        /* host [n_envs]: per-side capacity of each env's book */
+    const int32_t *agent_kind; /* host [n_agents]: LOB_AGENT_* */
+    uint64_t seed;             /* shuffle keys and random-policy actions */
+    int32_t exec_task;         /* shares the execution agent sells per episode */
+    int32_t exec_q0;           /* execution order quantity */
+    int32_t mm_q;              /* market-maker quote quantity */
+    int32_t dir_q;             /* directional order quantity */
+    float exec_penalty;        /* end-of-episode penalty per unfilled share, times P_init */
+    float mm_lambda;           /* Spooner weight of positive inventory PnL (Eq. 3) */
+    float mm_rho;              /* quadratic inventory penalty factor */
+    uint32_t flags;            /* reserved, must be 0 */
+} lob_config;
+
+/* A market-by-order stream in CSR form (device arrays).  Env e's messages of step t are
+ * entries off[e*(n_steps+1)+t] .. off[e*(n_steps+1)+t+1]-1 of the seven arrays. */
+typedef struct {
+    const int32_t *ts, *price, *qty, *oid, *tid, *tsec, *tns; /* device [n_msgs] */
+    const int64_t *off;                                       /* device [n_envs][n_steps+1] */
+    int32_t n_steps;                                          /* CSR rows per env */
+    int64_t n_msgs;                                           /* entries of each array */
+} lob_msgs;
+
+/* Books in canonical layout (device arrays): field[e][side][slot] with side 0 = bids,
+ * 1 = asks, slots 0..n-1 in priority order (best price first, then arrival), unused slots
+ * zero on export; n[e][side] order counts. */
+typedef struct {
+    int32_t *price, *qty, *oid, *tid, *tsec, *tns; /* device [n_envs][2][max_cap] */
+    int32_t *n;                                    /* device [n_envs][2] */
+} lob_books;
+
+/* Outputs of lob_step / lob_rollout for n_steps steps (device arrays).
+ * trade record (8 int32): price, qty, aggressor oid, resting oid, aggressor tid,
+ *   resting tid, aggressor side | (message index within the step << 1), step index t.
+ * Env e's records go to trades[trade_off[e] + cursor ...], cursor = trade_cursor[e]
+ * (or 0 when trade_cursor is NULL), in processing order over the steps of the call;
+ * records beyond trade_off[e+1] are not written (counted as trade_overflow). */
+typedef struct {
+    int32_t *trades;          /* device [trade_off[n_envs]][8], or NULL (not recorded) */
+    const int64_t *trade_off; /* device [n_envs+1], required when trades != NULL */
+    int64_t *trade_cursor;    /* device [n_envs] in/out, or NULL */
+    int32_t *n_trades;        /* device [n_steps][n_envs]: trades per env-step */
+    int64_t *fills;           /* device [n_steps][n_agents][n_envs][4]: bought qty,
+                                 bought notional, sold qty, sold notional */
+    float *reward;            /* device [n_steps][n_agents][n_envs] */
+    float *obs;               /* device [n_steps][n_agents][n_envs][40], or NULL */
+    uint8_t *done;            /* device [n_steps][n_envs] */
+    int32_t *actions;         /* device [n_steps][n_agents][n_envs]: actions taken, or NULL */
+} lob_out;
+
+/* Create a context: validates cfg, allocates the books and per-env state on the current
+ * device.  Returns LOB_EINVAL / LOB_EUNSUPPORTED / LOB_ENOMEM / LOB_EHIP on failure. */
+int lob_init(const lob_config *cfg, lob_ctx **out);
+
+/* Load every env's book from `snapshot` (canonical layout, priority order, n <= cap;
+ * counts above an env's cap are clamped) and start a new episode: step 0, agents flat,
+ * the execution agent's task at exec_task, reference prices from the best prices (an
+ * empty side falls back to one tick beyond the other side, 0 if both are empty). */
+int lob_reset(lob_ctx *ctx, const lob_books *snapshot, void *stream);
+
+/* One env-step of every env (the plain per-step form: one launch, books loaded from
+ * and stored to device memory).  Messages of step t = the context's step counter are
+ * read from `msgs`.  actions: device int32 [n_agents][n_envs], or NULL for the uniform
+ * random policy drawn in-kernel from the counter hash.  Out-of-range actions act as 0
+ * (no quotes: every resting order of that agent is cancelled).  Outputs for 1 step.
+ * LOB_ESTATE if not reset, the episode is over, or msgs has no row for this step. */
+int lob_step(lob_ctx *ctx, const lob_msgs *msgs, const int32_t *actions, const lob_out *out,
+             void *stream);
+
+/* n_steps env-steps of every env in one persistent launch per capacity class, books
+ * resident in LDS for all steps, envs pulled from a work queue (longest first).
+ * actions: device int32 [n_steps][n_agents][n_envs] or NULL (random policy).  Results
+ * are identical to n_steps calls of lob_step. */
+int lob_rollout(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps, const int32_t *actions,
+                const lob_out *out, void *stream);
+
+/* Observation of the current state, device float [n_agents][n_envs][40] (equal to the
+ * last step's observation; after reset, the step statistics are zero). */
+int lob_observe(lob_ctx *ctx, float *obs, void *stream);
+
+/* Copy the books out in canonical layout (unused slots zero). */
+int lob_export_books(lob_ctx *ctx, const lob_books *out, void *stream);
+
+/* Copy the state out (device arrays):
+ *   env_state [n_envs][8]: last best bid, last best ask, mid2 (bid+ask) at the last step
+ *     end, mid2 at reset, time of the last processed message (s, ns), steps since reset,
+ *     mid2 change over the last step;
+ *   agent_state [n_envs][n_agents][4]: inventory, cash (ticks x shares), execution
+ *     remaining, order-id counter;
+ *   counters [n_envs][10]: messages, trades, cancel misses, evictions, evicted qty, drops,
+ *     dropped qty, unfilled market qty, bad messages, trade records not written.
+ * Any pointer may be NULL. */
+int lob_export_state(lob_ctx *ctx, int64_t *env_state, int64_t *agent_state, int64_t *counters,
+                     void *stream);
+
+/* Steps taken since the last reset (host-side counter). */
+int lob_current_step(const lob_ctx *ctx);
+
+/* Free the context (synchronises the device first).  NULL is a no-op. */
+int lob_destroy(lob_ctx *ctx);
+
+/* Static message for an error code. */
+const char *lob_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -49,6 +49,7 @@ class _OrCfg(ctypes.Structure):
         ("mm_lambda", ctypes.c_float),
         ("mm_rho", ctypes.c_float),
         ("pad_", ctypes.c_float),
+        ("env_id", ctypes.c_void_p),
     ]
 
 
@@ -142,7 +143,8 @@ class OracleEnvs:
 
     def __init__(self, caps: np.ndarray, max_cap: int, agent_kinds: Sequence[int], episode_len: int,
                  seed: int, exec_task: int = 500, exec_q0: int = 4, mm_q: int = 10, dir_q: int = 10,
-                 exec_penalty: float = 0.01, mm_lambda: float = 0.0, mm_rho: float = 0.0):
+                 exec_penalty: float = 0.01, mm_lambda: float = 0.0, mm_rho: float = 0.0,
+                 env_ids: Optional[np.ndarray] = None):
         self._lib = _load()
         self.caps = np.ascontiguousarray(caps, dtype=np.int32)
         self.kinds = np.ascontiguousarray(np.asarray(agent_kinds, dtype=np.int32).reshape(-1))
@@ -157,6 +159,11 @@ class OracleEnvs:
         c.seed = seed
         c.exec_task, c.exec_q0, c.mm_q, c.dir_q = exec_task, exec_q0, mm_q, dir_q
         c.exec_penalty, c.mm_lambda, c.mm_rho = exec_penalty, mm_lambda, mm_rho
+        self.env_ids = None
+        if env_ids is not None:
+            self.env_ids = np.ascontiguousarray(np.asarray(env_ids, dtype=np.int32).reshape(-1))
+            assert self.env_ids.shape[0] == self.n_envs
+            c.env_id = self.env_ids.ctypes.data
         self._h = self._lib.oe_new(ctypes.byref(c))
         if not self._h:
             raise ValueError("oracle rejected the configuration")

@@ -331,7 +331,7 @@ void decode_dir(int a, int32_t bb, int32_t ba, int32_t q, std::vector<Desire> &l
 
 struct Oracle {
     or_config cfg;
-    std::vector<int32_t> caps, kinds;
+    std::vector<int32_t> caps, kinds, ids;
     std::vector<Env> envs;
     bool was_reset = false;
 };
@@ -438,6 +438,7 @@ void env_step(Oracle &O, int e, int s, const StepIO &io, TradeSink &sink) {
     const int A = O.cfg.n_agents;
     const int N = O.cfg.n_envs;
     const int32_t t = env.t;
+    const uint64_t eid = (uint64_t)O.ids[(size_t)e]; /* env index in the hash keys */
     Book &bk = env.book;
 
     /* Reading: agents see the book as it stands at the start of the step; an empty side
@@ -455,8 +456,7 @@ void env_step(Oracle &O, int e, int s, const StepIO &io, TradeSink &sink) {
             a = io.actions[((int64_t)s * A + i) * N + e];
         } else {
             /* random policy: Lemire's multiply-shift of a 32-bit hash onto [0, n) */
-            uint32_t u = (uint32_t)(chain_hash(O.cfg.seed, DOM_ACTION, (uint64_t)e, (uint64_t)t,
-                                               (uint64_t)i) >> 32);
+            uint32_t u = (uint32_t)(chain_hash(O.cfg.seed, DOM_ACTION, eid, (uint64_t)t, (uint64_t)i) >> 32);
             a = (int)(((uint64_t)u * (uint64_t)n_actions(kind)) >> 32);
         }
         if (io.actions_out) io.actions_out[((int64_t)s * A + i) * N + e] = a;
@@ -538,7 +538,7 @@ void env_step(Oracle &O, int e, int s, const StepIO &io, TradeSink &sink) {
      * cancels are left in agent order (they commute with each other). */
     std::vector<std::pair<uint64_t, Msg>> keyed;
     for (size_t k = 0; k < actions.size(); ++k) {
-        uint32_t h = (uint32_t)(chain_hash(O.cfg.seed, DOM_SHUFFLE, (uint64_t)e, (uint64_t)t, (uint64_t)k) >> 32);
+        uint32_t h = (uint32_t)(chain_hash(O.cfg.seed, DOM_SHUFFLE, eid, (uint64_t)t, (uint64_t)k) >> 32);
         keyed.push_back({((uint64_t)h << 32) | (uint64_t)k, actions[k]});
     }
     std::sort(keyed.begin(), keyed.end(),
@@ -707,8 +707,10 @@ void *oe_new(const or_config *cfg) {
     for (int32_t c : O->caps)
         if (c < 1 || c > cfg->max_cap) { delete O; return nullptr; }
     if (cfg->n_agents > 0) O->kinds.assign(cfg->agent_kind, cfg->agent_kind + cfg->n_agents);
+    for (int32_t e = 0; e < cfg->n_envs; ++e) O->ids.push_back(cfg->env_id ? cfg->env_id[e] : e);
     O->cfg.cap = nullptr;
     O->cfg.agent_kind = nullptr;
+    O->cfg.env_id = nullptr;
     for (int32_t e = 0; e < cfg->n_envs; ++e) O->envs.emplace_back(O->caps[(size_t)e]);
     return O;
 }

@@ -43,6 +43,7 @@ typedef struct {
     float mm_lambda;          /* Spooner weighting of positive inventory PnL */
     float mm_rho;             /* quadratic inventory penalty factor */
     float pad_;
+    const int32_t *env_id;    /* [n_envs] env index used in the hash keys, or NULL (= position) */
 } or_config;
 
 /* ---- single book (unit tests) ---- */

@@ -1,0 +1,83 @@
+/*
+ * Device-side building blocks of the LOB environment step (gfx950, wave64).
+ *
+ * One wavefront owns one environment.  Its book lives in LDS as a structure of arrays:
+ * for side s (0 bids, 1 asks) and field f (price, qty, oid, tid, tsec, tns) the slots
+ * 0..n-1 are in priority order (best price first, then arrival).  Slot i of a side is
+ * handled by lane i % 64 in "row" i / 64, so every row access is one coalesced,
+ * bank-conflict-free LDS instruction.  Searches are ballots over rows, matching is a
+ * wave prefix scan over the crossing quantities, and insertion / removal shift a range
+ * of rows by whole-wave LDS copies.
+ *
+ * All control flow that decides what happens to the book is wave-uniform.  LDS accesses
+ * of one wavefront are performed in order by the hardware; WAVE_SYNC() stops the compiler
+ * from moving LDS loads and stores across the phases of a shift.
+ */
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define WAVE_SYNC() __asm__ volatile("" ::: "memory")
+
+namespace lobk {
+
+constexpr int WAVE = 64;
+constexpr int NF = 6; /* fields per slot */
+enum { FP = 0, FQ = 1, FO = 2, FT = 3, FS = 4, FN = 5 };
+enum { T_LIMIT = 1, T_PCANCEL = 2, T_DELETE = 3, T_MARKET = 4 };
+enum { C_MSGS, C_TRADES, C_MISS, C_EVICT, C_EVICTED_QTY, C_DROP, C_DROPPED_QTY, C_MARKET_UNFILLED,
+       C_BAD, C_TRADE_OVERFLOW, NCTR };
+
+/* ---------------------------------------------------------------- wave primitives */
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p ? 1 : 0); }
+
+__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ __forceinline__ int64_t rdlane64(int64_t v, int l) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+/* inclusive prefix sum over the 64 lanes (int64) */
+__device__ __forceinline__ int64_t wave_incl_scan64(int64_t x, int lane) {
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        int64_t y = __shfl_up(x, d, WAVE);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t x) {
+#pragma unroll
+    for (int d = WAVE / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, WAVE);
+    return x;
+}
+
+/* ---------------------------------------------------------------- counter hash
+ * SplitMix64's output function (Steele, Lea, Flood 2014) applied in a chain over the key
+ * words.  Used for the shuffle keys and the random policy. */
+__device__ __forceinline__ uint64_t sm64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t hash4(uint64_t seed, uint64_t dom, uint64_t a, uint64_t b, uint64_t c) {
+    return sm64(sm64(sm64(sm64(seed ^ dom) ^ a) ^ b) ^ c);
+}
+constexpr uint64_t DOM_SHUFFLE = 0x5348554646ULL;
+constexpr uint64_t DOM_ACTION = 0x414354ULL;
+
+} // namespace lobk

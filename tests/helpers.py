@@ -71,3 +71,18 @@ def book_lists(b, e):
 
 def msg(typ, side, price, qty, oid, tid=0, tsec=0, tns=0):
     return [typ | (side << 8), price, qty, oid, tid, tsec, tns]
+
+
+def subset_stream(stream, envs):
+    """The inputs of a subset of envs (same messages, CSR rebased), for sampled parity."""
+    envs = np.asarray(envs, dtype=np.int64)
+    off = stream.off
+    parts = [np.arange(off[e, 0], off[e, -1]) for e in envs]
+    idx = np.concatenate(parts) if parts else np.zeros(0, np.int64)
+    lens = off[envs, -1] - off[envs, 0]
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    new_off = off[envs] - off[envs, :1] + starts[:, None]
+    fields = [np.ascontiguousarray(f[idx]) for f in stream.msg_fields()]
+    hs = HandStream(np.ascontiguousarray(new_off), *fields)
+    book = {k: np.ascontiguousarray(v[envs]) for k, v in stream.book.items()}
+    return hs, book, np.ascontiguousarray(stream.caps[envs])

@@ -1,0 +1,260 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle, element by element.
+
+Books, trades, fills, counters and state must be bit-identical; rewards and
+observations are compared bit for bit as well (both sides evaluate the same double
+expression with contraction off and round once; observations are exact integers).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2511_02136_amd import synth
+from oracle import OracleEnvs
+from helpers import hand_stream, hand_book, msg, subset_stream
+from gpu_compare import assert_same_outputs, assert_same_books, assert_same_state
+
+pytestmark = pytest.mark.gpu
+
+LIMIT, PARTIAL_CANCEL, DELETE, MARKET = 1, 2, 3, 4
+BUY, SELL = 0, 1
+
+
+def _lob():
+    from paper_2511_02136_amd.lob import LobEnv, DeviceStream
+    return LobEnv, DeviceStream
+
+
+def oracle_for(stream_like, book, caps, max_cap, agents, ep_len, seed, env_ids=None, **kw):
+    o = OracleEnvs(caps, max_cap, synth.agent_kinds(agents), ep_len, seed, env_ids=env_ids, **kw)
+    o.reset(book)
+    return o
+
+
+def gpu_env(caps, max_cap, agents, ep_len, seed, book, **kw):
+    LobEnv, _ = _lob()
+    env = LobEnv(caps, max_cap, agents, ep_len, seed, **kw)
+    env.reset(book)
+    return env
+
+
+def run_steps(env, ds, n_steps, actions, trade_off):
+    """n_steps plain lob_step calls appending into one set of outputs."""
+    out = env._alloc_out(n_steps, True, True, trade_off, ds)
+    cursor = torch.zeros(env.n_envs, dtype=torch.int64, device=env.device)
+    for t in range(n_steps):
+        view = {k: (v[t:t + 1] if k not in ("trades", "trade_off") and v is not None else v) for k, v in out.items()}
+        a = None if actions is None else actions[t]
+        env.step(ds, a, out=view, cursor=cursor)
+    return out
+
+
+def parity_case(w: synth.Workload, n_steps: int, mode: str, given_actions=False, kw=None, name=""):
+    kw = kw or {}
+    print(f"\n[parity] {name or w.name} envs={w.n_envs} steps={n_steps} mode={mode}", flush=True)
+    _, DeviceStream = _lob()
+    s = synth.generate(w)
+    acts = None
+    if given_actions:
+        rng = np.random.default_rng(w.seed)
+        kinds = synth.agent_kinds(w.agents)
+        acts = np.stack([rng.integers(-1, 10 if k != 2 else 4, size=(n_steps, w.n_envs)) for k in kinds], 1).astype(np.int32)
+    o = oracle_for(s, s.book, s.caps, w.max_cap, w.agents, w.ep_len, w.seed, **kw)
+    ref = o.step(s, n_steps=n_steps, actions=acts)
+    env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book, **kw)
+    ds = DeviceStream.from_host(s)
+    toff = torch.from_numpy(ref["trade_off"]).cuda()
+    ta = None if acts is None else torch.from_numpy(acts).cuda()
+    if mode == "rollout":
+        got = env.rollout(ds, n_steps, actions=ta, trade_off=toff)
+    else:
+        got = run_steps(env, ds, n_steps, ta, toff)
+    torch.cuda.synchronize()
+    assert_same_outputs(got, ref, n_steps, what=name)
+    assert_same_books(env.books(), o.books(), what=name)
+    assert_same_state(env.state(), o.state(), what=name)
+    obs_now = env.observe().cpu().numpy()
+    assert np.array_equal(obs_now.view(np.int32), o.observe().view(np.int32))
+    return env, o
+
+
+SMALL = [
+    synth.Workload("replay_only", n_envs=3, n_steps=20, msgs_per_step=100, cap=100, seed=31),
+    synth.Workload("exec_mm", n_envs=64, n_steps=16, msgs_per_step=100, cap=100, agents=("exec", "mm"), seed=32),
+    synth.Workload("uneven", n_envs=96, n_steps=12, msgs_range=(1, 400), cap_choices=(50, 100, 200, 400),
+                   agents=("exec", "mm"), seed=33),
+    synth.Workload("three_agents_cap1000", n_envs=24, n_steps=10, msgs_per_step=400, burst_pct=10, burst_extra=480,
+                   cap=1000, agents=("exec", "mm", "dir"), seed=34),
+    synth.Workload("row_edges", n_envs=40, n_steps=12, msgs_range=(50, 300), cap_choices=(1, 2, 63, 64, 65, 127, 128, 129),
+                   agents=("mm", "dir"), seed=35, snapshot_fill_pct=100),
+    synth.Workload("tiny_books", n_envs=32, n_steps=16, msgs_per_step=60, cap=3, agents=("exec", "mm", "dir", "mm"),
+                   seed=36, snapshot_fill_pct=100),
+]
+
+
+@pytest.mark.parametrize("w", SMALL, ids=lambda w: w.name)
+@pytest.mark.parametrize("mode", ["step", "rollout"])
+def test_parity_small(w, mode):
+    parity_case(w, w.n_steps, mode, name=f"{w.name}/{mode}")
+
+
+@pytest.mark.parametrize("w", SMALL[1:4], ids=lambda w: w.name)
+def test_parity_given_actions(w):
+    parity_case(w, w.n_steps, "rollout", given_actions=True, name=f"{w.name}/given")
+
+
+def test_parity_reward_weights():
+    w = synth.Workload("weights", n_envs=48, n_steps=12, msgs_per_step=80, cap=64, agents=("mm", "exec", "mm"), seed=37)
+    parity_case(w, 12, "rollout", kw=dict(exec_penalty=0.07, mm_lambda=0.3, mm_rho=0.02, exec_task=60, exec_q0=3),
+                name="weights")
+
+
+def test_rollout_resumes_across_calls():
+    """128 = 5 + 7 steps in two rollouts equals the oracle's 12 steps (state carried)."""
+    _, DeviceStream = _lob()
+    w = synth.Workload("resume", n_envs=50, n_steps=12, msgs_range=(1, 200), cap_choices=(50, 100), agents=("exec", "mm"),
+                       seed=38)
+    s = synth.generate(w)
+    o = oracle_for(s, s.book, s.caps, w.max_cap, w.agents, w.ep_len, w.seed)
+    ref1 = o.step(s, n_steps=5)
+    ref2 = o.step(s, n_steps=7)
+    env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+    ds = DeviceStream.from_host(s)
+    g1 = env.rollout(ds, 5, trade_off=torch.from_numpy(ref1["trade_off"]).cuda())
+    g2 = env.rollout(ds, 7, trade_off=torch.from_numpy(ref2["trade_off"]).cuda())
+    assert_same_outputs(g1, ref1, 5, what="resume/1")
+    assert_same_outputs(g2, ref2, 7, what="resume/2")
+    assert_same_books(env.books(), o.books(), what="resume")
+
+
+def test_hand_scenario_on_gpu():
+    _, DeviceStream = _lob()
+    snap = hand_book([([[99, 10, 1, 0, 1, 0]], [[101, 10, 2, 0, 1, 5]])], 10)
+    steps = [[[msg(MARKET, BUY, 0, 15, 50, 0, 2, 0)], [msg(LIMIT, BUY, 103, 5, 51, 0, 2, 10)]]]
+    hs = hand_stream(steps)
+    kw = dict(exec_task=6, exec_q0=4, mm_q=10, exec_penalty=0.5)
+    o = oracle_for(hs, snap, np.array([10]), 10, ("exec", "mm"), 2, 5, **kw)
+    acts = np.array([[[4], [1]], [[8], [0]]], dtype=np.int32)
+    ref = o.step(hs, n_steps=2, actions=acts)
+    env = gpu_env(np.array([10]), 10, ("exec", "mm"), 2, 5, snap, **kw)
+    got = env.rollout(DeviceStream.from_host(hs), 2, actions=torch.from_numpy(acts).cuda(),
+                      trade_off=torch.from_numpy(ref["trade_off"]).cuda())
+    assert_same_outputs(got, ref, 2, what="hand")
+    assert got["reward"][:, :, 0].cpu().tolist() == [[4.0, 1.75], [6.0, -2.0]]
+
+
+def test_sweeps_across_rows_and_empty_sides():
+    """Market and limit orders that sweep several 64-slot rows; books emptied and
+    refilled; malformed messages; an empty side at reset."""
+    _, DeviceStream = _lob()
+    asks = [[1000 + k // 3, 1 + k % 5, 10 + k, 0, 1, k] for k in range(300)]
+    bids1 = [[990 - k // 4, 1 + k % 3, 20000 + k, 0, 1, k] for k in range(70)]
+    snap = hand_book([([], asks), (bids1, [])], 320)
+    e0 = [
+        [msg(MARKET, BUY, 0, 200, 5000), msg(LIMIT, BUY, 1030, 400, 5001), msg(9, BUY, 1, 1, 1),
+         msg(LIMIT, SELL, 1000, 0, 5002)],
+        [msg(MARKET, SELL, 0, 10_000, 5003), msg(PARTIAL_CANCEL, SELL, 0, 0, 200), msg(DELETE, SELL, 0, 0, 250)],
+        [msg(LIMIT, SELL, 1100, 3, 5004 + k) for k in range(150)] + [msg(LIMIT, BUY, 1200, 100, 6000)],
+    ]
+    e1 = [[msg(LIMIT, SELL, 999, 50, 7000)], [msg(MARKET, BUY, 0, 5, 7001)], [msg(DELETE, BUY, 0, 0, 10)]]
+    hs = hand_stream([e0, e1])
+    caps = np.array([320, 100])
+    for agents in ((), ("mm", "exec")):
+        o = oracle_for(hs, snap, caps, 320, agents, 3, 9)
+        ref = o.step(hs, n_steps=3)
+        env = gpu_env(caps, 320, agents, 3, 9, snap)
+        got = env.rollout(DeviceStream.from_host(hs), 3, trade_off=torch.from_numpy(ref["trade_off"]).cuda())
+        assert_same_outputs(got, ref, 3, what=f"sweeps{agents}")
+        assert_same_books(env.books(), o.books(), what=f"sweeps{agents}")
+        assert_same_state(env.state(), o.state(), what=f"sweeps{agents}")
+
+
+def test_trade_region_overflow_is_counted():
+    _, DeviceStream = _lob()
+    w = synth.Workload("overflow", n_envs=16, n_steps=8, msgs_per_step=100, cap=100, agents=("exec", "mm"), seed=39)
+    s = synth.generate(w)
+    small = np.concatenate([[0], np.cumsum(np.full(16, 5))]).astype(np.int64)
+    o = oracle_for(s, s.book, s.caps, w.max_cap, w.agents, w.ep_len, w.seed)
+    ref = o.step(s, n_steps=8, trade_off=small)
+    env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+    got = env.rollout(DeviceStream.from_host(s), 8, trade_off=torch.from_numpy(small).cuda())
+    assert_same_outputs(got, ref, 8, what="overflow")
+    st = o.state()
+    assert st["counters"][:, 9].sum() > 0
+    assert_same_state(env.state(), st, what="overflow")
+
+
+def test_call_order_errors():
+    LobEnv, DeviceStream = _lob()
+    from paper_2511_02136_amd.lob import LobError
+    w = synth.Workload("order", n_envs=4, n_steps=2, msgs_per_step=10, cap=16, agents=("mm",), seed=40)
+    s = synth.generate(w)
+    env = LobEnv(s.caps, 16, ("mm",), 2, 1)
+    ds = DeviceStream.from_host(s)
+    with pytest.raises(LobError):
+        env.step(ds)  # not reset
+    env.reset(s.book)
+    env.rollout(ds, 2)
+    with pytest.raises(LobError):
+        env.step(ds)  # episode over
+    with pytest.raises(LobError):
+        LobEnv(np.array([2000]), 2000, (), 2, 1)  # capacity beyond the supported maximum
+
+
+@pytest.mark.parametrize("name", ["uniform4096", "uneven8192"])
+def test_full_size_sampled_parity(name):
+    """Full-size workload in the launch configuration the benchmark times (persistent
+    rollout over all steps); a sample of envs is replayed on the oracle with the
+    recorded actions of the GPU and the same env ids."""
+    _, DeviceStream = _lob()
+    w = synth.WORKLOADS[name]
+    print(f"\n[parity] full-size {name}", flush=True)
+    s = synth.generate(w)
+    env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+    ds = DeviceStream.from_host(s)
+    got = env.rollout(ds, w.n_steps)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(w.n_envs, size=48, replace=False))
+    hs, book, caps = subset_stream(s, sample)
+    o = oracle_for(hs, book, caps, w.max_cap, w.agents, w.ep_len, w.seed, env_ids=sample)
+    acts = got["actions"].cpu().numpy()[:, :, sample]
+    ref = o.step(hs, n_steps=w.n_steps, actions=np.ascontiguousarray(acts))
+    # the GPU's trade regions differ from the subset's; compare records by content
+    g = {k: v for k, v in got.items()}
+    goff = got["trade_off"].cpu().numpy()
+    for j, e in enumerate(sample):
+        cnt = int(ref["n_trades"][:, j].sum())
+        gt = got["trades"][goff[e]: goff[e] + cnt].cpu().numpy()
+        assert np.array_equal(gt, ref["trades"][ref["trade_off"][j]: ref["trade_off"][j] + cnt]), e
+    g["trades"] = None
+    ref = dict(ref)
+    ref["trades"] = None
+    assert_same_outputs(g, ref, w.n_steps, envs=sample, what=name)
+    assert_same_books(env.books(), o.books(), envs=sample, what=name)
+    assert_same_state(env.state(), o.state(), envs=sample, what=name)
+    # random actions are uniform over each agent's action set
+    a = got["actions"].cpu().numpy()
+    assert a.min() >= 0 and a[:, 0].max() <= 8
+
+
+def test_plain_and_persistent_forms_identical_full_size():
+    """Property at full size: the per-step form and the persistent form agree exactly."""
+    _, DeviceStream = _lob()
+    w = synth.WORKLOADS["uneven8192"].scaled(n_steps=16)
+    s = synth.generate(w)
+    ds = DeviceStream.from_host(s)
+    e1 = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+    toff = ds.trade_regions(e1.caps, 0, 16, 2)
+    a = e1.rollout(ds, 16, trade_off=toff)
+    e2 = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+    b = run_steps(e2, ds, 16, None, toff)
+    torch.cuda.synchronize()
+    for k in ("n_trades", "fills", "reward", "obs", "done", "actions"):
+        assert torch.equal(a[k], b[k]), k
+    n = a["n_trades"].sum(0).cpu().numpy()
+    off = toff.cpu().numpy()
+    for e in range(0, w.n_envs, 97):
+        assert torch.equal(a["trades"][off[e]: off[e] + n[e]], b["trades"][off[e]: off[e] + n[e]]), e
+    ba, bb = e1.books(), e2.books()
+    for k in ba:
+        assert torch.equal(ba[k], bb[k]), k
