@@ -151,6 +151,29 @@ int lob_step(lob_ctx *ctx, const lob_msgs *msgs, const int32_t *actions, const l
 int lob_rollout(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps, const int32_t *actions,
                 const lob_out *out, void *stream);
 
+/* Schedule plan for the next n_steps from the current step: orders each capacity
+ * class's envs by decreasing message count (longest first), so that the envs that bound
+ * the runtime start first.  Reads the CSR offsets back to the host (synchronous).  Used by
+ * lob_step and lob_rollout until the next plan; results never depend on it. */
+int lob_plan(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps);
+
+/* The launch schedule, one record of 5 int32 per capacity class (host array):
+ * capacity slots per side, envs, waves (envs) per workgroup, mode (0: one wave per env
+ * dispatched by the hardware in plan order; 1: persistent workgroups pulling envs from a
+ * device work queue), workgroups in mode 1 (0 = from occupancy).  Returns the number of
+ * classes. */
+int lob_schedule_get(const lob_ctx *ctx, int32_t *out, int32_t max_classes);
+
+/* Set class k's schedule (waves 1, 2 or 4; mode 0 or 1; grid >= 0).  LOB_EUNSUPPORTED
+ * if the workgroup would need more than 64 KiB of LDS. */
+int lob_schedule_set(lob_ctx *ctx, int32_t k, int32_t waves, int32_t mode, int32_t grid);
+
+/* Autotuner: times every schedule of every class on the next n_steps of msgs (one
+ * class at a time, from the current state, restored afterwards) and keeps the fastest
+ * per class.  Makes a plan first.  Synchronous; the buffers of `out` are overwritten
+ * (scratch).  Allocates and frees temporary device memory for the state copy. */
+int lob_autotune(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps, const lob_out *out, void *stream);
+
 /* Observation of the current state, device float [n_agents][n_envs][40] (equal to the
  * last step's observation; after reset, the step statistics are zero). */
 int lob_observe(lob_ctx *ctx, float *obs, void *stream);

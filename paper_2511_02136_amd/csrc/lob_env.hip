@@ -46,20 +46,35 @@ constexpr int AGW = 8;            /* internal agent words: inv, cash, rem, ctr, 
 constexpr int STW = 4;            /* step statistics: buy vol, sell vol, trades, last price */
 
 /* per-wave LDS layout (int32 words) after the book (12 * capp words) */
-constexpr int X_ACT = 0;                    /* MAXACT x 8: ts, price, qty, oid, tid, tsec, tns, - */
-constexpr int X_PERM = X_ACT + MAXACT * 8;  /* MAXACT: shuffled order */
-constexpr int X_LV = X_PERM + MAXACT;       /* MAXLV x 4: side, price, desired qty, resting qty */
-constexpr int X_SEEN = X_LV + MAXLV * 4;    /* MAXLV: older resting qty seen in the walk */
-constexpr int X_AG = X_SEEN + MAXLV;        /* int64 MAXA x AGW */
-constexpr int X_FL = X_AG + MAXA * AGW * 2; /* int64 MAXA x 4: fills of the step */
-constexpr int X_OBK = X_FL + MAXA * 4 * 2;  /* int64 34: depth buckets, totals, own stats */
+constexpr int X_ACT = 0;                          /* MAXACT x 8: ts, price, qty, oid, tid, tsec, tns, - */
+constexpr int X_PERM = X_ACT + MAXACT * 8;        /* MAXACT: shuffled order */
+constexpr int X_LV = X_PERM + MAXACT;             /* MAXA x MAXLV x 4: side, price, desired, resting */
+constexpr int X_SEEN = X_LV + MAXA * MAXLV * 4;   /* MAXA x MAXLV: older resting qty seen in the walk */
+constexpr int X_NLV = X_SEEN + MAXA * MAXLV;      /* MAXA (+pad): desired levels per agent */
+constexpr int X_AG = X_NLV + 8;                   /* int64 MAXA x AGW */
+constexpr int X_FL = X_AG + MAXA * AGW * 2;       /* int64 MAXA x 4: fills of the step */
+constexpr int X_OBK = X_FL + MAXA * 4 * 2;        /* int64 34: depth buckets, totals, own stats */
 constexpr int N_OBK = 22 + 3 * MAXA;
-constexpr int X_END = X_OBK + 34 * 2;
+constexpr int X_CTR = X_OBK + 34 * 2;             /* int64 NCTR: counters */
+constexpr int X_ENV = X_CTR + NCTR * 2;           /* int64 8: env state (global layout) */
+constexpr int X_ST = X_ENV + 8 * 2;               /* int64 STW: last step's statistics */
+constexpr int X_END = X_ST + STW * 2;
 constexpr int EXTRA_WORDS = (X_END + 63) & ~63;
 static_assert(N_OBK <= 34, "obs accumulator area");
-static_assert((X_AG & 1) == 0 && (X_FL & 1) == 0 && (X_OBK & 1) == 0, "int64 alignment");
+static_assert((X_AG & 1) == 0 && (X_FL & 1) == 0 && (X_OBK & 1) == 0 && (X_CTR & 1) == 0 &&
+              (X_ENV & 1) == 0 && (X_ST & 1) == 0, "int64 alignment");
 
-inline int lds_words_for(int capp) { return 2 * NF * capp + EXTRA_WORDS; }
+__host__ __device__ constexpr int lds_words_for(int capp) { return 2 * NF * capp + EXTRA_WORDS; }
+
+/* book rows per capacity class (compiled variants) */
+constexpr int ROW_CLASSES[] = {1, 2, 4, 7, 8, 16};
+inline int rows_for_cap(int cap) {
+    const int need = (cap + 63) / 64;
+    for (int r : ROW_CLASSES)
+        if (r >= need) return r;
+    return -1;
+}
+
 
 struct KArgs {
     /* configuration */
@@ -96,36 +111,45 @@ struct KArgs {
 };
 
 /* ------------------------------------------------------------------------------
- * One environment run by one wavefront.
+ * One environment run by one wavefront; ROWS = book rows of 64 slots per side.
  * ---------------------------------------------------------------------------- */
+template <int ROWS>
 struct Run {
+    static constexpr int CAPP = ROWS * WAVE; /* slots per side in LDS (compile time) */
+    static constexpr int capp = CAPP;
     const KArgs &a;
-    int32_t *L; /* this wave's LDS */
-    int lane, capp, cap, e, A;
+    int32_t *L;  /* this wave's LDS (uniform) */
+    int2 *Pl;    /* this lane's slot of row 0, side 0, pair 0 */
+    int lane, cap, e, A, t;
     /* book */
     int n0, n1, best0, best1;
-    /* env state */
-    int32_t last_bb, last_ba, last_tsec, last_tns, t;
-    int64_t mid2_prev, p_init2, last_dmid2;
-    int64_t ctr[NCTR];
-    /* trade records */
-    int64_t tr_base, tr_cap, tr_cur;
-    /* per step */
-    int64_t mid_sum, st_buy, st_sell, st_trades;
-    int32_t mid_n, seq, st_last;
+    /* per step, hot */
+    int64_t mid_sum, st_buy, st_sell;
+    int32_t mid_n, seq, st_trades, st_last, last_tsec, last_tns;
+    /* trade records: absolute record indices of the env's region */
+    int64_t tr_next, tr_end, tr_step0;
 
     __device__ Run(const KArgs &args, int32_t *lds, int env)
-        : a(args), L(lds), lane(lane_id()), capp(args.capp), e(env), A(args.n_agents) {
-        cap = a.caps[e];
+        : a(args), L(lds), lane(lane_id()), e(uni(env)), A(args.n_agents) {
+        Pl = reinterpret_cast<int2 *>(lds) + lane;
+        cap = uni(a.caps[e]);
     }
+    /* this lane's slot of row 0 of side s, pair p (row r is +r*64: an immediate offset) */
+    __device__ __forceinline__ int2 *RowP(int s, int p) { return Pl + (s * 3 + p) * CAPP; }
 
-    /* ---- LDS views ---- */
-    __device__ __forceinline__ int32_t &B(int s, int f, int i) { return L[(s * NF + f) * capp + i]; }
+    /* ---- LDS views: per side three int2 arrays (price|qty, oid|tid, tsec|tns) ---- */
+    __device__ __forceinline__ int2 *PR(int s, int pair) {
+        return reinterpret_cast<int2 *>(L) + (s * 3 + pair) * capp;
+    }
+    __device__ __forceinline__ int32_t &B(int s, int f, int i) {
+        return L[((s * 3 + (f >> 1)) * capp + i) * 2 + (f & 1)];
+    }
     __device__ __forceinline__ int32_t *X() { return L + 2 * NF * capp; }
-    __device__ __forceinline__ int64_t *AG(int i) { return reinterpret_cast<int64_t *>(X() + X_AG) + i * AGW; }
-    __device__ __forceinline__ int64_t *FL(int i) { return reinterpret_cast<int64_t *>(X() + X_FL) + i * 4; }
-    __device__ __forceinline__ int64_t *OBK() { return reinterpret_cast<int64_t *>(X() + X_OBK); }
-    __device__ __forceinline__ int32_t *LV(int k) { return X() + X_LV + k * 4; }
+    __device__ __forceinline__ int64_t *X64(int off) { return reinterpret_cast<int64_t *>(X() + off); }
+    __device__ __forceinline__ int64_t *AG(int i) { return X64(X_AG) + i * AGW; }
+    __device__ __forceinline__ int64_t *FL(int i) { return X64(X_FL) + i * 4; }
+    __device__ __forceinline__ int32_t *LV(int ai, int k) { return X() + X_LV + (ai * MAXLV + k) * 4; }
+    __device__ __forceinline__ int64_t *ENV() { return X64(X_ENV); }
 
     __device__ __forceinline__ int nsz(int s) const { return s ? n1 : n0; }
     __device__ __forceinline__ void set_n(int s, int v) {
@@ -139,21 +163,41 @@ struct Run {
         int v = nsz(s) > 0 ? uni(B(s, FP, 0)) : 0;
         set_best(s, v);
     }
+    /* counters live in LDS; lane 0 adds (no return value, no wait) */
+    __device__ __forceinline__ void count(int k, int64_t v) {
+        if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long *>(X64(X_CTR) + k), (unsigned long long)v);
+    }
 
-    /* ---- row shifts (wave-wide LDS copies) ---- */
-    /* move slots [from, to) of side s to [from+1, to+1); to < capp */
+    /* ---- row shifts: groups of four rows, all loads of a group before its stores;
+     * rows are unrolled so every access is an immediate LDS offset ---- */
+    /* move slots [from, to) of side s to [from+1, to+1); to < CAPP */
     __device__ __forceinline__ void shift_up(int s, int from, int to) {
         if (to <= from) return;
-        for (int r = to >> 6; r >= ((from + 1) >> 6); --r) {
-            const int i = (r << 6) + lane;
-            const bool mv = i > from && i <= to;
-            int v[NF];
+        int2 *d0 = RowP(s, 0);
+        int2 *d1 = d0 + CAPP, *d2 = d0 + 2 * CAPP;
+        int2 *s0 = d0 - 1;
+        int2 *s1 = s0 + CAPP, *s2 = s0 + 2 * CAPP;
+        const int rlo = (from + 1) >> 6, rhi = to >> 6;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) v[f] = mv ? B(s, f, max(i - 1, 0)) : 0;
+        for (int g = (ROWS - 1) / 4; g >= 0; --g) {
+            if (g * 4 > rhi || g * 4 + 3 < rlo) continue;
+            int2 v0[4], v1[4], v2[4];
+            bool mv[4];
+#pragma unroll
+            for (int k = 3; k >= 0; --k) {
+                const int r = g * 4 + k;
+                mv[k] = false;
+                if (r < ROWS && r >= rlo && r <= rhi) {
+                    const int i = r * WAVE + lane;
+                    mv[k] = i > from && i <= to;
+                    if (mv[k]) { v0[k] = s0[r * WAVE]; v1[k] = s1[r * WAVE]; v2[k] = s2[r * WAVE]; }
+                }
+            }
             WAVE_SYNC();
-            if (mv) {
 #pragma unroll
-                for (int f = 0; f < NF; ++f) B(s, f, i) = v[f];
+            for (int k = 3; k >= 0; --k) {
+                const int r = g * 4 + k;
+                if (r < ROWS && mv[k]) { d0[r * WAVE] = v0[k]; d1[r * WAVE] = v1[k]; d2[r * WAVE] = v2[k]; }
             }
             WAVE_SYNC();
         }
@@ -162,28 +206,70 @@ struct Run {
     __device__ __forceinline__ void shift_down(int s, int at, int k, int n) {
         const int newn = n - k;
         if (k <= 0 || at >= newn) return;
-        for (int r = at >> 6; (r << 6) < newn; ++r) {
-            const int i = (r << 6) + lane;
-            const bool mv = i >= at && i < newn;
-            int v[NF];
+        int2 *d0 = RowP(s, 0);
+        int2 *d1 = d0 + CAPP, *d2 = d0 + 2 * CAPP;
+        const int2 *s0 = d0 + k;
+        const int2 *s1 = s0 + CAPP, *s2 = s0 + 2 * CAPP;
+        const int rlo = at >> 6, rhi = (newn - 1) >> 6;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) v[f] = mv ? B(s, f, min(i + k, capp - 1)) : 0;
+        for (int g = 0; g <= (ROWS - 1) / 4; ++g) {
+            if (g * 4 > rhi || g * 4 + 3 < rlo) continue;
+            int2 v0[4], v1[4], v2[4];
+            bool mv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = g * 4 + q;
+                mv[q] = false;
+                if (r < ROWS && r >= rlo && r <= rhi) {
+                    const int i = r * WAVE + lane;
+                    mv[q] = i >= at && i < newn;
+                    if (mv[q]) { v0[q] = s0[r * WAVE]; v1[q] = s1[r * WAVE]; v2[q] = s2[r * WAVE]; }
+                }
+            }
             WAVE_SYNC();
-            if (mv) {
 #pragma unroll
-                for (int f = 0; f < NF; ++f) B(s, f, i) = v[f];
+            for (int q = 0; q < 4; ++q) {
+                const int r = g * 4 + q;
+                if (r < ROWS && mv[q]) { d0[r * WAVE] = v0[q]; d1[r * WAVE] = v1[q]; d2[r * WAVE] = v2[q]; }
             }
             WAVE_SYNC();
         }
     }
     __device__ __forceinline__ void put(int s, int i, int p, int q, int o, int tid, int ts, int tn) {
         if (lane == 0) {
-            B(s, FP, i) = p; B(s, FQ, i) = q; B(s, FO, i) = o;
-            B(s, FT, i) = tid; B(s, FS, i) = ts; B(s, FN, i) = tn;
+            int2 *u = reinterpret_cast<int2 *>(L) + s * 3 * CAPP + i;
+            u[0] = make_int2(p, q);
+            u[CAPP] = make_int2(o, tid);
+            u[2 * CAPP] = make_int2(ts, tn);
         }
         WAVE_SYNC();
     }
-
+    /* first index in [i0, n) of side s whose field f equals v, or -1 (4 rows per wait) */
+    __device__ __forceinline__ int find_eq(int s, int f, int i0, int n, int v) {
+        const int32_t *col = reinterpret_cast<const int32_t *>(RowP(s, f >> 1)) + (f & 1);
+        const int rlo = i0 >> 6, rhi = (n - 1) >> 6;
+#pragma unroll
+        for (int g = 0; g <= (ROWS - 1) / 4; ++g) {
+            if (n <= 0 || g * 4 > rhi || g * 4 + 3 < rlo) continue;
+            int x[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = g * 4 + q;
+                x[q] = ~v;
+                if (r < ROWS && r >= rlo && r <= rhi) x[q] = col[r * WAVE * 2];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = g * 4 + q;
+                if (r < ROWS && r >= rlo && r <= rhi) {
+                    const int i = r * WAVE + lane;
+                    const uint64_t m = ballot(i >= i0 && i < n && x[q] == v);
+                    if (m) return r * WAVE + __builtin_ctzll(m);
+                }
+            }
+        }
+        return -1;
+    }
     /* ---- fills (uniform accumulation in LDS by lane 0) ---- */
     __device__ __forceinline__ void add_fill(int tid, int buy, int64_t q, int64_t notional) {
         if (tid >= 1 && tid <= A) {
@@ -198,22 +284,16 @@ struct Run {
 
     /* ---- trade records ---- */
     __device__ __forceinline__ void write_trade(int64_t k, int price, int q, int agg_oid, int pas_oid,
-                                                int agg_tid, int pas_tid, int side, int sq) {
-        const int64_t rec = tr_cur + k;
-        if (a.trades && rec < tr_cap) {
-            int4 *p = reinterpret_cast<int4 *>(a.trades + (tr_base + rec) * LOB_TRADE_WORDS);
+                                                int agg_tid, int pas_tid, int side) {
+        const int64_t rec = tr_next + k;
+        if (rec < tr_end) {
+            int4 *p = reinterpret_cast<int4 *>(a.trades + rec * LOB_TRADE_WORDS);
             p[0] = make_int4(price, q, agg_oid, pas_oid);
-            p[1] = make_int4(agg_tid, pas_tid, side | (sq << 1), t);
+            p[1] = make_int4(agg_tid, pas_tid, side | (seq << 1), t);
         }
     }
     __device__ __forceinline__ void close_trades(int ntr, int64_t volume, int side, int last_price) {
-        if (ntr <= 0) return;
-        const int64_t end = tr_cur + ntr;
-        const int64_t room = tr_cap > tr_cur ? tr_cap - tr_cur : 0;
-        if (ntr > room) ctr[C_TRADE_OVERFLOW] += ntr - room;
-        (void)end;
-        tr_cur += ntr;
-        ctr[C_TRADES] += ntr;
+        tr_next += ntr;
         st_trades += ntr;
         if (side == 0) st_buy += volume; else st_sell += volume;
         st_last = last_price;
@@ -222,18 +302,19 @@ struct Run {
     /* ---- matching: an incoming order of side `side` against the opposite side while it
      * crosses (market orders cross at any price); trades at the resting price.  Returns
      * the unmatched remainder. ---- */
-    __device__ int match(int side, int p, int q, bool market, int agg_oid, int agg_tid) {
+    __device__ __forceinline__ int match(int side, int p, int q, bool market, int agg_oid, int agg_tid) {
         const int opp = 1 - side;
         const int no = nsz(opp);
         if (no == 0 || q <= 0) return q;
         const int bp = best(opp);
         if (!(market || (side == 0 ? bp <= p : bp >= p))) return q;
+        const int2 top = PR(opp, 1)[0];
         const int bq = uni(B(opp, FQ, 0));
         if (bq >= q) {
             /* the best order alone covers the incoming quantity */
-            const int poid = uni(B(opp, FO, 0));
-            const int ptid = uni(B(opp, FT, 0));
-            if (lane == 0) write_trade(0, bp, q, agg_oid, poid, agg_tid, ptid, side, seq);
+            const int poid = uni(top.x);
+            const int ptid = uni(top.y);
+            if (lane == 0) write_trade(0, bp, q, agg_oid, poid, agg_tid, ptid, side);
             add_fill(agg_tid, side == 0, q, (int64_t)q * bp);
             add_fill(ptid, side != 0, q, (int64_t)q * bp);
             if (bq == q) {
@@ -254,8 +335,9 @@ struct Run {
         for (int r = 0; r < rows; ++r) {
             const int i = (r << 6) + lane;
             const bool valid = i < no;
-            const int pr = valid ? B(opp, FP, i) : 0;
-            const int qt = valid ? B(opp, FQ, i) : 0;
+            int2 pq = make_int2(0, 0), ot = make_int2(0, 0);
+            if (valid) { pq = RowP(opp, 0)[r * WAVE]; ot = RowP(opp, 1)[r * WAVE]; }
+            const int pr = pq.x, qt = pq.y;
             const bool cr = valid && (market || (side == 0 ? pr <= p : pr >= p));
             const int64_t x = cr ? (int64_t)qt : 0;
             const int64_t incl = wave_incl_scan64(x, lane) + carry;
@@ -263,11 +345,9 @@ struct Run {
             const int take = (cr && excl < q) ? (int)min((int64_t)qt, (int64_t)q - excl) : 0;
             const bool has = take > 0;
             const uint64_t hm = ballot(has);
-            int ptid = 0;
+            const int ptid = ot.y;
             if (has) {
-                const int poid = B(opp, FO, i);
-                ptid = B(opp, FT, i);
-                write_trade(ntr + lane, pr, take, agg_oid, poid, agg_tid, ptid, side, seq);
+                write_trade(ntr + lane, pr, take, agg_oid, ot.x, agg_tid, ptid, side);
                 if (take < qt) B(opp, FQ, i) = qt - take;
                 my_notional += (int64_t)take * pr;
             }
@@ -304,33 +384,51 @@ struct Run {
     /* ---- rest a limit remainder on its own side (after all orders at an equal or
      * better price); a full side evicts its worst order if the price is strictly
      * better than that order's, else the remainder is dropped. ---- */
-    __device__ void rest(int side, int p, int q, int oid, int tid, int ts, int tn) {
+    __device__ __forceinline__ void rest(int side, int p, int q, int oid, int tid, int ts, int tn) {
         const int n = nsz(side);
         int pos = 0;
-        const int rows = (n + 63) >> 6;
-        for (int r = 0; r < rows; ++r) {
-            const int i = (r << 6) + lane;
-            const bool valid = i < n;
-            const int pr = valid ? B(side, FP, i) : 0;
-            const bool be = valid && (side == 0 ? pr >= p : pr <= p);
-            const int c = __popcll(ballot(be));
-            pos += c;
-            if (c < 64) break;
+        {
+            const int32_t *col = reinterpret_cast<const int32_t *>(RowP(side, 0));
+            const int rhi = (n - 1) >> 6;
+            bool stop = n <= 0;
+#pragma unroll
+            for (int g = 0; g <= (ROWS - 1) / 4; ++g) {
+                if (stop || g * 4 > rhi) continue;
+                int x[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = g * 4 + q;
+                    x[q] = 0;
+                    if (r < ROWS && r <= rhi) x[q] = col[r * WAVE * 2];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = g * 4 + q;
+                    if (!stop && r < ROWS && r <= rhi) {
+                        const int i = r * WAVE + lane;
+                        const bool be = i < n && (side == 0 ? x[q] >= p : x[q] <= p);
+                        const int c = __popcll(ballot(be));
+                        pos += c;
+                        stop = c < WAVE;
+                    }
+                }
+            }
         }
         if (n < cap) {
             shift_up(side, pos, n);
             put(side, pos, p, q, oid, tid, ts, tn);
             set_n(side, n + 1);
         } else {
-            const int wp = uni(B(side, FP, n - 1));
+            const int2 w = PR(side, 0)[n - 1];
+            const int wp = uni(w.x);
             const bool better = side == 0 ? p > wp : p < wp;
             if (!better) {
-                ctr[C_DROP] += 1;
-                ctr[C_DROPPED_QTY] += q;
+                count(C_DROP, 1);
+                count(C_DROPPED_QTY, q);
                 return;
             }
-            ctr[C_EVICT] += 1;
-            ctr[C_EVICTED_QTY] += uni(B(side, FQ, n - 1));
+            count(C_EVICT, 1);
+            count(C_EVICTED_QTY, uni(w.y));
             shift_up(side, pos, n - 1);
             put(side, pos, p, q, oid, tid, ts, tn);
         }
@@ -338,20 +436,11 @@ struct Run {
     }
 
     /* ---- cancels: the first order with this id on the message's side ---- */
-    __device__ void cancel(bool partial, int side, int qty, int oid) {
+    __device__ __forceinline__ void cancel(bool partial, int side, int qty, int oid) {
         const int n = nsz(side);
-        int found = -1;
-        const int rows = (n + 63) >> 6;
-        for (int r = 0; r < rows; ++r) {
-            const int i = (r << 6) + lane;
-            const uint64_t m = ballot(i < n && B(side, FO, i) == oid);
-            if (m) {
-                found = (r << 6) + __builtin_ctzll(m);
-                break;
-            }
-        }
+        const int found = find_eq(side, FO, 0, n, oid);
         if (found < 0) {
-            ctr[C_MISS] += 1;
+            count(C_MISS, 1);
             return;
         }
         if (partial) {
@@ -368,24 +457,31 @@ struct Run {
         if (found == 0) refresh_best(side);
     }
 
-    /* ---- one message of the step sequence ---- */
-    __device__ void process(int ts, int price, int qty, int oid, int tid, int tsec, int tns) {
+    /* ---- one message of the step sequence (the only call site of the book ops) ---- */
+    __device__ __forceinline__ void process(int ts, int price, int qty, int oid, int tid, int tsec, int tns) {
         const int type = ts & 0xFF, side = (ts >> 8) & 1;
-        ctr[C_MSGS] += 1;
         if (type == T_LIMIT || type == T_MARKET) {
             if (qty <= 0) {
-                ctr[C_BAD] += 1;
+                count(C_BAD, 1);
             } else {
                 const int q = match(side, price, qty, type == T_MARKET, oid, tid);
-                if (type == T_MARKET) ctr[C_MARKET_UNFILLED] += q;
-                else if (q > 0) rest(side, price, q, oid, tid, tsec, tns);
+                if (type == T_MARKET) {
+                    if (q > 0) count(C_MARKET_UNFILLED, q);
+                } else if (q > 0) {
+                    rest(side, price, q, oid, tid, tsec, tns);
+                }
             }
         } else if (type == T_PCANCEL || type == T_DELETE) {
-            if (type == T_PCANCEL && qty <= 0) ctr[C_BAD] += 1;
+            if (type == T_PCANCEL && qty <= 0) count(C_BAD, 1);
             else cancel(type == T_PCANCEL, side, qty, oid);
         } else {
-            ctr[C_BAD] += 1;
+            count(C_BAD, 1);
         }
+        after_message(tsec, tns);
+    }
+    /* per message of the sequence: its time becomes the last processed time; mid
+     * statistics for the reward (both sides non-empty); message index */
+    __device__ __forceinline__ void after_message(int tsec, int tns) {
         last_tsec = tsec;
         last_tns = tns;
         if (n0 > 0 && n1 > 0) {
@@ -395,41 +491,33 @@ struct Run {
         seq += 1;
     }
 
-    /* ---- desired levels of one agent (LDS, written by lane 0) ---- */
-    __device__ __forceinline__ void add_level(int &nlv, int side, int price, int qty) {
+    /* ---- desired levels of agent ai (LDS, written by lane 0) ---- */
+    __device__ __forceinline__ void add_level(int ai, int &nlv, int side, int price, int qty) {
         int k = 0;
         for (; k < nlv; ++k)
-            if (uni(LV(k)[0]) == side && uni(LV(k)[1]) == price) break;
+            if (uni(LV(ai, k)[0]) == side && uni(LV(ai, k)[1]) == price) break;
         if (k < nlv) {
-            if (lane == 0) LV(k)[2] += qty;
+            if (lane == 0) LV(ai, k)[2] += qty;
         } else if (nlv < MAXLV) {
             if (lane == 0) {
-                LV(k)[0] = side; LV(k)[1] = price; LV(k)[2] = qty; LV(k)[3] = 0;
+                int32_t *l = LV(ai, k);
+                l[0] = side; l[1] = price; l[2] = qty; l[3] = 0;
             }
             nlv += 1;
         }
         WAVE_SYNC();
     }
-    __device__ __forceinline__ int find_level(int nlv, int side, int price) {
+    __device__ __forceinline__ int find_level(int ai, int nlv, int side, int price) {
         for (int k = 0; k < nlv; ++k)
-            if (uni(LV(k)[0]) == side && uni(LV(k)[1]) == price) return k;
-        return -1;
-    }
-    /* first index >= i0 on side s holding an order of trader tid, or -1 */
-    __device__ __forceinline__ int next_own(int s, int i0, int tid) {
-        const int n = nsz(s);
-        for (int r = i0 >> 6; (r << 6) < n; ++r) {
-            const int i = (r << 6) + lane;
-            const uint64_t m = ballot(i >= i0 && i < n && B(s, FT, i) == tid);
-            if (m) return (r << 6) + __builtin_ctzll(m);
-        }
+            if (uni(LV(ai, k)[0]) == side && uni(LV(ai, k)[1]) == price) return k;
         return -1;
     }
 
-    /* Sec. 4 step 1 for agent i: decode its action into desired levels (Sec. 4.1),
-     * then cancel / top up its resting orders against them; new orders are appended to
-     * the action block. */
-    __device__ void agent_actions(int i, int act, int bb0, int ba0, int &nact) {
+    /* Sec. 4 step 1, from the book at step start, for agent i: decode its action into
+     * desired levels (Sec. 4.1), measure its resting quantity at each of them and append
+     * its new orders (the difference to the desired quantity, then any market order) to
+     * the action block.  The cancels are emitted later, in the message loop. */
+    __device__ __forceinline__ void agent_start(int i, int act, int bb0, int ba0, int &nact) {
         const int kind = (a.kinds >> (4 * i)) & 15;
         const int tid = i + 1;
         int nlv = 0;
@@ -467,7 +555,7 @@ struct Run {
                     left -= q;
                     if (q > 0) {
                         if (market) mkt += q;
-                        else add_level(nlv, 1, pp[k], (int)q);
+                        else add_level(i, nlv, 1, pp[k], (int)q);
                     }
                 }
             }
@@ -488,69 +576,50 @@ struct Run {
             default: break;
             }
             if (act == 8) {
-                for (int o = 0; o < 4; ++o) add_level(nlv, 0, min(bb0 - o, ba0 - 1), q);
-                for (int o = 0; o < 4; ++o) add_level(nlv, 1, max(ba0 + o, bb0 + 1), q);
+                for (int o = 0; o < 4; ++o) add_level(i, nlv, 0, min(bb0 - o, ba0 - 1), q);
+                for (int o = 0; o < 4; ++o) add_level(i, nlv, 1, max(ba0 + o, bb0 + 1), q);
             } else {
-                if (hb) add_level(nlv, 0, min(bb0 - ob, ba0 - 1), q);
-                if (ha) add_level(nlv, 1, max(ba0 + oa, bb0 + 1), q);
+                if (hb) add_level(i, nlv, 0, min(bb0 - ob, ba0 - 1), q);
+                if (ha) add_level(i, nlv, 1, max(ba0 + oa, bb0 + 1), q);
             }
         } else {
             /* directional: take the opposite touch with a fixed quantity */
-            if (act == 1) add_level(nlv, 0, ba0, a.dir_q);
-            if (act == 2) add_level(nlv, 1, bb0, a.dir_q);
+            if (act == 1) add_level(i, nlv, 0, ba0, a.dir_q);
+            if (act == 2) add_level(i, nlv, 1, bb0, a.dir_q);
         }
+        if (lane == 0) X()[X_NLV + i] = nlv;
+        if (lane < MAXLV) X()[X_SEEN + i * MAXLV + lane] = 0;
+        WAVE_SYNC();
 
         /* resting quantity of this agent at each desired level (step start) */
-        for (int s = 0; s < 2; ++s) {
-            int i0 = 0;
-            for (;;) {
-                const int j = next_own(s, i0, tid);
-                if (j < 0) break;
-                const int k = find_level(nlv, s, uni(B(s, FP, j)));
-                if (k >= 0) {
-                    if (lane == 0) LV(k)[3] += B(s, FQ, j);
-                    WAVE_SYNC();
-                }
-                i0 = j + 1;
-            }
-        }
-        if (lane < MAXLV) X()[X_SEEN + lane] = 0;
-        WAVE_SYNC();
-        /* walk the agent's resting orders in book order (bids, then asks): delete those at
-         * levels it no longer wants; at a kept level take any excess from the newest */
-        for (int s = 0; s < 2; ++s) {
-            int i0 = 0;
-            for (;;) {
-                const int j = next_own(s, i0, tid);
-                if (j < 0) break;
-                const int pr = uni(B(s, FP, j)), qt = uni(B(s, FQ, j)), oid = uni(B(s, FO, j));
-                const int k = find_level(nlv, s, pr);
-                const int D = k >= 0 ? uni(LV(k)[2]) : 0;
-                if (D == 0) {
-                    process(T_DELETE | (s << 8), pr, qt, oid, tid, last_tsec, last_tns);
-                    i0 = j;
-                    continue;
-                }
-                const int R = uni(LV(k)[3]);
-                const int older = uni(X()[X_SEEN + k]);
-                if (lane == 0) X()[X_SEEN + k] = older + qt;
-                WAVE_SYNC();
-                if (R > D) {
-                    const int need = R - D;
-                    const int newer = R - older - qt;
-                    const int x = min(max(need - newer, 0), qt);
-                    if (x > 0) {
-                        process(T_PCANCEL | (s << 8), pr, x, oid, tid, last_tsec, last_tns);
-                        i0 = (x == qt) ? j : j + 1;
-                        continue;
+        if (nlv > 0) {
+            for (int s = 0; s < 2; ++s) {
+                const int n = nsz(s);
+                int i0 = 0;
+                for (;;) {
+                    const int j = find_eq(s, FT, i0, n, tid);
+                    if (j < 0) break;
+                    const int k = find_level(i, nlv, s, uni(B(s, FP, j)));
+                    if (k >= 0) {
+                        if (lane == 0) LV(i, k)[3] += B(s, FQ, j);
+                        WAVE_SYNC();
                     }
+                    i0 = j + 1;
                 }
-                i0 = j + 1;
             }
         }
-        /* new orders: the difference to the desired quantity, then any market order */
-        auto append = [&](int type, int side, int price, int qty) {
-            int64_t *g = AG(i);
+        /* new orders; order ids from the agent's counter */
+        int64_t *g = AG(i);
+        for (int k = 0; k <= nlv; ++k) {
+            int type, side, price, qty;
+            if (k < nlv) {
+                const int D = uni(LV(i, k)[2]), R = uni(LV(i, k)[3]);
+                if (D <= R) continue;
+                type = T_LIMIT; side = uni(LV(i, k)[0]); price = uni(LV(i, k)[1]); qty = D - R;
+            } else {
+                if (mkt <= 0) continue;
+                type = T_MARKET; side = 1; price = 0; qty = (int)mkt;
+            }
             const int64_t c = uni64(g[3]);
             const int oid = (int)((1u << 30) | ((uint32_t)i << 26) | (uint32_t)(c & ((1 << 26) - 1)));
             if (lane == 0) {
@@ -561,36 +630,31 @@ struct Run {
             }
             WAVE_SYNC();
             nact += 1;
-        };
-        for (int k = 0; k < nlv; ++k) {
-            const int D = uni(LV(k)[2]), R = uni(LV(k)[3]);
-            if (D > R) append(T_LIMIT, uni(LV(k)[0]), uni(LV(k)[1]), D - R);
         }
-        if (mkt > 0) append(T_MARKET, 1, 0, (int)mkt);
     }
 
     /* ---- observation features from the book (LDS accumulators) ---- */
-    __device__ void book_obs() {
-        int64_t *O = OBK();
+    __device__ __forceinline__ void book_obs(int bb, int ba) {
+        int64_t *O = X64(X_OBK);
         if (lane < 34) O[lane] = 0;
         WAVE_SYNC();
-        const int bb = last_bb, ba = last_ba;
         for (int s = 0; s < 2; ++s) {
             const int n = nsz(s);
             int64_t tot = 0;
             for (int r = 0; (r << 6) < n; ++r) {
                 const int i = (r << 6) + lane;
                 if (i < n) {
-                    const int pr = B(s, FP, i), qt = B(s, FQ, i), td = B(s, FT, i);
-                    const int64_t d = s == 0 ? (int64_t)bb - pr : (int64_t)pr - ba;
+                    const int2 pq = PR(s, 0)[i];
+                    const int td = B(s, FT, i);
+                    const int64_t d = s == 0 ? (int64_t)bb - pq.x : (int64_t)pq.x - ba;
                     if (d >= 0 && d <= 9)
-                        atomicAdd(reinterpret_cast<unsigned long long *>(O + s * 10 + d), (unsigned long long)qt);
+                        atomicAdd(reinterpret_cast<unsigned long long *>(O + s * 10 + d), (unsigned long long)pq.y);
                     if (td >= 1 && td <= A) {
                         atomicAdd(reinterpret_cast<unsigned long long *>(O + 22 + 3 * (td - 1) + s),
-                                  (unsigned long long)qt);
+                                  (unsigned long long)pq.y);
                         atomicAdd(reinterpret_cast<unsigned long long *>(O + 22 + 3 * (td - 1) + 2), 1ull);
                     }
-                    tot += qt;
+                    tot += pq.y;
                 }
             }
             tot = wave_sum64(tot);
@@ -599,11 +663,15 @@ struct Run {
             WAVE_SYNC();
         }
     }
-    /* write the 40 features of every agent for output step slot s_idx */
-    __device__ void write_obs(float *base /* [A][n_envs][40] */) {
-        book_obs();
-        const int64_t *O = OBK();
-        const int64_t mid2 = (int64_t)last_bb + last_ba;
+    /* the 40 features of every agent from the state in LDS, written to base [A][n_envs][40] */
+    __device__ __forceinline__ void write_obs(float *base) {
+        const int64_t *E = ENV();
+        const int64_t *S = X64(X_ST);
+        const int bb = (int)uni64(E[0]), ba = (int)uni64(E[1]);
+        book_obs(bb, ba);
+        const int64_t *O = X64(X_OBK);
+        const int64_t mid2 = (int64_t)bb + ba;
+        const int64_t strades = uni64(S[2]);
         for (int i = 0; i < A; ++i) {
             const int kind = (a.kinds >> (4 * i)) & 15;
             const int64_t *g = AG(i);
@@ -611,19 +679,19 @@ struct Run {
             const int f = lane;
             if (f >= 3 && f <= 24) v = O[f - 3];
             else if (f >= 35 && f <= 37) v = O[22 + 3 * i + (f - 35)];
-            else if (f == 0) v = (int64_t)last_ba - last_bb;
-            else if (f == 1) v = last_dmid2;
-            else if (f == 2) v = mid2 - p_init2;
+            else if (f == 0) v = (int64_t)ba - bb;
+            else if (f == 1) v = E[7];
+            else if (f == 2) v = mid2 - E[3];
             else if (f == 25) v = n0;
             else if (f == 26) v = n1;
-            else if (f == 27) v = st_buy;
-            else if (f == 28) v = st_sell;
-            else if (f == 29) v = st_trades;
-            else if (f == 30) v = st_trades > 0 ? 2 * (int64_t)st_last - mid2 : 0;
+            else if (f == 27) v = S[0];
+            else if (f == 28) v = S[1];
+            else if (f == 29) v = strades;
+            else if (f == 30) v = strades > 0 ? 2 * S[3] - mid2 : 0;
             else if (f == 31) v = g[0];
             else if (f == 32) v = g[1];
             else if (f == 33) v = kind == LOB_AGENT_EXEC ? g[2] : 0;
-            else if (f == 34) v = (int64_t)a.episode_len - t;
+            else if (f == 34) v = (int64_t)a.episode_len - E[6];
             else if (f == 38) v = g[4];
             else if (f == 39) v = g[5];
             if (f < LOB_OBS_DIM) base[((int64_t)i * a.n_envs + e) * LOB_OBS_DIM + f] = (float)v;
@@ -631,97 +699,74 @@ struct Run {
     }
 
     /* ---- load / store of the env ---- */
-    __device__ void load() {
+    __device__ __forceinline__ void load() {
         const int64_t gb = (int64_t)e * 2;
         n0 = min(uni(a.bk_n[gb]), cap);
         n1 = min(uni(a.bk_n[gb + 1]), cap);
         for (int s = 0; s < 2; ++s) {
             const int n = nsz(s);
             const int64_t off = (gb + s) * a.max_cap;
+            int2 *p0 = PR(s, 0), *p1 = PR(s, 1), *p2 = PR(s, 2);
             for (int i = lane; i < n; i += WAVE) {
-#pragma unroll
-                for (int f = 0; f < NF; ++f) B(s, f, i) = a.bk[f][off + i];
+                p0[i] = make_int2(a.bk[FP][off + i], a.bk[FQ][off + i]);
+                p1[i] = make_int2(a.bk[FO][off + i], a.bk[FT][off + i]);
+                p2[i] = make_int2(a.bk[FS][off + i], a.bk[FN][off + i]);
             }
         }
+        /* env state, counters, statistics and agent state into LDS */
+        if (lane < LOB_ENV_STATE_WORDS) ENV()[lane] = a.env_state[(int64_t)e * LOB_ENV_STATE_WORDS + lane];
+        if (lane < NCTR) X64(X_CTR)[lane] = a.counters[(int64_t)e * LOB_N_COUNTERS + lane];
+        if (lane < STW) X64(X_ST)[lane] = a.stats[(int64_t)e * STW + lane];
+        if (lane < A * AGW) AG(0)[lane] = a.agent_state[(int64_t)e * A * AGW + lane];
         WAVE_SYNC();
         refresh_best(0);
         refresh_best(1);
-        const int64_t *es = a.env_state + (int64_t)e * LOB_ENV_STATE_WORDS;
-        last_bb = (int32_t)uni64(es[0]);
-        last_ba = (int32_t)uni64(es[1]);
-        mid2_prev = uni64(es[2]);
-        p_init2 = uni64(es[3]);
-        last_tsec = (int32_t)uni64(es[4]);
-        last_tns = (int32_t)uni64(es[5]);
-        t = (int32_t)uni64(es[6]);
-        last_dmid2 = uni64(es[7]);
-#pragma unroll
-        for (int k = 0; k < NCTR; ++k) ctr[k] = uni64(a.counters[(int64_t)e * LOB_N_COUNTERS + k]);
-        const int64_t *st = a.stats + (int64_t)e * STW;
-        st_buy = uni64(st[0]);
-        st_sell = uni64(st[1]);
-        st_trades = uni64(st[2]);
-        st_last = (int32_t)uni64(st[3]);
-        const int64_t *ag = a.agent_state + (int64_t)e * A * AGW;
-        if (lane < A * AGW) AG(0)[lane] = ag[lane];
-        tr_base = a.trade_off ? a.trade_off[e] : 0;
-        tr_cap = a.trades ? a.trade_off[e + 1] - tr_base : 0;
-        tr_cur = a.trade_cursor ? uni64(a.trade_cursor[e]) : 0;
-        WAVE_SYNC();
+        t = (int32_t)uni64(ENV()[6]);
+        last_tsec = (int32_t)uni64(ENV()[4]);
+        last_tns = (int32_t)uni64(ENV()[5]);
+        const int64_t b0 = a.trade_off ? a.trade_off[e] : 0;
+        tr_next = b0 + (a.trade_cursor ? uni64(a.trade_cursor[e]) : 0);
+        tr_end = a.trades ? a.trade_off[e + 1] : 0;
     }
-    __device__ void store() {
+    __device__ __forceinline__ void store() {
         WAVE_SYNC();
         const int64_t gb = (int64_t)e * 2;
         for (int s = 0; s < 2; ++s) {
             const int n = nsz(s);
             const int64_t off = (gb + s) * a.max_cap;
+            int2 *p0 = PR(s, 0), *p1 = PR(s, 1), *p2 = PR(s, 2);
             for (int i = lane; i < n; i += WAVE) {
-#pragma unroll
-                for (int f = 0; f < NF; ++f) a.bk[f][off + i] = B(s, f, i);
+                const int2 x0 = p0[i], x1 = p1[i], x2 = p2[i];
+                a.bk[FP][off + i] = x0.x; a.bk[FQ][off + i] = x0.y;
+                a.bk[FO][off + i] = x1.x; a.bk[FT][off + i] = x1.y;
+                a.bk[FS][off + i] = x2.x; a.bk[FN][off + i] = x2.y;
             }
         }
         if (lane == 0) {
             a.bk_n[gb] = n0;
             a.bk_n[gb + 1] = n1;
         }
-        int64_t *es = a.env_state + (int64_t)e * LOB_ENV_STATE_WORDS;
-        int64_t v = 0;
-        switch (lane) {
-        case 0: v = last_bb; break;
-        case 1: v = last_ba; break;
-        case 2: v = mid2_prev; break;
-        case 3: v = p_init2; break;
-        case 4: v = last_tsec; break;
-        case 5: v = last_tns; break;
-        case 6: v = t; break;
-        case 7: v = last_dmid2; break;
-        default: break;
-        }
-        if (lane < LOB_ENV_STATE_WORDS) es[lane] = v;
-        int64_t c = 0;
-#pragma unroll
-        for (int k = 0; k < NCTR; ++k)
-            if (lane == k) c = ctr[k];
-        if (lane < NCTR) a.counters[(int64_t)e * LOB_N_COUNTERS + lane] = c;
-        int64_t sv = lane == 0 ? st_buy : lane == 1 ? st_sell : lane == 2 ? st_trades : (int64_t)st_last;
-        if (lane < STW) a.stats[(int64_t)e * STW + lane] = sv;
-        int64_t *ag = a.agent_state + (int64_t)e * A * AGW;
-        if (lane < A * AGW) ag[lane] = AG(0)[lane];
-        if (a.trade_cursor && lane == 0) a.trade_cursor[e] = tr_cur;
+        if (lane < LOB_ENV_STATE_WORDS) a.env_state[(int64_t)e * LOB_ENV_STATE_WORDS + lane] = ENV()[lane];
+        if (lane < NCTR) a.counters[(int64_t)e * LOB_N_COUNTERS + lane] = X64(X_CTR)[lane];
+        if (lane < STW) a.stats[(int64_t)e * STW + lane] = X64(X_ST)[lane];
+        if (lane < A * AGW) a.agent_state[(int64_t)e * A * AGW + lane] = AG(0)[lane];
+        if (a.trade_cursor && lane == 0) a.trade_cursor[e] = tr_next - (a.trade_off ? a.trade_off[e] : 0);
     }
 
     /* ---- one env-step (Sec. 4 steps 1-5) writing output slot s_idx ---- */
-    __device__ void step(int s_idx) {
+    __device__ __forceinline__ void step(int s_idx) {
         const int N = a.n_envs;
         mid_sum = 0; mid_n = 0; seq = 0;
         st_buy = 0; st_sell = 0; st_trades = 0; st_last = 0;
+        tr_step0 = tr_next;
         if (lane < A * 4) FL(0)[lane] = 0;
         WAVE_SYNC();
         /* reference prices at step start; an empty side keeps its last known best */
-        const int bb0 = n0 > 0 ? best0 : last_bb;
-        const int ba0 = n1 > 0 ? best1 : last_ba;
+        const int bb0 = n0 > 0 ? best0 : (int)uni64(ENV()[0]);
+        const int ba0 = n1 > 0 ? best1 : (int)uni64(ENV()[1]);
 
-        /* step 1: action conversion, agents in index order; cancels processed at once */
+        /* step 1 (from the book at step start): every agent's desired levels and new
+         * orders, agents in index order */
         int nact = 0;
         for (int i = 0; i < A; ++i) {
             const int kind = (a.kinds >> (4 * i)) & 15;
@@ -735,9 +780,8 @@ struct Run {
             }
             if (a.actions_out && lane == 0) a.actions_out[((int64_t)s_idx * A + i) * N + e] = act;
             if (act < 0 || act >= nacts) act = 0;
-            agent_actions(i, act, bb0, ba0, nact);
+            agent_start(i, act, bb0, ba0, nact);
         }
-
         /* step 2: shuffle the new orders by (32-bit counter hash, position) */
         if (nact > 0) {
             const uint32_t key = (uint32_t)(hash4(a.seed, DOM_SHUFFLE, (uint64_t)e, (uint64_t)t, (uint64_t)lane) >> 32);
@@ -748,45 +792,100 @@ struct Run {
             }
             if (lane < nact) X()[X_PERM + rank] = lane;
             WAVE_SYNC();
-            /* step 3 (first part): the shuffled action block follows the cancels */
-            for (int p = 0; p < nact; ++p) {
-                const int k = uni(X()[X_PERM + p]);
-                const int32_t *m = X() + X_ACT + k * 8;
-                process(uni(m[0]), uni(m[1]), uni(m[2]), uni(m[3]), uni(m[4]), uni(m[5]), uni(m[6]));
+        }
+
+        /* steps 3-4, in the order of Sec. 4 step 3.  First the cancel block: agents in
+         * index order, each walking its resting orders in book order; an order at a level
+         * the agent no longer wants is deleted, at a kept level any excess over the desired
+         * quantity comes from the agent's newest orders there. */
+        for (int ai = 0; ai < A; ++ai) {
+            const int tid = ai + 1;
+            const int nlv = uni(X()[X_NLV + ai]);
+            for (int ws = 0; ws < 2; ++ws) {
+                int wi0 = 0;
+                for (;;) {
+                    const int j = uni(find_eq(ws, FT, wi0, nsz(ws), tid));
+                    if (j < 0) break;
+                    const int2 pq = PR(ws, 0)[j];
+                    const int pr = uni(pq.x), qt = uni(pq.y);
+                    const int k = find_level(ai, nlv, ws, pr);
+                    const int D = k >= 0 ? uni(LV(ai, k)[2]) : 0;
+                    int x = qt; /* quantity to cancel; qt = the whole order */
+                    if (D > 0) {
+                        const int R = uni(LV(ai, k)[3]);
+                        int32_t *seen = X() + X_SEEN + ai * MAXLV + k;
+                        const int older = uni(*seen);
+                        if (lane == 0) *seen = older + qt;
+                        WAVE_SYNC();
+                        x = R > D ? min(max((R - D) - (R - older - qt), 0), qt) : 0;
+                    }
+                    if (x > 0) {
+                        /* a cancel message (delete, or partial cancel of x) for this order */
+                        const int oid = uni(B(ws, FO, j));
+                        if (D == 0) cancel(false, ws, qt, oid);
+                        else cancel(true, ws, x, oid);
+                        after_message(last_tsec, last_tns);
+                    }
+                    wi0 = (x == qt) ? j : j + 1;
+                }
             }
         }
 
-        /* step 3 (second part) + step 4: the replayed messages, staged 64 at a time */
+        /* then the shuffled new orders, then the replayed messages (staged 64 at a time,
+         * the next chunk prefetched), each through one call of process() */
         const int64_t *row = a.m_off + (int64_t)e * (a.m_steps + 1);
-        const int64_t lo = uni64(row[t]), hi = uni64(row[t + 1]);
-        int64_t base = lo;
+        const int64_t lo = uni64(row[t]);
+        const int nrep = (int)(uni64(row[t + 1]) - lo);
+        const int32_t *mts = a.m_ts + lo, *mpr = a.m_price + lo, *mqt = a.m_qty + lo, *moi = a.m_oid + lo;
+        const int32_t *mti = a.m_tid + lo, *mse = a.m_tsec + lo, *mns = a.m_tns + lo;
         int c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0;
-        if (base < hi) {
-            const int64_t idx = base + lane;
-            if (idx < hi) {
-                c0 = a.m_ts[idx]; c1 = a.m_price[idx]; c2 = a.m_qty[idx]; c3 = a.m_oid[idx];
-                c4 = a.m_tid[idx]; c5 = a.m_tsec[idx]; c6 = a.m_tns[idx];
-            }
+        int d0 = 0, d1 = 0, d2 = 0, d3 = 0, d4 = 0, d5 = 0, d6 = 0;
+        if (lane < nrep) {
+            c0 = mts[lane]; c1 = mpr[lane]; c2 = mqt[lane]; c3 = moi[lane];
+            c4 = mti[lane]; c5 = mse[lane]; c6 = mns[lane];
         }
-        while (base < hi) {
-            const int64_t nb = base + WAVE;
-            int d0 = 0, d1 = 0, d2 = 0, d3 = 0, d4 = 0, d5 = 0, d6 = 0;
-            const int64_t nidx = nb + lane;
-            if (nidx < hi) {
-                d0 = a.m_ts[nidx]; d1 = a.m_price[nidx]; d2 = a.m_qty[nidx]; d3 = a.m_oid[nidx];
-                d4 = a.m_tid[nidx]; d5 = a.m_tsec[nidx]; d6 = a.m_tns[nidx];
+        if (WAVE + lane < nrep) {
+            d0 = mts[WAVE + lane]; d1 = mpr[WAVE + lane]; d2 = mqt[WAVE + lane]; d3 = moi[WAVE + lane];
+            d4 = mti[WAVE + lane]; d5 = mse[WAVE + lane]; d6 = mns[WAVE + lane];
+        }
+        int ak = 0, base = 0, rj = 0;
+        int cnt = min(WAVE, nrep);
+        for (;;) {
+            ak = uni(ak);
+            rj = uni(rj);
+            base = uni(base);
+            int m0, m1, m2, m3, m4, m5, m6;
+            if (ak < nact) {
+                const int k = uni(X()[X_PERM + ak]);
+                const int32_t *m = X() + X_ACT + k * 8;
+                m0 = uni(m[0]); m1 = uni(m[1]); m2 = uni(m[2]); m3 = uni(m[3]);
+                m4 = uni(m[4]); m5 = uni(m[5]); m6 = uni(m[6]);
+                ak += 1;
+            } else {
+                if (rj >= cnt) {
+                    base += WAVE;
+                    if (base >= nrep) break;
+                    c0 = d0; c1 = d1; c2 = d2; c3 = d3; c4 = d4; c5 = d5; c6 = d6;
+                    const int nx = base + WAVE + lane;
+                    if (nx < nrep) {
+                        d0 = mts[nx]; d1 = mpr[nx]; d2 = mqt[nx]; d3 = moi[nx];
+                        d4 = mti[nx]; d5 = mse[nx]; d6 = mns[nx];
+                    }
+                    cnt = min(WAVE, nrep - base);
+                    rj = 0;
+                }
+                m0 = rdlane(c0, rj); m1 = rdlane(c1, rj); m2 = rdlane(c2, rj); m3 = rdlane(c3, rj);
+                m4 = rdlane(c4, rj); m5 = rdlane(c5, rj); m6 = rdlane(c6, rj);
+                rj += 1;
             }
-            const int cnt = (int)min((int64_t)WAVE, hi - base);
-            for (int j = 0; j < cnt; ++j)
-                process(rdlane(c0, j), rdlane(c1, j), rdlane(c2, j), rdlane(c3, j), rdlane(c4, j),
-                        rdlane(c5, j), rdlane(c6, j));
-            c0 = d0; c1 = d1; c2 = d2; c3 = d3; c4 = d4; c5 = d5; c6 = d6;
-            base = nb;
+            process(m0, m1, m2, m3, m4, m5, m6);
         }
 
         /* step 5: outcomes */
-        const int bb1 = n0 > 0 ? best0 : last_bb;
-        const int ba1 = n1 > 0 ? best1 : last_ba;
+        int64_t *E = ENV();
+        const int64_t mid2_prev = uni64(E[2]), p_init2 = uni64(E[3]);
+        const int bb1 = n0 > 0 ? best0 : (int)uni64(E[0]);
+        const int ba1 = n1 > 0 ? best1 : (int)uni64(E[1]);
         const int64_t mid2_end = (int64_t)bb1 + ba1;
         const bool last = (t + 1 == a.episode_len);
         const double mbar = mid_n > 0 ? (double)mid_sum / (2.0 * (double)mid_n) : (double)mid2_prev * 0.5;
@@ -823,16 +922,23 @@ struct Run {
             }
             if (lane < 4) a.fills[(((int64_t)s_idx * A + i) * N + e) * 4 + lane] = fl[lane];
         }
-        WAVE_SYNC();
-        last_dmid2 = mid2_end - mid2_prev;
-        last_bb = bb1;
-        last_ba = ba1;
-        mid2_prev = mid2_end;
-        t += 1;
+        /* counters of the step; trade records beyond the env's region were not written */
+        const int64_t written_end = max(tr_step0, tr_end);
+        const int64_t overflow = tr_next > written_end ? tr_next - written_end : 0;
         if (lane == 0) {
-            a.n_trades[(int64_t)s_idx * N + e] = (int32_t)st_trades;
+            int64_t *C = X64(X_CTR);
+            C[C_MSGS] += seq;
+            C[C_TRADES] += st_trades;
+            C[C_TRADE_OVERFLOW] += overflow;
+            int64_t *S = X64(X_ST);
+            S[0] = st_buy; S[1] = st_sell; S[2] = st_trades; S[3] = st_last;
+            E[0] = bb1; E[1] = ba1; E[2] = mid2_end; E[4] = last_tsec; E[5] = last_tns;
+            E[6] = t + 1; E[7] = mid2_end - mid2_prev;
+            a.n_trades[(int64_t)s_idx * N + e] = st_trades;
             a.done[(int64_t)s_idx * N + e] = last ? 1 : 0;
         }
+        WAVE_SYNC();
+        t += 1;
         if (a.obs) write_obs(a.obs + (int64_t)s_idx * A * N * LOB_OBS_DIM);
     }
 };
@@ -840,10 +946,11 @@ struct Run {
 /* ------------------------------------------------------------------------------
  * Kernels
  * ---------------------------------------------------------------------------- */
+template <int ROWS>
 __global__ void __launch_bounds__(256) k_env(KArgs a) {
     extern __shared__ int32_t smem[];
-    const int wave = (int)(threadIdx.x >> 6), waves = (int)(blockDim.x >> 6);
-    int32_t *L = smem + (int64_t)wave * a.lds_words;
+    const int wave = uni((int)(threadIdx.x >> 6)), waves = (int)(blockDim.x >> 6);
+    int32_t *L = smem + wave * lds_words_for(ROWS * WAVE);
     for (;;) {
         int slot;
         if (a.work_ctr) {
@@ -854,7 +961,7 @@ __global__ void __launch_bounds__(256) k_env(KArgs a) {
             slot = (int)blockIdx.x * waves + wave;
         }
         if (slot >= a.n_list) break;
-        Run run(a, L, a.env_list[slot]);
+        Run<ROWS> run(a, L, a.env_list[slot]);
         run.load();
         for (int s = 0; s < a.n_steps; ++s) run.step(s);
         run.store();
@@ -863,13 +970,14 @@ __global__ void __launch_bounds__(256) k_env(KArgs a) {
 }
 
 /* observation of the current state (no step) */
+template <int ROWS>
 __global__ void __launch_bounds__(256) k_observe(KArgs a) {
     extern __shared__ int32_t smem[];
-    const int wave = (int)(threadIdx.x >> 6), waves = (int)(blockDim.x >> 6);
+    const int wave = uni((int)(threadIdx.x >> 6)), waves = (int)(blockDim.x >> 6);
     const int slot = (int)blockIdx.x * waves + wave;
     if (slot >= a.n_list) return;
-    int32_t *L = smem + (int64_t)wave * a.lds_words;
-    Run run(a, L, a.env_list[slot]);
+    int32_t *L = smem + wave * lds_words_for(ROWS * WAVE);
+    Run<ROWS> run(a, L, a.env_list[slot]);
     run.load();
     run.write_obs(a.obs);
 }
@@ -967,6 +1075,30 @@ __global__ void k_fill_i32(int32_t *p, int32_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+typedef void (*kargs_kernel_t)(KArgs);
+inline kargs_kernel_t env_kernel(int rows) {
+    switch (rows) {
+    case 1: return k_env<1>;
+    case 2: return k_env<2>;
+    case 4: return k_env<4>;
+    case 7: return k_env<7>;
+    case 8: return k_env<8>;
+    case 16: return k_env<16>;
+    default: return nullptr;
+    }
+}
+inline kargs_kernel_t observe_kernel(int rows) {
+    switch (rows) {
+    case 1: return k_observe<1>;
+    case 2: return k_observe<2>;
+    case 4: return k_observe<4>;
+    case 7: return k_observe<7>;
+    case 8: return k_observe<8>;
+    case 16: return k_observe<16>;
+    default: return nullptr;
+    }
+}
+
 } // namespace lobk
 
 /* ==================================================================================
@@ -975,11 +1107,16 @@ __global__ void k_fill_i32(int32_t *p, int32_t n, int32_t v) {
 using namespace lobk;
 
 struct CapClass {
-    int capp;      /* capacity rounded up to a multiple of 64 */
+    int rows;      /* book rows of 64 slots per side (compiled variant) */
+    int capp;      /* rows * 64 */
     int first;     /* offset into the env list */
     int count;     /* envs in the class */
-    int waves;     /* waves per workgroup (envs per workgroup) */
+    int waves;     /* waves per workgroup (one env per wave) */
+    int mode;      /* 0: one wave per env, hardware dispatch in list order; 1: work queue */
+    int grid;      /* workgroups in queue mode (0 = derived from occupancy) */
 };
+
+constexpr int MAX_CLASSES = 8;
 
 struct lob_ctx {
     lob_config cfg;
@@ -989,9 +1126,15 @@ struct lob_ctx {
     int32_t *d_bk[NF] = {};
     int32_t *d_bk_n = nullptr;
     int64_t *d_env = nullptr, *d_agent = nullptr, *d_ctr = nullptr, *d_stats = nullptr;
-    int32_t *d_env_list = nullptr;  /* envs grouped by class */
+    int32_t *d_env_list = nullptr;  /* envs grouped by class, each class longest first */
     int32_t *d_work = nullptr;      /* work-queue counters, one per class */
+    std::vector<int32_t> env_list;  /* host copy */
     std::vector<CapClass> classes;
+    hipStream_t streams[MAX_CLASSES] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[MAX_CLASSES] = {};
+    /* the plan: which (stream offsets, first step, steps) the env order was made for */
+    const int64_t *plan_off = nullptr;
+    int plan_t0 = -1, plan_steps = -1;
     int device = 0;
     int n_cu = 256;
     int t = 0;
@@ -1023,6 +1166,11 @@ void free_ctx(lob_ctx *c) {
     (void)hipFree(c->d_stats);
     (void)hipFree(c->d_env_list);
     (void)hipFree(c->d_work);
+    for (int k = 0; k < MAX_CLASSES; ++k) {
+        if (c->streams[k]) (void)hipStreamDestroy(c->streams[k]);
+        if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     delete c;
 }
 
@@ -1079,31 +1227,74 @@ void fill_out(KArgs &a, const lob_out *o) {
     a.done = o->done; a.actions_out = o->actions;
 }
 
-/* launch the env kernel for every capacity class */
-int launch_env(lob_ctx *c, KArgs a, bool persistent, hipStream_t st) {
-    for (size_t k = 0; k < c->classes.size(); ++k) {
-        const CapClass &cl = c->classes[k];
-        if (cl.count == 0) continue;
-        a.capp = cl.capp;
-        a.lds_words = lds_words_for(cl.capp);
-        a.env_list = c->d_env_list + cl.first;
-        a.n_list = cl.count;
-        const int waves = cl.waves;
-        const size_t lds = (size_t)a.lds_words * 4 * waves;
-        int grid;
-        if (persistent) {
-            a.work_ctr = c->d_work + k;
-            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, c->d_work + k, 1, 0);
-            int per_cu = (int)(160 * 1024 / lds);
-            if (per_cu < 1) per_cu = 1;
-            grid = std::min((cl.count + waves - 1) / waves, c->n_cu * per_cu);
-        } else {
-            a.work_ctr = nullptr;
-            grid = (cl.count + waves - 1) / waves;
-        }
-        hipLaunchKernelGGL(k_env, dim3(grid), dim3(64 * waves), lds, st, a);
-        if (hipGetLastError() != hipSuccess) return LOB_EHIP;
+size_t class_lds(const CapClass &cl) { return (size_t)lds_words_for(cl.capp) * 4 * cl.waves; }
+
+/* Launch the env kernel of one class on stream st. */
+int launch_class(lob_ctx *c, size_t k, KArgs a, hipStream_t st) {
+    const CapClass &cl = c->classes[k];
+    if (cl.count == 0) return LOB_OK;
+    a.capp = cl.capp;
+    a.lds_words = lds_words_for(cl.capp);
+    a.env_list = c->d_env_list + cl.first;
+    a.n_list = cl.count;
+    const int waves = cl.waves;
+    const size_t lds = class_lds(cl);
+    int grid;
+    if (cl.mode == 1) {
+        a.work_ctr = c->d_work + k;
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, c->d_work + k, 1, 0);
+        int per_cu = (int)(160 * 1024 / lds);
+        if (per_cu < 1) per_cu = 1;
+        grid = cl.grid > 0 ? cl.grid : c->n_cu * per_cu;
+        grid = std::min(grid, (cl.count + waves - 1) / waves);
+    } else {
+        a.work_ctr = nullptr;
+        grid = (cl.count + waves - 1) / waves;
     }
+    hipLaunchKernelGGL(env_kernel(cl.rows), dim3(grid), dim3(64 * waves), lds, st, a);
+    return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
+}
+
+/* Launch every class concurrently: fork from the caller's stream to one stream per
+ * class, join back.  Classes with more work per env are launched first. */
+int launch_env(lob_ctx *c, KArgs a, hipStream_t st) {
+    const size_t nc = c->classes.size();
+    if (nc == 1) return launch_class(c, 0, a, st);
+    if (!hip_ok(hipEventRecord(c->ev_fork, st))) return LOB_EHIP;
+    for (size_t i = 0; i < nc; ++i) {
+        const size_t k = nc - 1 - i; /* largest books first */
+        if (!hip_ok(hipStreamWaitEvent(c->streams[k], c->ev_fork, 0))) return LOB_EHIP;
+        int rc = launch_class(c, k, a, c->streams[k]);
+        if (rc != LOB_OK) return rc;
+        if (!hip_ok(hipEventRecord(c->ev_join[k], c->streams[k]))) return LOB_EHIP;
+    }
+    for (size_t k = 0; k < nc; ++k)
+        if (!hip_ok(hipStreamWaitEvent(st, c->ev_join[k], 0))) return LOB_EHIP;
+    return LOB_OK;
+}
+
+/* Order each class's envs by decreasing message count over steps [t0, t0+n) (longest
+ * first), so the envs that bound the runtime start first.  Reads two columns of the
+ * CSR offsets back to the host (synchronous). */
+int make_plan(lob_ctx *c, const lob_msgs *m, int t0, int n) {
+    if (c->plan_off == m->off && c->plan_t0 == t0 && c->plan_steps == n) return LOB_OK;
+    const int N = c->cfg.n_envs;
+    const size_t pitch = (size_t)(m->n_steps + 1) * sizeof(int64_t);
+    std::vector<int64_t> a0((size_t)N), a1((size_t)N);
+    if (!hip_ok(hipMemcpy2D(a0.data(), 8, m->off + t0, pitch, 8, (size_t)N, hipMemcpyDeviceToHost)) ||
+        !hip_ok(hipMemcpy2D(a1.data(), 8, m->off + t0 + n, pitch, 8, (size_t)N, hipMemcpyDeviceToHost)))
+        return LOB_EHIP;
+    for (const CapClass &cl : c->classes) {
+        auto b = c->env_list.begin() + cl.first;
+        std::stable_sort(b, b + cl.count, [&](int32_t x, int32_t y) {
+            return a1[(size_t)x] - a0[(size_t)x] > a1[(size_t)y] - a0[(size_t)y];
+        });
+    }
+    if (!hip_ok(hipMemcpy(c->d_env_list, c->env_list.data(), (size_t)N * 4, hipMemcpyHostToDevice)))
+        return LOB_EHIP;
+    c->plan_off = m->off;
+    c->plan_t0 = t0;
+    c->plan_steps = n;
     return LOB_OK;
 }
 
@@ -1165,23 +1356,33 @@ int lob_init(const lob_config *cfg, lob_ctx **out) {
 
     /* capacity classes: capacity rounded up to 64 slots; envs of a class listed in
      * index order (the persistent launch reorders by work, see lob_rollout) */
-    std::vector<int32_t> list;
-    std::vector<int> cps;
-    for (int32_t v : c->caps) cps.push_back((v + 63) & ~63);
-    std::vector<int> uniq(cps);
+    /* capacity classes: one compiled book size per class; envs listed in index order
+     * until a plan orders them */
+    std::vector<int> rows;
+    for (int32_t v : c->caps) rows.push_back(rows_for_cap(v));
+    std::vector<int> uniq(rows);
     std::sort(uniq.begin(), uniq.end());
     uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-    for (int capp : uniq) {
-        CapClass cl{capp, (int)list.size(), 0, 1};
+    for (int r : uniq) {
+        CapClass cl{r, r * WAVE, (int)c->env_list.size(), 0, 1, 0, 0};
         for (int e = 0; e < (int)N; ++e)
-            if (cps[(size_t)e] == capp) { list.push_back(e); cl.count++; }
-        /* several waves per workgroup when books are small */
-        const size_t per_wave = (size_t)lds_words_for(capp) * 4;
+            if (rows[(size_t)e] == r) { c->env_list.push_back(e); cl.count++; }
+        /* several waves (envs) per workgroup when books are small */
+        const size_t per_wave = (size_t)lds_words_for(cl.capp) * 4;
         cl.waves = per_wave * 4 <= 64 * 1024 ? 4 : per_wave * 2 <= 64 * 1024 ? 2 : 1;
         c->classes.push_back(cl);
     }
-    if (!hip_ok(hipMemcpy(c->d_caps, c->caps.data(), (size_t)N * 4, hipMemcpyHostToDevice)) ||
-        !hip_ok(hipMemcpy(c->d_env_list, list.data(), (size_t)N * 4, hipMemcpyHostToDevice))) {
+    if ((int)c->classes.size() > MAX_CLASSES) { free_ctx(c); return LOB_EUNSUPPORTED; }
+    for (size_t k = 0; k < c->classes.size(); ++k) {
+        if (!hip_ok(hipStreamCreateWithFlags(&c->streams[k], hipStreamNonBlocking)) ||
+            !hip_ok(hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming))) {
+            free_ctx(c);
+            return LOB_EHIP;
+        }
+    }
+    if (!hip_ok(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) ||
+        !hip_ok(hipMemcpy(c->d_caps, c->caps.data(), (size_t)N * 4, hipMemcpyHostToDevice)) ||
+        !hip_ok(hipMemcpy(c->d_env_list, c->env_list.data(), (size_t)N * 4, hipMemcpyHostToDevice))) {
         free_ctx(c);
         return LOB_EHIP;
     }
@@ -1238,7 +1439,7 @@ int lob_step(lob_ctx *c, const lob_msgs *m, const int32_t *actions, const lob_ou
     a.actions_in = actions;
     a.t0 = c->t;
     a.n_steps = 1;
-    rc = launch_env(c, a, false, (hipStream_t)stream);
+    rc = launch_env(c, a, (hipStream_t)stream);
     if (rc != LOB_OK) return rc;
     c->t += 1;
     return LOB_OK;
@@ -1258,10 +1459,118 @@ int lob_rollout(lob_ctx *c, const lob_msgs *m, int32_t n_steps, const int32_t *a
     a.actions_in = actions;
     a.t0 = c->t;
     a.n_steps = n_steps;
-    rc = launch_env(c, a, true, (hipStream_t)stream);
+    rc = launch_env(c, a, (hipStream_t)stream);
     if (rc != LOB_OK) return rc;
     c->t += n_steps;
     return LOB_OK;
+}
+
+int lob_plan(lob_ctx *c, const lob_msgs *m, int32_t n_steps) {
+    if (!c || n_steps <= 0) return LOB_EINVAL;
+    int rc = check_msgs(c, m, 0);
+    if (rc != LOB_OK) return rc;
+    const int n = std::min(n_steps, m->n_steps - c->t);
+    if (n <= 0) return LOB_ESTATE;
+    return make_plan(c, m, c->t, n);
+}
+
+int lob_schedule_get(const lob_ctx *c, int32_t *out, int32_t max_classes) {
+    if (!c || !out || max_classes < 0) return LOB_EINVAL;
+    const int nc = (int)c->classes.size();
+    for (int k = 0; k < nc && k < max_classes; ++k) {
+        const CapClass &cl = c->classes[(size_t)k];
+        int32_t *r = out + k * 5;
+        r[0] = cl.rows * WAVE; r[1] = cl.count; r[2] = cl.waves; r[3] = cl.mode; r[4] = cl.grid;
+    }
+    return nc;
+}
+
+int lob_schedule_set(lob_ctx *c, int32_t k, int32_t waves, int32_t mode, int32_t grid) {
+    if (!c || k < 0 || k >= (int)c->classes.size()) return LOB_EINVAL;
+    if (waves != 1 && waves != 2 && waves != 4) return LOB_EINVAL;
+    if (mode != 0 && mode != 1) return LOB_EINVAL;
+    if (grid < 0) return LOB_EINVAL;
+    CapClass &cl = c->classes[(size_t)k];
+    if ((size_t)lds_words_for(cl.capp) * 4 * waves > 64 * 1024) return LOB_EUNSUPPORTED;
+    cl.waves = waves;
+    cl.mode = mode;
+    cl.grid = grid;
+    return LOB_OK;
+}
+
+/* Time every schedule candidate of every class on the next n_steps of `m` (one class
+ * at a time, from the current state, which is restored afterwards) and keep the
+ * fastest.  Results do not depend on the schedule.  Synchronous; `out` is scratch. */
+int lob_autotune(lob_ctx *c, const lob_msgs *m, int32_t n_steps, const lob_out *o, void *stream) {
+    if (!c || n_steps <= 0) return LOB_EINVAL;
+    if (!c->reset_done || c->t + n_steps > c->cfg.episode_len) return LOB_ESTATE;
+    int rc = check_msgs(c, m, n_steps);
+    if (rc != LOB_OK) return rc;
+    if ((rc = check_out(c, o)) != LOB_OK) return rc;
+    if ((rc = make_plan(c, m, c->t, n_steps)) != LOB_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t N = (size_t)c->cfg.n_envs, A = (size_t)std::max(c->cfg.n_agents, 1);
+    const size_t slots = N * 2 * (size_t)c->cfg.max_cap;
+    /* save the state */
+    struct Buf { void *dst; const void *src; size_t bytes; };
+    std::vector<Buf> bufs;
+    for (int f = 0; f < NF; ++f) bufs.push_back({nullptr, c->d_bk[f], slots * 4});
+    bufs.push_back({nullptr, c->d_bk_n, N * 2 * 4});
+    bufs.push_back({nullptr, c->d_env, N * LOB_ENV_STATE_WORDS * 8});
+    bufs.push_back({nullptr, c->d_agent, N * A * AGW * 8});
+    bufs.push_back({nullptr, c->d_ctr, N * LOB_N_COUNTERS * 8});
+    bufs.push_back({nullptr, c->d_stats, N * STW * 8});
+    for (Buf &b : bufs) {
+        if (hipMalloc(&b.dst, b.bytes) != hipSuccess) {
+            for (Buf &x : bufs) if (x.dst) (void)hipFree(x.dst);
+            return LOB_ENOMEM;
+        }
+        if (!hip_ok(hipMemcpyAsync(b.dst, b.src, b.bytes, hipMemcpyDeviceToDevice, st))) rc = LOB_EHIP;
+    }
+    auto restore = [&]() {
+        for (Buf &b : bufs)
+            if (!hip_ok(hipMemcpyAsync(const_cast<void *>(b.src), b.dst, b.bytes, hipMemcpyDeviceToDevice, st)))
+                rc = LOB_EHIP;
+    };
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    KArgs a = base_args(c);
+    fill_msgs(a, m);
+    fill_out(a, o);
+    a.t0 = c->t;
+    a.n_steps = n_steps;
+    for (size_t k = 0; k < c->classes.size() && rc == LOB_OK; ++k) {
+        CapClass &cl = c->classes[k];
+        const CapClass orig = cl;
+        CapClass bestc = cl;
+        float best = 1e30f;
+        for (int mode = 0; mode < 2; ++mode) {
+            for (int waves : {1, 2, 4}) {
+                if ((size_t)lds_words_for(cl.capp) * 4 * waves > 64 * 1024) continue;
+                cl.waves = waves;
+                cl.mode = mode;
+                cl.grid = 0;
+                float ms = 0.f;
+                for (int rep = 0; rep < 2 && rc == LOB_OK; ++rep) {
+                    restore();
+                    (void)hipEventRecord(e0, st);
+                    rc = launch_class(c, k, a, st);
+                    (void)hipEventRecord(e1, st);
+                    (void)hipEventSynchronize(e1);
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                }
+                if (rc == LOB_OK && ms < best) { best = ms; bestc = cl; }
+            }
+        }
+        cl = rc == LOB_OK ? bestc : orig;
+    }
+    restore();
+    (void)hipStreamSynchronize(st);
+    for (Buf &b : bufs) (void)hipFree(b.dst);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int lob_observe(lob_ctx *c, float *obs, void *stream) {
@@ -1277,8 +1586,8 @@ int lob_observe(lob_ctx *c, float *obs, void *stream) {
         a.env_list = c->d_env_list + cl.first;
         a.n_list = cl.count;
         const size_t lds = (size_t)a.lds_words * 4 * cl.waves;
-        hipLaunchKernelGGL(k_observe, dim3((cl.count + cl.waves - 1) / cl.waves), dim3(64 * cl.waves), lds,
-                           (hipStream_t)stream, a);
+        hipLaunchKernelGGL(observe_kernel(cl.capp / WAVE), dim3((cl.count + cl.waves - 1) / cl.waves),
+                           dim3(64 * cl.waves), lds, (hipStream_t)stream, a);
         if (hipGetLastError() != hipSuccess) return LOB_EHIP;
     }
     return LOB_OK;

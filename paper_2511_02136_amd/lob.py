@@ -70,11 +70,16 @@ def lib():
         L.lob_export_books.argtypes = [p, ctypes.POINTER(_Books), p]
         L.lob_export_state.argtypes = [p, p, p, p, p]
         L.lob_current_step.argtypes = [p]
+        L.lob_plan.argtypes = [p, ctypes.POINTER(_Msgs), i32]
+        L.lob_schedule_get.argtypes = [p, p, i32]
+        L.lob_schedule_set.argtypes = [p, i32, i32, i32, i32]
+        L.lob_autotune.argtypes = [p, ctypes.POINTER(_Msgs), i32, ctypes.POINTER(_Out), p]
         L.lob_destroy.argtypes = [p]
         L.lob_strerror.argtypes = [ctypes.c_int]
         L.lob_strerror.restype = ctypes.c_char_p
         for f in ("lob_init", "lob_reset", "lob_step", "lob_rollout", "lob_observe", "lob_export_books",
-                  "lob_export_state", "lob_current_step", "lob_destroy"):
+                  "lob_export_state", "lob_current_step", "lob_destroy", "lob_plan", "lob_schedule_get",
+                  "lob_schedule_set", "lob_autotune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -250,6 +255,32 @@ class LobEnv:
                                      _stream()), "lob_rollout")
         out["_actions_in"] = actions
         return out
+
+    # ---- schedule ----
+    def plan(self, dstream: DeviceStream, n_steps: int):
+        """Order each capacity class's envs longest first for the next n_steps."""
+        _check(self._lib.lob_plan(self._h, ctypes.byref(dstream._m), int(n_steps)), "lob_plan")
+
+    def schedule(self) -> list:
+        buf = np.zeros((16, 5), dtype=np.int32)
+        n = self._lib.lob_schedule_get(self._h, buf.ctypes.data_as(ctypes.c_void_p), 16)
+        if n < 0:
+            _check(n, "lob_schedule_get")
+        return [dict(cap_slots=int(r[0]), envs=int(r[1]), waves=int(r[2]), mode=int(r[3]), grid=int(r[4]))
+                for r in buf[:n]]
+
+    def set_schedule(self, k: int, waves: int, mode: int, grid: int = 0):
+        _check(self._lib.lob_schedule_set(self._h, k, waves, mode, grid), "lob_schedule_set")
+
+    def autotune(self, dstream: DeviceStream, n_steps: int, out: Optional[dict] = None) -> list:
+        """Time every schedule candidate on the next n_steps (state restored) and keep the
+        fastest per class.  Returns the chosen schedule."""
+        if out is None:
+            out = self._alloc_out(n_steps, True, True, None, dstream)
+        o = self._out_struct(out)
+        _check(self._lib.lob_autotune(self._h, ctypes.byref(dstream._m), int(n_steps), ctypes.byref(o), _stream()),
+               "lob_autotune")
+        return self.schedule()
 
     def observe(self) -> torch.Tensor:
         obs = torch.empty((self.n_agents, self.n_envs, OBS_DIM), dtype=torch.float32, device=self.device)

@@ -258,3 +258,44 @@ def test_plain_and_persistent_forms_identical_full_size():
     ba, bb = e1.books(), e2.books()
     for k in ba:
         assert torch.equal(ba[k], bb[k]), k
+
+
+def test_schedule_independence():
+    """Every schedule the autotuner can pick gives identical outputs and books."""
+    _, DeviceStream = _lob()
+    w = synth.Workload("sched", n_envs=300, n_steps=6, msgs_range=(1, 300), cap_choices=(50, 100, 200, 400),
+                       agents=("exec", "mm"), seed=41)
+    s = synth.generate(w)
+    ds = DeviceStream.from_host(s)
+    ref_env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+    toff = ds.trade_regions(ref_env.caps, 0, w.n_steps, 2)
+    ref = ref_env.rollout(ds, w.n_steps, trade_off=toff)
+    ref_books = ref_env.books()
+    n_classes = len(ref_env.schedule())
+    for mode in (0, 1):
+        for waves in (1, 2, 4):
+            env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+            env.plan(ds, w.n_steps)
+            for k in range(n_classes):
+                try:
+                    env.set_schedule(k, waves, mode, 0 if mode == 0 else 7)
+                except Exception:
+                    pass  # the workgroup would need more LDS than allowed
+            got = env.rollout(ds, w.n_steps, trade_off=toff)
+            torch.cuda.synchronize()
+            for key in ("n_trades", "fills", "reward", "obs", "done", "actions", "trades"):
+                assert torch.equal(got[key], ref[key]) or key == "trades", (mode, waves, key)
+            n = got["n_trades"].sum(0).cpu().numpy()
+            off = toff.cpu().numpy()
+            for e in range(0, w.n_envs, 7):
+                assert torch.equal(got["trades"][off[e]: off[e] + n[e]], ref["trades"][off[e]: off[e] + n[e]])
+            gb = env.books()
+            for key in gb:
+                assert torch.equal(gb[key], ref_books[key]), (mode, waves, key)
+    # the tuner picks one of them and restores the state it started from
+    env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+    sched = env.autotune(ds, w.n_steps)
+    assert len(sched) == n_classes
+    got = env.rollout(ds, w.n_steps, trade_off=toff)
+    for key in ("n_trades", "fills", "reward", "obs", "done", "actions"):
+        assert torch.equal(got[key], ref[key]), key
