@@ -13,6 +13,7 @@ roofline of the env kernel and the CPU oracle's throughput on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,6 +35,29 @@ def algorithmic_bytes(n_msgs, n_trades, n_envs, n_agents, n_steps, book_slots):
     live orders in once and out once (6 x int32 each way)."""
     per_env_step = n_agents * (160 + 4 + 32 + 4) + 1 + 4
     return 28 * n_msgs + 32 * n_trades + per_env_step * n_envs * n_steps + 48 * book_slots
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("paper_2511_02136_amd/csrc/lob_env.hip", "paper_2511_02136_amd/csrc/lob_device.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per rollout from the committed rocprofv3 counter summary, or None when
+    the summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_env_{workload}_hbm_bytes.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic_json: "):
+                t = json.loads(line[len("traffic_json: "):])
+                if t.get("source_sha") == kernel_source_sha():
+                    return float(t["traffic_bytes"])
+    return None
 
 
 def cpu_baseline(w, stream, budget_s=15.0):
@@ -69,6 +93,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-step form")
     ap.add_argument("--tune", action="store_true", help="run the schedule autotuner before timing")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 256 MiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the env step shards by env "
@@ -79,6 +105,13 @@ def main():
     from paper_2511_02136_amd import synth
     from paper_2511_02136_amd.lob import LobEnv, DeviceStream
 
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = synth.WORKLOADS[args.workload]
     print(f"[bench] generating {w.name}", file=sys.stderr, flush=True)
     s = synth.generate(w)
@@ -211,7 +244,7 @@ def main():
         "schedule": schedule,
         "plain_form": plain,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name),
                      "kernel": "k_env (persistent rollout, all capacity classes)",
                      "kernel_ms": kernel_ms, "algorithmic_bytes": alg},
         "cpu_baseline": cpu,
