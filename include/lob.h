@@ -193,6 +193,46 @@ int lob_export_books(lob_ctx *ctx, const lob_books *out, void *stream);
 int lob_export_state(lob_ctx *ctx, int64_t *env_state, int64_t *agent_state, int64_t *counters,
                      void *stream);
 
+/* ---- IPPO actor-critic (Sec. 4.2: independent PPO, separate weights per agent type) ----
+ * Network per agent type: MLP 40 -> 256 -> 256 -> (9 policy logits + 1 value), tanh,
+ * fp32, flat parameters W1 [40][256] (input-major), b1 [256], W2 [256][256], b2 [256],
+ * W3 [256][10], b3 [10]: LOB_PPO_PARAMS floats.  Products run on MFMA. */
+#define LOB_PPO_PARAMS 78858
+
+/* Policy forward for the rollout.  params: device [n_agents][LOB_PPO_PARAMS];
+ * obs: device [n_agents][n][40]; n_actions: host [n_agents] (1..9, the first n_actions
+ * logits are the policy).  Samples one action per row by Gumbel-max with noise from the
+ * counter hash of (seed, agent, action, t, row).  Outputs (device): logits [n_agents][n][10]
+ * (may be NULL), actions [n_agents][n] int32, logp [n_agents][n] (log-probability of the
+ * sampled action), value [n_agents][n].  Asynchronous on stream. */
+int lob_policy_forward(const float *params, const float *obs, int32_t n_agents, int32_t n, const int32_t *n_actions,
+                       uint64_t seed, int32_t t, float *logits, int32_t *actions, float *logp, float *value,
+                       void *stream);
+
+/* Generalised advantage estimation over a rollout, all arrays device [T][n] (column =
+ * env x agent): delta_t = r_t + gamma V_{t+1} (1 - d_t) - V_t with V_T = last_value [n],
+ * A_t = delta_t + gamma lam (1 - d_t) A_{t+1}, ret = A + V.  done: uint8 (1 = the episode
+ * ended at step t). */
+int lob_gae(const float *reward, const float *value, const uint8_t *done, const float *last_value, int32_t T,
+            int32_t n, float gamma, float lam, float *adv, float *ret, void *stream);
+
+/* Bytes of device workspace lob_ppo_fwd_bwd needs for a minibatch of m samples. */
+int64_t lob_ppo_workspace_bytes(int32_t m);
+
+/* Fused clipped-PPO loss and its gradient for one minibatch of one network, with the
+ * activations recomputed from obs (none stored between rollout and update).
+ * obs [m][40], act [m] int32, logp_old, adv, ret, v_old [m] (device).  Loss =
+ * policy + c_v value - c_e entropy with policy = -mean(min(r A, clip(r, 1-clip, 1+clip) A)),
+ * r = exp(logp - logp_old), value = 0.5 mean(max((V-R)^2, (V_old + clip(V - V_old, -clip,
+ * clip) - R)^2)), entropy = mean of the policy entropy.  Writes loss [4] = the sums over
+ * the minibatch of the per-sample total, policy, value and entropy terms (divide by m for
+ * the means) and grad [LOB_PPO_PARAMS] = gradient of the mean total loss (device).
+ * workspace: device, >= lob_ppo_workspace_bytes(m).  Deterministic (fixed reduction order). */
+int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, const float *logp_old,
+                    const float *adv, const float *ret, const float *v_old, int32_t m, int32_t n_actions, float clip,
+                    float c_v, float c_e, float *workspace, int64_t workspace_bytes, float *loss, float *grad,
+                    void *stream);
+
 /* Steps taken since the last reset (host-side counter). */
 int lob_current_step(const lob_ctx *ctx);
 

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblob.so")
 
-SOURCES = ["lob_env.hip"]
+SOURCES = ["lob_env.hip", "ippo.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -1,0 +1,494 @@
+/*
+ * IPPO actor-critic kernels for gfx950: policy forward with sampling, GAE, and the fused
+ * clipped-PPO forward + backward with activation recomputation.
+ *
+ * Each agent type has its own network (arXiv 2511.02136, Sec. 4.2: independent PPO with
+ * separate weights per type): an MLP 40 -> 256 -> 256 -> (9 logits + 1 value), tanh,
+ * fp32.  The dense products run on MFMA (v_mfma_f32_16x16x4f32): a wavefront computes
+ * 16x16 output tiles; for lane l, the A operand is A[l%16][k0 + l/16], the B operand
+ * B[k0 + l/16][l%16], and accumulator element i is C[4*(l/16) + i][l%16].
+ *
+ * Parameter layout (flat fp32): W1 [40][256] (input-major), b1 [256], W2 [256][256],
+ * b2 [256], W3 [256][10], b3 [10]  (78,858 values).
+ */
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "lob.h"
+#include "lob_device.h"
+
+#pragma clang fp contract(off)
+
+namespace ippo {
+
+using lobk::hash4;
+using lobk::uni;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int IN = LOB_OBS_DIM, HID = 256, OUT = 10, OUTP = 16;
+constexpr int O_W1 = 0, O_B1 = O_W1 + IN * HID, O_W2 = O_B1 + HID, O_B2 = O_W2 + HID * HID, O_W3 = O_B2 + HID,
+              O_B3 = O_W3 + HID * OUT, NPARAM = O_B3 + OUT;
+static_assert(NPARAM == 78858, "parameter count");
+
+constexpr int TR = 64;          /* samples per workgroup tile */
+constexpr int XS = 52;          /* LDS row stride of the input tile (cols 40..51 zero) */
+constexpr int HS = 260;         /* LDS row stride of hidden tiles */
+constexpr int OS = 17;          /* LDS row stride of the output tile */
+constexpr int LDS_FLOATS = TR * XS + 2 * TR * HS + TR * OS;
+constexpr uint64_t DOM_POLICY = 0x504F4C4943ULL; /* "POLIC" */
+
+__device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx4 zero4() { return floatx4{0.f, 0.f, 0.f, 0.f}; }
+
+/* acc[mt][nt] += A[r0+16mt .. +16][0..K) * B[0..K)[c0+16nt .. +16]; A(i, k), B(k, j) are
+ * accessors; K a multiple of 4. */
+template <int MT, int NT, class FA, class FB>
+__device__ __forceinline__ void gemm(floatx4 (&acc)[MT][NT], int K, int r0, int c0, FA A, FB B) {
+    const int l = (int)(threadIdx.x & 63);
+    const int li = l & 15, lk = l >> 4;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        float a[MT], b[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) a[m] = A(r0 + 16 * m + li, k0 + lk);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) b[n] = B(k0 + lk, c0 + 16 * n + li);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) acc[m][n] = mfma(a[m], b[n], acc[m][n]);
+    }
+}
+
+/* row / column of accumulator element i of a 16x16 tile held by this lane */
+__device__ __forceinline__ int acc_row(int i) { return 4 * ((int)(threadIdx.x & 63) >> 4) + i; }
+__device__ __forceinline__ int acc_col() { return (int)(threadIdx.x & 15); }
+
+/* ---- forward of a tile of TR samples into LDS: X, H1 = tanh(X W1 + b1),
+ * H2 = tanh(H1 W2 + b2), O = H2 W3 + b3 (O cols 10..15 zero) ---- */
+__device__ __forceinline__ void forward_tile(const float *__restrict__ P, const float *__restrict__ obs, int rows,
+                                             float *X, float *H1, float *H2, float *O) {
+    const int tid = (int)threadIdx.x, wave = tid >> 6;
+    for (int i = tid; i < TR * XS; i += blockDim.x) {
+        const int r = i / XS, c = i % XS;
+        X[i] = (r < rows && c < IN) ? obs[(int64_t)r * IN + c] : 0.f;
+    }
+    __syncthreads();
+    /* layer 1: each wave computes 64 rows x 64 cols */
+    {
+        floatx4 acc[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = zero4();
+        gemm<4, 4>(acc, IN, 0, 64 * wave, [&](int i, int k) { return X[i * XS + k]; },
+                   [&](int k, int j) { return P[O_W1 + k * HID + j]; });
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * m + acc_row(i), c = 64 * wave + 16 * n + acc_col();
+                    H1[r * HS + c] = tanhf(acc[m][n][i] + P[O_B1 + c]);
+                }
+    }
+    __syncthreads();
+    /* layer 2 */
+    {
+        floatx4 acc[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = zero4();
+        gemm<4, 4>(acc, HID, 0, 64 * wave, [&](int i, int k) { return H1[i * HS + k]; },
+                   [&](int k, int j) { return P[O_W2 + k * HID + j]; });
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * m + acc_row(i), c = 64 * wave + 16 * n + acc_col();
+                    H2[r * HS + c] = tanhf(acc[m][n][i] + P[O_B2 + c]);
+                }
+    }
+    __syncthreads();
+    /* layer 3: wave w computes rows 16w..16w+15, cols 0..15 */
+    {
+        floatx4 acc[1][1] = {{zero4()}};
+        gemm<1, 1>(acc, HID, 16 * wave, 0, [&](int i, int k) { return H2[i * HS + k]; },
+                   [&](int k, int j) { return j < OUT ? P[O_W3 + k * OUT + j] : 0.f; });
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * wave + acc_row(i), c = acc_col();
+            O[r * OS + c] = c < OUT ? acc[0][0][i] + P[O_B3 + c] : 0.f;
+        }
+    }
+    __syncthreads();
+}
+
+/* ------------------------------------------------------------------------------
+ * Policy forward for the rollout: logits, value, a sampled action (Gumbel-max on a
+ * counter hash) and its log-probability.  grid (ceil(n/TR), n_agents), 256 threads.
+ * ---------------------------------------------------------------------------- */
+struct FwdArgs {
+    const float *params; /* [A][NPARAM] */
+    const float *obs;    /* [A][n][40] */
+    int32_t n, n_agents;
+    int32_t n_act[LOB_MAX_AGENTS];
+    uint64_t seed;
+    int32_t t;
+    float *logits; /* [A][n][10] or null */
+    int32_t *actions;
+    float *logp, *value; /* [A][n] */
+};
+
+__global__ void __launch_bounds__(256) k_policy_forward(FwdArgs a) {
+    extern __shared__ float sm[];
+    float *X = sm, *H1 = X + TR * XS, *H2 = H1 + TR * HS, *O = H2 + TR * HS;
+    const int ag = (int)blockIdx.y;
+    const int row0 = (int)blockIdx.x * TR;
+    const int rows = min(TR, a.n - row0);
+    const float *P = a.params + (int64_t)ag * NPARAM;
+    forward_tile(P, a.obs + ((int64_t)ag * a.n + row0) * IN, rows, X, H1, H2, O);
+    const int tid = (int)threadIdx.x;
+    if (tid < rows) {
+        const int nact = a.n_act[ag];
+        const int e = row0 + tid;
+        const float *z = O + tid * OS;
+        float m = z[0];
+        for (int j = 1; j < nact; ++j) m = fmaxf(m, z[j]);
+        float s = 0.f;
+        for (int j = 0; j < nact; ++j) s += expf(z[j] - m);
+        const float lse = m + logf(s);
+        int best = 0;
+        float bv = -INFINITY;
+        for (int j = 0; j < nact; ++j) {
+            const uint64_t h = hash4(a.seed, DOM_POLICY, (uint64_t)ag << 8 | (uint64_t)j, (uint64_t)a.t, (uint64_t)e);
+            const float u = ((float)(uint32_t)(h >> 40) + 0.5f) * (1.0f / 16777216.0f);
+            const float g = -logf(-logf(u));
+            const float v = z[j] + g;
+            if (v > bv) { bv = v; best = j; }
+        }
+        const int64_t o = (int64_t)ag * a.n + e;
+        a.actions[o] = best;
+        a.logp[o] = z[best] - lse;
+        a.value[o] = z[9];
+        if (a.logits)
+            for (int j = 0; j < OUT; ++j) a.logits[o * OUT + j] = z[j];
+    }
+}
+
+/* ------------------------------------------------------------------------------
+ * GAE over [T][n]: one thread per column, reverse scan over time.
+ * ---------------------------------------------------------------------------- */
+__global__ void k_gae(const float *__restrict__ r, const float *__restrict__ v, const uint8_t *__restrict__ d,
+                      const float *__restrict__ last_v, int T, int n, float gamma, float lam, float *adv, float *ret) {
+    const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (c >= n) return;
+    float nv = last_v[c], na = 0.f;
+    for (int t = T - 1; t >= 0; --t) {
+        const int64_t i = (int64_t)t * n + c;
+        const float nd = d[i] ? 0.f : 1.f;
+        const float delta = r[i] + gamma * nv * nd - v[i];
+        na = delta + gamma * lam * nd * na;
+        adv[i] = na;
+        ret[i] = na + v[i];
+        nv = v[i];
+    }
+}
+
+/* ------------------------------------------------------------------------------
+ * Fused clipped-PPO loss forward + backward for one minibatch of one network.
+ * Each workgroup recomputes the forward of its TR samples in LDS, forms the per-sample
+ * gradient of the loss w.r.t. the outputs, back-propagates through the MLP in LDS and
+ * writes its parameter-gradient partial (NPARAM floats) and its loss sums.
+ * ---------------------------------------------------------------------------- */
+struct PpoArgs {
+    const float *params;
+    const float *obs;
+    const int32_t *act;
+    const float *logp_old, *adv, *ret, *v_old;
+    int32_t m, n_act;
+    float clip, c_v, c_e, scale; /* scale = 1 / m */
+    float *partial;              /* [grid][NPARAM] */
+    float *loss_partial;         /* [grid][4]: total, policy, value, entropy (sums) */
+};
+
+__global__ void __launch_bounds__(256) k_ppo_fwd_bwd(PpoArgs a) {
+    extern __shared__ float sm[];
+    float *X = sm, *H1 = X + TR * XS, *H2 = H1 + TR * HS, *O = H2 + TR * HS;
+    const int row0 = (int)blockIdx.x * TR;
+    const int rows = min(TR, a.m - row0);
+    const float *P = a.params;
+    float *G = a.partial + (int64_t)blockIdx.x * NPARAM;
+    const int tid = (int)threadIdx.x, wave = tid >> 6;
+    forward_tile(P, a.obs + (int64_t)row0 * IN, rows, X, H1, H2, O);
+
+    /* per-sample loss and its gradient w.r.t. the 10 outputs (scaled by 1/m) */
+    float lsum[4] = {0.f, 0.f, 0.f, 0.f};
+    if (tid < TR) {
+        float *z = O + tid * OS;
+        float dz[OUT];
+#pragma unroll
+        for (int j = 0; j < OUT; ++j) dz[j] = 0.f;
+        if (tid < rows) {
+            const int s = row0 + tid;
+            const int nact = a.n_act;
+            float mx = z[0];
+            for (int j = 1; j < nact; ++j) mx = fmaxf(mx, z[j]);
+            float se = 0.f;
+            for (int j = 0; j < nact; ++j) se += expf(z[j] - mx);
+            const float lse = mx + logf(se);
+            float H = 0.f;
+            for (int j = 0; j < nact; ++j) {
+                const float lp = z[j] - lse;
+                H -= expf(lp) * lp;
+            }
+            const int act = a.act[s];
+            const float logp = z[act] - lse;
+            const float ratio = expf(logp - a.logp_old[s]);
+            const float A = a.adv[s];
+            const float s1 = ratio * A;
+            const float rc = fminf(fmaxf(ratio, 1.f - a.clip), 1.f + a.clip);
+            const float s2 = rc * A;
+            const float pol = -fminf(s1, s2);
+            const float dlogp = s1 <= s2 ? -A * ratio : 0.f;
+            const float v = z[9], R = a.ret[s], vo = a.v_old[s];
+            const float dvv = v - vo;
+            const float vc = vo + fminf(fmaxf(dvv, -a.clip), a.clip);
+            const float l1 = (v - R) * (v - R), l2 = (vc - R) * (vc - R);
+            const float val = 0.5f * fmaxf(l1, l2);
+            const float dval = l1 >= l2 ? (v - R) : (fabsf(dvv) < a.clip ? (vc - R) : 0.f);
+            for (int j = 0; j < nact; ++j) {
+                const float lp = z[j] - lse;
+                const float p = expf(lp);
+                const float dlp = (j == act ? 1.f : 0.f) - p;
+                dz[j] = a.scale * (dlogp * dlp + a.c_e * p * (lp + H));
+            }
+            dz[9] = a.scale * a.c_v * dval;
+            lsum[0] = pol + a.c_v * val - a.c_e * H;
+            lsum[1] = pol;
+            lsum[2] = val;
+            lsum[3] = H;
+        }
+        /* the output tile now holds dOut (cols 10..15 stay zero) */
+        for (int j = 0; j < OUT; ++j) z[j] = dz[j];
+    }
+    /* loss sums of the tile: wave 0 reduces its 64 lanes */
+    if (wave == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float v = lsum[q];
+            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+            if (tid == 0) a.loss_partial[(int64_t)blockIdx.x * 4 + q] = v;
+        }
+    }
+    __syncthreads();
+
+    /* dW3 = H2^T dOut (256 x 16, cols < 10 kept), db3 = column sums of dOut */
+    {
+        floatx4 acc[4][1];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[m][0] = zero4();
+        gemm<4, 1>(acc, TR, 64 * wave, 0, [&](int i, int k) { return H2[k * HS + i]; },
+                   [&](int k, int j) { return O[k * OS + j]; });
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 64 * wave + 16 * m + acc_row(i), c = acc_col();
+                if (c < OUT) G[O_W3 + r * OUT + c] = acc[m][0][i];
+            }
+        if (tid < OUT) {
+            float s = 0.f;
+            for (int r = 0; r < TR; ++r) s += O[r * OS + tid];
+            G[O_B3 + tid] = s;
+        }
+    }
+    __syncthreads();
+    /* dH2 = (dOut W3^T) * (1 - H2^2), in place of H2 */
+    {
+        floatx4 acc[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = zero4();
+        gemm<4, 4>(acc, OUTP, 0, 64 * wave, [&](int i, int k) { return O[i * OS + k]; },
+                   [&](int k, int j) { return k < OUT ? P[O_W3 + j * OUT + k] : 0.f; });
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * m + acc_row(i), c = 64 * wave + 16 * n + acc_col();
+                    const float h = H2[r * HS + c];
+                    H2[r * HS + c] = acc[m][n][i] * (1.f - h * h);
+                }
+    }
+    __syncthreads();
+    /* dW2 = H1^T dH2 (256 x 256) in four passes of 64 x 64 per wave; db2 */
+    for (int pass = 0; pass < 4; ++pass) {
+        floatx4 acc[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = zero4();
+        const int r0 = 64 * pass, c0 = 64 * wave;
+        gemm<4, 4>(acc, TR, r0, c0, [&](int i, int k) { return H1[k * HS + i]; },
+                   [&](int k, int j) { return H2[k * HS + j]; });
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = r0 + 16 * m + acc_row(i), c = c0 + 16 * n + acc_col();
+                    G[O_W2 + r * HID + c] = acc[m][n][i];
+                }
+    }
+    {
+        float s = 0.f;
+        for (int r = 0; r < TR; ++r) s += H2[r * HS + tid];
+        G[O_B2 + tid] = s;
+    }
+    __syncthreads();
+    /* dH1 = (dH2 W2^T) * (1 - H1^2), in place of H1 */
+    {
+        floatx4 acc[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = zero4();
+        gemm<4, 4>(acc, HID, 0, 64 * wave, [&](int i, int k) { return H2[i * HS + k]; },
+                   [&](int k, int j) { return P[O_W2 + j * HID + k]; });
+        /* each element of H1 is read and rewritten by the lane that owns it */
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * m + acc_row(i), c = 64 * wave + 16 * n + acc_col();
+                    const float h = H1[r * HS + c];
+                    H1[r * HS + c] = acc[m][n][i] * (1.f - h * h);
+                }
+    }
+    __syncthreads();
+    /* dW1 = X^T dH1 (40 x 256, computed as 48 x 256 with zero rows), db1 */
+    {
+        floatx4 acc[3][4];
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = zero4();
+        gemm<3, 4>(acc, TR, 0, 64 * wave, [&](int i, int k) { return X[k * XS + i]; },
+                   [&](int k, int j) { return H1[k * HS + j]; });
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * m + acc_row(i), c = 64 * wave + 16 * n + acc_col();
+                    if (r < IN) G[O_W1 + r * HID + c] = acc[m][n][i];
+                }
+        float s = 0.f;
+        for (int r = 0; r < TR; ++r) s += H1[r * HS + tid];
+        G[O_B1 + tid] = s;
+    }
+}
+
+/* sum of the per-workgroup partials, in workgroup order (deterministic) */
+__global__ void k_reduce(const float *__restrict__ partial, int nwg, int width, float *out) {
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= width) return;
+    float s = 0.f;
+    for (int w = 0; w < nwg; ++w) s += partial[(int64_t)w * width + j];
+    out[j] = s;
+}
+
+} // namespace ippo
+
+using namespace ippo;
+
+namespace {
+bool lds_opt_in() {
+    static bool done = false;
+    if (!done) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_policy_forward),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, LDS_FLOATS * 4) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(k_ppo_fwd_bwd),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, LDS_FLOATS * 4) != hipSuccess)
+            return false;
+        done = true;
+    }
+    return true;
+}
+} // namespace
+
+extern "C" {
+
+int lob_policy_forward(const float *params, const float *obs, int32_t n_agents, int32_t n, const int32_t *n_actions,
+                       uint64_t seed, int32_t t, float *logits, int32_t *actions, float *logp, float *value,
+                       void *stream) {
+    if (!params || !obs || !n_actions || !actions || !logp || !value) return LOB_EINVAL;
+    if (n_agents < 1 || n_agents > LOB_MAX_AGENTS || n <= 0) return LOB_EINVAL;
+    FwdArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.params = params; a.obs = obs; a.n = n; a.n_agents = n_agents;
+    for (int i = 0; i < n_agents; ++i) {
+        if (n_actions[i] < 1 || n_actions[i] > 9) return LOB_EINVAL;
+        a.n_act[i] = n_actions[i];
+    }
+    a.seed = seed; a.t = t; a.logits = logits; a.actions = actions; a.logp = logp; a.value = value;
+    if (!lds_opt_in()) return LOB_EHIP;
+    const dim3 grid((unsigned)((n + TR - 1) / TR), (unsigned)n_agents);
+    hipLaunchKernelGGL(k_policy_forward, grid, dim3(256), LDS_FLOATS * 4, (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
+}
+
+int lob_gae(const float *reward, const float *value, const uint8_t *done, const float *last_value, int32_t T,
+            int32_t n, float gamma, float lam, float *adv, float *ret, void *stream) {
+    if (!reward || !value || !done || !last_value || !adv || !ret || T <= 0 || n <= 0) return LOB_EINVAL;
+    hipLaunchKernelGGL(k_gae, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, reward, value,
+                       done, last_value, T, n, gamma, lam, adv, ret);
+    return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
+}
+
+int64_t lob_ppo_workspace_bytes(int32_t m) {
+    if (m <= 0) return LOB_EINVAL;
+    const int64_t nwg = (m + TR - 1) / TR;
+    return nwg * (NPARAM + 4) * 4;
+}
+
+int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, const float *logp_old,
+                    const float *adv, const float *ret, const float *v_old, int32_t m, int32_t n_actions, float clip,
+                    float c_v, float c_e, float *workspace, int64_t workspace_bytes, float *loss, float *grad,
+                    void *stream) {
+    if (!params || !obs || !act || !logp_old || !adv || !ret || !v_old || !workspace || !loss || !grad)
+        return LOB_EINVAL;
+    if (m <= 0 || n_actions < 1 || n_actions > 9 || !(clip > 0.f)) return LOB_EINVAL;
+    const int nwg = (m + TR - 1) / TR;
+    if (workspace_bytes < (int64_t)nwg * (NPARAM + 4) * 4) return LOB_EINVAL;
+    PpoArgs a;
+    a.params = params; a.obs = obs; a.act = act; a.logp_old = logp_old; a.adv = adv; a.ret = ret; a.v_old = v_old;
+    a.m = m; a.n_act = n_actions; a.clip = clip; a.c_v = c_v; a.c_e = c_e; a.scale = 1.0f / (float)m;
+    a.partial = workspace;
+    a.loss_partial = workspace + (int64_t)nwg * NPARAM;
+    if (!lds_opt_in()) return LOB_EHIP;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_ppo_fwd_bwd, dim3((unsigned)nwg), dim3(256), LDS_FLOATS * 4, st, a);
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((NPARAM + 255) / 256)), dim3(256), 0, st, (const float *)a.partial, nwg,
+                       NPARAM, grad);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, st, (const float *)a.loss_partial, nwg, 4, loss);
+    return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
+}
+
+} // extern "C"

@@ -1,0 +1,121 @@
+"""IPPO actor-critic on the GPU: policy forward with sampling, GAE, and the fused
+clipped-PPO loss with its hand-written backward behind ``torch.autograd.Function``.
+
+Argument marshalling only; the computation runs in ``liblob.so`` (MFMA kernels).
+Each agent type has its own network (independent PPO, Sec. 4.2 of the paper).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from .lob import lib, _check, _p, _stream, LobError
+
+N_PARAMS = 78858
+OBS_DIM = 40
+
+_ready = False
+
+
+def _lib():
+    global _ready
+    L = lib()
+    if not _ready:
+        p, i32, i64, f32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_uint64
+        L.lob_policy_forward.argtypes = [p, p, i32, i32, p, u64, i32, p, p, p, p, p]
+        L.lob_policy_forward.restype = ctypes.c_int
+        L.lob_gae.argtypes = [p, p, p, p, i32, i32, f32, f32, p, p, p]
+        L.lob_gae.restype = ctypes.c_int
+        L.lob_ppo_workspace_bytes.argtypes = [i32]
+        L.lob_ppo_workspace_bytes.restype = i64
+        L.lob_ppo_fwd_bwd.argtypes = [p, p, p, p, p, p, p, i32, i32, f32, f32, f32, p, i64, p, p, p]
+        L.lob_ppo_fwd_bwd.restype = ctypes.c_int
+        _ready = True
+    return L
+
+
+def _f32(t: torch.Tensor) -> torch.Tensor:
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise LobError("expected a contiguous float32 tensor")
+    return t
+
+
+def xavier_params(n_agents: int, seed: int, device="cuda") -> torch.Tensor:
+    """Glorot-uniform weights and zero biases for n_agents networks, [n_agents, N_PARAMS]."""
+    g = torch.Generator().manual_seed(seed)
+    out = torch.zeros(n_agents, N_PARAMS, dtype=torch.float32)
+    shapes = ((40, 256), (256,), (256, 256), (256,), (256, 10), (10,))
+    for a in range(n_agents):
+        o = 0
+        for s in shapes:
+            n = int(np.prod(s))
+            if len(s) == 2:
+                lim = float(np.sqrt(6.0 / (s[0] + s[1])))
+                out[a, o:o + n] = (torch.rand(n, generator=g) * 2 - 1) * lim
+            o += n
+    return out.to(device)
+
+
+def policy_forward(params: torch.Tensor, obs: torch.Tensor, n_actions: Sequence[int], seed: int, t: int,
+                   want_logits: bool = False) -> dict:
+    """params [A, N_PARAMS], obs [A, n, 40] (float32, device) -> actions, logp, value [A, n]."""
+    A, n = obs.shape[0], obs.shape[1]
+    dev = obs.device
+    acts = torch.empty((A, n), dtype=torch.int32, device=dev)
+    logp = torch.empty((A, n), dtype=torch.float32, device=dev)
+    value = torch.empty((A, n), dtype=torch.float32, device=dev)
+    logits = torch.empty((A, n, 10), dtype=torch.float32, device=dev) if want_logits else None
+    na = (ctypes.c_int32 * A)(*[int(x) for x in n_actions])
+    _check(_lib().lob_policy_forward(_p(_f32(params)), _p(_f32(obs)), A, n, na, seed, t, _p(logits), _p(acts),
+                                     _p(logp), _p(value), _stream()), "lob_policy_forward")
+    return {"actions": acts, "logp": logp, "value": value, "logits": logits}
+
+
+def gae(rewards: torch.Tensor, values: torch.Tensor, dones: torch.Tensor, last_value: torch.Tensor,
+        gamma: float = 0.99, lam: float = 0.95):
+    """rewards, values [T, n] float32, dones [T, n] uint8, last_value [n] -> (adv, ret)."""
+    T, n = rewards.shape
+    adv = torch.empty_like(rewards)
+    ret = torch.empty_like(rewards)
+    d = dones.to(torch.uint8).contiguous()
+    _check(_lib().lob_gae(_p(_f32(rewards)), _p(_f32(values)), _p(d), _p(_f32(last_value)), T, n, gamma, lam,
+                          _p(adv), _p(ret), _stream()), "lob_gae")
+    return adv, ret
+
+
+def ppo_fwd_bwd(params, obs, act, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01,
+                workspace=None):
+    """Loss sums [4] (total, policy, value, entropy) and the gradient of the mean loss."""
+    m = obs.shape[0]
+    L = _lib()
+    need = int(L.lob_ppo_workspace_bytes(m))
+    if workspace is None or workspace.numel() * 4 < need:
+        workspace = torch.empty((need + 3) // 4, dtype=torch.float32, device=obs.device)
+    loss = torch.empty(4, dtype=torch.float32, device=obs.device)
+    grad = torch.empty(N_PARAMS, dtype=torch.float32, device=obs.device)
+    _check(L.lob_ppo_fwd_bwd(_p(_f32(params)), _p(_f32(obs)), _p(act.to(torch.int32).contiguous()),
+                             _p(_f32(logp_old)), _p(_f32(adv)), _p(_f32(ret)), _p(_f32(v_old)), m, int(n_actions),
+                             clip, c_v, c_e, _p(workspace), workspace.numel() * 4, _p(loss), _p(grad), _stream()),
+           "lob_ppo_fwd_bwd")
+    return loss, grad
+
+
+class FusedPPOLoss(torch.autograd.Function):
+    """Mean clipped-PPO loss of one minibatch; forward runs the fused kernel, which also
+    produces the parameter gradient (activations recomputed, none stored); backward
+    scales that gradient by the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, params, obs, act, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01):
+        loss, grad = ppo_fwd_bwd(params.detach().contiguous(), obs, act, logp_old, adv, ret, v_old, n_actions,
+                                 clip, c_v, c_e)
+        ctx.save_for_backward(grad)
+        return loss[0] / obs.shape[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return (g * grad,) + (None,) * 10
