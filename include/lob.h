@@ -202,12 +202,17 @@ int lob_export_state(lob_ctx *ctx, int64_t *env_state, int64_t *agent_state, int
 /* Policy forward for the rollout.  params: device [n_agents][LOB_PPO_PARAMS];
  * obs: device [n_agents][n][40]; n_actions: host [n_agents] (1..9, the first n_actions
  * logits are the policy).  Samples one action per row by Gumbel-max with noise from the
- * counter hash of (seed, agent, action, t, row).  Outputs (device): logits [n_agents][n][10]
- * (may be NULL), actions [n_agents][n] int32, logp [n_agents][n] (log-probability of the
- * sampled action), value [n_agents][n].  Asynchronous on stream. */
+ * counter hash of (seed', agent, action, t, row), seed' = seed + golden * (*epoch) when
+ * epoch (a device uint64 counter, so that a captured graph draws new noise on each replay)
+ * is given, else seed.  Outputs (device): logits [n_agents][n][10] (may be NULL), actions
+ * [n_agents][n] int32, logp [n_agents][n] (log-probability of the sampled action), value
+ * [n_agents][n].  Asynchronous on stream. */
 int lob_policy_forward(const float *params, const float *obs, int32_t n_agents, int32_t n, const int32_t *n_actions,
-                       uint64_t seed, int32_t t, float *logits, int32_t *actions, float *logp, float *value,
-                       void *stream);
+                       uint64_t seed, const uint64_t *epoch, int32_t t, float *logits, int32_t *actions, float *logp,
+                       float *value, void *stream);
+
+/* Add one to a device uint64 counter (a kernel, so it can be captured in a graph). */
+int lob_counter_bump(uint64_t *counter, void *stream);
 
 /* Generalised advantage estimation over a rollout, all arrays device [T][n] (column =
  * env x agent): delta_t = r_t + gamma V_{t+1} (1 - d_t) - V_t with V_T = last_value [n],

@@ -142,6 +142,7 @@ struct FwdArgs {
     int32_t n, n_agents;
     int32_t n_act[LOB_MAX_AGENTS];
     uint64_t seed;
+    const uint64_t *epoch; /* device counter mixed into the seed, or null */
     int32_t t;
     float *logits; /* [A][n][10] or null */
     int32_t *actions;
@@ -160,6 +161,7 @@ __global__ void __launch_bounds__(256) k_policy_forward(FwdArgs a) {
     if (tid < rows) {
         const int nact = a.n_act[ag];
         const int e = row0 + tid;
+        const uint64_t seed = a.epoch ? a.seed + 0x9E3779B97F4A7C15ULL * a.epoch[0] : a.seed;
         const float *z = O + tid * OS;
         float m = z[0];
         for (int j = 1; j < nact; ++j) m = fmaxf(m, z[j]);
@@ -169,7 +171,7 @@ __global__ void __launch_bounds__(256) k_policy_forward(FwdArgs a) {
         int best = 0;
         float bv = -INFINITY;
         for (int j = 0; j < nact; ++j) {
-            const uint64_t h = hash4(a.seed, DOM_POLICY, (uint64_t)ag << 8 | (uint64_t)j, (uint64_t)a.t, (uint64_t)e);
+            const uint64_t h = hash4(seed, DOM_POLICY, (uint64_t)ag << 8 | (uint64_t)j, (uint64_t)a.t, (uint64_t)e);
             const float u = ((float)(uint32_t)(h >> 40) + 0.5f) * (1.0f / 16777216.0f);
             const float g = -logf(-logf(u));
             const float v = z[j] + g;
@@ -414,6 +416,10 @@ __global__ void k_reduce(const float *__restrict__ partial, int nwg, int width, 
     out[j] = s;
 }
 
+__global__ void k_bump(uint64_t *c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) c[0] += 1;
+}
+
 } // namespace ippo
 
 using namespace ippo;
@@ -436,8 +442,8 @@ bool lds_opt_in() {
 extern "C" {
 
 int lob_policy_forward(const float *params, const float *obs, int32_t n_agents, int32_t n, const int32_t *n_actions,
-                       uint64_t seed, int32_t t, float *logits, int32_t *actions, float *logp, float *value,
-                       void *stream) {
+                       uint64_t seed, const uint64_t *epoch, int32_t t, float *logits, int32_t *actions, float *logp,
+                       float *value, void *stream) {
     if (!params || !obs || !n_actions || !actions || !logp || !value) return LOB_EINVAL;
     if (n_agents < 1 || n_agents > LOB_MAX_AGENTS || n <= 0) return LOB_EINVAL;
     FwdArgs a;
@@ -447,10 +453,16 @@ int lob_policy_forward(const float *params, const float *obs, int32_t n_agents, 
         if (n_actions[i] < 1 || n_actions[i] > 9) return LOB_EINVAL;
         a.n_act[i] = n_actions[i];
     }
-    a.seed = seed; a.t = t; a.logits = logits; a.actions = actions; a.logp = logp; a.value = value;
+    a.seed = seed; a.epoch = epoch; a.t = t; a.logits = logits; a.actions = actions; a.logp = logp; a.value = value;
     if (!lds_opt_in()) return LOB_EHIP;
     const dim3 grid((unsigned)((n + TR - 1) / TR), (unsigned)n_agents);
     hipLaunchKernelGGL(k_policy_forward, grid, dim3(256), LDS_FLOATS * 4, (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
+}
+
+int lob_counter_bump(uint64_t *counter, void *stream) {
+    if (!counter) return LOB_EINVAL;
+    hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, (hipStream_t)stream, counter);
     return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
 }
 

@@ -25,7 +25,9 @@ def _lib():
     L = lib()
     if not _ready:
         p, i32, i64, f32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_uint64
-        L.lob_policy_forward.argtypes = [p, p, i32, i32, p, u64, i32, p, p, p, p, p]
+        L.lob_policy_forward.argtypes = [p, p, i32, i32, p, u64, p, i32, p, p, p, p, p]
+        L.lob_counter_bump.argtypes = [p, p]
+        L.lob_counter_bump.restype = ctypes.c_int
         L.lob_policy_forward.restype = ctypes.c_int
         L.lob_gae.argtypes = [p, p, p, p, i32, i32, f32, f32, p, p, p]
         L.lob_gae.restype = ctypes.c_int
@@ -59,19 +61,26 @@ def xavier_params(n_agents: int, seed: int, device="cuda") -> torch.Tensor:
     return out.to(device)
 
 
+def counter_bump(counter: torch.Tensor):
+    """counter += 1 on the device (graph-capturable); counter: uint64/int64 [1]."""
+    _check(_lib().lob_counter_bump(_p(counter), _stream()), "lob_counter_bump")
+
+
 def policy_forward(params: torch.Tensor, obs: torch.Tensor, n_actions: Sequence[int], seed: int, t: int,
-                   want_logits: bool = False) -> dict:
+                   want_logits: bool = False, epoch: torch.Tensor = None, out: dict = None) -> dict:
     """params [A, N_PARAMS], obs [A, n, 40] (float32, device) -> actions, logp, value [A, n]."""
     A, n = obs.shape[0], obs.shape[1]
     dev = obs.device
-    acts = torch.empty((A, n), dtype=torch.int32, device=dev)
-    logp = torch.empty((A, n), dtype=torch.float32, device=dev)
-    value = torch.empty((A, n), dtype=torch.float32, device=dev)
-    logits = torch.empty((A, n, 10), dtype=torch.float32, device=dev) if want_logits else None
+    if out is None:
+        out = {"actions": torch.empty((A, n), dtype=torch.int32, device=dev),
+               "logp": torch.empty((A, n), dtype=torch.float32, device=dev),
+               "value": torch.empty((A, n), dtype=torch.float32, device=dev),
+               "logits": torch.empty((A, n, 10), dtype=torch.float32, device=dev) if want_logits else None}
     na = (ctypes.c_int32 * A)(*[int(x) for x in n_actions])
-    _check(_lib().lob_policy_forward(_p(_f32(params)), _p(_f32(obs)), A, n, na, seed, t, _p(logits), _p(acts),
-                                     _p(logp), _p(value), _stream()), "lob_policy_forward")
-    return {"actions": acts, "logp": logp, "value": value, "logits": logits}
+    _check(_lib().lob_policy_forward(_p(_f32(params)), _p(_f32(obs)), A, n, na, seed, _p(epoch), t,
+                                     _p(out.get("logits")), _p(out["actions"]), _p(out["logp"]), _p(out["value"]),
+                                     _stream()), "lob_policy_forward")
+    return out
 
 
 def gae(rewards: torch.Tensor, values: torch.Tensor, dones: torch.Tensor, last_value: torch.Tensor,

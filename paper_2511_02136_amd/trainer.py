@@ -1,0 +1,118 @@
+"""IPPO on the batched LOB environment: learned-policy rollouts and PPO updates.
+
+One independent actor-critic per agent (Sec. 4.2 of the paper: separate networks, no
+shared weights).  A rollout step is the policy forward (MFMA kernel, sampling
+in-kernel) followed by one env step with the sampled actions; the whole T-step rollout
+(reset included) can be captured once in a HIP graph and replayed, with a device counter
+giving every replay fresh sampling noise.  The update runs GAE and, per agent, epochs of
+shuffled minibatches through the fused clipped-PPO kernel (activations recomputed) and
+torch's Adam.  Orchestration only: every step of the method runs in liblob's kernels.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import torch
+
+from . import ippo
+from .lob import LobEnv, DeviceStream
+
+# Fixed input scaling of the 40 observation features (part of the policy, not the env):
+# roughly the typical magnitude of each feature on the synthetic workloads.
+OBS_SCALE = ([10.0, 10.0, 100.0] + [100.0] * 20 + [1e4, 1e4, 100.0, 100.0, 1e3, 1e3, 100.0, 10.0, 100.0, 1e7,
+                                                    500.0, 128.0, 50.0, 50.0, 10.0, 50.0, 50.0])
+assert len(OBS_SCALE) == 40
+
+
+class IppoTrainer:
+    def __init__(self, env: LobEnv, dstream: DeviceStream, book: dict, n_steps: int, seed: int = 0,
+                 param_seed: int = 0, lr: float = 3e-4, epochs: int = 4, minibatches: int = 4, gamma: float = 0.99,
+                 lam: float = 0.95, clip: float = 0.2, c_v: float = 0.5, c_e: float = 0.01, record_trades: bool = True):
+        self.env, self.ds, self.book, self.T = env, dstream, book, n_steps
+        self.A, self.N = env.n_agents, env.n_envs
+        self.n_act = [3 if int(k) == 2 else 9 for k in env.kinds]
+        self.seed = seed
+        self.epochs, self.minibatches = epochs, minibatches
+        self.gamma, self.lam, self.clip, self.c_v, self.c_e = gamma, lam, clip, c_v, c_e
+        dev = env.device
+        self.params = torch.nn.Parameter(ippo.xavier_params(self.A, param_seed, device=dev))
+        self.opt = torch.optim.Adam([self.params], lr=lr)
+        self.inv_scale = (1.0 / torch.tensor(OBS_SCALE, dtype=torch.float32)).to(dev)
+        T, A, N = n_steps, self.A, self.N
+        self.obs = torch.empty((T + 1, A, N, 40), dtype=torch.float32, device=dev)
+        self.pol = {"actions": torch.empty((T, A, N), dtype=torch.int32, device=dev),
+                    "logp": torch.empty((T, A, N), dtype=torch.float32, device=dev),
+                    "value": torch.empty((T, A, N), dtype=torch.float32, device=dev)}
+        self.out = env._alloc_out(T, True, record_trades, None, dstream, actions_out=False)
+        self.cursor = torch.zeros(N, dtype=torch.int64, device=dev)
+        self.epoch = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.graph: Optional[torch.cuda.CUDAGraph] = None
+
+    # ---- rollout ----
+    def _rollout_body(self):
+        env, T = self.env, self.T
+        ippo.counter_bump(self.epoch)
+        env.reset(self.book)
+        self.cursor.zero_()
+        torch.mul(env.observe(), self.inv_scale, out=self.obs[0])
+        for t in range(T):
+            pf = {k: v[t] for k, v in self.pol.items()}
+            ippo.policy_forward(self.params.detach(), self.obs[t], self.n_act, self.seed, t, epoch=self.epoch, out=pf)
+            view = {k: (v[t:t + 1] if k not in ("trades", "trade_off") and v is not None else v)
+                    for k, v in self.out.items()}
+            env.step(self.ds, pf["actions"], out=view, cursor=self.cursor)
+            torch.mul(view["obs"][0], self.inv_scale, out=self.obs[t + 1])
+
+    def rollout(self, use_graph: bool = False):
+        """Reset and run T steps with the current policy; results stay in the buffers."""
+        if not use_graph:
+            self._rollout_body()
+            return
+        if self.graph is None:
+            self.env.reset(self.book)
+            self.env.plan(self.ds, self.T)
+            # warm up on a side stream (library state, allocator), then capture
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                self._rollout_body()
+            torch.cuda.current_stream().wait_stream(s)
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph):
+                self._rollout_body()
+        self.graph.replay()
+
+    # ---- update ----
+    def update(self) -> dict:
+        T, A, N = self.T, self.A, self.N
+        rew = self.out["reward"].reshape(T, A * N)
+        val = self.pol["value"].reshape(T, A * N)
+        done = self.out["done"].unsqueeze(1).expand(T, A, N).reshape(T, A * N).contiguous()
+        adv, ret = ippo.gae(rew.contiguous(), val.contiguous(), done, torch.zeros(A * N, device=rew.device),
+                            self.gamma, self.lam)
+        adv, ret = adv.reshape(T, A, N), ret.reshape(T, A, N)
+        M = T * N
+        mb = M // self.minibatches
+        stats = {"loss": 0.0, "minibatches": 0}
+        for _ in range(self.epochs):
+            perms = [torch.randperm(M, device=rew.device) for _ in range(A)]
+            for k in range(self.minibatches):
+                self.opt.zero_grad(set_to_none=True)
+                total = 0.0
+                for a in range(A):
+                    idx = perms[a][k * mb:(k + 1) * mb]
+                    obs = self.obs[:T, a].reshape(M, 40)[idx].contiguous()
+                    act = self.pol["actions"][:, a].reshape(M)[idx].contiguous()
+                    lpo = self.pol["logp"][:, a].reshape(M)[idx].contiguous()
+                    ad = adv[:, a].reshape(M)[idx].contiguous()
+                    rt = ret[:, a].reshape(M)[idx].contiguous()
+                    vo = self.pol["value"][:, a].reshape(M)[idx].contiguous()
+                    loss = ippo.FusedPPOLoss.apply(self.params[a], obs, act, lpo, ad, rt, vo, self.n_act[a],
+                                                   self.clip, self.c_v, self.c_e)
+                    total = total + loss
+                total.backward()
+                self.opt.step()
+                stats["loss"] += float(total.detach())
+                stats["minibatches"] += 1
+        stats["loss"] /= max(1, stats["minibatches"])
+        return stats
