@@ -20,6 +20,10 @@ HIPCC_FLAGS = [
     "-ffp-contract=off",
     "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # lane-0 LDS counter updates need no wave-level reduction of the atomic operand
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
+    # wave-uniform branches stay plain scalar branches (no exec-mask flow blocks)
+    "-mllvm", "-structurizecfg-skip-uniform-regions",
     "-Wall",
     "-Wno-unused-function",
 ]

@@ -55,13 +55,12 @@ constexpr int X_AG = X_NLV + 8;                   /* int64 MAXA x AGW */
 constexpr int X_FL = X_AG + MAXA * AGW * 2;       /* int64 MAXA x 4: fills of the step */
 constexpr int X_OBK = X_FL + MAXA * 4 * 2;        /* int64 34: depth buckets, totals, own stats */
 constexpr int N_OBK = 22 + 3 * MAXA;
-constexpr int X_CTR = X_OBK + 34 * 2;             /* int64 NCTR: counters */
-constexpr int X_ENV = X_CTR + NCTR * 2;           /* int64 8: env state (global layout) */
+constexpr int X_ENV = X_OBK + 34 * 2;             /* int64 8: env state (global layout) */
 constexpr int X_ST = X_ENV + 8 * 2;               /* int64 STW: last step's statistics */
 constexpr int X_END = X_ST + STW * 2;
 constexpr int EXTRA_WORDS = (X_END + 63) & ~63;
 static_assert(N_OBK <= 34, "obs accumulator area");
-static_assert((X_AG & 1) == 0 && (X_FL & 1) == 0 && (X_OBK & 1) == 0 && (X_CTR & 1) == 0 &&
+static_assert((X_AG & 1) == 0 && (X_FL & 1) == 0 && (X_OBK & 1) == 0 &&
               (X_ENV & 1) == 0 && (X_ST & 1) == 0, "int64 alignment");
 
 __host__ __device__ constexpr int lds_words_for(int capp) { return 2 * NF * capp + EXTRA_WORDS; }
@@ -116,35 +115,39 @@ struct KArgs {
 template <int ROWS>
 struct Run {
     static constexpr int CAPP = ROWS * WAVE; /* slots per side in LDS (compile time) */
-    static constexpr int capp = CAPP;
     const KArgs &a;
     int32_t *L;  /* this wave's LDS (uniform) */
     int2 *Pl;    /* this lane's slot of row 0, side 0, pair 0 */
     int lane, cap, e, A, t;
-    /* book */
+    /* book: live orders and best price per side */
     int n0, n1, best0, best1;
     /* per step, hot */
     int64_t mid_sum, st_buy, st_sell;
-    int32_t mid_n, seq, st_trades, st_last, last_tsec, last_tns;
-    /* trade records: absolute record indices of the env's region */
-    int64_t tr_next, tr_end, tr_step0;
+    int32_t mid_n, seq, st_last, last_tsec, last_tns;
+    /* trade records: this launch's part of the env's region starts at tr_base; records
+     * produced so far in the launch, room left in the region, value at step start */
+    int32_t *tr_base;
+    int64_t tr_cur0;
+    int32_t tr_next, tr_room, tr_step0;
+    /* counters: lane k holds counter k */
+    int64_t ctr;
 
     __device__ Run(const KArgs &args, int32_t *lds, int env)
         : a(args), L(lds), lane(lane_id()), e(uni(env)), A(args.n_agents) {
         Pl = reinterpret_cast<int2 *>(lds) + lane;
         cap = uni(a.caps[e]);
     }
-    /* this lane's slot of row 0 of side s, pair p (row r is +r*64: an immediate offset) */
-    __device__ __forceinline__ int2 *RowP(int s, int p) { return Pl + (s * 3 + p) * CAPP; }
 
-    /* ---- LDS views: per side three int2 arrays (price|qty, oid|tid, tsec|tns) ---- */
-    __device__ __forceinline__ int2 *PR(int s, int pair) {
-        return reinterpret_cast<int2 *>(L) + (s * 3 + pair) * capp;
+    /* ---- LDS views.  Per side three int2 arrays of CAPP slots (price|qty, oid|tid,
+     * tsec|tns).  Internal slot j counts from the worst order (j = 0) to the best
+     * (j = n - 1), so the top of the book is at the end of the live range. ---- */
+    /* this lane's slot in row 0 of side s, pair 0 (pair p is +p*CAPP, row r is +r*64) */
+    __device__ __forceinline__ int2 *SB(int s) { return Pl + s * (3 * CAPP); }
+    /* slot i of side s, pair p (any index, e.g. uniform) */
+    __device__ __forceinline__ int2 &U(int s, int p, int i) {
+        return reinterpret_cast<int2 *>(L)[(s * 3 + p) * CAPP + i];
     }
-    __device__ __forceinline__ int32_t &B(int s, int f, int i) {
-        return L[((s * 3 + (f >> 1)) * capp + i) * 2 + (f & 1)];
-    }
-    __device__ __forceinline__ int32_t *X() { return L + 2 * NF * capp; }
+    __device__ __forceinline__ int32_t *X() { return L + 2 * NF * CAPP; }
     __device__ __forceinline__ int64_t *X64(int off) { return reinterpret_cast<int64_t *>(X() + off); }
     __device__ __forceinline__ int64_t *AG(int i) { return X64(X_AG) + i * AGW; }
     __device__ __forceinline__ int64_t *FL(int i) { return X64(X_FL) + i * 4; }
@@ -160,116 +163,84 @@ struct Run {
         if (s) best1 = v; else best0 = v;
     }
     __device__ __forceinline__ void refresh_best(int s) {
-        int v = nsz(s) > 0 ? uni(B(s, FP, 0)) : 0;
-        set_best(s, v);
+        const int n = nsz(s);
+        set_best(s, n > 0 ? uni(U(s, 0, n - 1).x) : 0);
     }
-    /* counters live in LDS; lane 0 adds (no return value, no wait) */
-    __device__ __forceinline__ void count(int k, int64_t v) {
-        if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long *>(X64(X_CTR) + k), (unsigned long long)v);
-    }
+    __device__ __forceinline__ void count(int k, int64_t v) { ctr += (lane == k) ? v : 0; }
 
-    /* ---- row shifts: groups of four rows, all loads of a group before its stores;
-     * rows are unrolled so every access is an immediate LDS offset ---- */
-    /* move slots [from, to) of side s to [from+1, to+1); to < CAPP */
-    __device__ __forceinline__ void shift_up(int s, int from, int to) {
-        if (to <= from) return;
-        int2 *d0 = RowP(s, 0);
-        int2 *d1 = d0 + CAPP, *d2 = d0 + 2 * CAPP;
-        int2 *s0 = d0 - 1;
-        int2 *s1 = s0 + CAPP, *s2 = s0 + 2 * CAPP;
-        const int rlo = (from + 1) >> 6, rhi = to >> 6;
-#pragma unroll
-        for (int g = (ROWS - 1) / 4; g >= 0; --g) {
-            if (g * 4 > rhi || g * 4 + 3 < rlo) continue;
-            int2 v0[4], v1[4], v2[4];
-            bool mv[4];
-#pragma unroll
-            for (int k = 3; k >= 0; --k) {
-                const int r = g * 4 + k;
-                mv[k] = false;
-                if (r < ROWS && r >= rlo && r <= rhi) {
-                    const int i = r * WAVE + lane;
-                    mv[k] = i > from && i <= to;
-                    if (mv[k]) { v0[k] = s0[r * WAVE]; v1[k] = s1[r * WAVE]; v2[k] = s2[r * WAVE]; }
-                }
-            }
-            WAVE_SYNC();
-#pragma unroll
-            for (int k = 3; k >= 0; --k) {
-                const int r = g * 4 + k;
-                if (r < ROWS && mv[k]) { d0[r * WAVE] = v0[k]; d1[r * WAVE] = v1[k]; d2[r * WAVE] = v2[k]; }
-            }
-            WAVE_SYNC();
-        }
-    }
-    /* remove k slots at [at, at+k) of a side holding n: [at+k, n) moves to [at, n-k) */
-    __device__ __forceinline__ void shift_down(int s, int at, int k, int n) {
-        const int newn = n - k;
-        if (k <= 0 || at >= newn) return;
-        int2 *d0 = RowP(s, 0);
-        int2 *d1 = d0 + CAPP, *d2 = d0 + 2 * CAPP;
-        const int2 *s0 = d0 + k;
-        const int2 *s1 = s0 + CAPP, *s2 = s0 + 2 * CAPP;
-        const int rlo = at >> 6, rhi = (newn - 1) >> 6;
-#pragma unroll
-        for (int g = 0; g <= (ROWS - 1) / 4; ++g) {
-            if (g * 4 > rhi || g * 4 + 3 < rlo) continue;
-            int2 v0[4], v1[4], v2[4];
-            bool mv[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = g * 4 + q;
-                mv[q] = false;
-                if (r < ROWS && r >= rlo && r <= rhi) {
-                    const int i = r * WAVE + lane;
-                    mv[q] = i >= at && i < newn;
-                    if (mv[q]) { v0[q] = s0[r * WAVE]; v1[q] = s1[r * WAVE]; v2[q] = s2[r * WAVE]; }
-                }
-            }
-            WAVE_SYNC();
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = g * 4 + q;
-                if (r < ROWS && mv[q]) { d0[r * WAVE] = v0[q]; d1[r * WAVE] = v1[q]; d2[r * WAVE] = v2[q]; }
-            }
-            WAVE_SYNC();
-        }
-    }
-    __device__ __forceinline__ void put(int s, int i, int p, int q, int o, int tid, int ts, int tn) {
-        if (lane == 0) {
-            int2 *u = reinterpret_cast<int2 *>(L) + s * 3 * CAPP + i;
-            u[0] = make_int2(p, q);
-            u[CAPP] = make_int2(o, tid);
-            u[2 * CAPP] = make_int2(ts, tn);
-        }
-        WAVE_SYNC();
-    }
-    /* first index in [i0, n) of side s whose field f equals v, or -1 (4 rows per wait) */
-    __device__ __forceinline__ int find_eq(int s, int f, int i0, int n, int v) {
-        const int32_t *col = reinterpret_cast<const int32_t *>(RowP(s, f >> 1)) + (f & 1);
-        const int rlo = i0 >> 6, rhi = (n - 1) >> 6;
-#pragma unroll
-        for (int g = 0; g <= (ROWS - 1) / 4; ++g) {
-            if (n <= 0 || g * 4 > rhi || g * 4 + 3 < rlo) continue;
-            int x[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = g * 4 + q;
-                x[q] = ~v;
-                if (r < ROWS && r >= rlo && r <= rhi) x[q] = col[r * WAVE * 2];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = g * 4 + q;
-                if (r < ROWS && r >= rlo && r <= rhi) {
-                    const int i = r * WAVE + lane;
-                    const uint64_t m = ballot(i >= i0 && i < n && x[q] == v);
-                    if (m) return r * WAVE + __builtin_ctzll(m);
-                }
-            }
+    /* ---- searches: rows from the top of the book down, stopping at the first hit ---- */
+    /* highest slot <= hi of side s whose field f (FO or FT) equals v, or -1; for oids this
+     * is the first order with that id in priority order */
+    __device__ __forceinline__ int find_top(int s, int f, int hi, int v) {
+        const int32_t *col = reinterpret_cast<const int32_t *>(SB(s) + (f >> 1) * CAPP) + (f & 1);
+        for (int r = hi >> 6; r >= 0; --r) {
+            const int j = (r << 6) + lane;
+            const int x = col[r * (2 * WAVE)];
+            const uint64_t m = ballot(j <= hi && x == v);
+            if (m) return (r << 6) + 63 - __builtin_clzll(m);
         }
         return -1;
     }
+    /* orders of side s (n live) whose price is equal to or better than the one with key
+     * kp: prices compare as (price ^ m) with m = -1 for bids and 0 for asks, so "better or
+     * equal" is "key <=" on both sides.  They are the top slots of the side. */
+    __device__ __forceinline__ int count_ahead(int s, int n, int kp, int m) {
+        const int32_t *col = reinterpret_cast<const int32_t *>(SB(s));
+        int cnt = 0;
+        for (int r = (n - 1) >> 6; r >= 0; --r) {
+            const int j = (r << 6) + lane;
+            const int x = col[r * (2 * WAVE)];
+            const int c = __popcll(ballot(j < n && (x ^ m) <= kp));
+            cnt += c;
+            if (c < min(WAVE, n - (r << 6))) break;
+        }
+        return cnt;
+    }
+
+    /* ---- book edits: one pass over the rows they touch, loads of a row before its
+     * stores; each lane moves its own slot ---- */
+    /* slots [ins, n) of side s move up by one; the new order takes slot ins (n < CAPP) */
+    __device__ __forceinline__ void insert_at(int s, int ins, int n, int2 v0, int2 v1, int2 v2) {
+        int2 *S = SB(s);
+        for (int r = n >> 6; r >= (ins >> 6); --r) {
+            const int j = (r << 6) + lane;
+            int2 *d = S + r * WAVE;
+            int2 x0 = v0, x1 = v1, x2 = v2;
+            if (j > ins && j <= n) { x0 = d[-1]; x1 = d[CAPP - 1]; x2 = d[2 * CAPP - 1]; }
+            WAVE_SYNC();
+            if (j >= ins && j <= n) { d[0] = x0; d[CAPP] = x1; d[2 * CAPP] = x2; }
+            WAVE_SYNC();
+        }
+    }
+    /* slot k of side s (n live) leaves: [k+1, n) moves down by one */
+    __device__ __forceinline__ void remove_at(int s, int k, int n) {
+        int2 *S = SB(s);
+        for (int r = k >> 6; r <= (n - 2) >> 6; ++r) {
+            const int j = (r << 6) + lane;
+            int2 *d = S + r * WAVE;
+            const bool mv = j >= k && j < n - 1;
+            int2 x0 = make_int2(0, 0), x1 = x0, x2 = x0;
+            if (mv) { x0 = d[1]; x1 = d[CAPP + 1]; x2 = d[2 * CAPP + 1]; }
+            WAVE_SYNC();
+            if (mv) { d[0] = x0; d[CAPP] = x1; d[2 * CAPP] = x2; }
+            WAVE_SYNC();
+        }
+    }
+    /* full side: the worst order (slot 0) leaves, [1, ins) moves down by one and the new
+     * order takes slot ins - 1 (ins >= 1) */
+    __device__ __forceinline__ void evict_insert(int s, int ins, int2 v0, int2 v1, int2 v2) {
+        int2 *S = SB(s);
+        for (int r = 0; r <= (ins - 1) >> 6; ++r) {
+            const int j = (r << 6) + lane;
+            int2 *d = S + r * WAVE;
+            int2 x0 = v0, x1 = v1, x2 = v2;
+            if (j < ins - 1) { x0 = d[1]; x1 = d[CAPP + 1]; x2 = d[2 * CAPP + 1]; }
+            WAVE_SYNC();
+            if (j < ins) { d[0] = x0; d[CAPP] = x1; d[2 * CAPP] = x2; }
+            WAVE_SYNC();
+        }
+    }
+
     /* ---- fills (uniform accumulation in LDS by lane 0) ---- */
     __device__ __forceinline__ void add_fill(int tid, int buy, int64_t q, int64_t notional) {
         if (tid >= 1 && tid <= A) {
@@ -283,88 +254,90 @@ struct Run {
     }
 
     /* ---- trade records ---- */
-    __device__ __forceinline__ void write_trade(int64_t k, int price, int q, int agg_oid, int pas_oid,
+    __device__ __forceinline__ void write_trade(int k, int price, int q, int agg_oid, int pas_oid,
                                                 int agg_tid, int pas_tid, int side) {
-        const int64_t rec = tr_next + k;
-        if (rec < tr_end) {
-            int4 *p = reinterpret_cast<int4 *>(a.trades + rec * LOB_TRADE_WORDS);
+        const int rec = tr_next + k;
+        if (rec < tr_room) {
+            int4 *p = reinterpret_cast<int4 *>(tr_base + (int64_t)rec * LOB_TRADE_WORDS);
             p[0] = make_int4(price, q, agg_oid, pas_oid);
             p[1] = make_int4(agg_tid, pas_tid, side | (seq << 1), t);
         }
     }
     __device__ __forceinline__ void close_trades(int ntr, int64_t volume, int side, int last_price) {
         tr_next += ntr;
-        st_trades += ntr;
         if (side == 0) st_buy += volume; else st_sell += volume;
         st_last = last_price;
     }
 
     /* ---- matching: an incoming order of side `side` against the opposite side while it
-     * crosses (market orders cross at any price); trades at the resting price.  Returns
-     * the unmatched remainder. ---- */
+     * crosses (market orders cross at any price); trades at the resting price, best
+     * first.  Returns the unmatched remainder. ---- */
     __device__ __forceinline__ int match(int side, int p, int q, bool market, int agg_oid, int agg_tid) {
-        const int opp = 1 - side;
+        const int opp = side ^ 1;
         const int no = nsz(opp);
-        if (no == 0 || q <= 0) return q;
+        if (no == 0) return q;
         const int bp = best(opp);
-        if (!(market || (side == 0 ? bp <= p : bp >= p))) return q;
-        const int2 top = PR(opp, 1)[0];
-        const int bq = uni(B(opp, FQ, 0));
-        if (bq >= q) {
+        const int mo = opp ? 0 : -1;
+        const int kp = p ^ mo;
+        if (!market && (bp ^ mo) > kp) return q;
+        const int jt = no - 1;
+        const int tq = uni(U(opp, 0, jt).y);
+        if (tq >= q) {
             /* the best order alone covers the incoming quantity */
-            const int poid = uni(top.x);
-            const int ptid = uni(top.y);
+            const int2 ot = U(opp, 1, jt);
+            const int poid = uni(ot.x), ptid = uni(ot.y);
             if (lane == 0) write_trade(0, bp, q, agg_oid, poid, agg_tid, ptid, side);
             add_fill(agg_tid, side == 0, q, (int64_t)q * bp);
             add_fill(ptid, side != 0, q, (int64_t)q * bp);
-            if (bq == q) {
-                shift_down(opp, 0, 1, no);
-                set_n(opp, no - 1);
+            if (tq == q) {
+                set_n(opp, jt);
                 refresh_best(opp);
             } else {
-                if (lane == 0) B(opp, FQ, 0) = bq - q;
+                if (lane == 0) U(opp, 0, jt).y = tq - q;
                 WAVE_SYNC();
             }
             close_trades(1, q, side, bp);
             return 0;
         }
-        /* general case: prefix scan of the crossing quantities, row by row */
+        /* general case: rows from the top down; in a row priority runs from the highest
+         * lane down, so the quantity ahead of a lane is a suffix sum */
+        int2 *O = SB(opp);
         int64_t carry = 0, my_notional = 0;
         int ntr = 0, nfull = 0, last_price = bp;
-        const int rows = (no + 63) >> 6;
-        for (int r = 0; r < rows; ++r) {
-            const int i = (r << 6) + lane;
-            const bool valid = i < no;
-            int2 pq = make_int2(0, 0), ot = make_int2(0, 0);
-            if (valid) { pq = RowP(opp, 0)[r * WAVE]; ot = RowP(opp, 1)[r * WAVE]; }
-            const int pr = pq.x, qt = pq.y;
-            const bool cr = valid && (market || (side == 0 ? pr <= p : pr >= p));
-            const int64_t x = cr ? (int64_t)qt : 0;
-            const int64_t incl = wave_incl_scan64(x, lane) + carry;
-            const int64_t excl = incl - x;
-            const int take = (cr && excl < q) ? (int)min((int64_t)qt, (int64_t)q - excl) : 0;
-            const bool has = take > 0;
-            const uint64_t hm = ballot(has);
-            const int ptid = ot.y;
-            if (has) {
-                write_trade(ntr + lane, pr, take, agg_oid, ot.x, agg_tid, ptid, side);
-                if (take < qt) B(opp, FQ, i) = qt - take;
-                my_notional += (int64_t)take * pr;
+        for (int r = jt >> 6; r >= 0; --r) {
+            const int j = (r << 6) + lane;
+            const bool valid = j < no;
+            int2 *d = O + r * WAVE;
+            const int2 pq = d[0], ot = d[CAPP];
+            const bool cr = valid && (market || (pq.x ^ mo) <= kp);
+            const int64_t x = cr ? (int64_t)pq.y : 0;
+            const int64_t pre = wave_incl_scan64(x, lane);
+            const int64_t tot = rdlane64(pre, 63);
+            const int64_t ahead = carry + (tot - pre);
+            const int take = (cr && ahead < q) ? (int)min((int64_t)pq.y, (int64_t)q - ahead) : 0;
+            const uint64_t hm = ballot(take > 0);
+            if (hm) {
+                /* the taking lanes are contiguous and end at this row's best order */
+                const int ltop = 63 - __builtin_clzll(hm);
+                if (take > 0) {
+                    write_trade(ntr + (ltop - lane), pq.x, take, agg_oid, ot.x, agg_tid, ot.y, side);
+                    if (take < pq.y) d[0].y = pq.y - take;
+                    my_notional += (int64_t)take * pq.x;
+                }
+                WAVE_SYNC();
+                /* resting orders of agents filled in this row (rare): accumulate uniformly */
+                uint64_t pm = ballot(take > 0 && ot.y >= 1 && ot.y <= A);
+                while (pm) {
+                    const int jj = __builtin_ctzll(pm);
+                    pm &= pm - 1;
+                    const int tj = rdlane(ot.y, jj), kj = rdlane(take, jj), pj = rdlane(pq.x, jj);
+                    add_fill(tj, side != 0, kj, (int64_t)kj * pj);
+                }
+                nfull += __popcll(ballot(take > 0 && take == pq.y));
+                last_price = rdlane(pq.x, __builtin_ctzll(hm));
+                ntr += __popcll(hm);
             }
-            WAVE_SYNC();
-            /* resting orders of agents filled in this row (rare): accumulate uniformly */
-            uint64_t pm = ballot(has && ptid >= 1 && ptid <= A);
-            while (pm) {
-                const int j = __builtin_ctzll(pm);
-                pm &= pm - 1;
-                const int tj = rdlane(ptid, j), kj = rdlane(take, j), pj = rdlane(pr, j);
-                add_fill(tj, side != 0, kj, (int64_t)kj * pj);
-            }
-            nfull += __popcll(ballot(has && take == qt));
-            const int c = __popcll(hm);
-            if (c > 0) last_price = rdlane(pr, 63 - __builtin_clzll(hm));
-            ntr += c;
-            carry = rdlane64(incl, 63);
+            carry += tot;
             if (carry >= q || ballot(cr) != ballot(valid)) break;
         }
         const int traded = (int)min((int64_t)q, carry);
@@ -373,7 +346,7 @@ struct Run {
             add_fill(agg_tid, side == 0, traded, notional);
         }
         if (nfull > 0) {
-            shift_down(opp, 0, nfull, no);
+            /* the fully filled orders are the top nfull slots */
             set_n(opp, no - nfull);
             refresh_best(opp);
         }
@@ -386,78 +359,51 @@ struct Run {
      * better than that order's, else the remainder is dropped. ---- */
     __device__ __forceinline__ void rest(int side, int p, int q, int oid, int tid, int ts, int tn) {
         const int n = nsz(side);
-        int pos = 0;
-        {
-            const int32_t *col = reinterpret_cast<const int32_t *>(RowP(side, 0));
-            const int rhi = (n - 1) >> 6;
-            bool stop = n <= 0;
-#pragma unroll
-            for (int g = 0; g <= (ROWS - 1) / 4; ++g) {
-                if (stop || g * 4 > rhi) continue;
-                int x[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = g * 4 + q;
-                    x[q] = 0;
-                    if (r < ROWS && r <= rhi) x[q] = col[r * WAVE * 2];
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = g * 4 + q;
-                    if (!stop && r < ROWS && r <= rhi) {
-                        const int i = r * WAVE + lane;
-                        const bool be = i < n && (side == 0 ? x[q] >= p : x[q] <= p);
-                        const int c = __popcll(ballot(be));
-                        pos += c;
-                        stop = c < WAVE;
-                    }
-                }
-            }
-        }
+        const int m = side ? 0 : -1;
+        const int kp = p ^ m;
+        const int cnt = count_ahead(side, n, kp, m);
+        const int ins = n - cnt;
         if (n < cap) {
-            shift_up(side, pos, n);
-            put(side, pos, p, q, oid, tid, ts, tn);
+            insert_at(side, ins, n, make_int2(p, q), make_int2(oid, tid), make_int2(ts, tn));
             set_n(side, n + 1);
         } else {
-            const int2 w = PR(side, 0)[n - 1];
+            const int2 w = U(side, 0, 0);
             const int wp = uni(w.x);
-            const bool better = side == 0 ? p > wp : p < wp;
-            if (!better) {
+            if (kp >= (wp ^ m)) {
                 count(C_DROP, 1);
                 count(C_DROPPED_QTY, q);
                 return;
             }
             count(C_EVICT, 1);
             count(C_EVICTED_QTY, uni(w.y));
-            shift_up(side, pos, n - 1);
-            put(side, pos, p, q, oid, tid, ts, tn);
+            evict_insert(side, ins, make_int2(p, q), make_int2(oid, tid), make_int2(ts, tn));
         }
-        if (pos == 0) set_best(side, p);
+        if (cnt == 0) set_best(side, p);
     }
 
-    /* ---- cancels: the first order with this id on the message's side ---- */
+    /* ---- cancels: the first order with this id (priority order) on the message's side ---- */
     __device__ __forceinline__ void cancel(bool partial, int side, int qty, int oid) {
         const int n = nsz(side);
-        const int found = find_eq(side, FO, 0, n, oid);
-        if (found < 0) {
+        const int k = find_top(side, FO, n - 1, oid);
+        if (k < 0) {
             count(C_MISS, 1);
             return;
         }
         if (partial) {
-            const int cq = uni(B(side, FQ, found));
+            const int cq = uni(U(side, 0, k).y);
             const int left = cq - min(qty, cq);
             if (left > 0) {
-                if (lane == 0) B(side, FQ, found) = left;
+                if (lane == 0) U(side, 0, k).y = left;
                 WAVE_SYNC();
                 return;
             }
         }
-        shift_down(side, found, 1, n);
+        remove_at(side, k, n);
         set_n(side, n - 1);
-        if (found == 0) refresh_best(side);
+        if (k == n - 1) refresh_best(side);
     }
 
-    /* ---- one message of the step sequence (the only call site of the book ops) ---- */
+    /* ---- one message of the step sequence ---- */
     __device__ __forceinline__ void process(int ts, int price, int qty, int oid, int tid, int tsec, int tns) {
         const int type = ts & 0xFF, side = (ts >> 8) & 1;
         if (type == T_LIMIT || type == T_MARKET) {
@@ -477,13 +423,11 @@ struct Run {
         } else {
             count(C_BAD, 1);
         }
-        after_message(tsec, tns);
+        after_message();
     }
-    /* per message of the sequence: its time becomes the last processed time; mid
-     * statistics for the reward (both sides non-empty); message index */
-    __device__ __forceinline__ void after_message(int tsec, int tns) {
-        last_tsec = tsec;
-        last_tns = tns;
+    /* per message of the sequence: mid statistics for the reward (both sides non-empty)
+     * and the message index */
+    __device__ __forceinline__ void after_message() {
         if (n0 > 0 && n1 > 0) {
             mid_sum += (int64_t)best0 + best1;
             mid_n += 1;
@@ -594,17 +538,17 @@ struct Run {
         /* resting quantity of this agent at each desired level (step start) */
         if (nlv > 0) {
             for (int s = 0; s < 2; ++s) {
-                const int n = nsz(s);
-                int i0 = 0;
+                int hi = nsz(s) - 1;
                 for (;;) {
-                    const int j = find_eq(s, FT, i0, n, tid);
+                    const int j = find_top(s, FT, hi, tid);
                     if (j < 0) break;
-                    const int k = find_level(i, nlv, s, uni(B(s, FP, j)));
+                    const int2 pq = U(s, 0, j);
+                    const int k = find_level(i, nlv, s, uni(pq.x));
                     if (k >= 0) {
-                        if (lane == 0) LV(i, k)[3] += B(s, FQ, j);
+                        if (lane == 0) LV(i, k)[3] += pq.y;
                         WAVE_SYNC();
                     }
-                    i0 = j + 1;
+                    hi = j - 1;
                 }
             }
         }
@@ -644,8 +588,8 @@ struct Run {
             for (int r = 0; (r << 6) < n; ++r) {
                 const int i = (r << 6) + lane;
                 if (i < n) {
-                    const int2 pq = PR(s, 0)[i];
-                    const int td = B(s, FT, i);
+                    const int2 pq = U(s, 0, i);
+                    const int td = U(s, 1, i).y;
                     const int64_t d = s == 0 ? (int64_t)bb - pq.x : (int64_t)pq.x - ba;
                     if (d >= 0 && d <= 9)
                         atomicAdd(reinterpret_cast<unsigned long long *>(O + s * 10 + d), (unsigned long long)pq.y);
@@ -698,7 +642,7 @@ struct Run {
         }
     }
 
-    /* ---- load / store of the env ---- */
+    /* ---- load / store of the env (books in HBM are in priority order, best first) ---- */
     __device__ __forceinline__ void load() {
         const int64_t gb = (int64_t)e * 2;
         n0 = min(uni(a.bk_n[gb]), cap);
@@ -706,27 +650,34 @@ struct Run {
         for (int s = 0; s < 2; ++s) {
             const int n = nsz(s);
             const int64_t off = (gb + s) * a.max_cap;
-            int2 *p0 = PR(s, 0), *p1 = PR(s, 1), *p2 = PR(s, 2);
             for (int i = lane; i < n; i += WAVE) {
-                p0[i] = make_int2(a.bk[FP][off + i], a.bk[FQ][off + i]);
-                p1[i] = make_int2(a.bk[FO][off + i], a.bk[FT][off + i]);
-                p2[i] = make_int2(a.bk[FS][off + i], a.bk[FN][off + i]);
+                const int j = n - 1 - i;
+                U(s, 0, j) = make_int2(a.bk[FP][off + i], a.bk[FQ][off + i]);
+                U(s, 1, j) = make_int2(a.bk[FO][off + i], a.bk[FT][off + i]);
+                U(s, 2, j) = make_int2(a.bk[FS][off + i], a.bk[FN][off + i]);
             }
         }
-        /* env state, counters, statistics and agent state into LDS */
+        /* env state, statistics and agent state into LDS, counters into lanes */
         if (lane < LOB_ENV_STATE_WORDS) ENV()[lane] = a.env_state[(int64_t)e * LOB_ENV_STATE_WORDS + lane];
-        if (lane < NCTR) X64(X_CTR)[lane] = a.counters[(int64_t)e * LOB_N_COUNTERS + lane];
         if (lane < STW) X64(X_ST)[lane] = a.stats[(int64_t)e * STW + lane];
         if (lane < A * AGW) AG(0)[lane] = a.agent_state[(int64_t)e * A * AGW + lane];
+        ctr = lane < NCTR ? a.counters[(int64_t)e * LOB_N_COUNTERS + lane] : 0;
         WAVE_SYNC();
         refresh_best(0);
         refresh_best(1);
         t = (int32_t)uni64(ENV()[6]);
         last_tsec = (int32_t)uni64(ENV()[4]);
         last_tns = (int32_t)uni64(ENV()[5]);
-        const int64_t b0 = a.trade_off ? a.trade_off[e] : 0;
-        tr_next = b0 + (a.trade_cursor ? uni64(a.trade_cursor[e]) : 0);
-        tr_end = a.trades ? a.trade_off[e + 1] : 0;
+        tr_cur0 = a.trade_cursor ? uni64(a.trade_cursor[e]) : 0;
+        tr_next = 0;
+        tr_base = nullptr;
+        tr_room = 0;
+        if (a.trades) {
+            const int64_t b0 = a.trade_off[e] + tr_cur0;
+            const int64_t room = a.trade_off[e + 1] - b0;
+            tr_room = (int)max(min(room, (int64_t)1 << 30), -((int64_t)1 << 30));
+            if (room > 0) tr_base = a.trades + b0 * LOB_TRADE_WORDS;
+        }
     }
     __device__ __forceinline__ void store() {
         WAVE_SYNC();
@@ -734,9 +685,9 @@ struct Run {
         for (int s = 0; s < 2; ++s) {
             const int n = nsz(s);
             const int64_t off = (gb + s) * a.max_cap;
-            int2 *p0 = PR(s, 0), *p1 = PR(s, 1), *p2 = PR(s, 2);
             for (int i = lane; i < n; i += WAVE) {
-                const int2 x0 = p0[i], x1 = p1[i], x2 = p2[i];
+                const int j = n - 1 - i;
+                const int2 x0 = U(s, 0, j), x1 = U(s, 1, j), x2 = U(s, 2, j);
                 a.bk[FP][off + i] = x0.x; a.bk[FQ][off + i] = x0.y;
                 a.bk[FO][off + i] = x1.x; a.bk[FT][off + i] = x1.y;
                 a.bk[FS][off + i] = x2.x; a.bk[FN][off + i] = x2.y;
@@ -747,17 +698,17 @@ struct Run {
             a.bk_n[gb + 1] = n1;
         }
         if (lane < LOB_ENV_STATE_WORDS) a.env_state[(int64_t)e * LOB_ENV_STATE_WORDS + lane] = ENV()[lane];
-        if (lane < NCTR) a.counters[(int64_t)e * LOB_N_COUNTERS + lane] = X64(X_CTR)[lane];
+        if (lane < NCTR) a.counters[(int64_t)e * LOB_N_COUNTERS + lane] = ctr;
         if (lane < STW) a.stats[(int64_t)e * STW + lane] = X64(X_ST)[lane];
         if (lane < A * AGW) a.agent_state[(int64_t)e * A * AGW + lane] = AG(0)[lane];
-        if (a.trade_cursor && lane == 0) a.trade_cursor[e] = tr_next - (a.trade_off ? a.trade_off[e] : 0);
+        if (a.trade_cursor && lane == 0) a.trade_cursor[e] = tr_cur0 + tr_next;
     }
 
     /* ---- one env-step (Sec. 4 steps 1-5) writing output slot s_idx ---- */
     __device__ __forceinline__ void step(int s_idx) {
         const int N = a.n_envs;
         mid_sum = 0; mid_n = 0; seq = 0;
-        st_buy = 0; st_sell = 0; st_trades = 0; st_last = 0;
+        st_buy = 0; st_sell = 0; st_last = 0;
         tr_step0 = tr_next;
         if (lane < A * 4) FL(0)[lane] = 0;
         WAVE_SYNC();
@@ -795,18 +746,19 @@ struct Run {
         }
 
         /* steps 3-4, in the order of Sec. 4 step 3.  First the cancel block: agents in
-         * index order, each walking its resting orders in book order; an order at a level
-         * the agent no longer wants is deleted, at a kept level any excess over the desired
-         * quantity comes from the agent's newest orders there. */
+         * index order, each walking its resting orders in book order (best first); an
+         * order at a level the agent no longer wants is deleted, at a kept level any
+         * excess over the desired quantity comes from the agent's newest orders there.
+         * A cancel at slot j moves only slots above j, so the walk continues below j. */
         for (int ai = 0; ai < A; ++ai) {
             const int tid = ai + 1;
             const int nlv = uni(X()[X_NLV + ai]);
             for (int ws = 0; ws < 2; ++ws) {
-                int wi0 = 0;
+                int hi = nsz(ws) - 1;
                 for (;;) {
-                    const int j = uni(find_eq(ws, FT, wi0, nsz(ws), tid));
+                    const int j = find_top(ws, FT, hi, tid);
                     if (j < 0) break;
-                    const int2 pq = PR(ws, 0)[j];
+                    const int2 pq = U(ws, 0, j);
                     const int pr = uni(pq.x), qt = uni(pq.y);
                     const int k = find_level(ai, nlv, ws, pr);
                     const int D = k >= 0 ? uni(LV(ai, k)[2]) : 0;
@@ -821,64 +773,53 @@ struct Run {
                     }
                     if (x > 0) {
                         /* a cancel message (delete, or partial cancel of x) for this order */
-                        const int oid = uni(B(ws, FO, j));
+                        const int oid = uni(U(ws, 1, j).x);
                         if (D == 0) cancel(false, ws, qt, oid);
                         else cancel(true, ws, x, oid);
-                        after_message(last_tsec, last_tns);
+                        after_message();
                     }
-                    wi0 = (x == qt) ? j : j + 1;
+                    hi = j - 1;
                 }
             }
         }
 
-        /* then the shuffled new orders, then the replayed messages (staged 64 at a time,
-         * the next chunk prefetched), each through one call of process() */
+        /* then the shuffled new orders (staged as the first chunk) and the replayed
+         * messages (64 per chunk, the next chunk prefetched), one process() each */
         const int64_t *row = a.m_off + (int64_t)e * (a.m_steps + 1);
         const int64_t lo = uni64(row[t]);
         const int nrep = (int)(uni64(row[t + 1]) - lo);
-        const int32_t *mts = a.m_ts + lo, *mpr = a.m_price + lo, *mqt = a.m_qty + lo, *moi = a.m_oid + lo;
-        const int32_t *mti = a.m_tid + lo, *mse = a.m_tsec + lo, *mns = a.m_tns + lo;
         int c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0;
         int d0 = 0, d1 = 0, d2 = 0, d3 = 0, d4 = 0, d5 = 0, d6 = 0;
+        if (lane < nact) {
+            const int32_t *m = X() + X_ACT + X()[X_PERM + lane] * 8;
+            c0 = m[0]; c1 = m[1]; c2 = m[2]; c3 = m[3]; c4 = m[4]; c5 = m[5]; c6 = m[6];
+        }
         if (lane < nrep) {
-            c0 = mts[lane]; c1 = mpr[lane]; c2 = mqt[lane]; c3 = moi[lane];
-            c4 = mti[lane]; c5 = mse[lane]; c6 = mns[lane];
+            const int64_t g = lo + lane;
+            d0 = a.m_ts[g]; d1 = a.m_price[g]; d2 = a.m_qty[g]; d3 = a.m_oid[g];
+            d4 = a.m_tid[g]; d5 = a.m_tsec[g]; d6 = a.m_tns[g];
         }
-        if (WAVE + lane < nrep) {
-            d0 = mts[WAVE + lane]; d1 = mpr[WAVE + lane]; d2 = mqt[WAVE + lane]; d3 = moi[WAVE + lane];
-            d4 = mti[WAVE + lane]; d5 = mse[WAVE + lane]; d6 = mns[WAVE + lane];
-        }
-        int ak = 0, base = 0, rj = 0;
-        int cnt = min(WAVE, nrep);
+        int cnt = nact, base = -WAVE;
         for (;;) {
-            ak = uni(ak);
-            rj = uni(rj);
-            base = uni(base);
-            int m0, m1, m2, m3, m4, m5, m6;
-            if (ak < nact) {
-                const int k = uni(X()[X_PERM + ak]);
-                const int32_t *m = X() + X_ACT + k * 8;
-                m0 = uni(m[0]); m1 = uni(m[1]); m2 = uni(m[2]); m3 = uni(m[3]);
-                m4 = uni(m[4]); m5 = uni(m[5]); m6 = uni(m[6]);
-                ak += 1;
-            } else {
-                if (rj >= cnt) {
-                    base += WAVE;
-                    if (base >= nrep) break;
-                    c0 = d0; c1 = d1; c2 = d2; c3 = d3; c4 = d4; c5 = d5; c6 = d6;
-                    const int nx = base + WAVE + lane;
-                    if (nx < nrep) {
-                        d0 = mts[nx]; d1 = mpr[nx]; d2 = mqt[nx]; d3 = moi[nx];
-                        d4 = mti[nx]; d5 = mse[nx]; d6 = mns[nx];
-                    }
-                    cnt = min(WAVE, nrep - base);
-                    rj = 0;
-                }
-                m0 = rdlane(c0, rj); m1 = rdlane(c1, rj); m2 = rdlane(c2, rj); m3 = rdlane(c3, rj);
-                m4 = rdlane(c4, rj); m5 = rdlane(c5, rj); m6 = rdlane(c6, rj);
-                rj += 1;
+            for (int rj = 0; rj < cnt; ++rj)
+                process(rdlane(c0, rj), rdlane(c1, rj), rdlane(c2, rj), rdlane(c3, rj), rdlane(c4, rj),
+                        rdlane(c5, rj), rdlane(c6, rj));
+            base += WAVE;
+            if (base >= nrep) break;
+            c0 = d0; c1 = d1; c2 = d2; c3 = d3; c4 = d4; c5 = d5; c6 = d6;
+            const int nx = base + WAVE + lane;
+            if (nx < nrep) {
+                const int64_t g = lo + nx;
+                d0 = a.m_ts[g]; d1 = a.m_price[g]; d2 = a.m_qty[g]; d3 = a.m_oid[g];
+                d4 = a.m_tid[g]; d5 = a.m_tsec[g]; d6 = a.m_tns[g];
             }
-            process(m0, m1, m2, m3, m4, m5, m6);
+            cnt = min(WAVE, nrep - base);
+        }
+        /* the last processed time: agent messages carry the previous one, so it changes
+         * only with a replayed message */
+        if (nrep > 0) {
+            last_tsec = rdlane(c5, cnt - 1);
+            last_tns = rdlane(c6, cnt - 1);
         }
 
         /* step 5: outcomes */
@@ -923,13 +864,13 @@ struct Run {
             if (lane < 4) a.fills[(((int64_t)s_idx * A + i) * N + e) * 4 + lane] = fl[lane];
         }
         /* counters of the step; trade records beyond the env's region were not written */
-        const int64_t written_end = max(tr_step0, tr_end);
-        const int64_t overflow = tr_next > written_end ? tr_next - written_end : 0;
+        const int st_trades = tr_next - tr_step0;
+        const int written_end = max(tr_step0, tr_room);
+        const int overflow = tr_next > written_end ? tr_next - written_end : 0;
+        count(C_MSGS, seq);
+        count(C_TRADES, st_trades);
+        count(C_TRADE_OVERFLOW, overflow);
         if (lane == 0) {
-            int64_t *C = X64(X_CTR);
-            C[C_MSGS] += seq;
-            C[C_TRADES] += st_trades;
-            C[C_TRADE_OVERFLOW] += overflow;
             int64_t *S = X64(X_ST);
             S[0] = st_buy; S[1] = st_sell; S[2] = st_trades; S[3] = st_last;
             E[0] = bb1; E[1] = ba1; E[2] = mid2_end; E[4] = last_tsec; E[5] = last_tns;
