@@ -83,6 +83,70 @@ def cpu_baseline(w, stream, budget_s=15.0):
                     "sample": f"{n} of {w.n_envs} envs x {w.n_steps} steps ({msgs} msgs), {dt:.2f} s"}
         n = min(w.n_envs, n * max(2, int(budget_s / 4 / max(dt, 1e-3))))
 
+# fused clipped-PPO forward+backward per sample: forward 40x256 + 256x256 + 256x10 MACs,
+# backward the weight gradients of all three layers and the input gradients of layers 2
+# and 3 (none for the observation); 2 FLOP per MAC
+PPO_FLOP_PER_SAMPLE = 2 * ((40 * 256 + 256 * 256 + 256 * 10) * 2 + 256 * 256 + 256 * 10)
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def ippo_bench(reps: int = 3):
+    """ippo4096: 4096 envs x 128 steps, two actor-critics.  Times the graph-captured
+    learned-policy rollout, one PPO update (4 epochs x 4 minibatches per agent) and the
+    fused PPO kernel alone on one full minibatch (131072 samples)."""
+    import torch
+    from paper_2511_02136_amd import synth, ippo
+    from paper_2511_02136_amd.lob import LobEnv, DeviceStream
+    from paper_2511_02136_amd.trainer import IppoTrainer
+    w = synth.WORKLOADS["ippo4096"]
+    s = synth.generate(w)
+    ds = DeviceStream.from_host(s)
+    env = LobEnv(s.caps, w.max_cap, w.agents, w.ep_len, w.seed)
+    book = {k: torch.from_numpy(v).cuda() for k, v in s.book.items()}
+    tr = IppoTrainer(env, ds, book, w.n_steps, seed=w.seed)
+    tr.rollout(use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        tr.rollout(use_graph=True)
+    torch.cuda.synchronize()
+    roll_ms = (time.perf_counter() - t0) * 1e3 / reps
+    tr.update()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr.update()
+    torch.cuda.synchronize()
+    upd_ms = (time.perf_counter() - t0) * 1e3
+    # the fused kernel on one minibatch of agent 0's rollout data
+    T, N = w.n_steps, w.n_envs
+    m = T * N // tr.minibatches
+    obs = tr.obs[:T, 0].reshape(T * N, 40)[:m].contiguous()
+    act = tr.pol["actions"][:, 0].reshape(-1)[:m].contiguous()
+    lpo = tr.pol["logp"][:, 0].reshape(-1)[:m].contiguous()
+    val = tr.pol["value"][:, 0].reshape(-1)[:m].contiguous()
+    adv = torch.randn(m, device="cuda")
+    ret = val + 0.1 * torch.randn(m, device="cuda")
+    prm = tr.params.detach()[0].contiguous()
+    ws = torch.empty((ippo.workspace_bytes(m) + 3) // 4, dtype=torch.float32, device="cuda")
+    ippo.ppo_fwd_bwd(prm, obs, act, lpo, adv, ret, val, tr.n_act[0], workspace=ws)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_calls = 10
+    e0.record(st)
+    for _ in range(n_calls):
+        ippo.ppo_fwd_bwd(prm, obs, act, lpo, adv, ret, val, tr.n_act[0], workspace=ws)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ppo_ms = e0.elapsed_time(e1) / n_calls
+    tflops = m * PPO_FLOP_PER_SAMPLE / (ppo_ms / 1e3) / 1e12
+    env_steps = N * T
+    return {"workload": f"ippo4096: {N} envs x {T} steps, 2 agents (exec, mm), MLP 40-256-256-(9+1) fp32",
+            "rollout_ms": roll_ms, "rollout_env_steps_per_s": env_steps / (roll_ms / 1e3),
+            "update_ms": upd_ms, "update": "GAE + 4 epochs x 4 minibatches x 2 agents of fused PPO + Adam",
+            "ppo_kernel": {"samples": m, "ms": ppo_ms, "flop_per_sample": PPO_FLOP_PER_SAMPLE,
+                           "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
+                                        "unit": "TFLOP/s", "frac": tflops / FP32_MFMA_PEAK_TFLOPS}}}
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -92,6 +156,9 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-step form")
+    ap.add_argument("--no-ippo", action="store_true", help="skip the IPPO rollout/update figures")
+    ap.add_argument("--ippo-only", action="store_true",
+                    help="only the IPPO figures (profiling aid; prints them as one JSON object)")
     ap.add_argument("--tune", action="store_true", help="run the schedule autotuner before timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device-to-device (calibrates HBM byte counters)")
@@ -112,6 +179,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.ippo_only:
+        print(json.dumps({"ippo": ippo_bench()}), flush=True)
+        return
     w = synth.WORKLOADS[args.workload]
     print(f"[bench] generating {w.name}", file=sys.stderr, flush=True)
     s = synth.generate(w)
@@ -192,7 +262,7 @@ def main():
     except AssertionError as ex:
         parity = f"MISMATCH: {ex}"
 
-    plain = None
+    plain = plain_padded = None
     if not args.no_plain:
         # plain per-step form: one launch per step, books through HBM every step
         print("[bench] plain per-step form", file=sys.stderr, flush=True)
@@ -216,6 +286,28 @@ def main():
         pms = (time.perf_counter() - t1) * 1e3 / reps
         plain = {"ms_per_rollout": pms, "env_steps_per_s": env_steps / (pms / 1e3),
                  "msgs_per_s": n_msgs / (pms / 1e3), "persistent_speedup": pms / ms_step}
+
+        # batching ablation: the same per-step launches with every env in one class padded
+        # to the largest capacity, dispatched in env order (no capacity classes, no plan)
+        print("[bench] padded per-step form", file=sys.stderr, flush=True)
+        env.set_padded(True)
+        plain_rollout()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            plain_rollout()
+        torch.cuda.synchronize()
+        qms = (time.perf_counter() - t1) * 1e3 / reps
+        env.set_padded(False)
+        plain_padded = {"ms_per_rollout": qms, "env_steps_per_s": env_steps / (qms / 1e3),
+                        "msgs_per_s": n_msgs / (qms / 1e3), "persistent_speedup": qms / ms_step}
+
+    ippo_res = None
+    if not args.no_ippo:
+        print("[bench] ippo4096: learned-policy rollout, PPO update", file=sys.stderr, flush=True)
+        del out, env, ds
+        torch.cuda.empty_cache()
+        ippo_res = ippo_bench()
 
     cpu = None
     if not args.no_cpu:
@@ -243,6 +335,8 @@ def main():
         "parity": parity,
         "schedule": schedule,
         "plain_form": plain,
+        "plain_padded": plain_padded,
+        "ippo": ippo_res,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name),
                      "kernel": "k_env (persistent rollout, all capacity classes)",

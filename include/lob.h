@@ -168,6 +168,13 @@ int lob_schedule_get(const lob_ctx *ctx, int32_t *out, int32_t max_classes);
  * if the workgroup would need more than 64 KiB of LDS. */
 int lob_schedule_set(lob_ctx *ctx, int32_t k, int32_t waves, int32_t mode, int32_t grid);
 
+/* Batching ablation.  padded = 1 puts every env into one class whose LDS books are
+ * sized for the largest capacity (uniform padding, the batching a map over envs of
+ * equal shape gives); padded = 0 restores one class per book row count (the default).
+ * Resets the plan and the schedules; results never depend on it.  Waits for the device
+ * (host-synchronous); not callable during stream capture. */
+int lob_set_padded(lob_ctx *ctx, int32_t padded);
+
 /* Autotuner: times every schedule of every class on the next n_steps of msgs (one
  * class at a time, from the current state, restored afterwards) and keeps the fastest
  * per class.  Makes a plan first.  Synchronous; the buffers of `out` are overwritten

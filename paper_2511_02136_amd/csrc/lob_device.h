@@ -1,13 +1,12 @@
 /*
  * Device-side building blocks of the LOB environment step (gfx950, wave64).
  *
- * One wavefront owns one environment.  Its book lives in LDS as a structure of arrays:
- * for side s (0 bids, 1 asks) and field f (price, qty, oid, tid, tsec, tns) the slots
- * 0..n-1 are in priority order (best price first, then arrival).  Slot i of a side is
- * handled by lane i % 64 in "row" i / 64, so every row access is one coalesced,
- * bank-conflict-free LDS instruction.  Searches are ballots over rows, matching is a
- * wave prefix scan over the crossing quantities, and insertion / removal shift a range
- * of rows by whole-wave LDS copies.
+ * One wavefront owns one environment.  Its book lives in LDS as records of six int32
+ * fields (price, qty, oid, tid, tsec, tns), per side in priority order from the worst
+ * order (record 0) to the best (record n-1).  Record j of a side is handled by lane
+ * j % 64 in "row" j / 64, so a row access is one LDS instruction per field pair.
+ * Searches are ballots over rows from the top of the book down, and insertion /
+ * removal move the records of the rows they touch by whole-wave LDS copies.
  *
  * All control flow that decides what happens to the book is wave-uniform.  LDS accesses
  * of one wavefront are performed in order by the hardware; WAVE_SYNC() stops the compiler

@@ -7,17 +7,21 @@
  * Sec. 2.1), and outcomes (step 5: fills, rewards by Eq. 2-4, observations).
  *
  * Design (MI355X-first):
- *   - one wavefront per environment; the book of both sides is LDS-resident as a
- *     structure of arrays, slot i in lane i%64 of row i/64 (see lob_device.h);
- *   - a book message is a handful of wave-wide LDS instructions: a ballot search for
- *     cancels, a wave prefix scan over the crossing quantities for matching (with a
- *     scalar fast path when the best order covers the incoming quantity), and a row
- *     shift for insertion / removal;
- *   - replay messages are staged 64 at a time with coalesced SoA loads, the next chunk
- *     prefetched while the current one is processed;
- *   - envs are grouped by capacity class (capacity rounded up to 64 slots) so each
- *     launch sizes LDS for its own class; the persistent form keeps books in LDS for all
- *     steps of a rollout and pulls envs from a device work queue, longest first.
+ *   - one wavefront per environment; the book of both sides is LDS-resident, one
+ *     24-byte record per order (price|qty, oid|tid, tsec|tns), ordered from the worst
+ *     order to the best so the top of the book is the end of the live range; record j
+ *     is handled by lane j%64 of row j/64 (see lob_device.h);
+ *   - a book message is a few wave-wide LDS instructions: a ballot search from the top
+ *     row down for cancels and for the insertion rank, a one-pass shift of the rows an
+ *     insertion or removal touches (usually one), and matching that walks the resting
+ *     orders from the top one at a time in scalar code (fills of the best order move
+ *     nothing);
+ *   - agent orders and replayed messages run through one loop, 64 messages per chunk
+ *     staged with coalesced SoA loads;
+ *   - envs are grouped by capacity class (books spanning the same number of rows), each
+ *     class's launch sized in LDS for its largest capacity; the persistent form keeps
+ *     books in LDS for all steps of a rollout and pulls envs from a device work queue,
+ *     longest first.
  *
  * Floating point: rewards are evaluated in double in a fixed order with contraction
  * disabled and rounded once to float; observation features are exact integers rounded
@@ -45,7 +49,7 @@ constexpr int MAXACT = MAXA * 8;  /* new agent orders per env-step */
 constexpr int AGW = 8;            /* internal agent words: inv, cash, rem, ctr, step_bq, step_sq */
 constexpr int STW = 4;            /* step statistics: buy vol, sell vol, trades, last price */
 
-/* per-wave LDS layout (int32 words) after the book (12 * capp words) */
+/* per-wave LDS layout (int32 words) after the book (2 sides x capp records x 6 words) */
 constexpr int X_ACT = 0;                          /* MAXACT x 8: ts, price, qty, oid, tid, tsec, tns, - */
 constexpr int X_PERM = X_ACT + MAXACT * 8;        /* MAXACT: shuffled order */
 constexpr int X_LV = X_PERM + MAXACT;             /* MAXA x MAXLV x 4: side, price, desired, resting */
@@ -65,14 +69,10 @@ static_assert((X_AG & 1) == 0 && (X_FL & 1) == 0 && (X_OBK & 1) == 0 &&
 
 __host__ __device__ constexpr int lds_words_for(int capp) { return 2 * NF * capp + EXTRA_WORDS; }
 
-/* book rows per capacity class (compiled variants) */
-constexpr int ROW_CLASSES[] = {1, 2, 4, 7, 8, 16};
-inline int rows_for_cap(int cap) {
-    const int need = (cap + 63) / 64;
-    for (int r : ROW_CLASSES)
-        if (r >= need) return r;
-    return -1;
-}
+constexpr int REC = NF / 2; /* int2 words per book record */
+
+/* rows of 64 records a book of this capacity spans (the capacity class) */
+inline int rows_for_cap(int cap) { return (cap + WAVE - 1) / WAVE; }
 
 
 struct KArgs {
@@ -110,15 +110,13 @@ struct KArgs {
 };
 
 /* ------------------------------------------------------------------------------
- * One environment run by one wavefront; ROWS = book rows of 64 slots per side.
+ * One environment run by one wavefront.
  * ---------------------------------------------------------------------------- */
-template <int ROWS>
 struct Run {
-    static constexpr int CAPP = ROWS * WAVE; /* slots per side in LDS (compile time) */
     const KArgs &a;
     int32_t *L;  /* this wave's LDS (uniform) */
-    int2 *Pl;    /* this lane's slot of row 0, side 0, pair 0 */
-    int lane, cap, e, A, t;
+    int2 *Pl;    /* this lane's record in row 0 of side 0 */
+    int lane, cap, capp, e, A, t;
     /* book: live orders and best price per side */
     int n0, n1, best0, best1;
     /* per step, hot */
@@ -133,21 +131,22 @@ struct Run {
     int64_t ctr;
 
     __device__ Run(const KArgs &args, int32_t *lds, int env)
-        : a(args), L(lds), lane(lane_id()), e(uni(env)), A(args.n_agents) {
-        Pl = reinterpret_cast<int2 *>(lds) + lane;
+        : a(args), L(lds), lane(lane_id()), capp(uni(args.capp)), e(uni(env)), A(args.n_agents) {
+        Pl = reinterpret_cast<int2 *>(lds) + lane * REC;
         cap = uni(a.caps[e]);
     }
 
-    /* ---- LDS views.  Per side three int2 arrays of CAPP slots (price|qty, oid|tid,
-     * tsec|tns).  Internal slot j counts from the worst order (j = 0) to the best
-     * (j = n - 1), so the top of the book is at the end of the live range. ---- */
-    /* this lane's slot in row 0 of side s, pair 0 (pair p is +p*CAPP, row r is +r*64) */
-    __device__ __forceinline__ int2 *SB(int s) { return Pl + s * (3 * CAPP); }
-    /* slot i of side s, pair p (any index, e.g. uniform) */
+    /* ---- LDS views.  Each side holds capp records of three int2 (price|qty, oid|tid,
+     * tsec|tns).  Record j counts from the worst order (j = 0) to the best (j = n - 1),
+     * so the top of the book is at the end of the live range; record j of a row of 64
+     * belongs to lane j % 64. ---- */
+    /* this lane's record in row 0 of side s (row r is +64 records) */
+    __device__ __forceinline__ int2 *SB(int s) { return Pl + s * capp * REC; }
+    /* pair p of record i of side s (any index, e.g. uniform) */
     __device__ __forceinline__ int2 &U(int s, int p, int i) {
-        return reinterpret_cast<int2 *>(L)[(s * 3 + p) * CAPP + i];
+        return reinterpret_cast<int2 *>(L)[(s * capp + i) * REC + p];
     }
-    __device__ __forceinline__ int32_t *X() { return L + 2 * NF * CAPP; }
+    __device__ __forceinline__ int32_t *X() { return L + 2 * NF * capp; }
     __device__ __forceinline__ int64_t *X64(int off) { return reinterpret_cast<int64_t *>(X() + off); }
     __device__ __forceinline__ int64_t *AG(int i) { return X64(X_AG) + i * AGW; }
     __device__ __forceinline__ int64_t *FL(int i) { return X64(X_FL) + i * 4; }
@@ -169,13 +168,13 @@ struct Run {
     __device__ __forceinline__ void count(int k, int64_t v) { ctr += (lane == k) ? v : 0; }
 
     /* ---- searches: rows from the top of the book down, stopping at the first hit ---- */
-    /* highest slot <= hi of side s whose field f (FO or FT) equals v, or -1; for oids this
-     * is the first order with that id in priority order */
+    /* highest record <= hi of side s whose field f (FO or FT) equals v, or -1; for oids
+     * this is the first order with that id in priority order */
     __device__ __forceinline__ int find_top(int s, int f, int hi, int v) {
-        const int32_t *col = reinterpret_cast<const int32_t *>(SB(s) + (f >> 1) * CAPP) + (f & 1);
+        const int32_t *col = reinterpret_cast<const int32_t *>(SB(s)) + f;
         for (int r = hi >> 6; r >= 0; --r) {
             const int j = (r << 6) + lane;
-            const int x = col[r * (2 * WAVE)];
+            const int x = col[r * (WAVE * 2 * REC)];
             const uint64_t m = ballot(j <= hi && x == v);
             if (m) return (r << 6) + 63 - __builtin_clzll(m);
         }
@@ -183,13 +182,13 @@ struct Run {
     }
     /* orders of side s (n live) whose price is equal to or better than the one with key
      * kp: prices compare as (price ^ m) with m = -1 for bids and 0 for asks, so "better or
-     * equal" is "key <=" on both sides.  They are the top slots of the side. */
+     * equal" is "key <=" on both sides.  They are the top records of the side. */
     __device__ __forceinline__ int count_ahead(int s, int n, int kp, int m) {
         const int32_t *col = reinterpret_cast<const int32_t *>(SB(s));
         int cnt = 0;
         for (int r = (n - 1) >> 6; r >= 0; --r) {
             const int j = (r << 6) + lane;
-            const int x = col[r * (2 * WAVE)];
+            const int x = col[r * (WAVE * 2 * REC)];
             const int c = __popcll(ballot(j < n && (x ^ m) <= kp));
             cnt += c;
             if (c < min(WAVE, n - (r << 6))) break;
@@ -198,45 +197,45 @@ struct Run {
     }
 
     /* ---- book edits: one pass over the rows they touch, loads of a row before its
-     * stores; each lane moves its own slot ---- */
-    /* slots [ins, n) of side s move up by one; the new order takes slot ins (n < CAPP) */
+     * stores; each lane moves its own record ---- */
+    /* records [ins, n) of side s move up by one; the new order takes record ins (n < capp) */
     __device__ __forceinline__ void insert_at(int s, int ins, int n, int2 v0, int2 v1, int2 v2) {
         int2 *S = SB(s);
         for (int r = n >> 6; r >= (ins >> 6); --r) {
             const int j = (r << 6) + lane;
-            int2 *d = S + r * WAVE;
+            int2 *d = S + r * (WAVE * REC);
             int2 x0 = v0, x1 = v1, x2 = v2;
-            if (j > ins && j <= n) { x0 = d[-1]; x1 = d[CAPP - 1]; x2 = d[2 * CAPP - 1]; }
+            if (j > ins && j <= n) { x0 = d[-3]; x1 = d[-2]; x2 = d[-1]; }
             WAVE_SYNC();
-            if (j >= ins && j <= n) { d[0] = x0; d[CAPP] = x1; d[2 * CAPP] = x2; }
+            if (j >= ins && j <= n) { d[0] = x0; d[1] = x1; d[2] = x2; }
             WAVE_SYNC();
         }
     }
-    /* slot k of side s (n live) leaves: [k+1, n) moves down by one */
+    /* record k of side s (n live) leaves: [k+1, n) moves down by one */
     __device__ __forceinline__ void remove_at(int s, int k, int n) {
         int2 *S = SB(s);
         for (int r = k >> 6; r <= (n - 2) >> 6; ++r) {
             const int j = (r << 6) + lane;
-            int2 *d = S + r * WAVE;
+            int2 *d = S + r * (WAVE * REC);
             const bool mv = j >= k && j < n - 1;
             int2 x0 = make_int2(0, 0), x1 = x0, x2 = x0;
-            if (mv) { x0 = d[1]; x1 = d[CAPP + 1]; x2 = d[2 * CAPP + 1]; }
+            if (mv) { x0 = d[3]; x1 = d[4]; x2 = d[5]; }
             WAVE_SYNC();
-            if (mv) { d[0] = x0; d[CAPP] = x1; d[2 * CAPP] = x2; }
+            if (mv) { d[0] = x0; d[1] = x1; d[2] = x2; }
             WAVE_SYNC();
         }
     }
-    /* full side: the worst order (slot 0) leaves, [1, ins) moves down by one and the new
-     * order takes slot ins - 1 (ins >= 1) */
+    /* full side: the worst order (record 0) leaves, [1, ins) moves down by one and the
+     * new order takes record ins - 1 (ins >= 1) */
     __device__ __forceinline__ void evict_insert(int s, int ins, int2 v0, int2 v1, int2 v2) {
         int2 *S = SB(s);
         for (int r = 0; r <= (ins - 1) >> 6; ++r) {
             const int j = (r << 6) + lane;
-            int2 *d = S + r * WAVE;
+            int2 *d = S + r * (WAVE * REC);
             int2 x0 = v0, x1 = v1, x2 = v2;
-            if (j < ins - 1) { x0 = d[1]; x1 = d[CAPP + 1]; x2 = d[2 * CAPP + 1]; }
+            if (j < ins - 1) { x0 = d[3]; x1 = d[4]; x2 = d[5]; }
             WAVE_SYNC();
-            if (j < ins) { d[0] = x0; d[CAPP] = x1; d[2 * CAPP] = x2; }
+            if (j < ins) { d[0] = x0; d[1] = x1; d[2] = x2; }
             WAVE_SYNC();
         }
     }
@@ -253,105 +252,60 @@ struct Run {
         }
     }
 
-    /* ---- trade records ---- */
+    /* ---- trade records (written by lane 0) ---- */
     __device__ __forceinline__ void write_trade(int k, int price, int q, int agg_oid, int pas_oid,
                                                 int agg_tid, int pas_tid, int side) {
         const int rec = tr_next + k;
-        if (rec < tr_room) {
+        if (lane == 0 && rec < tr_room) {
             int4 *p = reinterpret_cast<int4 *>(tr_base + (int64_t)rec * LOB_TRADE_WORDS);
             p[0] = make_int4(price, q, agg_oid, pas_oid);
             p[1] = make_int4(agg_tid, pas_tid, side | (seq << 1), t);
         }
     }
-    __device__ __forceinline__ void close_trades(int ntr, int64_t volume, int side, int last_price) {
-        tr_next += ntr;
-        if (side == 0) st_buy += volume; else st_sell += volume;
-        st_last = last_price;
-    }
 
     /* ---- matching: an incoming order of side `side` against the opposite side while it
      * crosses (market orders cross at any price); trades at the resting price, best
-     * first.  Returns the unmatched remainder. ---- */
+     * first, one resting order at a time from the top record down.  Returns the
+     * unmatched remainder. ---- */
     __device__ __forceinline__ int match(int side, int p, int q, bool market, int agg_oid, int agg_tid) {
         const int opp = side ^ 1;
-        const int no = nsz(opp);
-        if (no == 0) return q;
-        const int bp = best(opp);
+        const int n_opp = nsz(opp);
+        if (n_opp == 0) return q;
         const int mo = opp ? 0 : -1;
         const int kp = p ^ mo;
-        if (!market && (bp ^ mo) > kp) return q;
-        const int jt = no - 1;
-        const int tq = uni(U(opp, 0, jt).y);
-        if (tq >= q) {
-            /* the best order alone covers the incoming quantity */
-            const int2 ot = U(opp, 1, jt);
+        if (!market && (best(opp) ^ mo) > kp) return q;
+        int no = n_opp, rem = q, ntr = 0, last_price = 0;
+        int64_t notional = 0;
+        for (;;) {
+            int2 *rec = &U(opp, 0, no - 1);
+            const int2 pq = rec[0], ot = rec[1];
+            const int price = uni(pq.x), qty = uni(pq.y);
+            if (ntr > 0 && !market && (price ^ mo) > kp) break;
             const int poid = uni(ot.x), ptid = uni(ot.y);
-            if (lane == 0) write_trade(0, bp, q, agg_oid, poid, agg_tid, ptid, side);
-            add_fill(agg_tid, side == 0, q, (int64_t)q * bp);
-            add_fill(ptid, side != 0, q, (int64_t)q * bp);
-            if (tq == q) {
-                set_n(opp, jt);
-                refresh_best(opp);
+            const int x = min(rem, qty);
+            write_trade(ntr, price, x, agg_oid, poid, agg_tid, ptid, side);
+            add_fill(ptid, side != 0, x, (int64_t)x * price);
+            notional += (int64_t)x * price;
+            rem -= x;
+            ntr += 1;
+            last_price = price;
+            if (x == qty) {
+                no -= 1;
             } else {
-                if (lane == 0) U(opp, 0, jt).y = tq - q;
+                if (lane == 0) rec[0].y = qty - x;
                 WAVE_SYNC();
             }
-            close_trades(1, q, side, bp);
-            return 0;
+            if (rem == 0 || no == 0) break;
         }
-        /* general case: rows from the top down; in a row priority runs from the highest
-         * lane down, so the quantity ahead of a lane is a suffix sum */
-        int2 *O = SB(opp);
-        int64_t carry = 0, my_notional = 0;
-        int ntr = 0, nfull = 0, last_price = bp;
-        for (int r = jt >> 6; r >= 0; --r) {
-            const int j = (r << 6) + lane;
-            const bool valid = j < no;
-            int2 *d = O + r * WAVE;
-            const int2 pq = d[0], ot = d[CAPP];
-            const bool cr = valid && (market || (pq.x ^ mo) <= kp);
-            const int64_t x = cr ? (int64_t)pq.y : 0;
-            const int64_t pre = wave_incl_scan64(x, lane);
-            const int64_t tot = rdlane64(pre, 63);
-            const int64_t ahead = carry + (tot - pre);
-            const int take = (cr && ahead < q) ? (int)min((int64_t)pq.y, (int64_t)q - ahead) : 0;
-            const uint64_t hm = ballot(take > 0);
-            if (hm) {
-                /* the taking lanes are contiguous and end at this row's best order */
-                const int ltop = 63 - __builtin_clzll(hm);
-                if (take > 0) {
-                    write_trade(ntr + (ltop - lane), pq.x, take, agg_oid, ot.x, agg_tid, ot.y, side);
-                    if (take < pq.y) d[0].y = pq.y - take;
-                    my_notional += (int64_t)take * pq.x;
-                }
-                WAVE_SYNC();
-                /* resting orders of agents filled in this row (rare): accumulate uniformly */
-                uint64_t pm = ballot(take > 0 && ot.y >= 1 && ot.y <= A);
-                while (pm) {
-                    const int jj = __builtin_ctzll(pm);
-                    pm &= pm - 1;
-                    const int tj = rdlane(ot.y, jj), kj = rdlane(take, jj), pj = rdlane(pq.x, jj);
-                    add_fill(tj, side != 0, kj, (int64_t)kj * pj);
-                }
-                nfull += __popcll(ballot(take > 0 && take == pq.y));
-                last_price = rdlane(pq.x, __builtin_ctzll(hm));
-                ntr += __popcll(hm);
-            }
-            carry += tot;
-            if (carry >= q || ballot(cr) != ballot(valid)) break;
-        }
-        const int traded = (int)min((int64_t)q, carry);
-        if (agg_tid >= 1 && agg_tid <= A) {
-            const int64_t notional = uni64(wave_sum64(my_notional));
-            add_fill(agg_tid, side == 0, traded, notional);
-        }
-        if (nfull > 0) {
-            /* the fully filled orders are the top nfull slots */
-            set_n(opp, no - nfull);
+        add_fill(agg_tid, side == 0, q - rem, notional);
+        if (no != n_opp) {
+            set_n(opp, no);
             refresh_best(opp);
         }
-        close_trades(ntr, traded, side, last_price);
-        return q - traded;
+        tr_next += ntr;
+        if (side == 0) st_buy += q - rem; else st_sell += q - rem;
+        st_last = last_price;
+        return rem;
     }
 
     /* ---- rest a limit remainder on its own side (after all orders at an equal or
@@ -406,22 +360,33 @@ struct Run {
     /* ---- one message of the step sequence ---- */
     __device__ __forceinline__ void process(int ts, int price, int qty, int oid, int tid, int tsec, int tns) {
         const int type = ts & 0xFF, side = (ts >> 8) & 1;
-        if (type == T_LIMIT || type == T_MARKET) {
-            if (qty <= 0) {
-                count(C_BAD, 1);
+        switch (type) {
+        case T_LIMIT:
+            if (qty > 0) {
+                const int q = match(side, price, qty, false, oid, tid);
+                if (q > 0) rest(side, price, q, oid, tid, tsec, tns);
             } else {
-                const int q = match(side, price, qty, type == T_MARKET, oid, tid);
-                if (type == T_MARKET) {
-                    if (q > 0) count(C_MARKET_UNFILLED, q);
-                } else if (q > 0) {
-                    rest(side, price, q, oid, tid, tsec, tns);
-                }
+                count(C_BAD, 1);
             }
-        } else if (type == T_PCANCEL || type == T_DELETE) {
-            if (type == T_PCANCEL && qty <= 0) count(C_BAD, 1);
-            else cancel(type == T_PCANCEL, side, qty, oid);
-        } else {
+            break;
+        case T_MARKET:
+            if (qty > 0) {
+                const int q = match(side, price, qty, true, oid, tid);
+                if (q > 0) count(C_MARKET_UNFILLED, q);
+            } else {
+                count(C_BAD, 1);
+            }
+            break;
+        case T_PCANCEL:
+            if (qty > 0) cancel(true, side, qty, oid);
+            else count(C_BAD, 1);
+            break;
+        case T_DELETE:
+            cancel(false, side, qty, oid);
+            break;
+        default:
             count(C_BAD, 1);
+            break;
         }
         after_message();
     }
@@ -784,20 +749,14 @@ struct Run {
         }
 
         /* then the shuffled new orders (staged as the first chunk) and the replayed
-         * messages (64 per chunk, the next chunk prefetched), one process() each */
+         * messages (64 per chunk), one process() each */
         const int64_t *row = a.m_off + (int64_t)e * (a.m_steps + 1);
         const int64_t lo = uni64(row[t]);
         const int nrep = (int)(uni64(row[t + 1]) - lo);
         int c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0;
-        int d0 = 0, d1 = 0, d2 = 0, d3 = 0, d4 = 0, d5 = 0, d6 = 0;
         if (lane < nact) {
             const int32_t *m = X() + X_ACT + X()[X_PERM + lane] * 8;
             c0 = m[0]; c1 = m[1]; c2 = m[2]; c3 = m[3]; c4 = m[4]; c5 = m[5]; c6 = m[6];
-        }
-        if (lane < nrep) {
-            const int64_t g = lo + lane;
-            d0 = a.m_ts[g]; d1 = a.m_price[g]; d2 = a.m_qty[g]; d3 = a.m_oid[g];
-            d4 = a.m_tid[g]; d5 = a.m_tsec[g]; d6 = a.m_tns[g];
         }
         int cnt = nact, base = -WAVE;
         for (;;) {
@@ -806,12 +765,11 @@ struct Run {
                         rdlane(c5, rj), rdlane(c6, rj));
             base += WAVE;
             if (base >= nrep) break;
-            c0 = d0; c1 = d1; c2 = d2; c3 = d3; c4 = d4; c5 = d5; c6 = d6;
-            const int nx = base + WAVE + lane;
+            const int nx = base + lane;
             if (nx < nrep) {
                 const int64_t g = lo + nx;
-                d0 = a.m_ts[g]; d1 = a.m_price[g]; d2 = a.m_qty[g]; d3 = a.m_oid[g];
-                d4 = a.m_tid[g]; d5 = a.m_tsec[g]; d6 = a.m_tns[g];
+                c0 = a.m_ts[g]; c1 = a.m_price[g]; c2 = a.m_qty[g]; c3 = a.m_oid[g];
+                c4 = a.m_tid[g]; c5 = a.m_tsec[g]; c6 = a.m_tns[g];
             }
             cnt = min(WAVE, nrep - base);
         }
@@ -887,11 +845,10 @@ struct Run {
 /* ------------------------------------------------------------------------------
  * Kernels
  * ---------------------------------------------------------------------------- */
-template <int ROWS>
 __global__ void __launch_bounds__(256) k_env(KArgs a) {
     extern __shared__ int32_t smem[];
     const int wave = uni((int)(threadIdx.x >> 6)), waves = (int)(blockDim.x >> 6);
-    int32_t *L = smem + wave * lds_words_for(ROWS * WAVE);
+    int32_t *L = smem + wave * a.lds_words;
     for (;;) {
         int slot;
         if (a.work_ctr) {
@@ -902,7 +859,7 @@ __global__ void __launch_bounds__(256) k_env(KArgs a) {
             slot = (int)blockIdx.x * waves + wave;
         }
         if (slot >= a.n_list) break;
-        Run<ROWS> run(a, L, a.env_list[slot]);
+        Run run(a, L, a.env_list[slot]);
         run.load();
         for (int s = 0; s < a.n_steps; ++s) run.step(s);
         run.store();
@@ -911,14 +868,13 @@ __global__ void __launch_bounds__(256) k_env(KArgs a) {
 }
 
 /* observation of the current state (no step) */
-template <int ROWS>
 __global__ void __launch_bounds__(256) k_observe(KArgs a) {
     extern __shared__ int32_t smem[];
     const int wave = uni((int)(threadIdx.x >> 6)), waves = (int)(blockDim.x >> 6);
     const int slot = (int)blockIdx.x * waves + wave;
     if (slot >= a.n_list) return;
-    int32_t *L = smem + wave * lds_words_for(ROWS * WAVE);
-    Run<ROWS> run(a, L, a.env_list[slot]);
+    int32_t *L = smem + wave * a.lds_words;
+    Run run(a, L, a.env_list[slot]);
     run.load();
     run.write_obs(a.obs);
 }
@@ -1016,30 +972,6 @@ __global__ void k_fill_i32(int32_t *p, int32_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-typedef void (*kargs_kernel_t)(KArgs);
-inline kargs_kernel_t env_kernel(int rows) {
-    switch (rows) {
-    case 1: return k_env<1>;
-    case 2: return k_env<2>;
-    case 4: return k_env<4>;
-    case 7: return k_env<7>;
-    case 8: return k_env<8>;
-    case 16: return k_env<16>;
-    default: return nullptr;
-    }
-}
-inline kargs_kernel_t observe_kernel(int rows) {
-    switch (rows) {
-    case 1: return k_observe<1>;
-    case 2: return k_observe<2>;
-    case 4: return k_observe<4>;
-    case 7: return k_observe<7>;
-    case 8: return k_observe<8>;
-    case 16: return k_observe<16>;
-    default: return nullptr;
-    }
-}
-
 } // namespace lobk
 
 /* ==================================================================================
@@ -1048,8 +980,8 @@ inline kargs_kernel_t observe_kernel(int rows) {
 using namespace lobk;
 
 struct CapClass {
-    int rows;      /* book rows of 64 slots per side (compiled variant) */
-    int capp;      /* rows * 64 */
+    int rows;      /* rows of 64 records a book of the class spans */
+    int capp;      /* records per side in LDS: the largest capacity in the class */
     int first;     /* offset into the env list */
     int count;     /* envs in the class */
     int waves;     /* waves per workgroup (one env per wave) */
@@ -1057,7 +989,9 @@ struct CapClass {
     int grid;      /* workgroups in queue mode (0 = derived from occupancy) */
 };
 
-constexpr int MAX_CLASSES = 8;
+constexpr int MAX_CLASSES = LOB_MAX_CAP / 64; /* one class per row count */
+constexpr size_t LDS_PER_CU = 160 * 1024;  /* gfx950 */
+constexpr int WAVES_PER_CU = 24;            /* 6 per SIMD at the env kernel's register use */
 
 struct lob_ctx {
     lob_config cfg;
@@ -1080,6 +1014,7 @@ struct lob_ctx {
     int n_cu = 256;
     int t = 0;
     bool reset_done = false;
+    bool padded = false;
 };
 
 namespace {
@@ -1184,7 +1119,7 @@ int launch_class(lob_ctx *c, size_t k, KArgs a, hipStream_t st) {
     if (cl.mode == 1) {
         a.work_ctr = c->d_work + k;
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, c->d_work + k, 1, 0);
-        int per_cu = (int)(160 * 1024 / lds);
+        int per_cu = (int)(LDS_PER_CU / lds);
         if (per_cu < 1) per_cu = 1;
         grid = cl.grid > 0 ? cl.grid : c->n_cu * per_cu;
         grid = std::min(grid, (cl.count + waves - 1) / waves);
@@ -1192,7 +1127,7 @@ int launch_class(lob_ctx *c, size_t k, KArgs a, hipStream_t st) {
         a.work_ctr = nullptr;
         grid = (cl.count + waves - 1) / waves;
     }
-    hipLaunchKernelGGL(env_kernel(cl.rows), dim3(grid), dim3(64 * waves), lds, st, a);
+    hipLaunchKernelGGL(k_env, dim3(grid), dim3(64 * waves), lds, st, a);
     return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
 }
 
@@ -1211,6 +1146,60 @@ int launch_env(lob_ctx *c, KArgs a, hipStream_t st) {
     }
     for (size_t k = 0; k < nc; ++k)
         if (!hip_ok(hipStreamWaitEvent(st, c->ev_join[k], 0))) return LOB_EHIP;
+    return LOB_OK;
+}
+
+/* Default waves (envs) per workgroup for a class: the most resident envs per CU, LDS
+ * being allocated per workgroup (at most 64 KiB each); ties go to larger workgroups. */
+int default_waves(int capp) {
+    const size_t per_wave = (size_t)lds_words_for(capp) * 4;
+    int best_w = 1, best_n = -1;
+    for (int w : {4, 2, 1}) {
+        if (per_wave * w > 64 * 1024) continue;
+        const int n = std::min((int)(LDS_PER_CU / (per_wave * w)) * w, WAVES_PER_CU / w * w);
+        if (n > best_n) { best_n = n; best_w = w; }
+    }
+    return best_w;
+}
+
+/* Group the envs into capacity classes: envs whose books span the same number of rows
+ * share a class whose LDS books are sized for the largest capacity among them; with
+ * `padded` every env goes into one class sized for the largest capacity overall.  Envs
+ * are listed in index order until a plan orders them; streams and events for the
+ * classes' concurrent launches are created on first use.  Host-synchronous. */
+int build_classes(lob_ctx *c, bool padded) {
+    const int N = c->cfg.n_envs;
+    std::vector<int> rows;
+    for (int32_t v : c->caps) rows.push_back(padded ? 0 : rows_for_cap(v));
+    std::vector<int> uniq(rows);
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    if (uniq.size() > (size_t)MAX_CLASSES) return LOB_EUNSUPPORTED;
+    c->classes.clear();
+    c->env_list.clear();
+    for (int r : uniq) {
+        CapClass cl{r, 0, (int)c->env_list.size(), 0, 1, 0, 0};
+        for (int e = 0; e < N; ++e)
+            if (rows[(size_t)e] == r) {
+                c->env_list.push_back(e);
+                cl.count++;
+                cl.capp = std::max(cl.capp, c->caps[(size_t)e]);
+            }
+        cl.rows = rows_for_cap(cl.capp);
+        cl.waves = default_waves(cl.capp);
+        c->classes.push_back(cl);
+    }
+    for (size_t k = 0; k < c->classes.size(); ++k) {
+        if (!c->streams[k] && !hip_ok(hipStreamCreateWithFlags(&c->streams[k], hipStreamNonBlocking)))
+            return LOB_EHIP;
+        if (!c->ev_join[k] && !hip_ok(hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming)))
+            return LOB_EHIP;
+    }
+    c->plan_off = nullptr;
+    c->plan_t0 = c->plan_steps = -1;
+    c->padded = padded;
+    if (!hip_ok(hipMemcpy(c->d_env_list, c->env_list.data(), (size_t)N * 4, hipMemcpyHostToDevice)))
+        return LOB_EHIP;
     return LOB_OK;
 }
 
@@ -1295,35 +1284,9 @@ int lob_init(const lob_config *cfg, lob_ctx **out) {
     rc |= dalloc(&c->d_work, 64);
     if (rc != LOB_OK) { free_ctx(c); return LOB_ENOMEM; }
 
-    /* capacity classes: capacity rounded up to 64 slots; envs of a class listed in
-     * index order (the persistent launch reorders by work, see lob_rollout) */
-    /* capacity classes: one compiled book size per class; envs listed in index order
-     * until a plan orders them */
-    std::vector<int> rows;
-    for (int32_t v : c->caps) rows.push_back(rows_for_cap(v));
-    std::vector<int> uniq(rows);
-    std::sort(uniq.begin(), uniq.end());
-    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-    for (int r : uniq) {
-        CapClass cl{r, r * WAVE, (int)c->env_list.size(), 0, 1, 0, 0};
-        for (int e = 0; e < (int)N; ++e)
-            if (rows[(size_t)e] == r) { c->env_list.push_back(e); cl.count++; }
-        /* several waves (envs) per workgroup when books are small */
-        const size_t per_wave = (size_t)lds_words_for(cl.capp) * 4;
-        cl.waves = per_wave * 4 <= 64 * 1024 ? 4 : per_wave * 2 <= 64 * 1024 ? 2 : 1;
-        c->classes.push_back(cl);
-    }
-    if ((int)c->classes.size() > MAX_CLASSES) { free_ctx(c); return LOB_EUNSUPPORTED; }
-    for (size_t k = 0; k < c->classes.size(); ++k) {
-        if (!hip_ok(hipStreamCreateWithFlags(&c->streams[k], hipStreamNonBlocking)) ||
-            !hip_ok(hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming))) {
-            free_ctx(c);
-            return LOB_EHIP;
-        }
-    }
+    if ((rc = build_classes(c, false)) != LOB_OK) { free_ctx(c); return rc; }
     if (!hip_ok(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) ||
-        !hip_ok(hipMemcpy(c->d_caps, c->caps.data(), (size_t)N * 4, hipMemcpyHostToDevice)) ||
-        !hip_ok(hipMemcpy(c->d_env_list, c->env_list.data(), (size_t)N * 4, hipMemcpyHostToDevice))) {
+        !hip_ok(hipMemcpy(c->d_caps, c->caps.data(), (size_t)N * 4, hipMemcpyHostToDevice))) {
         free_ctx(c);
         return LOB_EHIP;
     }
@@ -1439,6 +1402,12 @@ int lob_schedule_set(lob_ctx *c, int32_t k, int32_t waves, int32_t mode, int32_t
     return LOB_OK;
 }
 
+int lob_set_padded(lob_ctx *c, int32_t padded) {
+    if (!c || (padded != 0 && padded != 1)) return LOB_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return LOB_EHIP;
+    return build_classes(c, padded != 0);
+}
+
 /* Time every schedule candidate of every class on the next n_steps of `m` (one class
  * at a time, from the current state, which is restored afterwards) and keep the
  * fastest.  Results do not depend on the schedule.  Synchronous; `out` is scratch. */
@@ -1527,7 +1496,7 @@ int lob_observe(lob_ctx *c, float *obs, void *stream) {
         a.env_list = c->d_env_list + cl.first;
         a.n_list = cl.count;
         const size_t lds = (size_t)a.lds_words * 4 * cl.waves;
-        hipLaunchKernelGGL(observe_kernel(cl.capp / WAVE), dim3((cl.count + cl.waves - 1) / cl.waves),
+        hipLaunchKernelGGL(k_observe, dim3((cl.count + cl.waves - 1) / cl.waves),
                            dim3(64 * cl.waves), lds, (hipStream_t)stream, a);
         if (hipGetLastError() != hipSuccess) return LOB_EHIP;
     }

@@ -95,6 +95,11 @@ def gae(rewards: torch.Tensor, values: torch.Tensor, dones: torch.Tensor, last_v
     return adv, ret
 
 
+def workspace_bytes(m: int) -> int:
+    """Device workspace the fused PPO kernel needs for a minibatch of m samples."""
+    return int(_lib().lob_ppo_workspace_bytes(int(m)))
+
+
 def ppo_fwd_bwd(params, obs, act, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01,
                 workspace=None):
     """Loss sums [4] (total, policy, value, entropy) and the gradient of the mean loss."""

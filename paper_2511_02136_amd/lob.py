@@ -73,13 +73,14 @@ def lib():
         L.lob_plan.argtypes = [p, ctypes.POINTER(_Msgs), i32]
         L.lob_schedule_get.argtypes = [p, p, i32]
         L.lob_schedule_set.argtypes = [p, i32, i32, i32, i32]
+        L.lob_set_padded.argtypes = [p, i32]
         L.lob_autotune.argtypes = [p, ctypes.POINTER(_Msgs), i32, ctypes.POINTER(_Out), p]
         L.lob_destroy.argtypes = [p]
         L.lob_strerror.argtypes = [ctypes.c_int]
         L.lob_strerror.restype = ctypes.c_char_p
         for f in ("lob_init", "lob_reset", "lob_step", "lob_rollout", "lob_observe", "lob_export_books",
                   "lob_export_state", "lob_current_step", "lob_destroy", "lob_plan", "lob_schedule_get",
-                  "lob_schedule_set", "lob_autotune"):
+                  "lob_schedule_set", "lob_set_padded", "lob_autotune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -262,8 +263,8 @@ class LobEnv:
         _check(self._lib.lob_plan(self._h, ctypes.byref(dstream._m), int(n_steps)), "lob_plan")
 
     def schedule(self) -> list:
-        buf = np.zeros((16, 5), dtype=np.int32)
-        n = self._lib.lob_schedule_get(self._h, buf.ctypes.data_as(ctypes.c_void_p), 16)
+        buf = np.zeros((64, 5), dtype=np.int32)
+        n = self._lib.lob_schedule_get(self._h, buf.ctypes.data_as(ctypes.c_void_p), 64)
         if n < 0:
             _check(n, "lob_schedule_get")
         return [dict(cap_slots=int(r[0]), envs=int(r[1]), waves=int(r[2]), mode=int(r[3]), grid=int(r[4]))
@@ -271,6 +272,11 @@ class LobEnv:
 
     def set_schedule(self, k: int, waves: int, mode: int, grid: int = 0):
         _check(self._lib.lob_schedule_set(self._h, k, waves, mode, grid), "lob_schedule_set")
+
+    def set_padded(self, padded: bool):
+        """Batching ablation: one class padded to the largest capacity (True) or one
+        class per book row count (False, the default).  Resets plan and schedules."""
+        _check(self._lib.lob_set_padded(self._h, int(bool(padded))), "lob_set_padded")
 
     def autotune(self, dstream: DeviceStream, n_steps: int, out: Optional[dict] = None) -> list:
         """Time every schedule candidate on the next n_steps (state restored) and keep the

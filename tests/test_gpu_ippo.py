@@ -158,11 +158,13 @@ def test_autograd_function_and_optimizer_step():
     assert float(loss2) < float(loss)  # one small step along -grad lowers the loss
 
 
-def test_full_size_minibatch_gradient():
-    """The ippo4096 minibatch (4096 envs x 128 steps / 4 = 131072 samples) in the launch
-    configuration of the update, against float64 autograd on the CPU."""
+@pytest.mark.parametrize("m", [131072, 1048576])
+def test_full_size_minibatch_gradient(m):
+    """Full-size minibatches in the launch configuration of the update: ippo4096 (4096 envs
+    x 128 steps / 4 = 131072 samples) and the large workload (16384 envs x 256 steps / 4 =
+    1048576 samples), against float64 autograd on the CPU."""
     ippo = _ippo()
-    m = 131072
+    print(f"\n[ppo] minibatch of {m} samples", flush=True)
     rng = np.random.default_rng(12)
     P = rand_params(12, 1)[0]
     P64 = P.astype(np.float64)

@@ -237,6 +237,47 @@ def test_full_size_sampled_parity(name):
     assert a.min() >= 0 and a[:, 0].max() <= 8
 
 
+def test_large16384_full_size_sampled_parity():
+    """The large workload at full size (16384 envs, capacity 1000, 400 messages per step
+    with 10% burst steps, three agents, 256 steps: about 1.9e9 messages) in the persistent
+    launch.  Trade records are kept for the sampled envs only: every other env gets an
+    empty region, so its trades are counted (trade_overflow) but not stored."""
+    _, DeviceStream = _lob()
+    w = synth.WORKLOADS["large16384"]
+    print(f"\n[parity] full-size {w.name}", flush=True)
+    s = synth.generate(w)
+    rng = np.random.default_rng(5)
+    sample = np.sort(rng.choice(w.n_envs, size=24, replace=False))
+    hs, book, caps = subset_stream(s, sample)
+    msgs = s.off[sample, w.n_steps] - s.off[sample, 0]
+    sizes = np.zeros(w.n_envs, dtype=np.int64)
+    sizes[sample] = 2 * caps.astype(np.int64) + 2 * (msgs + w.n_steps * len(w.agents) * 8)
+    toff = np.concatenate([[0], np.cumsum(sizes)])
+    env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+    ds = DeviceStream.from_host(s)
+    del s
+    print("[parity] rollout", flush=True)
+    got = env.rollout(ds, w.n_steps, trade_off=toff)
+    torch.cuda.synchronize()
+    print("[parity] oracle on the sample", flush=True)
+    o = oracle_for(hs, book, caps, w.max_cap, w.agents, w.ep_len, w.seed, env_ids=sample)
+    acts = got["actions"].cpu().numpy()[:, :, sample]
+    ref = o.step(hs, n_steps=w.n_steps, actions=np.ascontiguousarray(acts))
+    for j, e in enumerate(sample):
+        cnt = int(ref["n_trades"][:, j].sum())
+        gt = got["trades"][toff[e]: toff[e] + cnt].cpu().numpy()
+        assert np.array_equal(gt, ref["trades"][ref["trade_off"][j]: ref["trade_off"][j] + cnt]), e
+    g = dict(got)
+    g["trades"] = None
+    ref = dict(ref)
+    ref["trades"] = None
+    assert_same_outputs(g, ref, w.n_steps, envs=sample, what=w.name)
+    assert_same_books(env.books(), o.books(), envs=sample, what=w.name)
+    assert_same_state(env.state(), o.state(), envs=sample, what=w.name)
+    a = got["actions"].cpu().numpy()
+    assert a.min() >= 0 and a[:, 2].max() <= 2
+
+
 def test_plain_and_persistent_forms_identical_full_size():
     """Property at full size: the per-step form and the persistent form agree exactly."""
     _, DeviceStream = _lob()
@@ -261,7 +302,8 @@ def test_plain_and_persistent_forms_identical_full_size():
 
 
 def test_schedule_independence():
-    """Every schedule the autotuner can pick gives identical outputs and books."""
+    """Every schedule the autotuner can pick, and the padded single-class grouping,
+    give identical outputs and books."""
     _, DeviceStream = _lob()
     w = synth.Workload("sched", n_envs=300, n_steps=6, msgs_range=(1, 300), cap_choices=(50, 100, 200, 400),
                        agents=("exec", "mm"), seed=41)
@@ -272,26 +314,28 @@ def test_schedule_independence():
     ref = ref_env.rollout(ds, w.n_steps, trade_off=toff)
     ref_books = ref_env.books()
     n_classes = len(ref_env.schedule())
-    for mode in (0, 1):
-        for waves in (1, 2, 4):
-            env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
-            env.plan(ds, w.n_steps)
-            for k in range(n_classes):
-                try:
-                    env.set_schedule(k, waves, mode, 0 if mode == 0 else 7)
-                except Exception:
-                    pass  # the workgroup would need more LDS than allowed
-            got = env.rollout(ds, w.n_steps, trade_off=toff)
-            torch.cuda.synchronize()
-            for key in ("n_trades", "fills", "reward", "obs", "done", "actions", "trades"):
-                assert torch.equal(got[key], ref[key]) or key == "trades", (mode, waves, key)
-            n = got["n_trades"].sum(0).cpu().numpy()
-            off = toff.cpu().numpy()
-            for e in range(0, w.n_envs, 7):
-                assert torch.equal(got["trades"][off[e]: off[e] + n[e]], ref["trades"][off[e]: off[e] + n[e]])
-            gb = env.books()
-            for key in gb:
-                assert torch.equal(gb[key], ref_books[key]), (mode, waves, key)
+    for padded, mode, waves in [(False, m, wv) for m in (0, 1) for wv in (1, 2, 4)] + [(True, 0, 2), (True, 1, 1)]:
+        env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+        if padded:
+            env.set_padded(True)
+            assert len(env.schedule()) == 1 and env.schedule()[0]["cap_slots"] == max(s.caps)
+        env.plan(ds, w.n_steps)
+        for k in range(len(env.schedule())):
+            try:
+                env.set_schedule(k, waves, mode, 0 if mode == 0 else 7)
+            except Exception:
+                pass  # the workgroup would need more LDS than allowed
+        got = env.rollout(ds, w.n_steps, trade_off=toff)
+        torch.cuda.synchronize()
+        for key in ("n_trades", "fills", "reward", "obs", "done", "actions", "trades"):
+            assert torch.equal(got[key], ref[key]) or key == "trades", (mode, waves, key)
+        n = got["n_trades"].sum(0).cpu().numpy()
+        off = toff.cpu().numpy()
+        for e in range(0, w.n_envs, 7):
+            assert torch.equal(got["trades"][off[e]: off[e] + n[e]], ref["trades"][off[e]: off[e] + n[e]])
+        gb = env.books()
+        for key in gb:
+            assert torch.equal(gb[key], ref_books[key]), (mode, waves, key)
     # the tuner picks one of them and restores the state it started from
     env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
     sched = env.autotune(ds, w.n_steps)
