@@ -158,7 +158,8 @@ int lob_rollout(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps, const int32
 int lob_plan(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps);
 
 /* The launch schedule, one record of 5 int32 per capacity class (host array):
- * capacity slots per side, envs, waves (envs) per workgroup, mode (0: one wave per env
+ * book records per side in LDS (the class's largest capacity), envs, waves (envs) per
+ * workgroup, mode (0: one wave per env
  * dispatched by the hardware in plan order; 1: persistent workgroups pulling envs from a
  * device work queue), workgroups in mode 1 (0 = from occupancy).  Returns the number of
  * classes. */

@@ -49,25 +49,36 @@ constexpr int MAXACT = MAXA * 8;  /* new agent orders per env-step */
 constexpr int AGW = 8;            /* internal agent words: inv, cash, rem, ctr, step_bq, step_sq */
 constexpr int STW = 4;            /* step statistics: buy vol, sell vol, trades, last price */
 
-/* per-wave LDS layout (int32 words) after the book (2 sides x capp records x 6 words) */
-constexpr int X_ACT = 0;                          /* MAXACT x 8: ts, price, qty, oid, tid, tsec, tns, - */
-constexpr int X_PERM = X_ACT + MAXACT * 8;        /* MAXACT: shuffled order */
-constexpr int X_LV = X_PERM + MAXACT;             /* MAXA x MAXLV x 4: side, price, desired, resting */
-constexpr int X_SEEN = X_LV + MAXA * MAXLV * 4;   /* MAXA x MAXLV: older resting qty seen in the walk */
-constexpr int X_NLV = X_SEEN + MAXA * MAXLV;      /* MAXA (+pad): desired levels per agent */
-constexpr int X_AG = X_NLV + 8;                   /* int64 MAXA x AGW */
-constexpr int X_FL = X_AG + MAXA * AGW * 2;       /* int64 MAXA x 4: fills of the step */
-constexpr int X_OBK = X_FL + MAXA * 4 * 2;        /* int64 34: depth buckets, totals, own stats */
-constexpr int N_OBK = 22 + 3 * MAXA;
-constexpr int X_ENV = X_OBK + 34 * 2;             /* int64 8: env state (global layout) */
-constexpr int X_ST = X_ENV + 8 * 2;               /* int64 STW: last step's statistics */
-constexpr int X_END = X_ST + STW * 2;
-constexpr int EXTRA_WORDS = (X_END + 63) & ~63;
-static_assert(N_OBK <= 34, "obs accumulator area");
-static_assert((X_AG & 1) == 0 && (X_FL & 1) == 0 && (X_OBK & 1) == 0 &&
-              (X_ENV & 1) == 0 && (X_ST & 1) == 0, "int64 alignment");
+/* Per-wave LDS layout after the book (int32 word offsets), for A agents (at most 8 new
+ * orders per agent per step):
+ *   act  8A x 8: new orders of the step (ts, price, qty, oid, tid, tsec, tns, -)
+ *   perm 8A: shuffled order          lv   A x MAXLV x 4: side, price, desired, resting
+ *   seen A x MAXLV: older resting qty seen in the walk      nlv  A: desired levels
+ *   ag   int64 A x AGW: agent state  fl   int64 A x 4: fills of the step
+ *   obk  int64 22 + 3A: depth buckets, totals, own stats    env  int64 8  st  int64 STW */
+struct XL {
+    int act, perm, lv, seen, nlv, ag, fl, obk, env, st, words;
+};
+__host__ __device__ constexpr XL x_layout(int A) {
+    XL x{};
+    x.act = 0;
+    x.perm = x.act + 8 * A * 8;
+    x.lv = x.perm + 8 * A;
+    x.seen = x.lv + A * MAXLV * 4;
+    x.nlv = x.seen + A * MAXLV;
+    x.ag = (x.nlv + A + 1) & ~1;
+    x.fl = x.ag + A * AGW * 2;
+    x.obk = x.fl + A * 4 * 2;
+    x.env = x.obk + (22 + 3 * A) * 2;
+    x.st = x.env + 8 * 2;
+    x.words = x.st + STW * 2;
+    return x;
+}
+static_assert(x_layout(MAXA).words < 1024, "extra LDS");
 
-__host__ __device__ constexpr int lds_words_for(int capp) { return 2 * NF * capp + EXTRA_WORDS; }
+__host__ __device__ constexpr int lds_words_for(int capp, int n_agents) {
+    return 2 * NF * capp + x_layout(n_agents).words;
+}
 
 constexpr int REC = NF / 2; /* int2 words per book record */
 
@@ -147,11 +158,12 @@ struct Run {
         return reinterpret_cast<int2 *>(L)[(s * capp + i) * REC + p];
     }
     __device__ __forceinline__ int32_t *X() { return L + 2 * NF * capp; }
+    __device__ __forceinline__ XL xl() const { return x_layout(A); }
     __device__ __forceinline__ int64_t *X64(int off) { return reinterpret_cast<int64_t *>(X() + off); }
-    __device__ __forceinline__ int64_t *AG(int i) { return X64(X_AG) + i * AGW; }
-    __device__ __forceinline__ int64_t *FL(int i) { return X64(X_FL) + i * 4; }
-    __device__ __forceinline__ int32_t *LV(int ai, int k) { return X() + X_LV + (ai * MAXLV + k) * 4; }
-    __device__ __forceinline__ int64_t *ENV() { return X64(X_ENV); }
+    __device__ __forceinline__ int64_t *AG(int i) { return X64(xl().ag) + i * AGW; }
+    __device__ __forceinline__ int64_t *FL(int i) { return X64(xl().fl) + i * 4; }
+    __device__ __forceinline__ int32_t *LV(int ai, int k) { return X() + xl().lv + (ai * MAXLV + k) * 4; }
+    __device__ __forceinline__ int64_t *ENV() { return X64(xl().env); }
 
     __device__ __forceinline__ int nsz(int s) const { return s ? n1 : n0; }
     __device__ __forceinline__ void set_n(int s, int v) {
@@ -496,8 +508,8 @@ struct Run {
             if (act == 1) add_level(i, nlv, 0, ba0, a.dir_q);
             if (act == 2) add_level(i, nlv, 1, bb0, a.dir_q);
         }
-        if (lane == 0) X()[X_NLV + i] = nlv;
-        if (lane < MAXLV) X()[X_SEEN + i * MAXLV + lane] = 0;
+        if (lane == 0) X()[xl().nlv + i] = nlv;
+        if (lane < MAXLV) X()[xl().seen + i * MAXLV + lane] = 0;
         WAVE_SYNC();
 
         /* resting quantity of this agent at each desired level (step start) */
@@ -532,7 +544,7 @@ struct Run {
             const int64_t c = uni64(g[3]);
             const int oid = (int)((1u << 30) | ((uint32_t)i << 26) | (uint32_t)(c & ((1 << 26) - 1)));
             if (lane == 0) {
-                int32_t *m = X() + X_ACT + nact * 8;
+                int32_t *m = X() + xl().act + nact * 8;
                 m[0] = type | (side << 8); m[1] = price; m[2] = qty; m[3] = oid;
                 m[4] = tid; m[5] = last_tsec; m[6] = last_tns;
                 g[3] = c + 1;
@@ -544,8 +556,8 @@ struct Run {
 
     /* ---- observation features from the book (LDS accumulators) ---- */
     __device__ __forceinline__ void book_obs(int bb, int ba) {
-        int64_t *O = X64(X_OBK);
-        if (lane < 34) O[lane] = 0;
+        int64_t *O = X64(xl().obk);
+        if (lane < 22 + 3 * A) O[lane] = 0;
         WAVE_SYNC();
         for (int s = 0; s < 2; ++s) {
             const int n = nsz(s);
@@ -575,10 +587,10 @@ struct Run {
     /* the 40 features of every agent from the state in LDS, written to base [A][n_envs][40] */
     __device__ __forceinline__ void write_obs(float *base) {
         const int64_t *E = ENV();
-        const int64_t *S = X64(X_ST);
+        const int64_t *S = X64(xl().st);
         const int bb = (int)uni64(E[0]), ba = (int)uni64(E[1]);
         book_obs(bb, ba);
-        const int64_t *O = X64(X_OBK);
+        const int64_t *O = X64(xl().obk);
         const int64_t mid2 = (int64_t)bb + ba;
         const int64_t strades = uni64(S[2]);
         for (int i = 0; i < A; ++i) {
@@ -624,7 +636,7 @@ struct Run {
         }
         /* env state, statistics and agent state into LDS, counters into lanes */
         if (lane < LOB_ENV_STATE_WORDS) ENV()[lane] = a.env_state[(int64_t)e * LOB_ENV_STATE_WORDS + lane];
-        if (lane < STW) X64(X_ST)[lane] = a.stats[(int64_t)e * STW + lane];
+        if (lane < STW) X64(xl().st)[lane] = a.stats[(int64_t)e * STW + lane];
         if (lane < A * AGW) AG(0)[lane] = a.agent_state[(int64_t)e * A * AGW + lane];
         ctr = lane < NCTR ? a.counters[(int64_t)e * LOB_N_COUNTERS + lane] : 0;
         WAVE_SYNC();
@@ -664,7 +676,7 @@ struct Run {
         }
         if (lane < LOB_ENV_STATE_WORDS) a.env_state[(int64_t)e * LOB_ENV_STATE_WORDS + lane] = ENV()[lane];
         if (lane < NCTR) a.counters[(int64_t)e * LOB_N_COUNTERS + lane] = ctr;
-        if (lane < STW) a.stats[(int64_t)e * STW + lane] = X64(X_ST)[lane];
+        if (lane < STW) a.stats[(int64_t)e * STW + lane] = X64(xl().st)[lane];
         if (lane < A * AGW) a.agent_state[(int64_t)e * A * AGW + lane] = AG(0)[lane];
         if (a.trade_cursor && lane == 0) a.trade_cursor[e] = tr_cur0 + tr_next;
     }
@@ -706,7 +718,7 @@ struct Run {
                 const uint32_t kj = (uint32_t)rdlane((int)key, j);
                 rank += (kj < key || (kj == key && j < lane)) ? 1 : 0;
             }
-            if (lane < nact) X()[X_PERM + rank] = lane;
+            if (lane < nact) X()[xl().perm + rank] = lane;
             WAVE_SYNC();
         }
 
@@ -717,7 +729,7 @@ struct Run {
          * A cancel at slot j moves only slots above j, so the walk continues below j. */
         for (int ai = 0; ai < A; ++ai) {
             const int tid = ai + 1;
-            const int nlv = uni(X()[X_NLV + ai]);
+            const int nlv = uni(X()[xl().nlv + ai]);
             for (int ws = 0; ws < 2; ++ws) {
                 int hi = nsz(ws) - 1;
                 for (;;) {
@@ -730,7 +742,7 @@ struct Run {
                     int x = qt; /* quantity to cancel; qt = the whole order */
                     if (D > 0) {
                         const int R = uni(LV(ai, k)[3]);
-                        int32_t *seen = X() + X_SEEN + ai * MAXLV + k;
+                        int32_t *seen = X() + xl().seen + ai * MAXLV + k;
                         const int older = uni(*seen);
                         if (lane == 0) *seen = older + qt;
                         WAVE_SYNC();
@@ -755,7 +767,7 @@ struct Run {
         const int nrep = (int)(uni64(row[t + 1]) - lo);
         int c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0;
         if (lane < nact) {
-            const int32_t *m = X() + X_ACT + X()[X_PERM + lane] * 8;
+            const int32_t *m = X() + xl().act + X()[xl().perm + lane] * 8;
             c0 = m[0]; c1 = m[1]; c2 = m[2]; c3 = m[3]; c4 = m[4]; c5 = m[5]; c6 = m[6];
         }
         int cnt = nact, base = -WAVE;
@@ -829,7 +841,7 @@ struct Run {
         count(C_TRADES, st_trades);
         count(C_TRADE_OVERFLOW, overflow);
         if (lane == 0) {
-            int64_t *S = X64(X_ST);
+            int64_t *S = X64(xl().st);
             S[0] = st_buy; S[1] = st_sell; S[2] = st_trades; S[3] = st_last;
             E[0] = bb1; E[1] = ba1; E[2] = mid2_end; E[4] = last_tsec; E[5] = last_tns;
             E[6] = t + 1; E[7] = mid2_end - mid2_prev;
@@ -1103,18 +1115,20 @@ void fill_out(KArgs &a, const lob_out *o) {
     a.done = o->done; a.actions_out = o->actions;
 }
 
-size_t class_lds(const CapClass &cl) { return (size_t)lds_words_for(cl.capp) * 4 * cl.waves; }
+size_t class_lds(const lob_ctx *c, const CapClass &cl) {
+    return (size_t)lds_words_for(cl.capp, c->cfg.n_agents) * 4 * cl.waves;
+}
 
 /* Launch the env kernel of one class on stream st. */
 int launch_class(lob_ctx *c, size_t k, KArgs a, hipStream_t st) {
     const CapClass &cl = c->classes[k];
     if (cl.count == 0) return LOB_OK;
     a.capp = cl.capp;
-    a.lds_words = lds_words_for(cl.capp);
+    a.lds_words = lds_words_for(cl.capp, c->cfg.n_agents);
     a.env_list = c->d_env_list + cl.first;
     a.n_list = cl.count;
     const int waves = cl.waves;
-    const size_t lds = class_lds(cl);
+    const size_t lds = class_lds(c, cl);
     int grid;
     if (cl.mode == 1) {
         a.work_ctr = c->d_work + k;
@@ -1151,8 +1165,8 @@ int launch_env(lob_ctx *c, KArgs a, hipStream_t st) {
 
 /* Default waves (envs) per workgroup for a class: the most resident envs per CU, LDS
  * being allocated per workgroup (at most 64 KiB each); ties go to larger workgroups. */
-int default_waves(int capp) {
-    const size_t per_wave = (size_t)lds_words_for(capp) * 4;
+int default_waves(int capp, int n_agents) {
+    const size_t per_wave = (size_t)lds_words_for(capp, n_agents) * 4;
     int best_w = 1, best_n = -1;
     for (int w : {4, 2, 1}) {
         if (per_wave * w > 64 * 1024) continue;
@@ -1186,7 +1200,7 @@ int build_classes(lob_ctx *c, bool padded) {
                 cl.capp = std::max(cl.capp, c->caps[(size_t)e]);
             }
         cl.rows = rows_for_cap(cl.capp);
-        cl.waves = default_waves(cl.capp);
+        cl.waves = default_waves(cl.capp, c->cfg.n_agents);
         c->classes.push_back(cl);
     }
     for (size_t k = 0; k < c->classes.size(); ++k) {
@@ -1384,7 +1398,7 @@ int lob_schedule_get(const lob_ctx *c, int32_t *out, int32_t max_classes) {
     for (int k = 0; k < nc && k < max_classes; ++k) {
         const CapClass &cl = c->classes[(size_t)k];
         int32_t *r = out + k * 5;
-        r[0] = cl.rows * WAVE; r[1] = cl.count; r[2] = cl.waves; r[3] = cl.mode; r[4] = cl.grid;
+        r[0] = cl.capp; r[1] = cl.count; r[2] = cl.waves; r[3] = cl.mode; r[4] = cl.grid;
     }
     return nc;
 }
@@ -1395,7 +1409,7 @@ int lob_schedule_set(lob_ctx *c, int32_t k, int32_t waves, int32_t mode, int32_t
     if (mode != 0 && mode != 1) return LOB_EINVAL;
     if (grid < 0) return LOB_EINVAL;
     CapClass &cl = c->classes[(size_t)k];
-    if ((size_t)lds_words_for(cl.capp) * 4 * waves > 64 * 1024) return LOB_EUNSUPPORTED;
+    if ((size_t)lds_words_for(cl.capp, c->cfg.n_agents) * 4 * waves > 64 * 1024) return LOB_EUNSUPPORTED;
     cl.waves = waves;
     cl.mode = mode;
     cl.grid = grid;
@@ -1457,7 +1471,7 @@ int lob_autotune(lob_ctx *c, const lob_msgs *m, int32_t n_steps, const lob_out *
         float best = 1e30f;
         for (int mode = 0; mode < 2; ++mode) {
             for (int waves : {1, 2, 4}) {
-                if ((size_t)lds_words_for(cl.capp) * 4 * waves > 64 * 1024) continue;
+                if ((size_t)lds_words_for(cl.capp, c->cfg.n_agents) * 4 * waves > 64 * 1024) continue;
                 cl.waves = waves;
                 cl.mode = mode;
                 cl.grid = 0;
@@ -1492,7 +1506,7 @@ int lob_observe(lob_ctx *c, float *obs, void *stream) {
     for (const CapClass &cl : c->classes) {
         if (cl.count == 0) continue;
         a.capp = cl.capp;
-        a.lds_words = lds_words_for(cl.capp);
+        a.lds_words = lds_words_for(cl.capp, c->cfg.n_agents);
         a.env_list = c->d_env_list + cl.first;
         a.n_list = cl.count;
         const size_t lds = (size_t)a.lds_words * 4 * cl.waves;
