@@ -46,21 +46,34 @@ __device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
 __device__ __forceinline__ floatx4 zero4() { return floatx4{0.f, 0.f, 0.f, 0.f}; }
 
 /* acc[mt][nt] += A[r0+16mt .. +16][0..K) * B[0..K)[c0+16nt .. +16]; A(i, k), B(k, j) are
- * accessors; K a multiple of 4. */
+ * accessors; K a multiple of 4.  Software-pipelined: the operands of step k+4 are loaded
+ * before the MFMAs of step k are issued, so their latency (LDS, or L2 for weights) is
+ * covered by the previous step's MFMAs even with one wave per SIMD; the last step
+ * re-reads its own operands (in bounds). */
 template <int MT, int NT, class FA, class FB>
 __device__ __forceinline__ void gemm(floatx4 (&acc)[MT][NT], int K, int r0, int c0, FA A, FB B) {
     const int l = (int)(threadIdx.x & 63);
     const int li = l & 15, lk = l >> 4;
+    float a[MT], b[NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) a[m] = A(r0 + 16 * m + li, lk);
+#pragma unroll
+    for (int n = 0; n < NT; ++n) b[n] = B(lk, c0 + 16 * n + li);
     for (int k0 = 0; k0 < K; k0 += 4) {
-        float a[MT], b[NT];
+        const int kn = k0 + 4 < K ? k0 + 4 : k0;
+        float an[MT], bn[NT];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) a[m] = A(r0 + 16 * m + li, k0 + lk);
+        for (int m = 0; m < MT; ++m) an[m] = A(r0 + 16 * m + li, kn + lk);
 #pragma unroll
-        for (int n = 0; n < NT; ++n) b[n] = B(k0 + lk, c0 + 16 * n + li);
+        for (int n = 0; n < NT; ++n) bn[n] = B(kn + lk, c0 + 16 * n + li);
 #pragma unroll
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int n = 0; n < NT; ++n) acc[m][n] = mfma(a[m], b[n], acc[m][n]);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) a[m] = an[m];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) b[n] = bn[n];
     }
 }
 

@@ -45,7 +45,6 @@ namespace lobk {
 
 constexpr int MAXA = LOB_MAX_AGENTS;
 constexpr int MAXLV = 8;          /* desired price levels per agent per step */
-constexpr int MAXACT = MAXA * 8;  /* new agent orders per env-step */
 constexpr int AGW = 8;            /* internal agent words: inv, cash, rem, ctr, step_bq, step_sq */
 constexpr int STW = 4;            /* step statistics: buy vol, sell vol, trades, last price */
 
@@ -151,8 +150,6 @@ struct Run {
      * tsec|tns).  Record j counts from the worst order (j = 0) to the best (j = n - 1),
      * so the top of the book is at the end of the live range; record j of a row of 64
      * belongs to lane j % 64. ---- */
-    /* this lane's record in row 0 of side s (row r is +64 records) */
-    __device__ __forceinline__ int2 *SB(int s) { return Pl + s * capp * REC; }
     /* pair p of record i of side s (any index, e.g. uniform) */
     __device__ __forceinline__ int2 &U(int s, int p, int i) {
         return reinterpret_cast<int2 *>(L)[(s * capp + i) * REC + p];
@@ -166,24 +163,32 @@ struct Run {
     __device__ __forceinline__ int64_t *ENV() { return X64(xl().env); }
 
     __device__ __forceinline__ int nsz(int s) const { return s ? n1 : n0; }
-    __device__ __forceinline__ void set_n(int s, int v) {
-        if (s) n1 = v; else n0 = v;
-    }
-    __device__ __forceinline__ int best(int s) const { return s ? best1 : best0; }
-    __device__ __forceinline__ void set_best(int s, int v) {
-        if (s) best1 = v; else best0 = v;
-    }
-    __device__ __forceinline__ void refresh_best(int s) {
-        const int n = nsz(s);
-        set_best(s, n > 0 ? uni(U(s, 0, n - 1).x) : 0);
-    }
     __device__ __forceinline__ void count(int k, int64_t v) { ctr += (lane == k) ? v : 0; }
 
+    /* ---- side-specialised views (S = 0 bids, 1 asks, known at compile time) ---- */
+    template <int S> __device__ __forceinline__ int &nS() {
+        if constexpr (S == 0) return n0; else return n1;
+    }
+    template <int S> __device__ __forceinline__ int &bestS() {
+        if constexpr (S == 0) return best0; else return best1;
+    }
+    /* prices of side S compare as (price ^ km(S)): "equal or better" is "<=" for both */
+    static constexpr int km(int s) { return s == 0 ? -1 : 0; }
+    template <int S> __device__ __forceinline__ int2 *SBS() { return S == 0 ? Pl : Pl + capp * REC; }
+    template <int S> __device__ __forceinline__ int2 &US(int p, int i) {
+        int2 *base = reinterpret_cast<int2 *>(L) + (S == 0 ? 0 : capp * REC);
+        return base[i * REC + p];
+    }
+    template <int S> __device__ __forceinline__ void refresh_bestS() {
+        const int n = nS<S>();
+        bestS<S>() = n > 0 ? uni(US<S>(0, n - 1).x) : 0;
+    }
+
     /* ---- searches: rows from the top of the book down, stopping at the first hit ---- */
-    /* highest record <= hi of side s whose field f (FO or FT) equals v, or -1; for oids
+    /* highest record <= hi of side S whose field f (FO or FT) equals v, or -1; for oids
      * this is the first order with that id in priority order */
-    __device__ __forceinline__ int find_top(int s, int f, int hi, int v) {
-        const int32_t *col = reinterpret_cast<const int32_t *>(SB(s)) + f;
+    template <int S> __device__ __forceinline__ int find_top(int f, int hi, int v) {
+        const int32_t *col = reinterpret_cast<const int32_t *>(SBS<S>()) + f;
         for (int r = hi >> 6; r >= 0; --r) {
             const int j = (r << 6) + lane;
             const int x = col[r * (WAVE * 2 * REC)];
@@ -192,16 +197,15 @@ struct Run {
         }
         return -1;
     }
-    /* orders of side s (n live) whose price is equal to or better than the one with key
-     * kp: prices compare as (price ^ m) with m = -1 for bids and 0 for asks, so "better or
-     * equal" is "key <=" on both sides.  They are the top records of the side. */
-    __device__ __forceinline__ int count_ahead(int s, int n, int kp, int m) {
-        const int32_t *col = reinterpret_cast<const int32_t *>(SB(s));
+    /* orders of side S (n live) whose price is equal to or better than the one with key
+     * kp (= price ^ km(S)): they are the top records of the side */
+    template <int S> __device__ __forceinline__ int count_ahead(int n, int kp) {
+        const int32_t *col = reinterpret_cast<const int32_t *>(SBS<S>());
         int cnt = 0;
         for (int r = (n - 1) >> 6; r >= 0; --r) {
             const int j = (r << 6) + lane;
             const int x = col[r * (WAVE * 2 * REC)];
-            const int c = __popcll(ballot(j < n && (x ^ m) <= kp));
+            const int c = __popcll(ballot(j < n && (x ^ km(S)) <= kp));
             cnt += c;
             if (c < min(WAVE, n - (r << 6))) break;
         }
@@ -210,12 +214,12 @@ struct Run {
 
     /* ---- book edits: one pass over the rows they touch, loads of a row before its
      * stores; each lane moves its own record ---- */
-    /* records [ins, n) of side s move up by one; the new order takes record ins (n < capp) */
-    __device__ __forceinline__ void insert_at(int s, int ins, int n, int2 v0, int2 v1, int2 v2) {
-        int2 *S = SB(s);
+    /* records [ins, n) of side S move up by one; the new order takes record ins (n < capp) */
+    template <int S> __device__ __forceinline__ void insert_at(int ins, int n, int2 v0, int2 v1, int2 v2) {
+        int2 *B = SBS<S>();
         for (int r = n >> 6; r >= (ins >> 6); --r) {
             const int j = (r << 6) + lane;
-            int2 *d = S + r * (WAVE * REC);
+            int2 *d = B + r * (WAVE * REC);
             int2 x0 = v0, x1 = v1, x2 = v2;
             if (j > ins && j <= n) { x0 = d[-3]; x1 = d[-2]; x2 = d[-1]; }
             WAVE_SYNC();
@@ -223,12 +227,12 @@ struct Run {
             WAVE_SYNC();
         }
     }
-    /* record k of side s (n live) leaves: [k+1, n) moves down by one */
-    __device__ __forceinline__ void remove_at(int s, int k, int n) {
-        int2 *S = SB(s);
+    /* record k of side S (n live) leaves: [k+1, n) moves down by one */
+    template <int S> __device__ __forceinline__ void remove_at(int k, int n) {
+        int2 *B = SBS<S>();
         for (int r = k >> 6; r <= (n - 2) >> 6; ++r) {
             const int j = (r << 6) + lane;
-            int2 *d = S + r * (WAVE * REC);
+            int2 *d = B + r * (WAVE * REC);
             const bool mv = j >= k && j < n - 1;
             int2 x0 = make_int2(0, 0), x1 = x0, x2 = x0;
             if (mv) { x0 = d[3]; x1 = d[4]; x2 = d[5]; }
@@ -239,11 +243,11 @@ struct Run {
     }
     /* full side: the worst order (record 0) leaves, [1, ins) moves down by one and the
      * new order takes record ins - 1 (ins >= 1) */
-    __device__ __forceinline__ void evict_insert(int s, int ins, int2 v0, int2 v1, int2 v2) {
-        int2 *S = SB(s);
+    template <int S> __device__ __forceinline__ void evict_insert(int ins, int2 v0, int2 v1, int2 v2) {
+        int2 *B = SBS<S>();
         for (int r = 0; r <= (ins - 1) >> 6; ++r) {
             const int j = (r << 6) + lane;
-            int2 *d = S + r * (WAVE * REC);
+            int2 *d = B + r * (WAVE * REC);
             int2 x0 = v0, x1 = v1, x2 = v2;
             if (j < ins - 1) { x0 = d[3]; x1 = d[4]; x2 = d[5]; }
             WAVE_SYNC();
@@ -275,28 +279,28 @@ struct Run {
         }
     }
 
-    /* ---- matching: an incoming order of side `side` against the opposite side while it
+    /* ---- matching: an incoming order of side S against the opposite side while it
      * crosses (market orders cross at any price); trades at the resting price, best
      * first, one resting order at a time from the top record down.  Returns the
      * unmatched remainder. ---- */
-    __device__ __forceinline__ int match(int side, int p, int q, bool market, int agg_oid, int agg_tid) {
-        const int opp = side ^ 1;
-        const int n_opp = nsz(opp);
+    template <int S>
+    __device__ __forceinline__ int match(int p, int q, bool market, int agg_oid, int agg_tid) {
+        constexpr int O = 1 - S;
+        const int n_opp = nS<O>();
         if (n_opp == 0) return q;
-        const int mo = opp ? 0 : -1;
-        const int kp = p ^ mo;
-        if (!market && (best(opp) ^ mo) > kp) return q;
+        const int kp = p ^ km(O);
+        if (!market && (bestS<O>() ^ km(O)) > kp) return q;
         int no = n_opp, rem = q, ntr = 0, last_price = 0;
         int64_t notional = 0;
         for (;;) {
-            int2 *rec = &U(opp, 0, no - 1);
+            int2 *rec = &US<O>(0, no - 1);
             const int2 pq = rec[0], ot = rec[1];
             const int price = uni(pq.x), qty = uni(pq.y);
-            if (ntr > 0 && !market && (price ^ mo) > kp) break;
+            if (ntr > 0 && !market && (price ^ km(O)) > kp) break;
             const int poid = uni(ot.x), ptid = uni(ot.y);
             const int x = min(rem, qty);
-            write_trade(ntr, price, x, agg_oid, poid, agg_tid, ptid, side);
-            add_fill(ptid, side != 0, x, (int64_t)x * price);
+            write_trade(ntr, price, x, agg_oid, poid, agg_tid, ptid, S);
+            add_fill(ptid, S != 0, x, (int64_t)x * price);
             notional += (int64_t)x * price;
             rem -= x;
             ntr += 1;
@@ -309,97 +313,93 @@ struct Run {
             }
             if (rem == 0 || no == 0) break;
         }
-        add_fill(agg_tid, side == 0, q - rem, notional);
+        add_fill(agg_tid, S == 0, q - rem, notional);
         if (no != n_opp) {
-            set_n(opp, no);
-            refresh_best(opp);
+            nS<O>() = no;
+            refresh_bestS<O>();
         }
         tr_next += ntr;
-        if (side == 0) st_buy += q - rem; else st_sell += q - rem;
+        if (S == 0) st_buy += q - rem; else st_sell += q - rem;
         st_last = last_price;
         return rem;
     }
 
-    /* ---- rest a limit remainder on its own side (after all orders at an equal or
+    /* ---- rest a limit remainder on its own side S (after all orders at an equal or
      * better price); a full side evicts its worst order if the price is strictly
      * better than that order's, else the remainder is dropped. ---- */
-    __device__ __forceinline__ void rest(int side, int p, int q, int oid, int tid, int ts, int tn) {
-        const int n = nsz(side);
-        const int m = side ? 0 : -1;
-        const int kp = p ^ m;
-        const int cnt = count_ahead(side, n, kp, m);
+    template <int S>
+    __device__ __forceinline__ void rest(int p, int q, int oid, int tid, int ts, int tn) {
+        const int n = nS<S>();
+        const int kp = p ^ km(S);
+        const int cnt = count_ahead<S>(n, kp);
         const int ins = n - cnt;
         if (n < cap) {
-            insert_at(side, ins, n, make_int2(p, q), make_int2(oid, tid), make_int2(ts, tn));
-            set_n(side, n + 1);
+            insert_at<S>(ins, n, make_int2(p, q), make_int2(oid, tid), make_int2(ts, tn));
+            nS<S>() = n + 1;
         } else {
-            const int2 w = U(side, 0, 0);
+            const int2 w = US<S>(0, 0);
             const int wp = uni(w.x);
-            if (kp >= (wp ^ m)) {
+            if (kp >= (wp ^ km(S))) {
                 count(C_DROP, 1);
                 count(C_DROPPED_QTY, q);
                 return;
             }
             count(C_EVICT, 1);
             count(C_EVICTED_QTY, uni(w.y));
-            evict_insert(side, ins, make_int2(p, q), make_int2(oid, tid), make_int2(ts, tn));
+            evict_insert<S>(ins, make_int2(p, q), make_int2(oid, tid), make_int2(ts, tn));
         }
-        if (cnt == 0) set_best(side, p);
+        if (cnt == 0) bestS<S>() = p;
     }
 
-    /* ---- cancels: the first order with this id (priority order) on the message's side ---- */
-    __device__ __forceinline__ void cancel(bool partial, int side, int qty, int oid) {
-        const int n = nsz(side);
-        const int k = find_top(side, FO, n - 1, oid);
+    /* ---- cancels: the first order with this id (priority order) on side S ---- */
+    template <int S>
+    __device__ __forceinline__ void cancel(bool partial, int qty, int oid) {
+        const int n = nS<S>();
+        const int k = find_top<S>(FO, n - 1, oid);
         if (k < 0) {
             count(C_MISS, 1);
             return;
         }
         if (partial) {
-            const int cq = uni(U(side, 0, k).y);
+            const int cq = uni(US<S>(0, k).y);
             const int left = cq - min(qty, cq);
             if (left > 0) {
-                if (lane == 0) U(side, 0, k).y = left;
+                if (lane == 0) US<S>(0, k).y = left;
                 WAVE_SYNC();
                 return;
             }
         }
-        remove_at(side, k, n);
-        set_n(side, n - 1);
-        if (k == n - 1) refresh_best(side);
+        remove_at<S>(k, n);
+        nS<S>() = n - 1;
+        if (k == n - 1) refresh_bestS<S>();
     }
 
     /* ---- one message of the step sequence ---- */
-    __device__ __forceinline__ void process(int ts, int price, int qty, int oid, int tid, int tsec, int tns) {
-        const int type = ts & 0xFF, side = (ts >> 8) & 1;
-        switch (type) {
-        case T_LIMIT:
-            if (qty > 0) {
-                const int q = match(side, price, qty, false, oid, tid);
-                if (q > 0) rest(side, price, q, oid, tid, tsec, tns);
-            } else {
+    template <int S>
+    __device__ __forceinline__ void process_side(int type, int price, int qty, int oid, int tid, int tsec, int tns) {
+        if (type == T_LIMIT || type == T_MARKET) {
+            if (qty <= 0) {
                 count(C_BAD, 1);
+                return;
             }
-            break;
-        case T_MARKET:
-            if (qty > 0) {
-                const int q = match(side, price, qty, true, oid, tid);
-                if (q > 0) count(C_MARKET_UNFILLED, q);
-            } else {
-                count(C_BAD, 1);
+            const bool mkt = type == T_MARKET;
+            const int q = match<S>(price, qty, mkt, oid, tid);
+            if (q > 0) {
+                if (mkt) count(C_MARKET_UNFILLED, q);
+                else rest<S>(price, q, oid, tid, tsec, tns);
             }
-            break;
-        case T_PCANCEL:
-            if (qty > 0) cancel(true, side, qty, oid);
-            else count(C_BAD, 1);
-            break;
-        case T_DELETE:
-            cancel(false, side, qty, oid);
-            break;
-        default:
+        } else if (type == T_PCANCEL || type == T_DELETE) {
+            const bool partial = type == T_PCANCEL;
+            if (partial && qty <= 0) count(C_BAD, 1);
+            else cancel<S>(partial, qty, oid);
+        } else {
             count(C_BAD, 1);
-            break;
         }
+    }
+    __device__ __forceinline__ void process(int ts, int price, int qty, int oid, int tid, int tsec, int tns) {
+        const int type = ts & 0xFF;
+        if (ts & 0x100) process_side<1>(type, price, qty, oid, tid, tsec, tns);
+        else process_side<0>(type, price, qty, oid, tid, tsec, tns);
         after_message();
     }
     /* per message of the sequence: mid statistics for the reward (both sides non-empty)
@@ -432,6 +432,22 @@ struct Run {
         for (int k = 0; k < nlv; ++k)
             if (uni(LV(ai, k)[0]) == side && uni(LV(ai, k)[1]) == price) return k;
         return -1;
+    }
+
+    /* the agent's resting quantity at each of its desired levels on side S */
+    template <int S> __device__ __forceinline__ void resting_side(int i, int nlv, int tid) {
+        int hi = nS<S>() - 1;
+        for (;;) {
+            const int j = find_top<S>(FT, hi, tid);
+            if (j < 0) break;
+            const int2 pq = US<S>(0, j);
+            const int k = find_level(i, nlv, S, uni(pq.x));
+            if (k >= 0) {
+                if (lane == 0) LV(i, k)[3] += pq.y;
+                WAVE_SYNC();
+            }
+            hi = j - 1;
+        }
     }
 
     /* Sec. 4 step 1, from the book at step start, for agent i: decode its action into
@@ -514,20 +530,8 @@ struct Run {
 
         /* resting quantity of this agent at each desired level (step start) */
         if (nlv > 0) {
-            for (int s = 0; s < 2; ++s) {
-                int hi = nsz(s) - 1;
-                for (;;) {
-                    const int j = find_top(s, FT, hi, tid);
-                    if (j < 0) break;
-                    const int2 pq = U(s, 0, j);
-                    const int k = find_level(i, nlv, s, uni(pq.x));
-                    if (k >= 0) {
-                        if (lane == 0) LV(i, k)[3] += pq.y;
-                        WAVE_SYNC();
-                    }
-                    hi = j - 1;
-                }
-            }
+            resting_side<0>(i, nlv, tid);
+            resting_side<1>(i, nlv, tid);
         }
         /* new orders; order ids from the agent's counter */
         int64_t *g = AG(i);
@@ -640,8 +644,8 @@ struct Run {
         if (lane < A * AGW) AG(0)[lane] = a.agent_state[(int64_t)e * A * AGW + lane];
         ctr = lane < NCTR ? a.counters[(int64_t)e * LOB_N_COUNTERS + lane] : 0;
         WAVE_SYNC();
-        refresh_best(0);
-        refresh_best(1);
+        refresh_bestS<0>();
+        refresh_bestS<1>();
         t = (int32_t)uni64(ENV()[6]);
         last_tsec = (int32_t)uni64(ENV()[4]);
         last_tns = (int32_t)uni64(ENV()[5]);
@@ -679,6 +683,39 @@ struct Run {
         if (lane < STW) a.stats[(int64_t)e * STW + lane] = X64(xl().st)[lane];
         if (lane < A * AGW) a.agent_state[(int64_t)e * A * AGW + lane] = AG(0)[lane];
         if (a.trade_cursor && lane == 0) a.trade_cursor[e] = tr_cur0 + tr_next;
+    }
+
+    /* The cancel block's walk for agent ai over side S: its resting orders in book order
+     * (best first); an order at a level the agent no longer wants is deleted, at a kept
+     * level any excess over the desired quantity comes from its newest orders there.  A
+     * cancel at record j moves only records above j, so the walk continues below j. */
+    template <int S> __device__ __forceinline__ void walk_side(int ai, int nlv, int tid) {
+        int hi = nS<S>() - 1;
+        for (;;) {
+            const int j = find_top<S>(FT, hi, tid);
+            if (j < 0) break;
+            const int2 pq = US<S>(0, j);
+            const int pr = uni(pq.x), qt = uni(pq.y);
+            const int k = find_level(ai, nlv, S, pr);
+            const int D = k >= 0 ? uni(LV(ai, k)[2]) : 0;
+            int x = qt; /* quantity to cancel; qt = the whole order */
+            if (D > 0) {
+                const int R = uni(LV(ai, k)[3]);
+                int32_t *seen = X() + xl().seen + ai * MAXLV + k;
+                const int older = uni(*seen);
+                if (lane == 0) *seen = older + qt;
+                WAVE_SYNC();
+                x = R > D ? min(max((R - D) - (R - older - qt), 0), qt) : 0;
+            }
+            if (x > 0) {
+                /* a cancel message (delete, or partial cancel of x) for this order */
+                const int oid = uni(US<S>(1, j).x);
+                if (D == 0) cancel<S>(false, qt, oid);
+                else cancel<S>(true, x, oid);
+                after_message();
+            }
+            hi = j - 1;
+        }
     }
 
     /* ---- one env-step (Sec. 4 steps 1-5) writing output slot s_idx ---- */
@@ -723,41 +760,12 @@ struct Run {
         }
 
         /* steps 3-4, in the order of Sec. 4 step 3.  First the cancel block: agents in
-         * index order, each walking its resting orders in book order (best first); an
-         * order at a level the agent no longer wants is deleted, at a kept level any
-         * excess over the desired quantity comes from the agent's newest orders there.
-         * A cancel at slot j moves only slots above j, so the walk continues below j. */
+         * index order, each walking its resting orders on both sides (walk_side). */
         for (int ai = 0; ai < A; ++ai) {
             const int tid = ai + 1;
             const int nlv = uni(X()[xl().nlv + ai]);
-            for (int ws = 0; ws < 2; ++ws) {
-                int hi = nsz(ws) - 1;
-                for (;;) {
-                    const int j = find_top(ws, FT, hi, tid);
-                    if (j < 0) break;
-                    const int2 pq = U(ws, 0, j);
-                    const int pr = uni(pq.x), qt = uni(pq.y);
-                    const int k = find_level(ai, nlv, ws, pr);
-                    const int D = k >= 0 ? uni(LV(ai, k)[2]) : 0;
-                    int x = qt; /* quantity to cancel; qt = the whole order */
-                    if (D > 0) {
-                        const int R = uni(LV(ai, k)[3]);
-                        int32_t *seen = X() + xl().seen + ai * MAXLV + k;
-                        const int older = uni(*seen);
-                        if (lane == 0) *seen = older + qt;
-                        WAVE_SYNC();
-                        x = R > D ? min(max((R - D) - (R - older - qt), 0), qt) : 0;
-                    }
-                    if (x > 0) {
-                        /* a cancel message (delete, or partial cancel of x) for this order */
-                        const int oid = uni(U(ws, 1, j).x);
-                        if (D == 0) cancel(false, ws, qt, oid);
-                        else cancel(true, ws, x, oid);
-                        after_message();
-                    }
-                    hi = j - 1;
-                }
-            }
+            walk_side<0>(ai, nlv, tid);
+            walk_side<1>(ai, nlv, tid);
         }
 
         /* then the shuffled new orders (staged as the first chunk) and the replayed
@@ -857,7 +865,9 @@ struct Run {
 /* ------------------------------------------------------------------------------
  * Kernels
  * ---------------------------------------------------------------------------- */
-__global__ void __launch_bounds__(256) k_env(KArgs a) {
+/* 256 threads, at least 6 waves per SIMD: caps registers at 80 VGPRs (the few spills
+ * are outside the message loop) */
+__global__ void __launch_bounds__(256, 6) k_env(KArgs a) {
     extern __shared__ int32_t smem[];
     const int wave = uni((int)(threadIdx.x >> 6)), waves = (int)(blockDim.x >> 6);
     int32_t *L = smem + wave * a.lds_words;
