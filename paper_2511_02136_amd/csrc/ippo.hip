@@ -32,6 +32,7 @@ constexpr int IN = LOB_OBS_DIM, HID = 256, OUT = 10, OUTP = 16;
 constexpr int O_W1 = 0, O_B1 = O_W1 + IN * HID, O_W2 = O_B1 + HID, O_B2 = O_W2 + HID * HID, O_W3 = O_B2 + HID,
               O_B3 = O_W3 + HID * OUT, NPARAM = O_B3 + OUT;
 static_assert(NPARAM == 78858, "parameter count");
+constexpr int PW = NPARAM + 4; /* per-workgroup partial: gradient, then the 4 loss sums */
 
 constexpr int TR = 64;          /* samples per workgroup tile */
 constexpr int XS = 52;          /* LDS row stride of the input tile (cols 40..51 zero) */
@@ -231,8 +232,7 @@ struct PpoArgs {
     const float *logp_old, *adv, *ret, *v_old;
     int32_t m, n_act;
     float clip, c_v, c_e, scale; /* scale = 1 / m */
-    float *partial;              /* [grid][NPARAM] */
-    float *loss_partial;         /* [grid][4]: total, policy, value, entropy (sums) */
+    float *partial;              /* [grid][PW]: gradient, then loss sums (total, policy, value, entropy) */
 };
 
 __global__ void __launch_bounds__(256) k_ppo_fwd_bwd(PpoArgs a) {
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(256) k_ppo_fwd_bwd(PpoArgs a) {
     const int row0 = (int)blockIdx.x * TR;
     const int rows = min(TR, a.m - row0);
     const float *P = a.params;
-    float *G = a.partial + (int64_t)blockIdx.x * NPARAM;
+    float *G = a.partial + (int64_t)blockIdx.x * PW;
     const int tid = (int)threadIdx.x, wave = tid >> 6;
     forward_tile(P, a.obs + (int64_t)row0 * IN, rows, X, H1, H2, O);
 
@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(256) k_ppo_fwd_bwd(PpoArgs a) {
         for (int q = 0; q < 4; ++q) {
             float v = lsum[q];
             for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-            if (tid == 0) a.loss_partial[(int64_t)blockIdx.x * 4 + q] = v;
+            if (tid == 0) G[NPARAM + q] = v;
         }
     }
     __syncthreads();
@@ -420,13 +420,34 @@ __global__ void __launch_bounds__(256) k_ppo_fwd_bwd(PpoArgs a) {
     }
 }
 
-/* sum of the per-workgroup partials, in workgroup order (deterministic) */
-__global__ void k_reduce(const float *__restrict__ partial, int nwg, int width, float *out) {
+/* Sum of the per-workgroup partials in a fixed order (deterministic), in two levels:
+ * chunk c of RCH consecutive workgroups is summed in workgroup order into sums[c], then
+ * the chunk sums in chunk order.  Level 1 keeps 8 loads in flight per thread. */
+constexpr int RCH = 64;
+__global__ void k_reduce_chunks(const float *__restrict__ partial, int nwg, int width, float *__restrict__ sums) {
     const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (j >= width) return;
+    const int w0 = (int)blockIdx.y * RCH, w1 = min(nwg, w0 + RCH);
     float s = 0.f;
-    for (int w = 0; w < nwg; ++w) s += partial[(int64_t)w * width + j];
-    out[j] = s;
+    int w = w0;
+    for (; w + 8 <= w1; w += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(w + u) * width + j];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; w < w1; ++w) s += partial[(int64_t)w * width + j];
+    sums[(int64_t)blockIdx.y * width + j] = s;
+}
+/* columns [0, NPARAM) go to grad, the last 4 to loss */
+__global__ void k_reduce_final(const float *__restrict__ sums, int nch, float *grad, float *loss) {
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= PW) return;
+    float s = 0.f;
+    for (int c = 0; c < nch; ++c) s += sums[(int64_t)c * PW + j];
+    if (j < NPARAM) grad[j] = s;
+    else loss[j - NPARAM] = s;
 }
 
 __global__ void k_bump(uint64_t *c) {
@@ -489,8 +510,8 @@ int lob_gae(const float *reward, const float *value, const uint8_t *done, const 
 
 int64_t lob_ppo_workspace_bytes(int32_t m) {
     if (m <= 0) return LOB_EINVAL;
-    const int64_t nwg = (m + TR - 1) / TR;
-    return nwg * (NPARAM + 4) * 4;
+    const int64_t nwg = (m + TR - 1) / TR, nch = (nwg + RCH - 1) / RCH;
+    return (nwg + nch) * PW * 4;
 }
 
 int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, const float *logp_old,
@@ -501,18 +522,20 @@ int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, c
         return LOB_EINVAL;
     if (m <= 0 || n_actions < 1 || n_actions > 9 || !(clip > 0.f)) return LOB_EINVAL;
     const int nwg = (m + TR - 1) / TR;
-    if (workspace_bytes < (int64_t)nwg * (NPARAM + 4) * 4) return LOB_EINVAL;
+    const int nch = (nwg + RCH - 1) / RCH;
+    if (workspace_bytes < (int64_t)(nwg + nch) * PW * 4) return LOB_EINVAL;
     PpoArgs a;
     a.params = params; a.obs = obs; a.act = act; a.logp_old = logp_old; a.adv = adv; a.ret = ret; a.v_old = v_old;
     a.m = m; a.n_act = n_actions; a.clip = clip; a.c_v = c_v; a.c_e = c_e; a.scale = 1.0f / (float)m;
     a.partial = workspace;
-    a.loss_partial = workspace + (int64_t)nwg * NPARAM;
     if (!lds_opt_in()) return LOB_EHIP;
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_ppo_fwd_bwd, dim3((unsigned)nwg), dim3(256), LDS_FLOATS * 4, st, a);
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((NPARAM + 255) / 256)), dim3(256), 0, st, (const float *)a.partial, nwg,
-                       NPARAM, grad);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, st, (const float *)a.loss_partial, nwg, 4, loss);
+    float *sums = workspace + (int64_t)nwg * PW;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((PW + 255) / 256), (unsigned)nch), dim3(256), 0, st,
+                       (const float *)a.partial, nwg, PW, sums);
+    hipLaunchKernelGGL(k_reduce_final, dim3((unsigned)((PW + 255) / 256)), dim3(256), 0, st, (const float *)sums, nch,
+                       grad, loss);
     return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
 }
 
