@@ -92,8 +92,9 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 
 def ippo_bench(reps: int = 3):
     """ippo4096: 4096 envs x 128 steps, two actor-critics.  Times the graph-captured
-    learned-policy rollout, one PPO update (4 epochs x 4 minibatches per agent) and the
-    fused PPO kernel alone on one full minibatch (131072 samples)."""
+    learned-policy rollout, one PPO update (4 epochs x 4 minibatches per agent) and one
+    fused PPO forward+backward call (fused kernel and its two reduction launches) on one
+    full minibatch (131072 samples)."""
     import torch
     from paper_2511_02136_amd import synth, ippo
     from paper_2511_02136_amd.lob import LobEnv, DeviceStream
@@ -143,7 +144,8 @@ def ippo_bench(reps: int = 3):
     return {"workload": f"ippo4096: {N} envs x {T} steps, 2 agents (exec, mm), MLP 40-256-256-(9+1) fp32",
             "rollout_ms": roll_ms, "rollout_env_steps_per_s": env_steps / (roll_ms / 1e3),
             "update_ms": upd_ms, "update": "GAE + 4 epochs x 4 minibatches x 2 agents of fused PPO + Adam",
-            "ppo_kernel": {"samples": m, "ms": ppo_ms, "flop_per_sample": PPO_FLOP_PER_SAMPLE,
+            "ppo_fwd_bwd_call": {"samples": m, "ms": ppo_ms, "flop_per_sample": PPO_FLOP_PER_SAMPLE,
+                                 "launches": "k_ppo_fwd_bwd, k_reduce_chunks, k_reduce_final",
                            "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
                                         "unit": "TFLOP/s", "frac": tflops / FP32_MFMA_PEAK_TFLOPS}}}
 
