@@ -60,6 +60,31 @@ def measured_traffic(workload: str):
     return None
 
 
+# one SALU instruction per CU per cycle (each SIMD issues one every 4 cycles)
+N_CU, CLOCK_HZ = 256, 2.4e9
+
+
+def measured_issue(workload: str, n_msgs: int, kernel_ms: float):
+    """Scalar-issue view of k_env from the committed instruction-mix summary (rocprofv3
+    SQ_INSTS_* counters), or None when it is missing or from a different kernel source:
+    the time the SALU instructions alone need at one per CU per cycle, as a fraction of
+    the measured kernel time."""
+    path = os.path.join(ROOT, "profiles", f"k_env_{workload}_instruction_mix.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("mix_json: "):
+                m = json.loads(line[len("mix_json: "):])
+                if m.get("source_sha") != kernel_source_sha():
+                    return None
+                salu_ms = m["salu_per_msg"] * n_msgs / (N_CU * CLOCK_HZ) * 1e3
+                return {"salu_per_msg": m["salu_per_msg"], "valu_per_msg": m["valu_per_msg"],
+                        "lds_per_msg": m["lds_per_msg"], "salu_issue_ms": salu_ms,
+                        "salu_issue_frac": salu_ms / kernel_ms}
+    return None
+
+
 def cpu_baseline(w, stream, budget_s=15.0):
     """The CPU oracle on a bounded sample of the same workload (first envs, all steps)."""
     import oracle
@@ -342,7 +367,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name),
                      "kernel": "k_env (persistent rollout, all capacity classes)",
-                     "kernel_ms": kernel_ms, "algorithmic_bytes": alg},
+                     "kernel_ms": kernel_ms, "algorithmic_bytes": alg,
+                     "scalar_issue": measured_issue(w.name, n_msgs, kernel_ms)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
