@@ -258,7 +258,7 @@ struct Run {
 
     /* ---- fills (uniform accumulation in LDS by lane 0) ---- */
     __device__ __forceinline__ void add_fill(int tid, int buy, int64_t q, int64_t notional) {
-        if (tid >= 1 && tid <= A) {
+        if ((unsigned)(tid - 1) < (unsigned)A) { /* agent tids are 1..A */
             if (lane == 0) {
                 int64_t *f = FL(tid - 1) + (buy ? 0 : 2);
                 f[0] += q;
@@ -283,20 +283,21 @@ struct Run {
      * crosses (market orders cross at any price); trades at the resting price, best
      * first, one resting order at a time from the top record down.  Returns the
      * unmatched remainder. ---- */
-    template <int S>
-    __device__ __forceinline__ int match(int p, int q, bool market, int agg_oid, int agg_tid) {
+    template <int S, bool MARKET>
+    __device__ __forceinline__ int match(int p, int q, int agg_oid, int agg_tid) {
         constexpr int O = 1 - S;
         const int n_opp = nS<O>();
         if (n_opp == 0) return q;
         const int kp = p ^ km(O);
-        if (!market && (bestS<O>() ^ km(O)) > kp) return q;
+        if (!MARKET && (bestS<O>() ^ km(O)) > kp) return q;
         int no = n_opp, rem = q, ntr = 0, last_price = 0;
         int64_t notional = 0;
+        int2 *rec = &US<O>(0, no - 1);
+        int2 pq = rec[0];
         for (;;) {
-            int2 *rec = &US<O>(0, no - 1);
-            const int2 pq = rec[0], ot = rec[1];
+            /* the order at the top crosses */
+            const int2 ot = rec[1];
             const int price = uni(pq.x), qty = uni(pq.y);
-            if (ntr > 0 && !market && (price ^ km(O)) > kp) break;
             const int poid = uni(ot.x), ptid = uni(ot.y);
             const int x = min(rem, qty);
             write_trade(ntr, price, x, agg_oid, poid, agg_tid, ptid, S);
@@ -305,13 +306,17 @@ struct Run {
             rem -= x;
             ntr += 1;
             last_price = price;
-            if (x == qty) {
-                no -= 1;
-            } else {
+            if (x < qty) {
+                /* partly filled: the incoming order is done */
                 if (lane == 0) rec[0].y = qty - x;
                 WAVE_SYNC();
+                break;
             }
-            if (rem == 0 || no == 0) break;
+            no -= 1;
+            if (min(rem, no) == 0) break;
+            rec = &US<O>(0, no - 1);
+            pq = rec[0];
+            if (!MARKET && (uni(pq.x) ^ km(O)) > kp) break;
         }
         add_fill(agg_tid, S == 0, q - rem, notional);
         if (no != n_opp) {
@@ -352,15 +357,15 @@ struct Run {
     }
 
     /* ---- cancels: the first order with this id (priority order) on side S ---- */
-    template <int S>
-    __device__ __forceinline__ void cancel(bool partial, int qty, int oid) {
+    template <int S, bool PARTIAL>
+    __device__ __forceinline__ void cancel(int qty, int oid) {
         const int n = nS<S>();
         const int k = find_top<S>(FO, n - 1, oid);
         if (k < 0) {
             count(C_MISS, 1);
             return;
         }
-        if (partial) {
+        if (PARTIAL) {
             const int cq = uni(US<S>(0, k).y);
             const int left = cq - min(qty, cq);
             if (left > 0) {
@@ -375,23 +380,26 @@ struct Run {
     }
 
     /* ---- one message of the step sequence ---- */
+    /* each test a single comparison (compound conditions on uniform values cost lane-mask
+     * arithmetic) */
     template <int S>
     __device__ __forceinline__ void process_side(int type, int price, int qty, int oid, int tid, int tsec, int tns) {
-        if (type == T_LIMIT || type == T_MARKET) {
-            if (qty <= 0) {
+        if ((unsigned)(type - T_PCANCEL) < 2u) {
+            if (type == T_DELETE) {
+                cancel<S, false>(qty, oid);
+            } else if (qty > 0) {
+                cancel<S, true>(qty, oid);
+            } else {
                 count(C_BAD, 1);
-                return;
             }
-            const bool mkt = type == T_MARKET;
-            const int q = match<S>(price, qty, mkt, oid, tid);
-            if (q > 0) {
-                if (mkt) count(C_MARKET_UNFILLED, q);
-                else rest<S>(price, q, oid, tid, tsec, tns);
-            }
-        } else if (type == T_PCANCEL || type == T_DELETE) {
-            const bool partial = type == T_PCANCEL;
-            if (partial && qty <= 0) count(C_BAD, 1);
-            else cancel<S>(partial, qty, oid);
+        } else if (qty <= 0) {
+            count(C_BAD, 1);
+        } else if (type == T_LIMIT) {
+            const int q = match<S, false>(price, qty, oid, tid);
+            if (q > 0) rest<S>(price, q, oid, tid, tsec, tns);
+        } else if (type == T_MARKET) {
+            const int q = match<S, true>(price, qty, oid, tid);
+            if (q > 0) count(C_MARKET_UNFILLED, q);
         } else {
             count(C_BAD, 1);
         }
@@ -405,7 +413,7 @@ struct Run {
     /* per message of the sequence: mid statistics for the reward (both sides non-empty)
      * and the message index */
     __device__ __forceinline__ void after_message() {
-        if (n0 > 0 && n1 > 0) {
+        if (min(n0, n1) > 0) {
             mid_sum += (int64_t)best0 + best1;
             mid_n += 1;
         }
@@ -710,8 +718,8 @@ struct Run {
             if (x > 0) {
                 /* a cancel message (delete, or partial cancel of x) for this order */
                 const int oid = uni(US<S>(1, j).x);
-                if (D == 0) cancel<S>(false, qt, oid);
-                else cancel<S>(true, x, oid);
+                if (D == 0) cancel<S, false>(qt, oid);
+                else cancel<S, true>(x, oid);
                 after_message();
             }
             hi = j - 1;
