@@ -272,10 +272,12 @@ struct Run {
     __device__ __forceinline__ void write_trade(int k, int price, int q, int agg_oid, int pas_oid,
                                                 int agg_tid, int pas_tid, int side) {
         const int rec = tr_next + k;
-        if (lane == 0 && rec < tr_room) {
-            int4 *p = reinterpret_cast<int4 *>(tr_base + (int64_t)rec * LOB_TRADE_WORDS);
-            p[0] = make_int4(price, q, agg_oid, pas_oid);
-            p[1] = make_int4(agg_tid, pas_tid, side | (seq << 1), t);
+        if (rec < tr_room) {
+            if (lane == 0) {
+                int4 *p = reinterpret_cast<int4 *>(tr_base + (int64_t)rec * LOB_TRADE_WORDS);
+                p[0] = make_int4(price, q, agg_oid, pas_oid);
+                p[1] = make_int4(agg_tid, pas_tid, side | (seq << 1), t);
+            }
         }
     }
 
@@ -1163,21 +1165,29 @@ int launch_class(lob_ctx *c, size_t k, KArgs a, hipStream_t st) {
     return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
 }
 
-/* Launch every class concurrently: fork from the caller's stream to one stream per
- * class, join back.  Classes with more work per env are launched first. */
+/* Launch every class concurrently.  A process has few hardware queues (4 by default) and
+ * streams beyond them share queues, serialising their kernels; so the classes go to at
+ * most CONC_LANES lanes: lane 0 is the caller's stream, lanes 1.. are forked streams
+ * joined back with events.  Classes are dealt to the lanes largest books first; classes
+ * sharing a lane run one after the other. */
+constexpr int CONC_LANES = 4;
 int launch_env(lob_ctx *c, KArgs a, hipStream_t st) {
-    const size_t nc = c->classes.size();
-    if (nc == 1) return launch_class(c, 0, a, st);
-    if (!hip_ok(hipEventRecord(c->ev_fork, st))) return LOB_EHIP;
-    for (size_t i = 0; i < nc; ++i) {
-        const size_t k = nc - 1 - i; /* largest books first */
-        if (!hip_ok(hipStreamWaitEvent(c->streams[k], c->ev_fork, 0))) return LOB_EHIP;
-        int rc = launch_class(c, k, a, c->streams[k]);
+    const int nc = (int)c->classes.size();
+    const int lanes = std::min(nc, CONC_LANES);
+    if (lanes > 1 && !hip_ok(hipEventRecord(c->ev_fork, st))) return LOB_EHIP;
+    for (int l = 1; l < lanes; ++l)
+        if (!hip_ok(hipStreamWaitEvent(c->streams[l], c->ev_fork, 0))) return LOB_EHIP;
+    for (int i = 0; i < nc; ++i) {
+        const int k = nc - 1 - i; /* largest books first */
+        const int l = i % lanes;
+        const int rc = launch_class(c, (size_t)k, a, l == 0 ? st : c->streams[l]);
         if (rc != LOB_OK) return rc;
-        if (!hip_ok(hipEventRecord(c->ev_join[k], c->streams[k]))) return LOB_EHIP;
     }
-    for (size_t k = 0; k < nc; ++k)
-        if (!hip_ok(hipStreamWaitEvent(st, c->ev_join[k], 0))) return LOB_EHIP;
+    for (int l = 1; l < lanes; ++l) {
+        if (!hip_ok(hipEventRecord(c->ev_join[l], c->streams[l])) ||
+            !hip_ok(hipStreamWaitEvent(st, c->ev_join[l], 0)))
+            return LOB_EHIP;
+    }
     return LOB_OK;
 }
 
