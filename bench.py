@@ -65,10 +65,10 @@ N_CU, CLOCK_HZ = 256, 2.4e9
 
 
 def measured_issue(workload: str, n_msgs: int, kernel_ms: float):
-    """Scalar-issue view of k_env from the committed instruction-mix summary (rocprofv3
+    """Issue view of k_env from the committed instruction-mix summary (rocprofv3
     SQ_INSTS_* counters), or None when it is missing or from a different kernel source:
-    the time the SALU instructions alone need at one per CU per cycle, as a fraction of
-    the measured kernel time."""
+    the time the SALU instructions alone need at one per CU per cycle, and the LDS
+    instructions at one per CU per cycle, as fractions of the measured kernel time."""
     path = os.path.join(ROOT, "profiles", f"k_env_{workload}_instruction_mix.md")
     if not os.path.exists(path):
         return None
@@ -79,20 +79,76 @@ def measured_issue(workload: str, n_msgs: int, kernel_ms: float):
                 if m.get("source_sha") != kernel_source_sha():
                     return None
                 salu_ms = m["salu_per_msg"] * n_msgs / (N_CU * CLOCK_HZ) * 1e3
+                lds_ms = m["lds_per_msg"] * n_msgs / (N_CU * CLOCK_HZ) * 1e3
                 return {"salu_per_msg": m["salu_per_msg"], "valu_per_msg": m["valu_per_msg"],
                         "lds_per_msg": m["lds_per_msg"], "salu_issue_ms": salu_ms,
-                        "salu_issue_frac": salu_ms / kernel_ms}
+                        "salu_issue_frac": salu_ms / kernel_ms, "lds_issue_ms": lds_ms,
+                        "lds_issue_frac": lds_ms / kernel_ms}
     return None
 
 
-def cpu_baseline(w, stream, budget_s=15.0):
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Device-to-device copy bandwidth on this GPU (read + write bytes per second, GB/s)."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del src, dst
+    return 2 * nbytes * reps / (ms / 1e3) / 1e9
+
+
+def workload_figures(name: str, reps: int = 2) -> dict:
+    """Persistent-rollout throughput of another workload (all outputs written), plus the
+    oracle on one host thread over a bounded sample of its envs."""
+    import torch
+    from paper_2511_02136_amd import synth
+    from paper_2511_02136_amd.lob import LobEnv, DeviceStream
+    w = synth.WORKLOADS[name]
+    s = synth.generate(w)
+    cpu1 = cpu_baseline(w, s, budget_s=6.0, threads=1)
+    ds = DeviceStream.from_host(s)
+    n_msgs = s.n_msgs
+    book = {k: torch.from_numpy(v).cuda() for k, v in s.book.items()}
+    caps = s.caps
+    del s
+    env = LobEnv(caps, w.max_cap, w.agents, w.ep_len, w.seed)
+    toff = ds.trade_regions(env.caps, 0, w.n_steps, len(w.agents))
+    out = env._alloc_out(w.n_steps, True, True, toff, ds)
+    env.reset(book)
+    env.plan(ds, w.n_steps)
+    env.reset(book)
+    env.rollout(ds, w.n_steps, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        env.reset(book)
+        env.rollout(ds, w.n_steps, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    all_msgs = int(env.state()["counters"][:, 0].sum().item())
+    return {"workload": name, "n_envs": w.n_envs, "n_steps": w.n_steps, "replay_msgs": n_msgs,
+            "ms_per_rollout": ms, "msgs_per_s": n_msgs / (ms / 1e3),
+            "all_msgs_per_s": all_msgs / (ms / 1e3),
+            "env_steps_per_s": w.n_envs * w.n_steps / (ms / 1e3), "cpu_oracle_1thread": cpu1}
+
+
+def cpu_baseline(w, stream, budget_s=15.0, threads=None):
     """The CPU oracle on a bounded sample of the same workload (first envs, all steps)."""
     import oracle
     from paper_2511_02136_amd import synth
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from helpers import subset_stream
-    threads = max(1, min(16, os.cpu_count() or 1))
-    n = 64
+    if threads is None:
+        threads = max(1, min(16, os.cpu_count() or 1))
+    n = min(w.n_envs, 64 if threads > 1 else 4)
     while True:
         envs = np.arange(n)
         hs, book, caps = subset_stream(stream, envs)
@@ -184,6 +240,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-step form")
     ap.add_argument("--no-ippo", action="store_true", help="skip the IPPO rollout/update figures")
+    ap.add_argument("--configs", default="",
+                    help="comma-separated extra workloads to report (e.g. replay1,uniform4096,large16384)")
     ap.add_argument("--ippo-only", action="store_true",
                     help="only the IPPO figures (profiling aid; prints them as one JSON object)")
     ap.add_argument("--tune", action="store_true", help="run the schedule autotuner before timing")
@@ -252,7 +310,9 @@ def main():
     ms_step = wall * 1e3 / args.steps
     kernel_ms = float(np.mean([mids[k].elapsed_time(ends[k]) for k in range(args.steps)]))
 
+    median_ms = float(np.median([starts[k].elapsed_time(ends[k]) for k in range(args.steps)]))
     n_msgs = s.n_msgs
+    all_msgs = int(env.state()["counters"][:, 0].sum().item())  # every processed message, agents' too
     n_trades = int(out["n_trades"].sum().item())
     book_slots = int(s.book["n"].sum()) + int(env.books()["n"].sum().item())
     book_slots //= 2
@@ -288,6 +348,9 @@ def main():
         parity = "bit-exact on 4 sampled envs"
     except AssertionError as ex:
         parity = f"MISMATCH: {ex}"
+
+    copy_gbs = copy_bandwidth()
+    traffic = measured_traffic(w.name)
 
     plain = plain_padded = None
     if not args.no_plain:
@@ -340,6 +403,17 @@ def main():
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w, s)
+        one = cpu_baseline(w, s, budget_s=8.0, threads=1)
+        cpu["one_thread"] = {"value": one["value"], "sample": one["sample"]}
+        cpu["host_cpus"] = os.cpu_count()
+
+    extra = None
+    if args.configs:
+        extra = []
+        for name in [c for c in args.configs.split(",") if c]:
+            print(f"[bench] workload {name}", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+            extra.append(workload_figures(name))
 
     line = {
         "metric": "MBO messages/sec and env-steps/sec at 8192 envs, bit-exact vs oracle",
@@ -358,6 +432,8 @@ def main():
                                f"{w.n_steps} steps, agents exec+mm, random policy",
                    "n_envs": w.n_envs, "n_steps": w.n_steps, "n_msgs": n_msgs},
         "env_steps_per_s": steps_per_s,
+        "all_msgs_per_s": all_msgs / (ms_step / 1e3),
+        "median_ms_per_step": median_ms,
         "trades": n_trades,
         "parity": parity,
         "schedule": schedule,
@@ -365,11 +441,14 @@ def main():
         "plain_padded": plain_padded,
         "ippo": ippo_res,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_gbs": None if traffic is None else traffic / (kernel_ms / 1e3) / 1e9,
+                     "copy_gbs": copy_gbs, "frac_vs_copy": achieved / copy_gbs,
                      "kernel": "k_env (persistent rollout, all capacity classes)",
                      "kernel_ms": kernel_ms, "algorithmic_bytes": alg,
                      "scalar_issue": measured_issue(w.name, n_msgs, kernel_ms)},
         "cpu_baseline": cpu,
+        "other_workloads": extra,
     }
     print(json.dumps(line), flush=True)
 
