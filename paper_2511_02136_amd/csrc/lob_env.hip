@@ -1023,6 +1023,7 @@ struct CapClass {
 
 constexpr int MAX_CLASSES = LOB_MAX_CAP / 64; /* one class per row count */
 constexpr size_t LDS_PER_CU = 160 * 1024;  /* gfx950 */
+constexpr int CONC_LANES = 3;               /* concurrent class launches (see launch_env) */
 constexpr int WAVES_PER_CU = 24;            /* 6 per SIMD at the env kernel's register use */
 
 struct lob_ctx {
@@ -1165,12 +1166,12 @@ int launch_class(lob_ctx *c, size_t k, KArgs a, hipStream_t st) {
     return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
 }
 
-/* Launch every class concurrently.  A process has few hardware queues (4 by default) and
- * streams beyond them share queues, serialising their kernels; so the classes go to at
- * most CONC_LANES lanes: lane 0 is the caller's stream, lanes 1.. are forked streams
- * joined back with events.  Classes are dealt to the lanes largest books first; classes
- * sharing a lane run one after the other. */
-constexpr int CONC_LANES = 4;
+/* Launch every class concurrently: lane 0 is the caller's stream, lanes 1.. are forked
+ * streams joined back with events.  A process has few hardware queues (4 by default, one
+ * of them taken by other work in practice) and streams beyond them share queues,
+ * serialising their kernels; so there are at most CONC_LANES lanes, and classes are
+ * merged to at most that many (build_classes).  Classes are dealt to the lanes largest
+ * books first; classes sharing a lane would run one after the other. */
 int launch_env(lob_ctx *c, KArgs a, hipStream_t st) {
     const int nc = (int)c->classes.size();
     const int lanes = std::min(nc, CONC_LANES);
@@ -1217,18 +1218,41 @@ int build_classes(lob_ctx *c, bool padded) {
     std::sort(uniq.begin(), uniq.end());
     uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
     if (uniq.size() > (size_t)MAX_CLASSES) return LOB_EUNSUPPORTED;
+    /* groups of row counts: start with one group per row count, then merge the adjacent
+     * pair whose merge adds the least LDS (the smaller group's envs sized for the larger
+     * capacity) until at most CONC_LANES groups remain, so every class runs concurrently */
+    struct Grp { int lo, hi, count, capp; };
+    std::vector<Grp> g;
+    for (int r : uniq) {
+        Grp x{r, r, 0, 0};
+        for (int e = 0; e < N; ++e)
+            if (rows[(size_t)e] == r) { x.count++; x.capp = std::max(x.capp, c->caps[(size_t)e]); }
+        g.push_back(x);
+    }
+    const int A = c->cfg.n_agents;
+    while ((int)g.size() > CONC_LANES) {
+        size_t bi = 0;
+        int64_t bcost = -1;
+        for (size_t i = 0; i + 1 < g.size(); ++i) {
+            const int64_t cost = (int64_t)g[i].count * (lds_words_for(g[i + 1].capp, A) - lds_words_for(g[i].capp, A));
+            if (bcost < 0 || cost < bcost) { bcost = cost; bi = i; }
+        }
+        g[bi + 1].lo = g[bi].lo;
+        g[bi + 1].count += g[bi].count;
+        g.erase(g.begin() + (std::ptrdiff_t)bi);
+    }
     c->classes.clear();
     c->env_list.clear();
-    for (int r : uniq) {
-        CapClass cl{r, 0, (int)c->env_list.size(), 0, 1, 0, 0};
+    for (const Grp &x : g) {
+        CapClass cl{0, 0, (int)c->env_list.size(), 0, 1, 0, 0};
         for (int e = 0; e < N; ++e)
-            if (rows[(size_t)e] == r) {
+            if (rows[(size_t)e] >= x.lo && rows[(size_t)e] <= x.hi) {
                 c->env_list.push_back(e);
                 cl.count++;
                 cl.capp = std::max(cl.capp, c->caps[(size_t)e]);
             }
         cl.rows = rows_for_cap(cl.capp);
-        cl.waves = default_waves(cl.capp, c->cfg.n_agents);
+        cl.waves = default_waves(cl.capp, A);
         c->classes.push_back(cl);
     }
     for (size_t k = 0; k < c->classes.size(); ++k) {
