@@ -120,6 +120,37 @@ struct KArgs {
 };
 
 /* ------------------------------------------------------------------------------
+ * A chunk of up to 64 messages staged in registers, message k in lane k: the dispatch
+ * code (below) and price, qty, oid, tid, tsec, tns.  Fields of message j are read into
+ * scalar registers where a handler needs them.
+ * ---------------------------------------------------------------------------- */
+/* dispatch code: side in bit 0, operation above it */
+enum { OP_LIMIT = 0, OP_DELETE = 2, OP_PCANCEL = 4, OP_MARKET = 6, OP_BAD = 8 };
+/* Sec. 4 step 4 message semantics: a delete ignores its quantity; a limit, market or
+ * partial cancel needs a positive one; other types are invalid */
+__device__ __forceinline__ int op_code(int ts, int qty) {
+    const int type = ts & 0xFF;
+    int op = OP_BAD;
+    if (type == T_LIMIT) op = OP_LIMIT;
+    if (type == T_DELETE) op = OP_DELETE;
+    if (type == T_PCANCEL) op = OP_PCANCEL;
+    if (type == T_MARKET) op = OP_MARKET;
+    if (qty <= 0 && type != T_DELETE) op = OP_BAD;
+    return op | ((ts >> 8) & 1);
+}
+struct Staged {
+    int c[7] = {0, 0, 0, 0, 0, 0, 0};
+    int j = 0;
+    __device__ __forceinline__ int code() const { return rdlane(c[0], j); }
+    __device__ __forceinline__ int price() const { return rdlane(c[1], j); }
+    __device__ __forceinline__ int qty() const { return rdlane(c[2], j); }
+    __device__ __forceinline__ int oid() const { return rdlane(c[3], j); }
+    __device__ __forceinline__ int tid() const { return rdlane(c[4], j); }
+    __device__ __forceinline__ int tsec() const { return rdlane(c[5], j); }
+    __device__ __forceinline__ int tns() const { return rdlane(c[6], j); }
+};
+
+/* ------------------------------------------------------------------------------
  * One environment run by one wavefront.
  * ---------------------------------------------------------------------------- */
 struct Run {
@@ -132,6 +163,11 @@ struct Run {
     /* per step, hot */
     int64_t mid_sum, st_buy, st_sell;
     int32_t mid_n, seq, st_last, last_tsec, last_tns;
+    /* mid statistics run-length encoded: the messages since index mid_at all leave the
+     * book with the same touch, contributing mid_c (best bid + best ask, or 0 when a side
+     * is empty) and mid_f (1, or 0 when a side is empty) each */
+    int64_t mid_c;
+    int32_t mid_f, mid_at;
     /* trade records: this launch's part of the env's region starts at tr_base; records
      * produced so far in the launch, room left in the region, value at step start */
     int32_t *tr_base;
@@ -141,7 +177,8 @@ struct Run {
     int64_t ctr;
 
     __device__ Run(const KArgs &args, int32_t *lds, int env)
-        : a(args), L(lds), lane(lane_id()), capp(uni(args.capp)), e(uni(env)), A(args.n_agents) {
+        : a(args), L(lds), lane(lane_id()), capp(uni(args.capp)), e(uni(env)), A(args.n_agents),
+          n0(0), n1(0), best0(0), best1(0), mid_sum(0), mid_n(0), seq(0), mid_c(0), mid_f(0), mid_at(0) {
         Pl = reinterpret_cast<int2 *>(lds) + lane * REC;
         cap = uni(a.caps[e]);
     }
@@ -182,6 +219,20 @@ struct Run {
     template <int S> __device__ __forceinline__ void refresh_bestS() {
         const int n = nS<S>();
         bestS<S>() = n > 0 ? uni(US<S>(0, n - 1).x) : 0;
+        touch_changed();
+    }
+    /* the touch (best prices, or a side's emptiness) may have changed during message seq:
+     * the messages of the closed run contribute the previous touch */
+    __device__ __forceinline__ void mid_flush() {
+        const int len = seq - mid_at;
+        mid_sum += mid_c * len;
+        mid_n += mid_f * len;
+        mid_at = seq;
+    }
+    __device__ __forceinline__ void touch_changed() {
+        mid_flush();
+        mid_f = min(n0, n1) > 0 ? 1 : 0;
+        mid_c = mid_f ? (int64_t)best0 + best1 : 0;
     }
 
     /* ---- searches: rows from the top of the book down, stopping at the first hit ---- */
@@ -335,13 +386,13 @@ struct Run {
      * better price); a full side evicts its worst order if the price is strictly
      * better than that order's, else the remainder is dropped. ---- */
     template <int S>
-    __device__ __forceinline__ void rest(int p, int q, int oid, int tid, int ts, int tn) {
+    __device__ __forceinline__ void rest(int p, int q, int oid, int tid, const Staged &m) {
         const int n = nS<S>();
         const int kp = p ^ km(S);
         const int cnt = count_ahead<S>(n, kp);
         const int ins = n - cnt;
         if (n < cap) {
-            insert_at<S>(ins, n, make_int2(p, q), make_int2(oid, tid), make_int2(ts, tn));
+            insert_at<S>(ins, n, make_int2(p, q), make_int2(oid, tid), make_int2(m.tsec(), m.tns()));
             nS<S>() = n + 1;
         } else {
             const int2 w = US<S>(0, 0);
@@ -353,9 +404,12 @@ struct Run {
             }
             count(C_EVICT, 1);
             count(C_EVICTED_QTY, uni(w.y));
-            evict_insert<S>(ins, make_int2(p, q), make_int2(oid, tid), make_int2(ts, tn));
+            evict_insert<S>(ins, make_int2(p, q), make_int2(oid, tid), make_int2(m.tsec(), m.tns()));
         }
-        if (cnt == 0) bestS<S>() = p;
+        if (cnt == 0) {
+            bestS<S>() = p;
+            touch_changed();
+        }
     }
 
     /* ---- cancels: the first order with this id (priority order) on side S ---- */
@@ -381,46 +435,42 @@ struct Run {
         if (k == n - 1) refresh_bestS<S>();
     }
 
-    /* ---- one message of the step sequence ---- */
-    /* each test a single comparison (compound conditions on uniform values cost lane-mask
-     * arithmetic) */
-    template <int S>
-    __device__ __forceinline__ void process_side(int type, int price, int qty, int oid, int tid, int tsec, int tns) {
-        if ((unsigned)(type - T_PCANCEL) < 2u) {
-            if (type == T_DELETE) {
-                cancel<S, false>(qty, oid);
-            } else if (qty > 0) {
-                cancel<S, true>(qty, oid);
+    /* ---- one message of the step sequence: m.code says which handler (the operation
+     * and side, with invalid messages already folded into OP_BAD); each test is a single
+     * comparison of that uniform code ---- */
+    template <int S> __device__ __forceinline__ void limit(const Staged &m) {
+        const int price = m.price(), qty = m.qty(), oid = m.oid(), tid = m.tid();
+        const int q = match<S, false>(price, qty, oid, tid);
+        if (q > 0) rest<S>(price, q, oid, tid, m);
+    }
+    template <int S> __device__ __forceinline__ void market(const Staged &m) {
+        const int q = match<S, true>(0, m.qty(), m.oid(), m.tid());
+        if (q > 0) count(C_MARKET_UNFILLED, q);
+    }
+    __device__ __forceinline__ void process(const Staged &m) {
+        const int code = m.code();
+        if (code < OP_DELETE) {
+            if (code == OP_LIMIT) limit<0>(m);
+            else limit<1>(m);
+        } else if (code < OP_MARKET) {
+            if (code < OP_PCANCEL) {
+                if (code == OP_DELETE) cancel<0, false>(0, m.oid());
+                else cancel<1, false>(0, m.oid());
             } else {
-                count(C_BAD, 1);
+                if (code == OP_PCANCEL) cancel<0, true>(m.qty(), m.oid());
+                else cancel<1, true>(m.qty(), m.oid());
             }
-        } else if (qty <= 0) {
-            count(C_BAD, 1);
-        } else if (type == T_LIMIT) {
-            const int q = match<S, false>(price, qty, oid, tid);
-            if (q > 0) rest<S>(price, q, oid, tid, tsec, tns);
-        } else if (type == T_MARKET) {
-            const int q = match<S, true>(price, qty, oid, tid);
-            if (q > 0) count(C_MARKET_UNFILLED, q);
+        } else if (code < OP_BAD) {
+            if (code == OP_MARKET) market<0>(m);
+            else market<1>(m);
         } else {
             count(C_BAD, 1);
         }
-    }
-    __device__ __forceinline__ void process(int ts, int price, int qty, int oid, int tid, int tsec, int tns) {
-        const int type = ts & 0xFF;
-        if (ts & 0x100) process_side<1>(type, price, qty, oid, tid, tsec, tns);
-        else process_side<0>(type, price, qty, oid, tid, tsec, tns);
         after_message();
     }
-    /* per message of the sequence: mid statistics for the reward (both sides non-empty)
-     * and the message index */
-    __device__ __forceinline__ void after_message() {
-        if (min(n0, n1) > 0) {
-            mid_sum += (int64_t)best0 + best1;
-            mid_n += 1;
-        }
-        seq += 1;
-    }
+    /* per message of the sequence: the message index (the mid statistics follow the
+     * touch, see touch_changed) */
+    __device__ __forceinline__ void after_message() { seq += 1; }
 
     /* ---- desired levels of agent ai (LDS, written by lane 0) ---- */
     __device__ __forceinline__ void add_level(int ai, int &nlv, int side, int price, int qty) {
@@ -731,7 +781,8 @@ struct Run {
     /* ---- one env-step (Sec. 4 steps 1-5) writing output slot s_idx ---- */
     __device__ __forceinline__ void step(int s_idx) {
         const int N = a.n_envs;
-        mid_sum = 0; mid_n = 0; seq = 0;
+        mid_sum = 0; mid_n = 0; seq = 0; mid_at = 0;
+        touch_changed();
         st_buy = 0; st_sell = 0; st_last = 0;
         tr_step0 = tr_next;
         if (lane < A * 4) FL(0)[lane] = 0;
@@ -783,34 +834,37 @@ struct Run {
         const int64_t *row = a.m_off + (int64_t)e * (a.m_steps + 1);
         const int64_t lo = uni64(row[t]);
         const int nrep = (int)(uni64(row[t + 1]) - lo);
-        int c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0;
+        Staged m;
         if (lane < nact) {
-            const int32_t *m = X() + xl().act + X()[xl().perm + lane] * 8;
-            c0 = m[0]; c1 = m[1]; c2 = m[2]; c3 = m[3]; c4 = m[4]; c5 = m[5]; c6 = m[6];
+            const int32_t *x = X() + xl().act + X()[xl().perm + lane] * 8;
+            m.c[0] = x[0]; m.c[1] = x[1]; m.c[2] = x[2]; m.c[3] = x[3]; m.c[4] = x[4]; m.c[5] = x[5]; m.c[6] = x[6];
         }
         int cnt = nact, base = -WAVE;
         for (;;) {
-            for (int rj = 0; rj < cnt; ++rj)
-                process(rdlane(c0, rj), rdlane(c1, rj), rdlane(c2, rj), rdlane(c3, rj), rdlane(c4, rj),
-                        rdlane(c5, rj), rdlane(c6, rj));
+            /* everything the chunk loaded has arrived before the first message is read
+             * (so no per-message waits on it) */
+            __builtin_amdgcn_s_waitcnt(0);
+            m.c[0] = op_code(m.c[0], m.c[2]);
+            for (m.j = 0; m.j < cnt; ++m.j) process(m);
             base += WAVE;
             if (base >= nrep) break;
             const int nx = base + lane;
             if (nx < nrep) {
                 const int64_t g = lo + nx;
-                c0 = a.m_ts[g]; c1 = a.m_price[g]; c2 = a.m_qty[g]; c3 = a.m_oid[g];
-                c4 = a.m_tid[g]; c5 = a.m_tsec[g]; c6 = a.m_tns[g];
+                m.c[0] = a.m_ts[g]; m.c[1] = a.m_price[g]; m.c[2] = a.m_qty[g]; m.c[3] = a.m_oid[g];
+                m.c[4] = a.m_tid[g]; m.c[5] = a.m_tsec[g]; m.c[6] = a.m_tns[g];
             }
             cnt = min(WAVE, nrep - base);
         }
         /* the last processed time: agent messages carry the previous one, so it changes
          * only with a replayed message */
         if (nrep > 0) {
-            last_tsec = rdlane(c5, cnt - 1);
-            last_tns = rdlane(c6, cnt - 1);
+            last_tsec = rdlane(m.c[5], cnt - 1);
+            last_tns = rdlane(m.c[6], cnt - 1);
         }
 
         /* step 5: outcomes */
+        mid_flush();
         int64_t *E = ENV();
         const int64_t mid2_prev = uni64(E[2]), p_init2 = uni64(E[3]);
         const int bb1 = n0 > 0 ? best0 : (int)uni64(E[0]);
