@@ -33,6 +33,18 @@ __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)
 /* the comparison's lane mask itself (no round trip through an int predicate) */
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+/* lane masks of a comparison (bit l = lane l); every lane of the wave is active where
+ * these are used */
+__device__ __forceinline__ uint64_t lanes_eq(int a, int b) { return __builtin_amdgcn_sicmp(a, b, 32); }
+__device__ __forceinline__ uint64_t lanes_gt(int a, int b) { return __builtin_amdgcn_sicmp(a, b, 38); }
+__device__ __forceinline__ uint64_t lanes_ge(int a, int b) { return __builtin_amdgcn_sicmp(a, b, 39); }
+__device__ __forceinline__ uint64_t lanes_lt(int a, int b) { return __builtin_amdgcn_sicmp(a, b, 40); }
+__device__ __forceinline__ uint64_t lanes_le(int a, int b) { return __builtin_amdgcn_sicmp(a, b, 41); }
+
+/* lane l takes lane l + 1's value (lane 63 takes 0): the whole-wave DPP shift */
+__device__ __forceinline__ int shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
+__device__ __forceinline__ int2 shl1(int2 v) { return make_int2(shl1(v.x), shl1(v.y)); }
+
 __device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
 __device__ __forceinline__ int64_t rdlane64(int64_t v, int l) {

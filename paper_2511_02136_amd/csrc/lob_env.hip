@@ -156,7 +156,6 @@ struct Staged {
 struct Run {
     const KArgs &a;
     int32_t *L;  /* this wave's LDS (uniform) */
-    int2 *Pl;    /* this lane's record in row 0 of side 0 */
     int lane, cap, capp, e, A, t;
     /* book: live orders and best price per side */
     int n0, n1, best0, best1;
@@ -179,7 +178,6 @@ struct Run {
     __device__ Run(const KArgs &args, int32_t *lds, int env)
         : a(args), L(lds), lane(lane_id()), capp(uni(args.capp)), e(uni(env)), A(args.n_agents),
           n0(0), n1(0), best0(0), best1(0), mid_sum(0), mid_n(0), seq(0), mid_c(0), mid_f(0), mid_at(0) {
-        Pl = reinterpret_cast<int2 *>(lds) + lane * REC;
         cap = uni(a.caps[e]);
     }
 
@@ -211,7 +209,6 @@ struct Run {
     }
     /* prices of side S compare as (price ^ km(S)): "equal or better" is "<=" for both */
     static constexpr int km(int s) { return s == 0 ? -1 : 0; }
-    template <int S> __device__ __forceinline__ int2 *SBS() { return S == 0 ? Pl : Pl + capp * REC; }
     template <int S> __device__ __forceinline__ int2 &US(int p, int i) {
         int2 *base = reinterpret_cast<int2 *>(L) + (S == 0 ? 0 : capp * REC);
         return base[i * REC + p];
@@ -235,76 +232,104 @@ struct Run {
         mid_c = mid_f ? (int64_t)best0 + best1 : 0;
     }
 
-    /* ---- searches: rows from the top of the book down, stopping at the first hit ---- */
+    /* record i of side S (any index; the side's base is uniform) */
+    template <int S> __device__ __forceinline__ int2 *RS(int i) {
+        return reinterpret_cast<int2 *>(L) + (S * capp + i) * REC;
+    }
+    /* lanes whose price x is equal to or better than p on side S */
+    template <int S> __device__ __forceinline__ uint64_t better_eq(int x, int p) {
+        return S == 0 ? lanes_ge(x, p) : lanes_le(x, p);
+    }
+
+    /* ---- searches: rows from the top of the book down, stopping at the first hit.  Every
+     * lane loads (indices clamped into the live range) and the lane range is a mask, so a
+     * row costs one LDS load and no branches on the execution mask. ---- */
     /* highest record <= hi of side S whose field f (FO or FT) equals v, or -1; for oids
      * this is the first order with that id in priority order */
     template <int S> __device__ __forceinline__ int find_top(int f, int hi, int v) {
-        const int32_t *col = reinterpret_cast<const int32_t *>(SBS<S>()) + f;
+        const int32_t *col = reinterpret_cast<const int32_t *>(RS<S>(0)) + f;
         for (int r = hi >> 6; r >= 0; --r) {
             const int j = (r << 6) + lane;
-            const int x = col[r * (WAVE * 2 * REC)];
-            const uint64_t m = ballot(j <= hi && x == v);
+            const int x = col[min(j, hi) * (2 * REC)];
+            const uint64_t m = lanes_eq(x, v) & lanes_le(j, hi);
             if (m) return (r << 6) + 63 - __builtin_clzll(m);
         }
         return -1;
     }
-    /* orders of side S (n live) whose price is equal to or better than the one with key
-     * kp (= price ^ km(S)): they are the top records of the side */
-    template <int S> __device__ __forceinline__ int count_ahead(int n, int kp) {
-        const int32_t *col = reinterpret_cast<const int32_t *>(SBS<S>());
+    /* orders equal to or better than price p in the full rows r, r-1, ..., 0 of side S,
+     * counted from the top while whole rows are */
+    template <int S> __device__ __forceinline__ int count_rows(int r, int p) {
         int cnt = 0;
-        for (int r = (n - 1) >> 6; r >= 0; --r) {
-            const int j = (r << 6) + lane;
-            const int x = col[r * (WAVE * 2 * REC)];
-            const int c = __popcll(ballot(j < n && (x ^ km(S)) <= kp));
+        for (; r >= 0; --r) {
+            const int c = __popcll(better_eq<S>(RS<S>((r << 6) + lane)->x, p));
             cnt += c;
-            if (c < min(WAVE, n - (r << 6))) break;
+            if (c < WAVE) break;
         }
         return cnt;
     }
+    /* orders of side S (n live) whose price is equal to or better than p: they are the
+     * top records of the side */
+    template <int S> __device__ __forceinline__ int count_ahead(int n, int p) {
+        if (n == 0) return 0;
+        const int rt = (n - 1) >> 6, top = n - (rt << 6);
+        const int x = RS<S>(min((rt << 6) + lane, n - 1))->x;
+        const int c = __popcll(better_eq<S>(x, p) & lanes_lt(lane, top));
+        return c < top ? c : c + count_rows<S>(rt - 1, p);
+    }
 
     /* ---- book edits: one pass over the rows they touch, loads of a row before its
-     * stores; each lane moves its own record ---- */
-    /* records [ins, n) of side S move up by one; the new order takes record ins (n < capp) */
-    template <int S> __device__ __forceinline__ void insert_at(int ins, int n, int2 v0, int2 v1, int2 v2) {
-        int2 *B = SBS<S>();
-        for (int r = n >> 6; r >= (ins >> 6); --r) {
+     * stores; each lane moves one record ---- */
+    /* rows r0 down to (ins >> 6): record j (ins < j, and j <= n in row r0) takes record j - 1 */
+    template <int S> __device__ __forceinline__ void shift_up_rows(int r0, int ins) {
+        for (int r = r0; r >= (ins >> 6); --r) {
             const int j = (r << 6) + lane;
-            int2 *d = B + r * (WAVE * REC);
-            int2 x0 = v0, x1 = v1, x2 = v2;
-            if (j > ins && j <= n) { x0 = d[-3]; x1 = d[-2]; x2 = d[-1]; }
+            const int2 *src = RS<S>(max(j - 1, 0));
+            const int2 x0 = src[0], x1 = src[1], x2 = src[2];
             WAVE_SYNC();
-            if (j >= ins && j <= n) { d[0] = x0; d[1] = x1; d[2] = x2; }
+            if (j > ins) {
+                int2 *d = RS<S>(j);
+                d[0] = x0; d[1] = x1; d[2] = x2;
+            }
             WAVE_SYNC();
         }
+    }
+    /* one record written by lane 0 */
+    template <int S> __device__ __forceinline__ void put(int i, int2 v0, int2 v1, int2 v2) {
+        if (lane == 0) {
+            int2 *d = RS<S>(i);
+            d[0] = v0; d[1] = v1; d[2] = v2;
+        }
+        WAVE_SYNC();
     }
     /* record k of side S (n live) leaves: [k+1, n) moves down by one */
     template <int S> __device__ __forceinline__ void remove_at(int k, int n) {
-        int2 *B = SBS<S>();
         for (int r = k >> 6; r <= (n - 2) >> 6; ++r) {
             const int j = (r << 6) + lane;
-            int2 *d = B + r * (WAVE * REC);
-            const bool mv = j >= k && j < n - 1;
-            int2 x0 = make_int2(0, 0), x1 = x0, x2 = x0;
-            if (mv) { x0 = d[3]; x1 = d[4]; x2 = d[5]; }
+            const int2 *src = RS<S>(min(j + 1, n - 1));
+            const int2 x0 = src[0], x1 = src[1], x2 = src[2];
             WAVE_SYNC();
-            if (mv) { d[0] = x0; d[1] = x1; d[2] = x2; }
+            if ((unsigned)(j - k) < (unsigned)(n - 1 - k)) {
+                int2 *d = RS<S>(j);
+                d[0] = x0; d[1] = x1; d[2] = x2;
+            }
             WAVE_SYNC();
         }
     }
-    /* full side: the worst order (record 0) leaves, [1, ins) moves down by one and the
-     * new order takes record ins - 1 (ins >= 1) */
+    /* full side (n = cap): the worst order (record 0) leaves, [1, ins) moves down by one and
+     * the new order takes record ins - 1 (ins >= 1) */
     template <int S> __device__ __forceinline__ void evict_insert(int ins, int2 v0, int2 v1, int2 v2) {
-        int2 *B = SBS<S>();
         for (int r = 0; r <= (ins - 1) >> 6; ++r) {
             const int j = (r << 6) + lane;
-            int2 *d = B + r * (WAVE * REC);
-            int2 x0 = v0, x1 = v1, x2 = v2;
-            if (j < ins - 1) { x0 = d[3]; x1 = d[4]; x2 = d[5]; }
+            const int2 *src = RS<S>(min(j + 1, ins - 1));
+            const int2 x0 = src[0], x1 = src[1], x2 = src[2];
             WAVE_SYNC();
-            if (j < ins) { d[0] = x0; d[1] = x1; d[2] = x2; }
+            if (j < ins - 1) {
+                int2 *d = RS<S>(j);
+                d[0] = x0; d[1] = x1; d[2] = x2;
+            }
             WAVE_SYNC();
         }
+        put<S>(ins - 1, v0, v1, v2);
     }
 
     /* ---- fills (uniform accumulation in LDS by lane 0) ---- */
@@ -388,23 +413,44 @@ struct Run {
     template <int S>
     __device__ __forceinline__ void rest(int p, int q, int oid, int tid, const Staged &m) {
         const int n = nS<S>();
-        const int kp = p ^ km(S);
-        const int cnt = count_ahead<S>(n, kp);
-        const int ins = n - cnt;
+        int cnt;
         if (n < cap) {
-            insert_at<S>(ins, n, make_int2(p, q), make_int2(oid, tid), make_int2(m.tsec(), m.tns()));
+            if (n > 0) {
+                /* the top row of the insertion, rt = n >> 6, loaded once: lane l holds
+                 * record j - 1 for j = 64 rt + l (clamped into the live range).  Lanes 1..top
+                 * hold the row's live records, so they also give the count from the top. */
+                const int rt = n >> 6, top = n - (rt << 6);
+                const int j = (rt << 6) + lane;
+                const int2 *src = RS<S>(min(max(j - 1, 0), n - 1));
+                const int2 y0 = src[0], y1 = src[1], y2 = src[2];
+                cnt = __popcll(better_eq<S>(y0.x, p) & lanes_gt(lane, 0) & lanes_le(lane, top));
+                if (cnt == top) cnt += count_rows<S>(rt - 1, p);
+                const int ins = n - cnt;
+                WAVE_SYNC();
+                if ((unsigned)(j - ins - 1) < (unsigned)(n - ins)) {
+                    int2 *d = RS<S>(j);
+                    d[0] = y0; d[1] = y1; d[2] = y2;
+                }
+                WAVE_SYNC();
+                shift_up_rows<S>(rt - 1, ins);
+                put<S>(ins, make_int2(p, q), make_int2(oid, tid), make_int2(m.tsec(), m.tns()));
+            } else {
+                cnt = 0;
+                put<S>(0, make_int2(p, q), make_int2(oid, tid), make_int2(m.tsec(), m.tns()));
+            }
             nS<S>() = n + 1;
         } else {
-            const int2 w = US<S>(0, 0);
+            const int2 w = *RS<S>(0);
             const int wp = uni(w.x);
-            if (kp >= (wp ^ km(S))) {
+            if ((p ^ km(S)) >= (wp ^ km(S))) {
                 count(C_DROP, 1);
                 count(C_DROPPED_QTY, q);
                 return;
             }
             count(C_EVICT, 1);
             count(C_EVICTED_QTY, uni(w.y));
-            evict_insert<S>(ins, make_int2(p, q), make_int2(oid, tid), make_int2(m.tsec(), m.tns()));
+            cnt = count_ahead<S>(n, p);
+            evict_insert<S>(n - cnt, make_int2(p, q), make_int2(oid, tid), make_int2(m.tsec(), m.tns()));
         }
         if (cnt == 0) {
             bestS<S>() = p;
@@ -412,25 +458,57 @@ struct Run {
         }
     }
 
-    /* ---- cancels: the first order with this id (priority order) on side S ---- */
+    /* ---- cancels: the first order with this id (priority order) on side S.  The top row
+     * is loaded whole; a hit there is removed from registers (each lane takes the record
+     * of the lane above it), deeper hits search and shift row by row. ---- */
     template <int S, bool PARTIAL>
     __device__ __forceinline__ void cancel(int qty, int oid) {
         const int n = nS<S>();
-        const int k = find_top<S>(FO, n - 1, oid);
-        if (k < 0) {
+        if (n == 0) {
             count(C_MISS, 1);
             return;
         }
-        if (PARTIAL) {
-            const int cq = uni(US<S>(0, k).y);
-            const int left = cq - min(qty, cq);
-            if (left > 0) {
-                if (lane == 0) US<S>(0, k).y = left;
-                WAVE_SYNC();
+        const int rt = (n - 1) >> 6;
+        const int j = (rt << 6) + lane;
+        const int2 *src = RS<S>(min(j, n - 1));
+        const int2 o0 = src[0], o1 = src[1], o2 = src[2];
+        const uint64_t mt = lanes_eq(o1.x, oid) & lanes_lt(j, n);
+        int k;
+        if (mt) {
+            k = (rt << 6) + 63 - __builtin_clzll(mt);
+            if (PARTIAL) {
+                const int cq = rdlane(o0.y, k & 63);
+                const int left = cq - min(qty, cq);
+                if (left > 0) {
+                    if (lane == 0) RS<S>(k)->y = left;
+                    WAVE_SYNC();
+                    return;
+                }
+            }
+            const int2 u0 = shl1(o0), u1 = shl1(o1), u2 = shl1(o2);
+            WAVE_SYNC();
+            if ((unsigned)(j - k) < (unsigned)(n - 1 - k)) {
+                int2 *d = RS<S>(j);
+                d[0] = u0; d[1] = u1; d[2] = u2;
+            }
+            WAVE_SYNC();
+        } else {
+            k = find_top<S>(FO, (rt << 6) - 1, oid);
+            if (k < 0) {
+                count(C_MISS, 1);
                 return;
             }
+            if (PARTIAL) {
+                const int cq = uni(RS<S>(k)->y);
+                const int left = cq - min(qty, cq);
+                if (left > 0) {
+                    if (lane == 0) RS<S>(k)->y = left;
+                    WAVE_SYNC();
+                    return;
+                }
+            }
+            remove_at<S>(k, n);
         }
-        remove_at<S>(k, n);
         nS<S>() = n - 1;
         if (k == n - 1) refresh_bestS<S>();
     }
