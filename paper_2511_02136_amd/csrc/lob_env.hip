@@ -54,7 +54,9 @@ constexpr int STW = 4;            /* step statistics: buy vol, sell vol, trades,
  *   perm 8A: shuffled order          lv   A x MAXLV x 4: side, price, desired, resting
  *   seen A x MAXLV: older resting qty seen in the walk      nlv  A: desired levels
  *   ag   int64 A x AGW: agent state  fl   int64 A x 4: fills of the step
- *   obk  int64 22 + 3A: depth buckets, totals, own stats    env  int64 8  st  int64 STW */
+ *   obk  int64 22 + 3A: depth buckets, totals, own stats (shares act's words: the
+ *        observation is built after the messages, the new orders before them)
+ *   env  int64 8  st  int64 STW */
 struct XL {
     int act, perm, lv, seen, nlv, ag, fl, obk, env, st, words;
 };
@@ -67,13 +69,14 @@ __host__ __device__ constexpr XL x_layout(int A) {
     x.nlv = x.seen + A * MAXLV;
     x.ag = (x.nlv + A + 1) & ~1;
     x.fl = x.ag + A * AGW * 2;
-    x.obk = x.fl + A * 4 * 2;
-    x.env = x.obk + (22 + 3 * A) * 2;
+    x.obk = x.act;
+    x.env = x.fl + A * 4 * 2;
     x.st = x.env + 8 * 2;
     x.words = x.st + STW * 2;
     return x;
 }
 static_assert(x_layout(MAXA).words < 1024, "extra LDS");
+static_assert((22 + 3 * 1) * 2 <= 8 * 1 * 8, "observation accumulators fit in the new-order block");
 
 __host__ __device__ constexpr int lds_words_for(int capp, int n_agents) {
     return 2 * NF * capp + x_layout(n_agents).words;
