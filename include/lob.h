@@ -153,8 +153,10 @@ int lob_rollout(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps, const int32
 
 /* Schedule plan for the next n_steps from the current step: orders each capacity
  * class's envs by decreasing message count (longest first), so that the envs that bound
- * the runtime start first.  Reads the CSR offsets back to the host (synchronous).  Used by
- * lob_step and lob_rollout until the next plan; results never depend on it. */
+ * the runtime start first; with several classes and a balance share set (the default,
+ * see lob_schedule_balance), it also sizes each class's work queue.  Reads the CSR
+ * offsets back to the host (synchronous).  Used by lob_step and lob_rollout until the
+ * next plan; results never depend on it. */
 int lob_plan(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps);
 
 /* The launch schedule, one record of 5 int32 per capacity class (host array):
@@ -166,8 +168,19 @@ int lob_plan(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps);
 int lob_schedule_get(const lob_ctx *ctx, int32_t *out, int32_t max_classes);
 
 /* Set class k's schedule (waves 1, 2 or 4; mode 0 or 1; grid >= 0).  LOB_EUNSUPPORTED
- * if the workgroup would need more than 64 KiB of LDS. */
+ * if the workgroup would need more than 64 KiB of LDS.  Turns the balance share off
+ * (lob_schedule_balance), so later plans keep the per-class schedules. */
 int lob_schedule_set(lob_ctx *ctx, int32_t k, int32_t waves, int32_t mode, int32_t grid);
+
+/* Schedule of several concurrent capacity classes.  permille in 1..1000: from the next
+ * plan on, every class runs as a work queue (mode 1) whose workgroups hold a number of
+ * envs proportional to the class's planned work (messages plus a fixed allowance per
+ * env-step), all classes together sized to permille/1000 of the chip's LDS, so that the
+ * classes finish together instead of the hardware dispatcher starving one of them
+ * (default 880).  permille = 0: every class returns to its default schedule (mode 0)
+ * and keeps whatever lob_schedule_set gives it.  A single class is never affected.
+ * LOB_EINVAL outside 0..1000; results never depend on it. */
+int lob_schedule_balance(lob_ctx *ctx, int32_t permille);
 
 /* Batching ablation.  padded = 1 puts every env into one class whose LDS books are
  * sized for the largest capacity (uniform padding, the batching a map over envs of
@@ -176,10 +189,12 @@ int lob_schedule_set(lob_ctx *ctx, int32_t k, int32_t waves, int32_t mode, int32
  * (host-synchronous); not callable during stream capture. */
 int lob_set_padded(lob_ctx *ctx, int32_t padded);
 
-/* Autotuner: times every schedule of every class on the next n_steps of msgs (one
- * class at a time, from the current state, restored afterwards) and keeps the fastest
- * per class.  Makes a plan first.  Synchronous; the buffers of `out` are overwritten
- * (scratch).  Allocates and frees temporary device memory for the state copy. */
+/* Autotuner: times schedules on the next n_steps of msgs from the current state
+ * (restored after every run) and keeps the fastest.  One class: every (waves, mode) of
+ * it.  Several classes (launched concurrently): the whole launch at balance shares 0,
+ * 800, 840, 880, 920 and 960 permille (lob_schedule_balance).  Makes a plan first.
+ * Synchronous; the buffers of `out` are overwritten (scratch).  Allocates and frees
+ * temporary device memory for the state copy. */
 int lob_autotune(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps, const lob_out *out, void *stream);
 
 /* Observation of the current state, device float [n_agents][n_envs][40] (equal to the

@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -1160,6 +1161,8 @@ constexpr int MAX_CLASSES = LOB_MAX_CAP / 64; /* one class per row count */
 constexpr size_t LDS_PER_CU = 160 * 1024;  /* gfx950 */
 constexpr int CONC_LANES = 3;               /* concurrent class launches (see launch_env) */
 constexpr int WAVES_PER_CU = 24;            /* 6 per SIMD at the env kernel's register use */
+constexpr int BALANCE_DEFAULT = 880;        /* permille of the LDS (measured best on uneven books) */
+constexpr int64_t STEP_ALLOWANCE = 8;       /* fixed per-env-step work, in messages */
 
 struct lob_ctx {
     lob_config cfg;
@@ -1183,6 +1186,10 @@ struct lob_ctx {
     int t = 0;
     bool reset_done = false;
     bool padded = false;
+    /* with several classes, the share of the chip's LDS (permille) that the proportional
+     * work-queue schedule gives the classes together; 0 = each class keeps its own
+     * schedule (see balance_classes) */
+    int balance = BALANCE_DEFAULT;
 };
 
 namespace {
@@ -1404,9 +1411,41 @@ int build_classes(lob_ctx *c, bool padded) {
     return LOB_OK;
 }
 
+/* Proportional work-queue schedule for several concurrent classes.  Left to the hardware
+ * dispatcher, the classes' workgroups compete for LDS as it frees and one class can be
+ * starved for most of the run, its long envs then forming a tail.  Instead each class
+ * runs as a work queue (mode 1) whose resident envs are proportional to the class's
+ * work, so that the classes finish together: work = planned messages plus a fixed
+ * allowance per env-step, and the classes together take `balance` permille of the
+ * chip's LDS (below 1000 to leave room for packing workgroups of different sizes). */
+void balance_classes(lob_ctx *c, const std::vector<int64_t> &a0, const std::vector<int64_t> &a1, int n) {
+    const int A = c->cfg.n_agents;
+    const size_t nc = c->classes.size();
+    std::vector<double> work(nc, 0.0);
+    double denom = 0.0;
+    for (size_t k = 0; k < nc; ++k) {
+        const CapClass &cl = c->classes[k];
+        for (int i = 0; i < cl.count; ++i) {
+            const size_t e = (size_t)c->env_list[(size_t)(cl.first + i)];
+            work[k] += (double)(a1[e] - a0[e] + STEP_ALLOWANCE * n);
+        }
+        denom += work[k] * (double)lds_words_for(cl.capp, A) * 4.0;
+    }
+    const double budget = (double)c->balance / 1000.0 * (double)LDS_PER_CU * (double)c->n_cu;
+    for (size_t k = 0; k < nc; ++k) {
+        CapClass &cl = c->classes[k];
+        cl.waves = default_waves(cl.capp, A);
+        const int most = (cl.count + cl.waves - 1) / cl.waves;
+        const double envs = denom > 0.0 ? budget * work[k] / denom : (double)cl.count;
+        cl.mode = 1;
+        cl.grid = std::max(1, std::min(most, (int)std::ceil(envs / cl.waves)));
+    }
+}
+
 /* Order each class's envs by decreasing message count over steps [t0, t0+n) (longest
- * first), so the envs that bound the runtime start first.  Reads two columns of the
- * CSR offsets back to the host (synchronous). */
+ * first), so the envs that bound the runtime start first; with several classes and a
+ * balance share set, size their work queues (balance_classes).  Reads two columns of
+ * the CSR offsets back to the host (synchronous). */
 int make_plan(lob_ctx *c, const lob_msgs *m, int t0, int n) {
     if (c->plan_off == m->off && c->plan_t0 == t0 && c->plan_steps == n) return LOB_OK;
     const int N = c->cfg.n_envs;
@@ -1421,6 +1460,7 @@ int make_plan(lob_ctx *c, const lob_msgs *m, int t0, int n) {
             return a1[(size_t)x] - a0[(size_t)x] > a1[(size_t)y] - a0[(size_t)y];
         });
     }
+    if (c->balance > 0 && c->classes.size() > 1) balance_classes(c, a0, a1, n);
     if (!hip_ok(hipMemcpy(c->d_env_list, c->env_list.data(), (size_t)N * 4, hipMemcpyHostToDevice)))
         return LOB_EHIP;
     c->plan_off = m->off;
@@ -1600,6 +1640,21 @@ int lob_schedule_set(lob_ctx *c, int32_t k, int32_t waves, int32_t mode, int32_t
     cl.waves = waves;
     cl.mode = mode;
     cl.grid = grid;
+    c->balance = 0; /* an explicit per-class schedule is kept by later plans */
+    return LOB_OK;
+}
+
+int lob_schedule_balance(lob_ctx *c, int32_t permille) {
+    if (!c || permille < 0 || permille > 1000) return LOB_EINVAL;
+    c->balance = permille;
+    if (permille == 0)
+        for (CapClass &cl : c->classes) {
+            cl.waves = default_waves(cl.capp, c->cfg.n_agents);
+            cl.mode = 0;
+            cl.grid = 0;
+        }
+    c->plan_off = nullptr; /* the next plan sizes the queues */
+    c->plan_t0 = c->plan_steps = -1;
     return LOB_OK;
 }
 
@@ -1609,9 +1664,11 @@ int lob_set_padded(lob_ctx *c, int32_t padded) {
     return build_classes(c, padded != 0);
 }
 
-/* Time every schedule candidate of every class on the next n_steps of `m` (one class
- * at a time, from the current state, which is restored afterwards) and keep the
- * fastest.  Results do not depend on the schedule.  Synchronous; `out` is scratch. */
+/* Time schedule candidates on the next n_steps of `m` from the current state (restored
+ * after every run) and keep the fastest.  One class: every (waves, mode) of it.  Several
+ * (concurrent) classes: the whole launch under the proportional work-queue schedule at
+ * several LDS shares, and under per-class hardware dispatch.  Results do not depend on
+ * the schedule.  Synchronous; `out` is scratch. */
 int lob_autotune(lob_ctx *c, const lob_msgs *m, int32_t n_steps, const lob_out *o, void *stream) {
     if (!c || n_steps <= 0) return LOB_EINVAL;
     if (!c->reset_done || c->t + n_steps > c->cfg.episode_len) return LOB_ESTATE;
@@ -1651,7 +1708,28 @@ int lob_autotune(lob_ctx *c, const lob_msgs *m, int32_t n_steps, const lob_out *
     fill_out(a, o);
     a.t0 = c->t;
     a.n_steps = n_steps;
-    for (size_t k = 0; k < c->classes.size() && rc == LOB_OK; ++k) {
+    if (c->classes.size() > 1) {
+        int best_b = c->balance;
+        float best = 1e30f;
+        for (int b : {0, 800, 840, 880, 920, 960}) {
+            if (rc != LOB_OK) break;
+            if ((rc = lob_schedule_balance(c, b)) != LOB_OK || (rc = make_plan(c, m, c->t, n_steps)) != LOB_OK)
+                break;
+            float ms = 0.f;
+            for (int rep = 0; rep < 2 && rc == LOB_OK; ++rep) {
+                restore();
+                (void)hipEventRecord(e0, st);
+                rc = launch_env(c, a, st);
+                (void)hipEventRecord(e1, st);
+                (void)hipEventSynchronize(e1);
+                (void)hipEventElapsedTime(&ms, e0, e1);
+            }
+            if (rc == LOB_OK && ms < best) { best = ms; best_b = b; }
+        }
+        if (rc == LOB_OK) rc = lob_schedule_balance(c, best_b);
+        if (rc == LOB_OK) rc = make_plan(c, m, c->t, n_steps);
+    }
+    for (size_t k = 0; k < c->classes.size() && c->classes.size() == 1 && rc == LOB_OK; ++k) {
         CapClass &cl = c->classes[k];
         const CapClass orig = cl;
         CapClass bestc = cl;

@@ -74,13 +74,14 @@ def lib():
         L.lob_schedule_get.argtypes = [p, p, i32]
         L.lob_schedule_set.argtypes = [p, i32, i32, i32, i32]
         L.lob_set_padded.argtypes = [p, i32]
+        L.lob_schedule_balance.argtypes = [p, i32]
         L.lob_autotune.argtypes = [p, ctypes.POINTER(_Msgs), i32, ctypes.POINTER(_Out), p]
         L.lob_destroy.argtypes = [p]
         L.lob_strerror.argtypes = [ctypes.c_int]
         L.lob_strerror.restype = ctypes.c_char_p
         for f in ("lob_init", "lob_reset", "lob_step", "lob_rollout", "lob_observe", "lob_export_books",
                   "lob_export_state", "lob_current_step", "lob_destroy", "lob_plan", "lob_schedule_get",
-                  "lob_schedule_set", "lob_set_padded", "lob_autotune"):
+                  "lob_schedule_set", "lob_set_padded", "lob_schedule_balance", "lob_autotune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -273,14 +274,20 @@ class LobEnv:
     def set_schedule(self, k: int, waves: int, mode: int, grid: int = 0):
         _check(self._lib.lob_schedule_set(self._h, k, waves, mode, grid), "lob_schedule_set")
 
+    def set_balance(self, permille: int):
+        """Proportional work-queue schedule of several concurrent classes sized to
+        permille/1000 of the LDS from the next plan on; 0 returns every class to its
+        default schedule (see lob_schedule_balance)."""
+        _check(self._lib.lob_schedule_balance(self._h, int(permille)), "lob_schedule_balance")
+
     def set_padded(self, padded: bool):
         """Batching ablation: one class padded to the largest capacity (True) or one
         class per book row count (False, the default).  Resets plan and schedules."""
         _check(self._lib.lob_set_padded(self._h, int(bool(padded))), "lob_set_padded")
 
     def autotune(self, dstream: DeviceStream, n_steps: int, out: Optional[dict] = None) -> list:
-        """Time every schedule candidate on the next n_steps (state restored) and keep the
-        fastest per class.  Returns the chosen schedule."""
+        """Time schedule candidates on the next n_steps (state restored) and keep the
+        fastest (see lob_autotune).  Returns the chosen schedule."""
         if out is None:
             out = self._alloc_out(n_steps, True, True, None, dstream)
         o = self._out_struct(out)

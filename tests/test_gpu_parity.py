@@ -336,6 +336,23 @@ def test_schedule_independence():
         gb = env.books()
         for key in gb:
             assert torch.equal(gb[key], ref_books[key]), (mode, waves, key)
+    # the proportional work-queue schedule of the concurrent classes, at several LDS
+    # shares (1 permille leaves a few envs resident), and switched off
+    for b in (1, 300, 880, 1000, 0):
+        env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+        env.set_balance(b)
+        env.plan(ds, w.n_steps)
+        sch = env.schedule()
+        assert all(c["mode"] == (1 if b > 0 and n_classes > 1 else 0) for c in sch), (b, sch)
+        if b == 1:
+            assert all(c["grid"] >= 1 for c in sch) and sum(c["grid"] * c["waves"] for c in sch) <= 12, sch
+        got = env.rollout(ds, w.n_steps, trade_off=toff)
+        torch.cuda.synchronize()
+        for key in ("n_trades", "fills", "reward", "obs", "done", "actions"):
+            assert torch.equal(got[key], ref[key]), (b, key)
+        gb = env.books()
+        for key in gb:
+            assert torch.equal(gb[key], ref_books[key]), (b, key)
     # the tuner picks one of them and restores the state it started from
     env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
     sched = env.autotune(ds, w.n_steps)
