@@ -431,13 +431,28 @@ struct Run {
                 if (cnt == top) cnt += count_rows<S>(rt - 1, p);
                 const int ins = n - cnt;
                 WAVE_SYNC();
-                if ((unsigned)(j - ins - 1) < (unsigned)(n - ins)) {
-                    int2 *d = RS<S>(j);
-                    d[0] = y0; d[1] = y1; d[2] = y2;
+                if ((ins >> 6) == rt) {
+                    /* the edit stays in row rt: lanes above ins take the record below,
+                     * lane ins the new order, in one store */
+                    const int ts = m.tsec(), tn = m.tns();
+                    const bool me = j == ins;
+                    const int2 v0 = make_int2(me ? p : y0.x, me ? q : y0.y);
+                    const int2 v1 = make_int2(me ? oid : y1.x, me ? tid : y1.y);
+                    const int2 v2 = make_int2(me ? ts : y2.x, me ? tn : y2.y);
+                    if ((unsigned)(j - ins) <= (unsigned)(n - ins)) {
+                        int2 *d = RS<S>(j);
+                        d[0] = v0; d[1] = v1; d[2] = v2;
+                    }
+                    WAVE_SYNC();
+                } else {
+                    if ((unsigned)(j - ins - 1) < (unsigned)(n - ins)) {
+                        int2 *d = RS<S>(j);
+                        d[0] = y0; d[1] = y1; d[2] = y2;
+                    }
+                    WAVE_SYNC();
+                    shift_up_rows<S>(rt - 1, ins);
+                    put<S>(ins, make_int2(p, q), make_int2(oid, tid), make_int2(m.tsec(), m.tns()));
                 }
-                WAVE_SYNC();
-                shift_up_rows<S>(rt - 1, ins);
-                put<S>(ins, make_int2(p, q), make_int2(oid, tid), make_int2(m.tsec(), m.tns()));
             } else {
                 cnt = 0;
                 put<S>(0, make_int2(p, q), make_int2(oid, tid), make_int2(m.tsec(), m.tns()));
