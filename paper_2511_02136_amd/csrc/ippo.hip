@@ -35,6 +35,13 @@ static_assert(NPARAM == 78858, "parameter count");
 constexpr int PW = NPARAM + 4; /* per-workgroup partial: gradient, then the 4 loss sums */
 
 constexpr int TR = 64;          /* samples per workgroup tile */
+/* waves per workgroup: four per SIMD (the LDS tile allows one workgroup per CU), so the
+ * address arithmetic and loads of some waves overlap the MFMAs of others (one wave per
+ * SIMD left the matrix pipe idle 60% of the time; two per SIMD took the fused call from
+ * 1.14 to 1.02 ms, four to 1.00 ms) */
+constexpr int NW = 16, NTH = 64 * NW;
+constexpr int CW = HID / NW, CT = CW / 16; /* hidden columns per wave, in 16-wide tiles */
+constexpr int RT = CT;                     /* 16-row tiles per wave over the 256 hidden rows */
 constexpr int XS = 52;          /* LDS row stride of the input tile (cols 40..51 zero) */
 constexpr int HS = 260;         /* LDS row stride of hidden tiles */
 constexpr int OS = 17;          /* LDS row stride of the output tile */
@@ -47,34 +54,41 @@ __device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
 __device__ __forceinline__ floatx4 zero4() { return floatx4{0.f, 0.f, 0.f, 0.f}; }
 
 /* acc[mt][nt] += A[r0+16mt .. +16][0..K) * B[0..K)[c0+16nt .. +16]; A(i, k), B(k, j) are
- * accessors; K a multiple of 4.  Software-pipelined: the operands of step k+4 are loaded
- * before the MFMAs of step k are issued, so their latency (LDS, or L2 for weights) is
- * covered by the previous step's MFMAs even with one wave per SIMD; the last step
- * re-reads its own operands (in bounds). */
+ * accessors; K a multiple of 4.  Software-pipelined GEMM_DEPTH steps deep: the operands
+ * of step k + 4 GEMM_DEPTH are loaded right after the MFMAs of step k are issued, so
+ * their latency (LDS, or L2 for weights) is covered by the MFMAs of the steps between,
+ * even with one wave per SIMD; loads past the end re-read the last step (in bounds). */
+constexpr int GEMM_DEPTH = 2;
 template <int MT, int NT, class FA, class FB>
 __device__ __forceinline__ void gemm(floatx4 (&acc)[MT][NT], int K, int r0, int c0, FA A, FB B) {
+    constexpr int D = GEMM_DEPTH;
     const int l = (int)(threadIdx.x & 63);
     const int li = l & 15, lk = l >> 4;
-    float a[MT], b[NT];
+    const int kl = K - 4; /* the last step */
+    float a[D][MT], b[D][NT];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) a[m] = A(r0 + 16 * m + li, lk);
+    for (int s = 0; s < D; ++s) {
+        const int k = min(4 * s, kl);
 #pragma unroll
-    for (int n = 0; n < NT; ++n) b[n] = B(lk, c0 + 16 * n + li);
-    for (int k0 = 0; k0 < K; k0 += 4) {
-        const int kn = k0 + 4 < K ? k0 + 4 : k0;
-        float an[MT], bn[NT];
+        for (int m = 0; m < MT; ++m) a[s][m] = A(r0 + 16 * m + li, k + lk);
 #pragma unroll
-        for (int m = 0; m < MT; ++m) an[m] = A(r0 + 16 * m + li, kn + lk);
+        for (int n = 0; n < NT; ++n) b[s][n] = B(k + lk, c0 + 16 * n + li);
+    }
+    for (int k0 = 0; k0 < K; k0 += 4 * D) {
 #pragma unroll
-        for (int n = 0; n < NT; ++n) bn[n] = B(kn + lk, c0 + 16 * n + li);
+        for (int s = 0; s < D; ++s) {
+            if (k0 + 4 * s < K) {
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
+                for (int m = 0; m < MT; ++m)
 #pragma unroll
-            for (int n = 0; n < NT; ++n) acc[m][n] = mfma(a[m], b[n], acc[m][n]);
+                    for (int n = 0; n < NT; ++n) acc[m][n] = mfma(a[s][m], b[s][n], acc[m][n]);
+                const int kn = min(k0 + 4 * s + 4 * D, kl);
 #pragma unroll
-        for (int m = 0; m < MT; ++m) a[m] = an[m];
+                for (int m = 0; m < MT; ++m) a[s][m] = A(r0 + 16 * m + li, kn + lk);
 #pragma unroll
-        for (int n = 0; n < NT; ++n) b[n] = bn[n];
+                for (int n = 0; n < NT; ++n) b[s][n] = B(kn + lk, c0 + 16 * n + li);
+            }
+        }
     }
 }
 
@@ -92,48 +106,48 @@ __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const 
         X[i] = (r < rows && c < IN) ? obs[(int64_t)r * IN + c] : 0.f;
     }
     __syncthreads();
-    /* layer 1: each wave computes 64 rows x 64 cols */
+    /* layer 1: each wave computes 64 rows x CW cols */
     {
-        floatx4 acc[4][4];
+        floatx4 acc[4][CT];
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] = zero4();
-        gemm<4, 4>(acc, IN, 0, 64 * wave, [&](int i, int k) { return X[i * XS + k]; },
-                   [&](int k, int j) { return P[O_W1 + k * HID + j]; });
+            for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
+        gemm<4, CT>(acc, IN, 0, CW * wave, [&](int i, int k) { return X[i * XS + k]; },
+                    [&](int k, int j) { return P[O_W1 + k * HID + j]; });
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n)
+            for (int n = 0; n < CT; ++n)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * m + acc_row(i), c = 64 * wave + 16 * n + acc_col();
+                    const int r = 16 * m + acc_row(i), c = CW * wave + 16 * n + acc_col();
                     H1[r * HS + c] = tanhf(acc[m][n][i] + P[O_B1 + c]);
                 }
     }
     __syncthreads();
     /* layer 2 */
     {
-        floatx4 acc[4][4];
+        floatx4 acc[4][CT];
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] = zero4();
-        gemm<4, 4>(acc, HID, 0, 64 * wave, [&](int i, int k) { return H1[i * HS + k]; },
-                   [&](int k, int j) { return P[O_W2 + k * HID + j]; });
+            for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
+        gemm<4, CT>(acc, HID, 0, CW * wave, [&](int i, int k) { return H1[i * HS + k]; },
+                    [&](int k, int j) { return P[O_W2 + k * HID + j]; });
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n)
+            for (int n = 0; n < CT; ++n)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * m + acc_row(i), c = 64 * wave + 16 * n + acc_col();
+                    const int r = 16 * m + acc_row(i), c = CW * wave + 16 * n + acc_col();
                     H2[r * HS + c] = tanhf(acc[m][n][i] + P[O_B2 + c]);
                 }
     }
     __syncthreads();
-    /* layer 3: wave w computes rows 16w..16w+15, cols 0..15 */
-    {
+    /* layer 3: wave w < 4 computes rows 16w..16w+15, cols 0..15 */
+    if (wave < TR / 16) {
         floatx4 acc[1][1] = {{zero4()}};
         gemm<1, 1>(acc, HID, 16 * wave, 0, [&](int i, int k) { return H2[i * HS + k]; },
                    [&](int k, int j) { return j < OUT ? P[O_W3 + k * OUT + j] : 0.f; });
@@ -148,7 +162,7 @@ __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const 
 
 /* ------------------------------------------------------------------------------
  * Policy forward for the rollout: logits, value, a sampled action (Gumbel-max on a
- * counter hash) and its log-probability.  grid (ceil(n/TR), n_agents), 256 threads.
+ * counter hash) and its log-probability.  grid (ceil(n/TR), n_agents), NTH threads.
  * ---------------------------------------------------------------------------- */
 struct FwdArgs {
     const float *params; /* [A][NPARAM] */
@@ -163,7 +177,7 @@ struct FwdArgs {
     float *logp, *value; /* [A][n] */
 };
 
-__global__ void __launch_bounds__(256) k_policy_forward(FwdArgs a) {
+__global__ void __launch_bounds__(NTH) k_policy_forward(FwdArgs a) {
     extern __shared__ float sm[];
     float *X = sm, *H1 = X + TR * XS, *H2 = H1 + TR * HS, *O = H2 + TR * HS;
     const int ag = (int)blockIdx.y;
@@ -235,7 +249,7 @@ struct PpoArgs {
     float *partial;              /* [grid][PW]: gradient, then loss sums (total, policy, value, entropy) */
 };
 
-__global__ void __launch_bounds__(256) k_ppo_fwd_bwd(PpoArgs a) {
+__global__ void __launch_bounds__(NTH) k_ppo_fwd_bwd(PpoArgs a) {
     extern __shared__ float sm[];
     float *X = sm, *H1 = X + TR * XS, *H2 = H1 + TR * HS, *O = H2 + TR * HS;
     const int row0 = (int)blockIdx.x * TR;
@@ -308,16 +322,16 @@ __global__ void __launch_bounds__(256) k_ppo_fwd_bwd(PpoArgs a) {
 
     /* dW3 = H2^T dOut (256 x 16, cols < 10 kept), db3 = column sums of dOut */
     {
-        floatx4 acc[4][1];
+        floatx4 acc[RT][1];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) acc[m][0] = zero4();
-        gemm<4, 1>(acc, TR, 64 * wave, 0, [&](int i, int k) { return H2[k * HS + i]; },
-                   [&](int k, int j) { return O[k * OS + j]; });
+        for (int m = 0; m < RT; ++m) acc[m][0] = zero4();
+        gemm<RT, 1>(acc, TR, CW * wave, 0, [&](int i, int k) { return H2[k * HS + i]; },
+                    [&](int k, int j) { return O[k * OS + j]; });
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < RT; ++m)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int r = 64 * wave + 16 * m + acc_row(i), c = acc_col();
+                const int r = CW * wave + 16 * m + acc_row(i), c = acc_col();
                 if (c < OUT) G[O_W3 + r * OUT + c] = acc[m][0][i];
             }
         if (tid < OUT) {
@@ -329,46 +343,46 @@ __global__ void __launch_bounds__(256) k_ppo_fwd_bwd(PpoArgs a) {
     __syncthreads();
     /* dH2 = (dOut W3^T) * (1 - H2^2), in place of H2 */
     {
-        floatx4 acc[4][4];
+        floatx4 acc[4][CT];
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] = zero4();
-        gemm<4, 4>(acc, OUTP, 0, 64 * wave, [&](int i, int k) { return O[i * OS + k]; },
-                   [&](int k, int j) { return k < OUT ? P[O_W3 + j * OUT + k] : 0.f; });
+            for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
+        gemm<4, CT>(acc, OUTP, 0, CW * wave, [&](int i, int k) { return O[i * OS + k]; },
+                    [&](int k, int j) { return k < OUT ? P[O_W3 + j * OUT + k] : 0.f; });
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n)
+            for (int n = 0; n < CT; ++n)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * m + acc_row(i), c = 64 * wave + 16 * n + acc_col();
+                    const int r = 16 * m + acc_row(i), c = CW * wave + 16 * n + acc_col();
                     const float h = H2[r * HS + c];
                     H2[r * HS + c] = acc[m][n][i] * (1.f - h * h);
                 }
     }
     __syncthreads();
-    /* dW2 = H1^T dH2 (256 x 256) in four passes of 64 x 64 per wave; db2 */
+    /* dW2 = H1^T dH2 (256 x 256) in four passes of 64 x CW per wave; db2 */
     for (int pass = 0; pass < 4; ++pass) {
-        floatx4 acc[4][4];
+        floatx4 acc[4][CT];
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] = zero4();
-        const int r0 = 64 * pass, c0 = 64 * wave;
-        gemm<4, 4>(acc, TR, r0, c0, [&](int i, int k) { return H1[k * HS + i]; },
-                   [&](int k, int j) { return H2[k * HS + j]; });
+            for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
+        const int r0 = 64 * pass, c0 = CW * wave;
+        gemm<4, CT>(acc, TR, r0, c0, [&](int i, int k) { return H1[k * HS + i]; },
+                    [&](int k, int j) { return H2[k * HS + j]; });
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n)
+            for (int n = 0; n < CT; ++n)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int r = r0 + 16 * m + acc_row(i), c = c0 + 16 * n + acc_col();
                     G[O_W2 + r * HID + c] = acc[m][n][i];
                 }
     }
-    {
+    if (tid < HID) {
         float s = 0.f;
         for (int r = 0; r < TR; ++r) s += H2[r * HS + tid];
         G[O_B2 + tid] = s;
@@ -376,21 +390,21 @@ __global__ void __launch_bounds__(256) k_ppo_fwd_bwd(PpoArgs a) {
     __syncthreads();
     /* dH1 = (dH2 W2^T) * (1 - H1^2), in place of H1 */
     {
-        floatx4 acc[4][4];
+        floatx4 acc[4][CT];
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] = zero4();
-        gemm<4, 4>(acc, HID, 0, 64 * wave, [&](int i, int k) { return H2[i * HS + k]; },
-                   [&](int k, int j) { return P[O_W2 + j * HID + k]; });
+            for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
+        gemm<4, CT>(acc, HID, 0, CW * wave, [&](int i, int k) { return H2[i * HS + k]; },
+                    [&](int k, int j) { return P[O_W2 + j * HID + k]; });
         /* each element of H1 is read and rewritten by the lane that owns it */
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n)
+            for (int n = 0; n < CT; ++n)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * m + acc_row(i), c = 64 * wave + 16 * n + acc_col();
+                    const int r = 16 * m + acc_row(i), c = CW * wave + 16 * n + acc_col();
                     const float h = H1[r * HS + c];
                     H1[r * HS + c] = acc[m][n][i] * (1.f - h * h);
                 }
@@ -398,25 +412,27 @@ __global__ void __launch_bounds__(256) k_ppo_fwd_bwd(PpoArgs a) {
     __syncthreads();
     /* dW1 = X^T dH1 (40 x 256, computed as 48 x 256 with zero rows), db1 */
     {
-        floatx4 acc[3][4];
+        floatx4 acc[3][CT];
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] = zero4();
-        gemm<3, 4>(acc, TR, 0, 64 * wave, [&](int i, int k) { return X[k * XS + i]; },
-                   [&](int k, int j) { return H1[k * HS + j]; });
+            for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
+        gemm<3, CT>(acc, TR, 0, CW * wave, [&](int i, int k) { return X[k * XS + i]; },
+                    [&](int k, int j) { return H1[k * HS + j]; });
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n)
+            for (int n = 0; n < CT; ++n)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * m + acc_row(i), c = 64 * wave + 16 * n + acc_col();
+                    const int r = 16 * m + acc_row(i), c = CW * wave + 16 * n + acc_col();
                     if (r < IN) G[O_W1 + r * HID + c] = acc[m][n][i];
                 }
-        float s = 0.f;
-        for (int r = 0; r < TR; ++r) s += H1[r * HS + tid];
-        G[O_B1 + tid] = s;
+        if (tid < HID) {
+            float s = 0.f;
+            for (int r = 0; r < TR; ++r) s += H1[r * HS + tid];
+            G[O_B1 + tid] = s;
+        }
     }
 }
 
@@ -490,7 +506,7 @@ int lob_policy_forward(const float *params, const float *obs, int32_t n_agents, 
     a.seed = seed; a.epoch = epoch; a.t = t; a.logits = logits; a.actions = actions; a.logp = logp; a.value = value;
     if (!lds_opt_in()) return LOB_EHIP;
     const dim3 grid((unsigned)((n + TR - 1) / TR), (unsigned)n_agents);
-    hipLaunchKernelGGL(k_policy_forward, grid, dim3(256), LDS_FLOATS * 4, (hipStream_t)stream, a);
+    hipLaunchKernelGGL(k_policy_forward, grid, dim3(NTH), LDS_FLOATS * 4, (hipStream_t)stream, a);
     return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
 }
 
@@ -530,7 +546,7 @@ int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, c
     a.partial = workspace;
     if (!lds_opt_in()) return LOB_EHIP;
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_ppo_fwd_bwd, dim3((unsigned)nwg), dim3(256), LDS_FLOATS * 4, st, a);
+    hipLaunchKernelGGL(k_ppo_fwd_bwd, dim3((unsigned)nwg), dim3(NTH), LDS_FLOATS * 4, st, a);
     float *sums = workspace + (int64_t)nwg * PW;
     hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((PW + 255) / 256), (unsigned)nch), dim3(256), 0, st,
                        (const float *)a.partial, nwg, PW, sums);
