@@ -8,9 +8,11 @@
  *
  * Design (MI355X-first):
  *   - one wavefront per environment; the book of both sides is LDS-resident, one
- *     24-byte record per order (price|qty, oid|tid, tsec|tns), ordered from the worst
- *     order to the best so the top of the book is the end of the live range; record j
- *     is handled by lane j%64 of row j/64 (see lob_device.h);
+ *     16-byte record per order (price|qty, oid|tid) and a 4-byte reference to its time
+ *     (the time itself stays in the message stream or in the book as loaded, and is
+ *     looked up when the books are stored), ordered from the worst order to the best so
+ *     the top of the book is the end of the live range; record j is handled by lane
+ *     j%64 of row j/64 (see lob_device.h);
  *   - a book message is a few wave-wide LDS instructions: a ballot search from the top
  *     row down for cancels and for the insertion rank, a one-pass shift of the rows an
  *     insertion or removal touches (usually one), and matching that walks the resting
@@ -51,7 +53,7 @@ constexpr int STW = 4;            /* step statistics: buy vol, sell vol, trades,
 
 /* Per-wave LDS layout after the book (int32 word offsets), for A agents (at most 8 new
  * orders per agent per step):
- *   act  8A x 8: new orders of the step (ts, price, qty, oid, tid, tsec, tns, -)
+ *   act  8A x 8: new orders of the step (ts, price, qty, oid, tid, time reference, -, -)
  *   perm 8A: shuffled order          lv   A x MAXLV x 4: side, price, desired, resting
  *   seen A x MAXLV: older resting qty seen in the walk      nlv  A: desired levels
  *   ag   int64 A x AGW: agent state  fl   int64 A x 4: fills of the step
@@ -79,11 +81,17 @@ __host__ __device__ constexpr XL x_layout(int A) {
 static_assert(x_layout(MAXA).words < 1024, "extra LDS");
 static_assert((22 + 3 * 1) * 2 <= 8 * 1 * 8, "observation accumulators fit in the new-order block");
 
+/* per side and order: a record of 4 words (price, qty, oid, tid) and a time reference */
 __host__ __device__ constexpr int lds_words_for(int capp, int n_agents) {
-    return 2 * NF * capp + x_layout(n_agents).words;
+    return 10 * capp + x_layout(n_agents).words;
 }
 
-constexpr int REC = NF / 2; /* int2 words per book record */
+constexpr int REC = 2; /* int2 pairs per book record: (price, qty), (oid, tid) */
+/* time references: >= 0 an index into the env's message stream (relative to its first
+ * message); TREF_LOADED | i slot i of the side as loaded at the launch's start (the
+ * time is in the books in memory); TREF_START the last processed time at the launch's
+ * start */
+constexpr int TREF_LOADED = (int)0x80000000u, TREF_START = (int)0xC0000000u;
 
 /* rows of 64 records a book of this capacity spans (the capacity class) */
 inline int rows_for_cap(int cap) { return (cap + WAVE - 1) / WAVE; }
@@ -125,8 +133,8 @@ struct KArgs {
 
 /* ------------------------------------------------------------------------------
  * A chunk of up to 64 messages staged in registers, message k in lane k: the dispatch
- * code (below) and price, qty, oid, tid, tsec, tns.  Fields of message j are read into
- * scalar registers where a handler needs them.
+ * code (below), price, qty, oid, tid and the time reference of the message.  Fields of
+ * message j are read into scalar registers where a handler needs them.
  * ---------------------------------------------------------------------------- */
 /* dispatch code: side in bit 0, operation above it */
 enum { OP_LIMIT = 0, OP_DELETE = 2, OP_PCANCEL = 4, OP_MARKET = 6, OP_BAD = 8 };
@@ -143,15 +151,14 @@ __device__ __forceinline__ int op_code(int ts, int qty) {
     return op | ((ts >> 8) & 1);
 }
 struct Staged {
-    int c[7] = {0, 0, 0, 0, 0, 0, 0};
+    int c[6] = {0, 0, 0, 0, 0, 0};
     int j = 0;
     __device__ __forceinline__ int code() const { return rdlane(c[0], j); }
     __device__ __forceinline__ int price() const { return rdlane(c[1], j); }
     __device__ __forceinline__ int qty() const { return rdlane(c[2], j); }
     __device__ __forceinline__ int oid() const { return rdlane(c[3], j); }
     __device__ __forceinline__ int tid() const { return rdlane(c[4], j); }
-    __device__ __forceinline__ int tsec() const { return rdlane(c[5], j); }
-    __device__ __forceinline__ int tns() const { return rdlane(c[6], j); }
+    __device__ __forceinline__ int tref() const { return rdlane(c[5], j); }
 };
 
 /* ------------------------------------------------------------------------------
@@ -166,6 +173,10 @@ struct Run {
     /* per step, hot */
     int64_t mid_sum, st_buy, st_sell;
     int32_t mid_n, seq, st_last, last_tsec, last_tns;
+    /* time references: of the last processed message (TREF_START before any in this
+     * launch), the launch's start time it stands for, and the stream's first message */
+    int32_t last_ref, start_tsec, start_tns;
+    int64_t sbase;
     /* mid statistics run-length encoded: the messages since index mid_at all leave the
      * book with the same touch, contributing mid_c (best bid + best ask, or 0 when a side
      * is empty) and mid_f (1, or 0 when a side is empty) each */
@@ -181,19 +192,23 @@ struct Run {
 
     __device__ Run(const KArgs &args, int32_t *lds, int env)
         : a(args), L(lds), lane(lane_id()), capp(uni(args.capp)), e(uni(env)), A(args.n_agents),
-          n0(0), n1(0), best0(0), best1(0), mid_sum(0), mid_n(0), seq(0), mid_c(0), mid_f(0), mid_at(0) {
+          n0(0), n1(0), best0(0), best1(0), mid_sum(0), mid_n(0), seq(0), last_ref(TREF_START), start_tsec(0),
+          start_tns(0), sbase(0), mid_c(0), mid_f(0), mid_at(0) {
         cap = uni(a.caps[e]);
     }
 
-    /* ---- LDS views.  Each side holds capp records of three int2 (price|qty, oid|tid,
-     * tsec|tns).  Record j counts from the worst order (j = 0) to the best (j = n - 1),
-     * so the top of the book is at the end of the live range; record j of a row of 64
-     * belongs to lane j % 64. ---- */
+    /* ---- LDS views.  Each side holds capp records of two int2 (price|qty, oid|tid),
+     * both sides' records first, then both sides' time references (capp words each).
+     * Record j counts from the worst order (j = 0) to the best (j = n - 1), so the top of
+     * the book is at the end of the live range; record j of a row of 64 belongs to lane
+     * j % 64. ---- */
     /* pair p of record i of side s (any index, e.g. uniform) */
     __device__ __forceinline__ int2 &U(int s, int p, int i) {
         return reinterpret_cast<int2 *>(L)[(s * capp + i) * REC + p];
     }
-    __device__ __forceinline__ int32_t *X() { return L + 2 * NF * capp; }
+    /* time reference of record i of side s */
+    __device__ __forceinline__ int32_t &T(int s, int i) { return L[2 * REC * 2 * capp + s * capp + i]; }
+    __device__ __forceinline__ int32_t *X() { return L + 10 * capp; }
     __device__ __forceinline__ XL xl() const { return x_layout(A); }
     __device__ __forceinline__ int64_t *X64(int off) { return reinterpret_cast<int64_t *>(X() + off); }
     __device__ __forceinline__ int64_t *AG(int i) { return X64(xl().ag) + i * AGW; }
@@ -240,6 +255,8 @@ struct Run {
     template <int S> __device__ __forceinline__ int2 *RS(int i) {
         return reinterpret_cast<int2 *>(L) + (S * capp + i) * REC;
     }
+    /* time reference of record i of side S */
+    template <int S> __device__ __forceinline__ int32_t *TS(int i) { return L + 2 * REC * 2 * capp + S * capp + i; }
     /* lanes whose price x is equal to or better than p on side S */
     template <int S> __device__ __forceinline__ uint64_t better_eq(int x, int p) {
         return S == 0 ? lanes_ge(x, p) : lanes_le(x, p);
@@ -288,20 +305,23 @@ struct Run {
         for (int r = r0; r >= (ins >> 6); --r) {
             const int j = (r << 6) + lane;
             const int2 *src = RS<S>(max(j - 1, 0));
-            const int2 x0 = src[0], x1 = src[1], x2 = src[2];
+            const int2 x0 = src[0], x1 = src[1];
+            const int xt = *TS<S>(max(j - 1, 0));
             WAVE_SYNC();
             if (j > ins) {
                 int2 *d = RS<S>(j);
-                d[0] = x0; d[1] = x1; d[2] = x2;
+                d[0] = x0; d[1] = x1;
+                *TS<S>(j) = xt;
             }
             WAVE_SYNC();
         }
     }
     /* one record written by lane 0 */
-    template <int S> __device__ __forceinline__ void put(int i, int2 v0, int2 v1, int2 v2) {
+    template <int S> __device__ __forceinline__ void put(int i, int2 v0, int2 v1, int vt) {
         if (lane == 0) {
             int2 *d = RS<S>(i);
-            d[0] = v0; d[1] = v1; d[2] = v2;
+            d[0] = v0; d[1] = v1;
+            *TS<S>(i) = vt;
         }
         WAVE_SYNC();
     }
@@ -310,30 +330,34 @@ struct Run {
         for (int r = k >> 6; r <= (n - 2) >> 6; ++r) {
             const int j = (r << 6) + lane;
             const int2 *src = RS<S>(min(j + 1, n - 1));
-            const int2 x0 = src[0], x1 = src[1], x2 = src[2];
+            const int2 x0 = src[0], x1 = src[1];
+            const int xt = *TS<S>(min(j + 1, n - 1));
             WAVE_SYNC();
             if ((unsigned)(j - k) < (unsigned)(n - 1 - k)) {
                 int2 *d = RS<S>(j);
-                d[0] = x0; d[1] = x1; d[2] = x2;
+                d[0] = x0; d[1] = x1;
+                *TS<S>(j) = xt;
             }
             WAVE_SYNC();
         }
     }
     /* full side (n = cap): the worst order (record 0) leaves, [1, ins) moves down by one and
      * the new order takes record ins - 1 (ins >= 1) */
-    template <int S> __device__ __forceinline__ void evict_insert(int ins, int2 v0, int2 v1, int2 v2) {
+    template <int S> __device__ __forceinline__ void evict_insert(int ins, int2 v0, int2 v1, int vt) {
         for (int r = 0; r <= (ins - 1) >> 6; ++r) {
             const int j = (r << 6) + lane;
             const int2 *src = RS<S>(min(j + 1, ins - 1));
-            const int2 x0 = src[0], x1 = src[1], x2 = src[2];
+            const int2 x0 = src[0], x1 = src[1];
+            const int xt = *TS<S>(min(j + 1, ins - 1));
             WAVE_SYNC();
             if (j < ins - 1) {
                 int2 *d = RS<S>(j);
-                d[0] = x0; d[1] = x1; d[2] = x2;
+                d[0] = x0; d[1] = x1;
+                *TS<S>(j) = xt;
             }
             WAVE_SYNC();
         }
-        put<S>(ins - 1, v0, v1, v2);
+        put<S>(ins - 1, v0, v1, vt);
     }
 
     /* ---- fills (uniform accumulation in LDS by lane 0) ---- */
@@ -425,8 +449,10 @@ struct Run {
                  * hold the row's live records, so they also give the count from the top. */
                 const int rt = n >> 6, top = n - (rt << 6);
                 const int j = (rt << 6) + lane;
-                const int2 *src = RS<S>(min(max(j - 1, 0), n - 1));
-                const int2 y0 = src[0], y1 = src[1], y2 = src[2];
+                const int js = min(max(j - 1, 0), n - 1);
+                const int2 *src = RS<S>(js);
+                const int2 y0 = src[0], y1 = src[1];
+                const int yt = *TS<S>(js);
                 cnt = __popcll(better_eq<S>(y0.x, p) & lanes_gt(lane, 0) & lanes_le(lane, top));
                 if (cnt == top) cnt += count_rows<S>(rt - 1, p);
                 const int ins = n - cnt;
@@ -434,28 +460,30 @@ struct Run {
                 if ((ins >> 6) == rt) {
                     /* the edit stays in row rt: lanes above ins take the record below,
                      * lane ins the new order, in one store */
-                    const int ts = m.tsec(), tn = m.tns();
+                    const int tr = m.tref();
                     const bool me = j == ins;
                     const int2 v0 = make_int2(me ? p : y0.x, me ? q : y0.y);
                     const int2 v1 = make_int2(me ? oid : y1.x, me ? tid : y1.y);
-                    const int2 v2 = make_int2(me ? ts : y2.x, me ? tn : y2.y);
+                    const int vt = me ? tr : yt;
                     if ((unsigned)(j - ins) <= (unsigned)(n - ins)) {
                         int2 *d = RS<S>(j);
-                        d[0] = v0; d[1] = v1; d[2] = v2;
+                        d[0] = v0; d[1] = v1;
+                        *TS<S>(j) = vt;
                     }
                     WAVE_SYNC();
                 } else {
                     if ((unsigned)(j - ins - 1) < (unsigned)(n - ins)) {
                         int2 *d = RS<S>(j);
-                        d[0] = y0; d[1] = y1; d[2] = y2;
+                        d[0] = y0; d[1] = y1;
+                        *TS<S>(j) = yt;
                     }
                     WAVE_SYNC();
                     shift_up_rows<S>(rt - 1, ins);
-                    put<S>(ins, make_int2(p, q), make_int2(oid, tid), make_int2(m.tsec(), m.tns()));
+                    put<S>(ins, make_int2(p, q), make_int2(oid, tid), m.tref());
                 }
             } else {
                 cnt = 0;
-                put<S>(0, make_int2(p, q), make_int2(oid, tid), make_int2(m.tsec(), m.tns()));
+                put<S>(0, make_int2(p, q), make_int2(oid, tid), m.tref());
             }
             nS<S>() = n + 1;
         } else {
@@ -469,7 +497,7 @@ struct Run {
             count(C_EVICT, 1);
             count(C_EVICTED_QTY, uni(w.y));
             cnt = count_ahead<S>(n, p);
-            evict_insert<S>(n - cnt, make_int2(p, q), make_int2(oid, tid), make_int2(m.tsec(), m.tns()));
+            evict_insert<S>(n - cnt, make_int2(p, q), make_int2(oid, tid), m.tref());
         }
         if (cnt == 0) {
             bestS<S>() = p;
@@ -490,7 +518,8 @@ struct Run {
         const int rt = (n - 1) >> 6;
         const int j = (rt << 6) + lane;
         const int2 *src = RS<S>(min(j, n - 1));
-        const int2 o0 = src[0], o1 = src[1], o2 = src[2];
+        const int2 o0 = src[0], o1 = src[1];
+        const int ot = *TS<S>(min(j, n - 1));
         const uint64_t mt = lanes_eq(o1.x, oid) & lanes_lt(j, n);
         int k;
         if (mt) {
@@ -504,11 +533,13 @@ struct Run {
                     return;
                 }
             }
-            const int2 u0 = shl1(o0), u1 = shl1(o1), u2 = shl1(o2);
+            const int2 u0 = shl1(o0), u1 = shl1(o1);
+            const int ut = shl1(ot);
             WAVE_SYNC();
             if ((unsigned)(j - k) < (unsigned)(n - 1 - k)) {
                 int2 *d = RS<S>(j);
-                d[0] = u0; d[1] = u1; d[2] = u2;
+                d[0] = u0; d[1] = u1;
+                *TS<S>(j) = ut;
             }
             WAVE_SYNC();
         } else {
@@ -707,7 +738,7 @@ struct Run {
             if (lane == 0) {
                 int32_t *m = X() + xl().act + nact * 8;
                 m[0] = type | (side << 8); m[1] = price; m[2] = qty; m[3] = oid;
-                m[4] = tid; m[5] = last_tsec; m[6] = last_tns;
+                m[4] = tid; m[5] = last_ref; m[6] = 0;
                 g[3] = c + 1;
             }
             WAVE_SYNC();
@@ -792,7 +823,7 @@ struct Run {
                 const int j = n - 1 - i;
                 U(s, 0, j) = make_int2(a.bk[FP][off + i], a.bk[FQ][off + i]);
                 U(s, 1, j) = make_int2(a.bk[FO][off + i], a.bk[FT][off + i]);
-                U(s, 2, j) = make_int2(a.bk[FS][off + i], a.bk[FN][off + i]);
+                T(s, j) = TREF_LOADED | i; /* its time stays in the books in memory */
             }
         }
         /* env state, statistics and agent state into LDS, counters into lanes */
@@ -806,6 +837,10 @@ struct Run {
         t = (int32_t)uni64(ENV()[6]);
         last_tsec = (int32_t)uni64(ENV()[4]);
         last_tns = (int32_t)uni64(ENV()[5]);
+        last_ref = TREF_START;
+        start_tsec = last_tsec;
+        start_tns = last_tns;
+        sbase = a.m_off ? uni64(a.m_off[(int64_t)e * (a.m_steps + 1)]) : 0;
         tr_cur0 = a.trade_cursor ? uni64(a.trade_cursor[e]) : 0;
         tr_next = 0;
         tr_base = nullptr;
@@ -820,16 +855,48 @@ struct Run {
     __device__ __forceinline__ void store() {
         WAVE_SYNC();
         const int64_t gb = (int64_t)e * 2;
+        constexpr int MAXR = LOB_MAX_CAP / WAVE;
         for (int s = 0; s < 2; ++s) {
             const int n = nsz(s);
             const int64_t off = (gb + s) * a.max_cap;
-            for (int i = lane; i < n; i += WAVE) {
-                const int j = n - 1 - i;
-                const int2 x0 = U(s, 0, j), x1 = U(s, 1, j), x2 = U(s, 2, j);
-                a.bk[FP][off + i] = x0.x; a.bk[FQ][off + i] = x0.y;
-                a.bk[FO][off + i] = x1.x; a.bk[FT][off + i] = x1.y;
-                a.bk[FS][off + i] = x2.x; a.bk[FN][off + i] = x2.y;
+            /* the orders' times, from their references, into registers: every read of the
+             * side's old time slots comes before any write to them */
+            int ts[MAXR], tn[MAXR];
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+                const int i = (r << 6) + lane;
+                ts[r] = 0;
+                tn[r] = 0;
+                if (i < n) {
+                    const int tr = T(s, n - 1 - i);
+                    if (tr >= 0) {
+                        const int64_t g = sbase + tr;
+                        ts[r] = a.m_tsec[g];
+                        tn[r] = a.m_tns[g];
+                    } else if (tr == TREF_START) {
+                        ts[r] = start_tsec;
+                        tn[r] = start_tns;
+                    } else {
+                        const int64_t k = off + (tr & 0x3FFFFFFF);
+                        ts[r] = a.bk[FS][k];
+                        tn[r] = a.bk[FN][k];
+                    }
+                }
             }
+            __builtin_amdgcn_s_waitcnt(0x0F70); /* vmcnt(0): the reads above have completed */
+            WAVE_SYNC();
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+                const int i = (r << 6) + lane;
+                if (i < n) {
+                    const int j = n - 1 - i;
+                    const int2 x0 = U(s, 0, j), x1 = U(s, 1, j);
+                    a.bk[FP][off + i] = x0.x; a.bk[FQ][off + i] = x0.y;
+                    a.bk[FO][off + i] = x1.x; a.bk[FT][off + i] = x1.y;
+                    a.bk[FS][off + i] = ts[r]; a.bk[FN][off + i] = tn[r];
+                }
+            }
+            WAVE_SYNC();
         }
         if (lane == 0) {
             a.bk_n[gb] = n0;
@@ -934,30 +1001,32 @@ struct Run {
         Staged m;
         if (lane < nact) {
             const int32_t *x = X() + xl().act + X()[xl().perm + lane] * 8;
-            m.c[0] = x[0]; m.c[1] = x[1]; m.c[2] = x[2]; m.c[3] = x[3]; m.c[4] = x[4]; m.c[5] = x[5]; m.c[6] = x[6];
+            m.c[0] = x[0]; m.c[1] = x[1]; m.c[2] = x[2]; m.c[3] = x[3]; m.c[4] = x[4]; m.c[5] = x[5];
         }
-        int cnt = nact, base = -WAVE;
+        int cnt = nact, cb = -WAVE; /* cb: first replayed message of the chunk */
         for (;;) {
             /* everything the chunk loaded has arrived before the first message is read
              * (so no per-message waits on it) */
             __builtin_amdgcn_s_waitcnt(0);
             m.c[0] = op_code(m.c[0], m.c[2]);
             for (m.j = 0; m.j < cnt; ++m.j) process(m);
-            base += WAVE;
-            if (base >= nrep) break;
-            const int nx = base + lane;
+            cb += WAVE;
+            if (cb >= nrep) break;
+            const int nx = cb + lane;
             if (nx < nrep) {
                 const int64_t g = lo + nx;
                 m.c[0] = a.m_ts[g]; m.c[1] = a.m_price[g]; m.c[2] = a.m_qty[g]; m.c[3] = a.m_oid[g];
-                m.c[4] = a.m_tid[g]; m.c[5] = a.m_tsec[g]; m.c[6] = a.m_tns[g];
+                m.c[4] = a.m_tid[g]; m.c[5] = (int)(g - sbase); /* the time stays in the stream */
             }
-            cnt = min(WAVE, nrep - base);
+            cnt = min(WAVE, nrep - cb);
         }
         /* the last processed time: agent messages carry the previous one, so it changes
          * only with a replayed message */
         if (nrep > 0) {
-            last_tsec = rdlane(m.c[5], cnt - 1);
-            last_tns = rdlane(m.c[6], cnt - 1);
+            const int64_t gl = lo + nrep - 1;
+            last_tsec = uni(a.m_tsec[gl]);
+            last_tns = uni(a.m_tns[gl]);
+            last_ref = (int)(gl - sbase);
         }
 
         /* step 5: outcomes */
