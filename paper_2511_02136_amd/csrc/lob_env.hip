@@ -81,9 +81,11 @@ __host__ __device__ constexpr XL x_layout(int A) {
 static_assert(x_layout(MAXA).words < 1024, "extra LDS");
 static_assert((22 + 3 * 1) * 2 <= 8 * 1 * 8, "observation accumulators fit in the new-order block");
 
-/* per side and order: a record of 4 words (price, qty, oid, tid) and a time reference */
+/* per side and order: a record of 4 words (price, qty, oid, tid) and a time reference;
+ * rounded to 16 bytes so that every wave's records are 16-byte aligned (one 128-bit LDS
+ * access per record, conflict-free across a row) */
 __host__ __device__ constexpr int lds_words_for(int capp, int n_agents) {
-    return 10 * capp + x_layout(n_agents).words;
+    return (10 * capp + x_layout(n_agents).words + 3) & ~3;
 }
 
 constexpr int REC = 2; /* int2 pairs per book record: (price, qty), (oid, tid) */
@@ -257,6 +259,8 @@ struct Run {
     }
     /* time reference of record i of side S */
     template <int S> __device__ __forceinline__ int32_t *TS(int i) { return L + 2 * REC * 2 * capp + S * capp + i; }
+    /* record i of side S as one 128-bit value (price, qty, oid, tid) */
+    template <int S> __device__ __forceinline__ int4 *RQ(int i) { return reinterpret_cast<int4 *>(L) + S * capp + i; }
     /* lanes whose price x is equal to or better than p on side S */
     template <int S> __device__ __forceinline__ uint64_t better_eq(int x, int p) {
         return S == 0 ? lanes_ge(x, p) : lanes_le(x, p);
@@ -304,23 +308,20 @@ struct Run {
     template <int S> __device__ __forceinline__ void shift_up_rows(int r0, int ins) {
         for (int r = r0; r >= (ins >> 6); --r) {
             const int j = (r << 6) + lane;
-            const int2 *src = RS<S>(max(j - 1, 0));
-            const int2 x0 = src[0], x1 = src[1];
+            const int4 x = *RQ<S>(max(j - 1, 0));
             const int xt = *TS<S>(max(j - 1, 0));
             WAVE_SYNC();
             if (j > ins) {
-                int2 *d = RS<S>(j);
-                d[0] = x0; d[1] = x1;
+                *RQ<S>(j) = x;
                 *TS<S>(j) = xt;
             }
             WAVE_SYNC();
         }
     }
     /* one record written by lane 0 */
-    template <int S> __device__ __forceinline__ void put(int i, int2 v0, int2 v1, int vt) {
+    template <int S> __device__ __forceinline__ void put(int i, int4 v, int vt) {
         if (lane == 0) {
-            int2 *d = RS<S>(i);
-            d[0] = v0; d[1] = v1;
+            *RQ<S>(i) = v;
             *TS<S>(i) = vt;
         }
         WAVE_SYNC();
@@ -329,13 +330,11 @@ struct Run {
     template <int S> __device__ __forceinline__ void remove_at(int k, int n) {
         for (int r = k >> 6; r <= (n - 2) >> 6; ++r) {
             const int j = (r << 6) + lane;
-            const int2 *src = RS<S>(min(j + 1, n - 1));
-            const int2 x0 = src[0], x1 = src[1];
+            const int4 x = *RQ<S>(min(j + 1, n - 1));
             const int xt = *TS<S>(min(j + 1, n - 1));
             WAVE_SYNC();
             if ((unsigned)(j - k) < (unsigned)(n - 1 - k)) {
-                int2 *d = RS<S>(j);
-                d[0] = x0; d[1] = x1;
+                *RQ<S>(j) = x;
                 *TS<S>(j) = xt;
             }
             WAVE_SYNC();
@@ -343,21 +342,19 @@ struct Run {
     }
     /* full side (n = cap): the worst order (record 0) leaves, [1, ins) moves down by one and
      * the new order takes record ins - 1 (ins >= 1) */
-    template <int S> __device__ __forceinline__ void evict_insert(int ins, int2 v0, int2 v1, int vt) {
+    template <int S> __device__ __forceinline__ void evict_insert(int ins, int4 v, int vt) {
         for (int r = 0; r <= (ins - 1) >> 6; ++r) {
             const int j = (r << 6) + lane;
-            const int2 *src = RS<S>(min(j + 1, ins - 1));
-            const int2 x0 = src[0], x1 = src[1];
+            const int4 x = *RQ<S>(min(j + 1, ins - 1));
             const int xt = *TS<S>(min(j + 1, ins - 1));
             WAVE_SYNC();
             if (j < ins - 1) {
-                int2 *d = RS<S>(j);
-                d[0] = x0; d[1] = x1;
+                *RQ<S>(j) = x;
                 *TS<S>(j) = xt;
             }
             WAVE_SYNC();
         }
-        put<S>(ins - 1, v0, v1, vt);
+        put<S>(ins - 1, v, vt);
     }
 
     /* ---- fills (uniform accumulation in LDS by lane 0) ---- */
@@ -450,10 +447,9 @@ struct Run {
                 const int rt = n >> 6, top = n - (rt << 6);
                 const int j = (rt << 6) + lane;
                 const int js = min(max(j - 1, 0), n - 1);
-                const int2 *src = RS<S>(js);
-                const int2 y0 = src[0], y1 = src[1];
+                const int4 y = *RQ<S>(js);
                 const int yt = *TS<S>(js);
-                cnt = __popcll(better_eq<S>(y0.x, p) & lanes_gt(lane, 0) & lanes_le(lane, top));
+                cnt = __popcll(better_eq<S>(y.x, p) & lanes_gt(lane, 0) & lanes_le(lane, top));
                 if (cnt == top) cnt += count_rows<S>(rt - 1, p);
                 const int ins = n - cnt;
                 WAVE_SYNC();
@@ -462,28 +458,25 @@ struct Run {
                      * lane ins the new order, in one store */
                     const int tr = m.tref();
                     const bool me = j == ins;
-                    const int2 v0 = make_int2(me ? p : y0.x, me ? q : y0.y);
-                    const int2 v1 = make_int2(me ? oid : y1.x, me ? tid : y1.y);
+                    const int4 v = make_int4(me ? p : y.x, me ? q : y.y, me ? oid : y.z, me ? tid : y.w);
                     const int vt = me ? tr : yt;
                     if ((unsigned)(j - ins) <= (unsigned)(n - ins)) {
-                        int2 *d = RS<S>(j);
-                        d[0] = v0; d[1] = v1;
+                        *RQ<S>(j) = v;
                         *TS<S>(j) = vt;
                     }
                     WAVE_SYNC();
                 } else {
                     if ((unsigned)(j - ins - 1) < (unsigned)(n - ins)) {
-                        int2 *d = RS<S>(j);
-                        d[0] = y0; d[1] = y1;
+                        *RQ<S>(j) = y;
                         *TS<S>(j) = yt;
                     }
                     WAVE_SYNC();
                     shift_up_rows<S>(rt - 1, ins);
-                    put<S>(ins, make_int2(p, q), make_int2(oid, tid), m.tref());
+                    put<S>(ins, make_int4(p, q, oid, tid), m.tref());
                 }
             } else {
                 cnt = 0;
-                put<S>(0, make_int2(p, q), make_int2(oid, tid), m.tref());
+                put<S>(0, make_int4(p, q, oid, tid), m.tref());
             }
             nS<S>() = n + 1;
         } else {
@@ -497,7 +490,7 @@ struct Run {
             count(C_EVICT, 1);
             count(C_EVICTED_QTY, uni(w.y));
             cnt = count_ahead<S>(n, p);
-            evict_insert<S>(n - cnt, make_int2(p, q), make_int2(oid, tid), m.tref());
+            evict_insert<S>(n - cnt, make_int4(p, q, oid, tid), m.tref());
         }
         if (cnt == 0) {
             bestS<S>() = p;
@@ -517,15 +510,14 @@ struct Run {
         }
         const int rt = (n - 1) >> 6;
         const int j = (rt << 6) + lane;
-        const int2 *src = RS<S>(min(j, n - 1));
-        const int2 o0 = src[0], o1 = src[1];
+        const int4 o = *RQ<S>(min(j, n - 1));
         const int ot = *TS<S>(min(j, n - 1));
-        const uint64_t mt = lanes_eq(o1.x, oid) & lanes_lt(j, n);
+        const uint64_t mt = lanes_eq(o.z, oid) & lanes_lt(j, n);
         int k;
         if (mt) {
             k = (rt << 6) + 63 - __builtin_clzll(mt);
             if (PARTIAL) {
-                const int cq = rdlane(o0.y, k & 63);
+                const int cq = rdlane(o.y, k & 63);
                 const int left = cq - min(qty, cq);
                 if (left > 0) {
                     if (lane == 0) RS<S>(k)->y = left;
@@ -533,12 +525,11 @@ struct Run {
                     return;
                 }
             }
-            const int2 u0 = shl1(o0), u1 = shl1(o1);
+            const int4 u = make_int4(shl1(o.x), shl1(o.y), shl1(o.z), shl1(o.w));
             const int ut = shl1(ot);
             WAVE_SYNC();
             if ((unsigned)(j - k) < (unsigned)(n - 1 - k)) {
-                int2 *d = RS<S>(j);
-                d[0] = u0; d[1] = u1;
+                *RQ<S>(j) = u;
                 *TS<S>(j) = ut;
             }
             WAVE_SYNC();
