@@ -88,6 +88,10 @@ SMALL = [
                    agents=("mm", "dir"), seed=35, snapshot_fill_pct=100),
     synth.Workload("tiny_books", n_envs=32, n_steps=16, msgs_per_step=60, cap=3, agents=("exec", "mm", "dir", "mm"),
                    seed=36, snapshot_fill_pct=100),
+    # the largest capacity the library accepts (16 rows of 64 orders per side), books full
+    # from the start: the last row, evictions and the time lookup of every row
+    synth.Workload("max_cap", n_envs=8, n_steps=6, msgs_per_step=400, cap=1024, agents=("exec", "mm"),
+                   seed=37, snapshot_fill_pct=100),
 ]
 
 
