@@ -1,10 +1,11 @@
 /*
  * Device-side building blocks of the LOB environment step (gfx950, wave64).
  *
- * One wavefront owns one environment.  Its book lives in LDS as records of six int32
- * fields (price, qty, oid, tid, tsec, tns), per side in priority order from the worst
- * order (record 0) to the best (record n-1).  Record j of a side is handled by lane
- * j % 64 in "row" j / 64, so a row access is one LDS instruction per field pair.
+ * One wavefront owns one environment.  Its book lives in LDS as records of four int32
+ * fields (price, qty, oid, tid) plus a time reference each, per side in priority order
+ * from the worst order (record 0) to the best (record n-1).  Record j of a side is
+ * handled by lane j % 64 in "row" j / 64, so a row access is one 128-bit LDS
+ * instruction for the records and one 32-bit one for the time references.
  * Searches are ballots over rows from the top of the book down, and insertion /
  * removal move the records of the rows they touch by whole-wave LDS copies.
  *
