@@ -27,8 +27,13 @@
  *
  * Message encoding (structure of arrays, int32 each, one entry per message):
  *   ts    = type | (side << 8); type 1 LIMIT, 2 PARTIAL_CANCEL, 3 DELETE, 4 MARKET
- *           (immediate-or-cancel, no price limit); side 0 buy, 1 sell; other types are
- *           counted as bad and ignored.
+ *           (immediate-or-cancel, no price limit), 5 EXECUTE (a replayed execution of
+ *           the resting order named by oid on `side`: min(qty, its qty) trades at its
+ *           price against an anonymous aggressor of the other side, oid 0 and tid 0, and
+ *           the rest keeps its priority; a missing id counts as a miss), 6 IGNORED (a
+ *           replayed message the book does not act on: hidden executions, cross trades,
+ *           trading halts; counted); side 0 buy, 1 sell; other types are counted as bad
+ *           and ignored.
  *   price (ticks), qty (> 0), oid (order id; cancels name the order by id on their
  *   side), tid (trader id; agents are tid 1..n_agents, replay data must not use them),
  *   tsec, tns (time payload, not used for priority: arrival order is time priority).
@@ -57,7 +62,7 @@ enum {
 #define LOB_MARKET 4
 #define LOB_OBS_DIM 40
 #define LOB_TRADE_WORDS 8
-#define LOB_N_COUNTERS 10
+#define LOB_N_COUNTERS 11
 #define LOB_ENV_STATE_WORDS 8
 #define LOB_AGENT_STATE_WORDS 4
 #define LOB_MAX_AGENTS 4
@@ -210,8 +215,9 @@ int lob_export_books(lob_ctx *ctx, const lob_books *out, void *stream);
  *     mid2 change over the last step;
  *   agent_state [n_envs][n_agents][4]: inventory, cash (ticks x shares), execution
  *     remaining, order-id counter;
- *   counters [n_envs][10]: messages, trades, cancel misses, evictions, evicted qty, drops,
- *     dropped qty, unfilled market qty, bad messages, trade records not written.
+ *   counters [n_envs][11]: messages, trades, cancel and execution misses, evictions,
+ *     evicted qty, drops, dropped qty, unfilled market qty, bad messages, trade records
+ *     not written, ignored messages.
  * Any pointer may be NULL. */
 int lob_export_state(lob_ctx *ctx, int64_t *env_state, int64_t *agent_state, int64_t *counters,
                      void *stream);

@@ -23,9 +23,9 @@ _lib = None
 
 OBS_DIM = 40
 TRADE_WORDS = 8
-N_COUNTERS = 10
+N_COUNTERS = 11
 COUNTER_NAMES = ("msgs", "trades", "miss", "evict", "evicted_qty", "drop", "dropped_qty",
-                 "market_unfilled", "bad", "trade_overflow")
+                 "market_unfilled", "bad", "trade_overflow", "ignored")
 ENV_STATE_NAMES = ("last_bb", "last_ba", "mid2_prev", "p_init2", "last_tsec", "last_tns", "t",
                    "last_dmid2")
 AGENT_STATE_NAMES = ("inventory", "cash", "remaining", "order_counter")

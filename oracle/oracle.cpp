@@ -25,12 +25,12 @@
 
 namespace {
 
-enum { LIMIT = 1, PARTIAL_CANCEL = 2, DELETE = 3, MARKET = 4 };
+enum { LIMIT = 1, PARTIAL_CANCEL = 2, DELETE = 3, MARKET = 4, EXECUTE = 5, IGNORED = 6 };
 enum { BUY = 0, SELL = 1 };
 enum { AG_EXEC = 0, AG_MM = 1, AG_DIR = 2 };
 /* per-env counters */
 enum { C_MSGS, C_TRADES, C_MISS, C_EVICT, C_EVICTED_QTY, C_DROP, C_DROPPED_QTY,
-       C_MARKET_UNFILLED, C_BAD, C_TRADE_OVERFLOW, N_COUNTERS };
+       C_MARKET_UNFILLED, C_BAD, C_TRADE_OVERFLOW, C_IGNORED, N_COUNTERS };
 constexpr int OBS_DIM = 40;
 constexpr int TRADE_WORDS = 8;
 
@@ -139,9 +139,7 @@ struct Book {
 
 /* Trade at the resting (passive) order's price.  Reading: the paper defers matching to
  * the JAX-LOB simulator; textbook price-time priority trades at the passive price. */
-void emit_trade(TradeSink &ts, int32_t price, int32_t x, const Msg &m, const Order &p, int32_t seq,
-                int32_t t) {
-    const int32_t rec[TRADE_WORDS] = {price, x, m.oid, p.oid, m.tid, p.tid, m.side | (seq << 1), t};
+void emit_record(TradeSink &ts, const int32_t (&rec)[TRADE_WORDS]) {
     if (ts.written < ts.cap && ts.buf) {
         std::memcpy(ts.buf + ts.written * TRADE_WORDS, rec, sizeof(rec));
     } else {
@@ -150,6 +148,12 @@ void emit_trade(TradeSink &ts, int32_t price, int32_t x, const Msg &m, const Ord
     if (ts.step) ts.step->insert(ts.step->end(), rec, rec + TRADE_WORDS);
     ts.written += 1;
     ts.counters[C_TRADES] += 1;
+}
+/* the incoming message m is the aggressor */
+void emit_trade(TradeSink &ts, int32_t price, int32_t x, const Msg &m, const Order &p, int32_t seq,
+                int32_t t) {
+    const int32_t rec[TRADE_WORDS] = {price, x, m.oid, p.oid, m.tid, p.tid, m.side | (seq << 1), t};
+    emit_record(ts, rec);
 }
 
 /* Match an incoming order against the opposite side while it crosses (a market order
@@ -171,7 +175,9 @@ int32_t match(Book &bk, const Msg &m, bool market, TradeSink &ts, int32_t seq, i
 }
 
 /* Process one message (Sec. 4 step 4).  Message types (Reading): 1 limit, 2 partial
- * cancel, 3 delete, 4 market (immediate-or-cancel, no price limit). */
+ * cancel, 3 delete, 4 market (immediate-or-cancel, no price limit), 5 execution of a
+ * named resting order (a replayed execution), 6 a message the book ignores (a replayed
+ * hidden execution, cross trade or trading halt). */
 void process(Book &bk, const Msg &m, TradeSink &ts, int32_t seq, int32_t t) {
     int64_t *ctr = ts.counters;
     ctr[C_MSGS] += 1;
@@ -225,6 +231,28 @@ void process(Book &bk, const Msg &m, TradeSink &ts, int32_t seq, int32_t t) {
         }
         return;
     }
+    case EXECUTE: {
+        /* Reading: a replayed execution names the resting order by id on the message's
+         * side (the side of the executed order); it trades min(qty, the order's qty) at the
+         * order's price against an anonymous aggressor of the other side (order id 0,
+         * trader 0) and leaves the rest of the order with its priority.  A missing id is
+         * a counted no-op, as for cancels. */
+        if (m.qty <= 0) { ctr[C_BAD] += 1; return; }
+        Side &sd = bk.side(m.side);
+        int64_t lk;
+        size_t pos;
+        Order *o = sd.find(m.oid, &lk, &pos);
+        if (!o) { ctr[C_MISS] += 1; return; }
+        const int32_t x = std::min(m.qty, o->qty);
+        const int32_t rec[TRADE_WORDS] = {o->price, x, 0, o->oid, 0, o->tid, (1 - m.side) | (seq << 1), t};
+        emit_record(ts, rec);
+        o->qty -= x;
+        if (o->qty == 0) sd.erase(lk, pos);
+        return;
+    }
+    case IGNORED:
+        ctr[C_IGNORED] += 1;
+        return;
     default:
         ctr[C_BAD] += 1;
         return;

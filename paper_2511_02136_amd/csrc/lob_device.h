@@ -24,9 +24,9 @@ namespace lobk {
 constexpr int WAVE = 64;
 constexpr int NF = 6; /* fields per slot */
 enum { FP = 0, FQ = 1, FO = 2, FT = 3, FS = 4, FN = 5 };
-enum { T_LIMIT = 1, T_PCANCEL = 2, T_DELETE = 3, T_MARKET = 4 };
+enum { T_LIMIT = 1, T_PCANCEL = 2, T_DELETE = 3, T_MARKET = 4, T_EXECUTE = 5, T_IGNORED = 6 };
 enum { C_MSGS, C_TRADES, C_MISS, C_EVICT, C_EVICTED_QTY, C_DROP, C_DROPPED_QTY, C_MARKET_UNFILLED,
-       C_BAD, C_TRADE_OVERFLOW, NCTR };
+       C_BAD, C_TRADE_OVERFLOW, C_IGNORED, NCTR };
 
 /* ---------------------------------------------------------------- wave primitives */
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }

@@ -139,9 +139,10 @@ struct KArgs {
  * message j are read into scalar registers where a handler needs them.
  * ---------------------------------------------------------------------------- */
 /* dispatch code: side in bit 0, operation above it */
-enum { OP_LIMIT = 0, OP_DELETE = 2, OP_PCANCEL = 4, OP_MARKET = 6, OP_BAD = 8 };
-/* Sec. 4 step 4 message semantics: a delete ignores its quantity; a limit, market or
- * partial cancel needs a positive one; other types are invalid */
+enum { OP_LIMIT = 0, OP_DELETE = 2, OP_PCANCEL = 4, OP_MARKET = 6, OP_EXECUTE = 8, OP_IGNORED = 10, OP_BAD = 12 };
+/* Sec. 4 step 4 message semantics: a delete ignores its quantity and an ignored message
+ * everything; a limit, market, partial cancel or execution needs a positive quantity;
+ * other types are invalid */
 __device__ __forceinline__ int op_code(int ts, int qty) {
     const int type = ts & 0xFF;
     int op = OP_BAD;
@@ -149,7 +150,9 @@ __device__ __forceinline__ int op_code(int ts, int qty) {
     if (type == T_DELETE) op = OP_DELETE;
     if (type == T_PCANCEL) op = OP_PCANCEL;
     if (type == T_MARKET) op = OP_MARKET;
-    if (qty <= 0 && type != T_DELETE) op = OP_BAD;
+    if (type == T_EXECUTE) op = OP_EXECUTE;
+    if (type == T_IGNORED) op = OP_IGNORED;
+    if (qty <= 0 && type != T_DELETE && type != T_IGNORED) op = OP_BAD;
     return op | ((ts >> 8) & 1);
 }
 struct Staged {
@@ -498,10 +501,22 @@ struct Run {
         }
     }
 
-    /* ---- cancels: the first order with this id (priority order) on side S.  The top row
-     * is loaded whole; a hit there is removed from registers (each lane takes the record
-     * of the lane above it), deeper hits search and shift row by row. ---- */
-    template <int S, bool PARTIAL>
+    /* ---- messages naming a resting order: the first order with this id (priority order)
+     * on side S.  A delete removes it; a partial cancel takes up to qty from it; a
+     * replayed execution trades up to qty of it at its price against an anonymous
+     * aggressor of the other side.  The top row is loaded whole; a hit there is removed
+     * from registers (each lane takes the record of the lane above it), deeper hits search
+     * and shift row by row. ---- */
+    enum { CX_DELETE = 0, CX_PARTIAL = 1, CX_EXECUTE = 2 };
+    /* the execution of x of the order (price, tid, id oid) of side S */
+    template <int S> __device__ __forceinline__ void executed(int price, int tid, int oid, int x) {
+        write_trade(0, price, x, 0, oid, 0, tid, 1 - S);
+        tr_next += 1;
+        add_fill(tid, S == 0, x, (int64_t)x * price);
+        if (S == 1) st_buy += x; else st_sell += x;
+        st_last = price;
+    }
+    template <int S, int MODE>
     __device__ __forceinline__ void cancel(int qty, int oid) {
         const int n = nS<S>();
         if (n == 0) {
@@ -516,9 +531,11 @@ struct Run {
         int k;
         if (mt) {
             k = (rt << 6) + 63 - __builtin_clzll(mt);
-            if (PARTIAL) {
+            if (MODE != CX_DELETE) {
                 const int cq = rdlane(o.y, k & 63);
-                const int left = cq - min(qty, cq);
+                const int x = min(qty, cq);
+                if (MODE == CX_EXECUTE) executed<S>(rdlane(o.x, k & 63), rdlane(o.w, k & 63), oid, x);
+                const int left = cq - x;
                 if (left > 0) {
                     if (lane == 0) RS<S>(k)->y = left;
                     WAVE_SYNC();
@@ -539,9 +556,12 @@ struct Run {
                 count(C_MISS, 1);
                 return;
             }
-            if (PARTIAL) {
-                const int cq = uni(RS<S>(k)->y);
-                const int left = cq - min(qty, cq);
+            if (MODE != CX_DELETE) {
+                const int4 rk = *RQ<S>(k);
+                const int cq = uni(rk.y);
+                const int x = min(qty, cq);
+                if (MODE == CX_EXECUTE) executed<S>(uni(rk.x), uni(rk.w), oid, x);
+                const int left = cq - x;
                 if (left > 0) {
                     if (lane == 0) RS<S>(k)->y = left;
                     WAVE_SYNC();
@@ -573,15 +593,20 @@ struct Run {
             else limit<1>(m);
         } else if (code < OP_MARKET) {
             if (code < OP_PCANCEL) {
-                if (code == OP_DELETE) cancel<0, false>(0, m.oid());
-                else cancel<1, false>(0, m.oid());
+                if (code == OP_DELETE) cancel<0, CX_DELETE>(0, m.oid());
+                else cancel<1, CX_DELETE>(0, m.oid());
             } else {
-                if (code == OP_PCANCEL) cancel<0, true>(m.qty(), m.oid());
-                else cancel<1, true>(m.qty(), m.oid());
+                if (code == OP_PCANCEL) cancel<0, CX_PARTIAL>(m.qty(), m.oid());
+                else cancel<1, CX_PARTIAL>(m.qty(), m.oid());
             }
-        } else if (code < OP_BAD) {
+        } else if (code < OP_EXECUTE) {
             if (code == OP_MARKET) market<0>(m);
             else market<1>(m);
+        } else if (code < OP_IGNORED) {
+            if (code == OP_EXECUTE) cancel<0, CX_EXECUTE>(m.qty(), m.oid());
+            else cancel<1, CX_EXECUTE>(m.qty(), m.oid());
+        } else if (code < OP_BAD) {
+            count(C_IGNORED, 1);
         } else {
             count(C_BAD, 1);
         }
@@ -925,8 +950,8 @@ struct Run {
             if (x > 0) {
                 /* a cancel message (delete, or partial cancel of x) for this order */
                 const int oid = uni(US<S>(1, j).x);
-                if (D == 0) cancel<S, false>(qt, oid);
-                else cancel<S, true>(x, oid);
+                if (D == 0) cancel<S, CX_DELETE>(qt, oid);
+                else cancel<S, CX_PARTIAL>(x, oid);
                 after_message();
             }
             hi = j - 1;

@@ -19,7 +19,7 @@ _lib = None
 
 OBS_DIM = 40
 TRADE_WORDS = 8
-N_COUNTERS = 10
+N_COUNTERS = 11
 ENV_STATE_WORDS = 8
 AGENT_STATE_WORDS = 4
 BOOK_FIELDS = ("price", "qty", "oid", "tid", "tsec", "tns")

@@ -42,6 +42,8 @@ class _Cfg(ctypes.Structure):
         ("cap_choices", ctypes.c_int32 * 8),
         ("mid0", ctypes.c_int32),
         ("snapshot_fill_pct", ctypes.c_int32),
+        ("exec_pct", ctypes.c_int32),
+        ("ignored_pct", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -85,6 +87,8 @@ class Workload:
     seed: int = SEED_BASE
     mid0: int = 100_000
     snapshot_fill_pct: int = 50
+    exec_pct: int = 0       # percent of replayed messages that are executions of named orders
+    ignored_pct: int = 0    # percent that the book ignores (hidden executions, halts)
 
     def scaled(self, n_envs: Optional[int] = None, n_steps: Optional[int] = None, **kw) -> "Workload":
         d = dataclasses.asdict(self)
@@ -122,6 +126,8 @@ class Workload:
             c.cap_choices[i] = v
         c.mid0 = self.mid0
         c.snapshot_fill_pct = self.snapshot_fill_pct
+        c.exec_pct = self.exec_pct
+        c.ignored_pct = self.ignored_pct
         c.seed = self.seed
         return c
 

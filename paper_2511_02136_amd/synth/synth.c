@@ -31,6 +31,8 @@
 #define SYN_PCANCEL 2
 #define SYN_DELETE 3
 #define SYN_MARKET 4
+#define SYN_EXECUTE 5
+#define SYN_IGNORED 6
 
 typedef struct {
     int32_t n_envs;
@@ -44,6 +46,8 @@ typedef struct {
     int32_t cap_choices[8];
     int32_t mid0;                /* initial mid price in ticks */
     int32_t snapshot_fill_pct;   /* percent of cap placed per side in the reset snapshot */
+    int32_t exec_pct;            /* percent of messages turned into replayed executions */
+    int32_t ignored_pct;         /* percent turned into messages the book ignores */
     uint64_t seed;
 } synth_config;
 
@@ -59,7 +63,8 @@ static inline uint64_t syn_mix(uint64_t z) {
 enum {
     F_TYPE = 1, F_SIDE, F_SIZE, F_MID, F_CANCEL, F_PQTY, F_TIME, F_BURSTTYPE,
     F_GEOM0 = 64,          /* F_GEOM0 + k: k-th geometric trial */
-    F_ENVCAP = 1001, F_ENVMSGS, F_BURST
+    F_ENVCAP = 1001, F_ENVMSGS, F_BURST,
+    F_XTYPE = 2001, F_XAGENT, F_XAGENTK
 };
 
 static inline uint64_t syn_base(uint64_t seed, uint64_t e, uint64_t t, uint64_t m) {
@@ -271,6 +276,12 @@ static void syn_env(const synth_config *c, int32_t e, const int64_t *off, int32_
             } else {
                 uint32_t ut = syn_u32(base, F_TYPE) % 100u;
                 type = ut < 50 ? SYN_LIMIT : ut < 70 ? SYN_PCANCEL : ut < 90 ? SYN_DELETE : SYN_MARKET;
+                if (c->exec_pct > 0 || c->ignored_pct > 0) {
+                    /* (draws that exist only in workloads using these types) */
+                    uint32_t ux = syn_u32(base, F_XTYPE) % 100u;
+                    if (ux < (uint32_t)c->exec_pct) type = SYN_EXECUTE;
+                    else if (ux < (uint32_t)(c->exec_pct + c->ignored_pct)) type = SYN_IGNORED;
+                }
             }
             int32_t side = (int32_t)(syn_u32(base, F_SIDE) & 1u);
             int32_t price = 0, qty = 0, oid = 0;
@@ -286,13 +297,24 @@ static void syn_env(const synth_config *c, int32_t e, const int64_t *off, int32_
                 qty = syn_size(base, F_SIZE);
                 oid = next_oid++;
                 price = mid;
+            } else if (type == SYN_IGNORED) {
+                qty = syn_size(base, F_SIZE);
+                price = mid;
+            } else if (type == SYN_EXECUTE && (syn_u32(base, F_XAGENT) & 3u) == 0) {
+                /* an execution naming one of the first 64 orders of agent 0 or 1 (agent
+                 * order ids are 2^30 | agent << 26 | counter), resting or not */
+                uint32_t ua = syn_u32(base, F_XAGENTK);
+                oid = (int32_t)((1u << 30) | ((ua & 1u) << 26) | ((ua >> 1) & 63u));
+                qty = syn_size(base, F_SIZE);
+                price = mid;
             } else {
                 if (ring_n > 0) {
                     uint32_t k = syn_u32(base, F_CANCEL) % (uint32_t)ring_n;
                     syn_ring_entry r = ring[(ring_head - 1 - (int32_t)k) & 255];
                     side = r.side; price = r.price; oid = r.oid;
-                    qty = type == SYN_PCANCEL ? 1 + (int32_t)(syn_u32(base, F_PQTY) % (uint32_t)r.qty)
-                                              : r.qty;
+                    /* partial cancels, and half of the executions, take part of the order */
+                    const int part = type == SYN_PCANCEL || (type == SYN_EXECUTE && (syn_u32(base, F_XAGENT) & 4u));
+                    qty = part ? 1 + (int32_t)(syn_u32(base, F_PQTY) % (uint32_t)r.qty) : r.qty;
                 } else {
                     oid = 0; qty = 1;
                 }

@@ -6,18 +6,18 @@ nothing else.  It shares no code with the oracle and is only used on tiny inputs
 """
 from __future__ import annotations
 
-LIMIT, PARTIAL_CANCEL, DELETE, MARKET = 1, 2, 3, 4
+LIMIT, PARTIAL_CANCEL, DELETE, MARKET, EXECUTE, IGNORED = 1, 2, 3, 4, 5, 6
 BUY, SELL = 0, 1
 
 # counters (same meaning and order as the oracle's)
-MSGS, TRADES, MISS, EVICT, EVICTED_QTY, DROP, DROPPED_QTY, MARKET_UNFILLED, BAD, OVERFLOW = range(10)
+MSGS, TRADES, MISS, EVICT, EVICTED_QTY, DROP, DROPPED_QTY, MARKET_UNFILLED, BAD, OVERFLOW, IGNORED_CT = range(11)
 
 
 class NaiveBook:
     def __init__(self, cap: int):
         self.cap = cap
         self.sides = {BUY: [], SELL: []}  # entries: [price, qty, oid, tid, tsec, tns]
-        self.counters = [0] * 10
+        self.counters = [0] * 11
 
     def _sort(self, s):
         # bids: highest price first; asks: lowest first; stable => arrival order kept
@@ -81,6 +81,27 @@ class NaiveBook:
                             lst.pop(j)
                     return trades
             c[MISS] += 1
+            return trades
+        if typ == EXECUTE:
+            # a replayed execution of the named resting order on `side`: the trade is at
+            # that order's price, the aggressor (id 0, trader 0) is on the other side
+            if qty <= 0:
+                c[BAD] += 1
+                return trades
+            lst = self.sides[side]
+            for j, o in enumerate(lst):
+                if o[2] == oid:
+                    x = min(qty, o[1])
+                    trades.append([o[0], x, 0, o[2], 0, o[3], (1 - side) | (seq << 1), t])
+                    c[TRADES] += 1
+                    o[1] -= x
+                    if o[1] == 0:
+                        lst.pop(j)
+                    return trades
+            c[MISS] += 1
+            return trades
+        if typ == IGNORED:
+            c[IGNORED_CT] += 1
             return trades
         c[BAD] += 1
         return trades

@@ -88,6 +88,9 @@ SMALL = [
                    agents=("mm", "dir"), seed=35, snapshot_fill_pct=100),
     synth.Workload("tiny_books", n_envs=32, n_steps=16, msgs_per_step=60, cap=3, agents=("exec", "mm", "dir", "mm"),
                    seed=36, snapshot_fill_pct=100),
+    # replayed executions of named orders (some of agents' orders) and ignored messages
+    synth.Workload("executions", n_envs=48, n_steps=12, msgs_range=(20, 300), cap_choices=(50, 100, 200),
+                   agents=("exec", "mm"), seed=38, exec_pct=12, ignored_pct=4),
     # the largest capacity the library accepts (16 rows of 64 orders per side), books full
     # from the start: the last row, evictions and the time lookup of every row
     synth.Workload("max_cap", n_envs=8, n_steps=6, msgs_per_step=400, cap=1024, agents=("exec", "mm"),

@@ -19,7 +19,7 @@ import pytest
 from naive_book import NaiveBook
 from oracle import OracleBook, COUNTER_NAMES
 
-LIMIT, PARTIAL_CANCEL, DELETE, MARKET = 1, 2, 3, 4
+LIMIT, PARTIAL_CANCEL, DELETE, MARKET, EXECUTE, IGNORED = 1, 2, 3, 4, 5, 6
 BUY, SELL = 0, 1
 CI = {n: i for i, n in enumerate(COUNTER_NAMES)}
 
@@ -125,6 +125,39 @@ def test_sell_side_mirror_and_evict_on_ask_side():
     assert book_view(b, SELL) == [] and book_view(b, BUY) == []
 
 
+def test_replayed_executions_of_named_orders():
+    """A replayed execution names a resting order by id on its own side: the trade is at
+    that order's price against an anonymous aggressor of the other side, the rest of the
+    order keeps its priority; a missing id is a miss, qty <= 0 is malformed."""
+    b = OracleBook(4)
+    for side, p, q, oid in [(BUY, 100, 5, 1), (BUY, 100, 3, 2), (BUY, 99, 4, 3), (SELL, 102, 2, 4)]:
+        b.process(ts(LIMIT, side), p, q, oid, tid=7)
+    # 2 of order #2 (second in the 100 queue): it keeps its place behind #1
+    tr = b.process(ts(EXECUTE, BUY), 0, 2, 2, tid=9, seq=4, t=3)
+    assert [list(map(int, x)) for x in tr] == [[100, 2, 0, 2, 0, 7, SELL | (4 << 1), 3]]
+    assert book_view(b, BUY) == [(100, 5, 1), (100, 1, 2), (99, 4, 3)]
+    # more than order #1 holds: only its 5, and it leaves the book
+    tr = b.process(ts(EXECUTE, BUY), 0, 9, 1)
+    assert trade_view(tr) == [(100, 5, 0, 1)]
+    assert book_view(b, BUY) == [(100, 1, 2), (99, 4, 3)]
+    # an ask executed whole: the aggressor is a buyer
+    tr = b.process(ts(EXECUTE, SELL), 0, 2, 4, seq=6)
+    assert [int(v) for v in tr[0]][:7] == [102, 2, 0, 4, 0, 7, BUY | (6 << 1)]
+    assert book_view(b, SELL) == []
+    # the id on the wrong side, an unknown id, and qty 0
+    assert len(b.process(ts(EXECUTE, SELL), 0, 1, 3)) == 0
+    assert len(b.process(ts(EXECUTE, BUY), 0, 1, 77)) == 0
+    assert len(b.process(ts(EXECUTE, BUY), 0, 0, 3)) == 0
+    assert b.counters[CI["miss"]] == 2 and b.counters[CI["bad"]] == 1
+    assert b.counters[CI["trades"]] == 3
+    # ignored messages (replayed hidden executions, cross trades, halts) change nothing
+    assert len(b.process(ts(IGNORED, BUY), 100, 5, 1)) == 0
+    assert len(b.process(ts(IGNORED, SELL), 0, 0, 0)) == 0
+    assert b.counters[CI["ignored"]] == 2
+    assert book_view(b, BUY) == [(100, 1, 2), (99, 4, 3)]
+    assert b.counters[CI["msgs"]] == 4 + 8
+
+
 def test_malformed_messages_are_counted_noops():
     b = OracleBook(3)
     b.process(ts(LIMIT, BUY), 100, 0, 1)
@@ -157,9 +190,9 @@ def total_qty(b, s):
 
 
 def random_msg(rng, issued, pmax=6, qmax=6):
-    typ = rng.choice([LIMIT, LIMIT, LIMIT, PARTIAL_CANCEL, DELETE, MARKET])
+    typ = rng.choice([LIMIT, LIMIT, LIMIT, PARTIAL_CANCEL, DELETE, MARKET, EXECUTE, IGNORED])
     side = rng.randrange(2)
-    if typ in (PARTIAL_CANCEL, DELETE):
+    if typ in (PARTIAL_CANCEL, DELETE, EXECUTE):
         if issued and rng.random() < 0.8:
             oid, side = rng.choice(issued)
         else:
@@ -203,6 +236,13 @@ def test_invariants_and_conservation_random(seed):
             for t in tr:
                 if typ == LIMIT:
                     assert (t[0] <= p) if side == BUY else (t[0] >= p)
+        elif typ == EXECUTE:
+            # the named side loses exactly the executed volume, at most q, in one trade
+            assert len(tr) <= 1 and traded <= q
+            assert before[side] - after[side] == traded
+            assert after[1 - side] == before[1 - side]
+        elif typ == IGNORED:
+            assert traded == 0 and after == before
         else:
             assert traded == 0
             assert after[1 - side] == before[1 - side]
@@ -233,6 +273,8 @@ def test_brute_force_exhaustive_tiny_alphabet():
         for oid in (1, 2):
             alphabet.append((PARTIAL_CANCEL, side, 0, 1, oid))
             alphabet.append((DELETE, side, 0, 0, oid))
+            alphabet.append((EXECUTE, side, 0, 1, oid))
+        alphabet.append((IGNORED, side, 0, 0, 0))
     n = 0
     for cap in (1, 2):
         for seq in itertools.product(alphabet, repeat=3):

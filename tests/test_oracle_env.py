@@ -111,7 +111,7 @@ def test_two_agent_scenario_step_by_step():
     st = o.state()
     assert st["env"][0].tolist() == [103, 103, 206, 200, 2, 10, 2, 4]
     assert st["agents"][0].tolist() == [[-6, 610, 0, 2], [-1, 103, 0, 2]]
-    assert st["counters"][0].tolist() == [8, 4, 0, 0, 0, 0, 0, 0, 0, 0]
+    assert st["counters"][0].tolist() == [8, 4, 0, 0, 0, 0, 0, 0, 0, 0, 0]
     # observations after step 0
     ob = out["obs"][0, :, 0]
     exec0 = [4, 2, 2, 10, 0, 10, 0, 0, 0, 0, 0, 0, 0, 9, 0, 0, 0, 0, 0, 0, 0, 0, 0,
@@ -246,6 +246,24 @@ def test_oracle_matches_naive_env(agents, policy):
     out = o.step(s, n_steps=12, actions=acts)
     envs, outs = run_naive(s, w, 12, acts, exec_task=60, q0=4)
     compare(o, out, envs, outs, 12, A)
+
+
+@pytest.mark.parametrize("agents", [("exec", "mm"), ("mm", "dir")])
+def test_oracle_matches_naive_env_with_executions_and_ignored(agents):
+    """Replayed executions (some naming agent orders, so passive agent fills) and ignored
+    messages in the stream."""
+    w = synth.Workload("t", n_envs=6, n_steps=12, msgs_range=(1, 60), cap_choices=(3, 6, 12),
+                       agents=agents, seed=120 + len(agents[0]), mid0=1000, snapshot_fill_pct=50,
+                       exec_pct=15, ignored_pct=5)
+    s = synth.generate(w, threads=2)
+    t = s.ts & 0xFF
+    assert (t == 5).sum() > 0 and (t == 6).sum() > 0
+    o = OracleEnvs(s.caps, w.max_cap, synth.agent_kinds(agents), w.ep_len, w.seed, exec_task=60, exec_q0=4)
+    o.reset(s.book)
+    out = o.step(s, n_steps=12)
+    envs, outs = run_naive(s, w, 12, None, exec_task=60, q0=4)
+    compare(o, out, envs, outs, 12, len(agents))
+    assert o.state()["counters"][:, 10].sum() == (t == 6).sum()
 
 
 def test_oracle_matches_naive_env_rewards_with_weights():
