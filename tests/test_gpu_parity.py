@@ -367,3 +367,35 @@ def test_schedule_independence():
     got = env.rollout(ds, w.n_steps, trade_off=toff)
     for key in ("n_trades", "fills", "reward", "obs", "done", "actions"):
         assert torch.equal(got[key], ref[key]), key
+
+
+@pytest.mark.parametrize("agents,mode", [((), "rollout"), (("exec", "mm"), "step"), (("exec", "mm"), "rollout")])
+def test_lobster_format_day_parity(tmp_path, agents, mode):
+    """A synthetic day in LOBSTER's file formats (messages with executions of named
+    orders and ignored messages; its order-book file), parsed, cut into env windows with
+    reset books from the order-book rows before them, replayed on the GPU and by the
+    oracle."""
+    from paper_2511_02136_amd import lobster
+    from lobster_files import synthetic_day
+    _, DeviceStream = _lob()
+    _, msg_path, book_path, _ = synthetic_day(str(tmp_path), n=3000)
+    m = lobster.read_messages(msg_path)
+    starts = [0, 150, 400, 900, 1200, 1500, 1800, 2100]
+    n_steps, per = 8, 60
+    s = lobster.build_stream(m, starts, n_steps=n_steps, msgs_per_step=per, cap=64,
+                             books=lobster.books_before(book_path, starts), agents=agents, seed=61)
+    w = s.workload
+    print(f"\n[parity] lobster day envs={w.n_envs} steps={n_steps} agents={agents} mode={mode}", flush=True)
+    o = oracle_for(s, s.book, s.caps, w.max_cap, agents, w.ep_len, w.seed)
+    ref = o.step(s, n_steps=n_steps)
+    env = gpu_env(s.caps, w.max_cap, agents, w.ep_len, w.seed, s.book)
+    ds = DeviceStream.from_host(s)
+    toff = torch.from_numpy(ref["trade_off"]).cuda()
+    got = env.rollout(ds, n_steps, trade_off=toff) if mode == "rollout" else run_steps(env, ds, n_steps, None, toff)
+    torch.cuda.synchronize()
+    name = f"lobster/{mode}"
+    assert_same_outputs(got, ref, n_steps, what=name)
+    assert_same_books(env.books(), o.books(), what=name)
+    assert_same_state(env.state(), o.state(), what=name)
+    ct = o.state()["counters"]
+    assert ct[:, 10].sum() > 0 and ct[:, 1].sum() > 0  # ignored messages and trades occurred
