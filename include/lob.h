@@ -72,6 +72,8 @@ enum {
 #define LOB_AGENT_EXEC 0 /* order execution, sell task; 9 actions */
 #define LOB_AGENT_MM 1   /* market making, fixed-quantity action space; 9 actions */
 #define LOB_AGENT_DIR 2  /* directional trading; 3 actions */
+#define LOB_AGENT_MM_BUYSELL 3 /* market making as LOB_AGENT_MM, rewarded by the buy-sell
+                                * PnL (Eq. 4) minus the quadratic inventory penalty */
 
 typedef struct lob_ctx lob_ctx;
 

@@ -27,7 +27,7 @@ namespace {
 
 enum { LIMIT = 1, PARTIAL_CANCEL = 2, DELETE = 3, MARKET = 4, EXECUTE = 5, IGNORED = 6 };
 enum { BUY = 0, SELL = 1 };
-enum { AG_EXEC = 0, AG_MM = 1, AG_DIR = 2 };
+enum { AG_EXEC = 0, AG_MM = 1, AG_DIR = 2, AG_MM_BUYSELL = 3 };
 /* per-env counters */
 enum { C_MSGS, C_TRADES, C_MISS, C_EVICT, C_EVICTED_QTY, C_DROP, C_DROPPED_QTY,
        C_MARKET_UNFILLED, C_BAD, C_TRADE_OVERFLOW, C_IGNORED, N_COUNTERS };
@@ -492,7 +492,7 @@ void env_step(Oracle &O, int e, int s, const StepIO &io, TradeSink &sink) {
 
         std::vector<Desire> lim, mkt;
         if (kind == AG_EXEC) decode_exec(a, bb0, ba0, ag.rem, O.cfg.exec_q0, lim, mkt);
-        else if (kind == AG_MM) decode_mm(a, bb0, ba0, O.cfg.mm_q, lim);
+        else if (kind == AG_MM || kind == AG_MM_BUYSELL) decode_mm(a, bb0, ba0, O.cfg.mm_q, lim);
         else decode_dir(a, bb0, ba0, O.cfg.dir_q, lim);
         /* desired quantity per (side, price), in order of first appearance */
         std::vector<Desire> levels;
@@ -649,6 +649,10 @@ void env_step(Oracle &O, int e, int s, const StepIO &io, TradeSink &sink) {
             const double pos = psi_inv > 0.0 ? psi_inv : 0.0;
             r = psi_b + psi_s + psi_inv - (1.0 - (double)O.cfg.mm_lambda) * pos -
                 (double)O.cfg.mm_rho * ((double)ag.inv * (double)ag.inv);
+        } else if (kind == AG_MM_BUYSELL) {
+            /* the market maker rewarded by Eq. 4 (buy-sell), minus the quadratic
+             * inventory penalty rho * I^2 */
+            r = psi_b + psi_s - (double)O.cfg.mm_rho * ((double)ag.inv * (double)ag.inv);
         } else if (kind == AG_DIR) {
             /* Eq. 4 (buy-sell) */
             r = psi_b + psi_s;

@@ -700,7 +700,7 @@ struct Run {
                     }
                 }
             }
-        } else if (kind == LOB_AGENT_MM) {
+        } else if (kind == LOB_AGENT_MM || kind == LOB_AGENT_MM_BUYSELL) {
             /* fixed-quantity quotes: bid = bb - ob (below the best ask), ask = ba + oa
              * (above the best bid); action 8 ladders offsets 0..3 on both sides */
             const int q = a.mm_q;
@@ -1072,6 +1072,9 @@ struct Run {
                 const double psi_inv = (double)inv * (mt - mprev);
                 const double pos = psi_inv > 0.0 ? psi_inv : 0.0;
                 r = psi_b + psi_s + psi_inv - (1.0 - (double)a.lam) * pos - (double)a.rho * ((double)inv * (double)inv);
+            } else if (kind == LOB_AGENT_MM_BUYSELL) {
+                /* Eq. 4 with the quadratic inventory penalty */
+                r = psi_b + psi_s - (double)a.rho * ((double)inv * (double)inv);
             } else if (kind == LOB_AGENT_DIR) {
                 /* Eq. 4 */
                 r = psi_b + psi_s;
@@ -1601,7 +1604,7 @@ int lob_init(const lob_config *cfg, lob_ctx **out) {
         if (v < 1 || v > cfg->max_cap) { delete c; return LOB_EINVAL; }
     for (int i = 0; i < cfg->n_agents; ++i) {
         const int k = cfg->agent_kind[i];
-        if (k < 0 || k > 2) { delete c; return LOB_EINVAL; }
+        if (k < 0 || k > LOB_AGENT_MM_BUYSELL) { delete c; return LOB_EINVAL; }
         c->kinds.push_back(k);
         c->kinds_packed |= k << (4 * i);
     }

@@ -23,7 +23,7 @@ N_COUNTERS = 11
 ENV_STATE_WORDS = 8
 AGENT_STATE_WORDS = 4
 BOOK_FIELDS = ("price", "qty", "oid", "tid", "tsec", "tns")
-AGENT_KINDS = {"exec": 0, "mm": 1, "dir": 2}
+AGENT_KINDS = {"exec": 0, "mm": 1, "dir": 2, "mm_buysell": 3}
 
 
 class LobError(RuntimeError):

@@ -11,7 +11,7 @@ from naive_book import NaiveBook, LIMIT, PARTIAL_CANCEL, DELETE, MARKET, BUY, SE
 M64 = (1 << 64) - 1
 DOM_SHUFFLE = 0x5348554646
 DOM_ACTION = 0x414354
-EXEC, MM, DIR = 0, 1, 2
+EXEC, MM, DIR, MM_BUYSELL = 0, 1, 2, 3
 
 
 def sm64(z):
@@ -82,7 +82,7 @@ class NaiveEnv:
                         mkt.append((SELL, q))
                     else:
                         lim.append((SELL, p, q))
-        elif k == MM:
+        elif k in (MM, MM_BUYSELL):
             offs = {1: [(BUY, 2), (SELL, 2)], 2: [(BUY, 4), (SELL, 4)], 3: [(BUY, -1), (SELL, -1)],
                     4: [(BUY, 2)], 5: [(SELL, 2)], 6: [(BUY, 5), (SELL, -1)], 7: [(BUY, -1), (SELL, 5)],
                     8: [(BUY, 0), (BUY, 1), (BUY, 2), (BUY, 3), (SELL, 0), (SELL, 1), (SELL, 2), (SELL, 3)]}
@@ -206,6 +206,8 @@ class NaiveEnv:
                 psi_inv = self.inv[i] * (mid2 * 0.5 - self.mid2_prev * 0.5)
                 r = psi_b + psi_s + psi_inv - (1.0 - self.lam) * (psi_inv if psi_inv > 0.0 else 0.0) \
                     - self.rho * (float(self.inv[i]) * float(self.inv[i]))
+            elif self.kinds[i] == MM_BUYSELL:
+                r = psi_b + psi_s - self.rho * (float(self.inv[i]) * float(self.inv[i]))
             elif self.kinds[i] == DIR:
                 r = psi_b + psi_s
             else:

@@ -115,6 +115,15 @@ def test_parity_reward_weights():
                 name="weights")
 
 
+@pytest.mark.parametrize("mode", ["step", "rollout"])
+def test_parity_buysell_market_maker(mode):
+    """The market maker with the buy-sell reward (Eq. 4) and the quadratic inventory
+    penalty, next to the Spooner market maker and the execution agent."""
+    w = synth.Workload("buysell", n_envs=40, n_steps=10, msgs_per_step=80, cap=64,
+                       agents=("mm_buysell", "exec", "mm"), seed=39)
+    parity_case(w, 10, mode, kw=dict(mm_lambda=0.3, mm_rho=0.02, exec_task=60, exec_q0=3), name=f"buysell/{mode}")
+
+
 def test_rollout_resumes_across_calls():
     """128 = 5 + 7 steps in two rollouts equals the oracle's 12 steps (state carried)."""
     _, DeviceStream = _lob()

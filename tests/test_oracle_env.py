@@ -266,6 +266,26 @@ def test_oracle_matches_naive_env_with_executions_and_ignored(agents):
     assert o.state()["counters"][:, 10].sum() == (t == 6).sum()
 
 
+def test_buysell_market_maker_matches_naive_env():
+    """The market maker rewarded by the buy-sell PnL (Eq. 4) and the quadratic inventory
+    penalty: same actions as the Spooner market maker, its own reward."""
+    agents = ("mm_buysell", "exec", "mm")
+    w = synth.Workload("t", n_envs=4, n_steps=10, msgs_per_step=30, cap=8, agents=agents, seed=131, mid0=1000)
+    s = synth.generate(w, threads=2)
+    kinds = synth.agent_kinds(agents)
+    assert kinds.tolist() == [3, 0, 1]
+    rng = np.random.default_rng(5)
+    acts = np.stack([rng.integers(0, 9, size=(10, w.n_envs)) for _ in kinds], 1).astype(np.int32)
+    acts[:, 2] = acts[:, 0]  # the two market makers act alike: only the rewards differ
+    kw = dict(exec_task=60, exec_q0=4)
+    o = OracleEnvs(s.caps, w.max_cap, kinds, w.ep_len, w.seed, mm_lambda=0.25, mm_rho=0.5, **kw)
+    o.reset(s.book)
+    out = o.step(s, n_steps=10, actions=acts)
+    envs, outs = run_naive(s, w, 10, acts, exec_task=60, q0=4, lam=0.25, rho=0.5)
+    compare(o, out, envs, outs, 10, len(agents))
+    assert np.isfinite(out["reward"]).all()
+
+
 def test_oracle_matches_naive_env_rewards_with_weights():
     w = synth.Workload("t", n_envs=3, n_steps=10, msgs_per_step=30, cap=8, agents=("mm", "exec", "mm"),
                        seed=5, mid0=500)
