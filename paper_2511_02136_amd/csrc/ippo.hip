@@ -33,6 +33,7 @@ constexpr int O_W1 = 0, O_B1 = O_W1 + IN * HID, O_W2 = O_B1 + HID, O_B2 = O_W2 +
               O_B3 = O_W3 + HID * OUT, NPARAM = O_B3 + OUT;
 static_assert(NPARAM == 78858, "parameter count");
 constexpr int PW = NPARAM + 4; /* per-workgroup partial: gradient, then the 4 loss sums */
+constexpr int64_t PARAM_COPY_BYTES = NPARAM * 4 + 16; /* workspace room for an aligned parameter copy */
 
 constexpr int TR = 64;          /* samples per workgroup tile */
 /* waves per workgroup: four per SIMD (the LDS tile allows one workgroup per CU), so the
@@ -43,6 +44,7 @@ constexpr int NW = 16, NTH = 64 * NW;
 constexpr int CW = HID / NW, CT = CW / 16; /* hidden columns per wave, in 16-wide tiles */
 constexpr int RT = CT;                     /* 16-row tiles per wave over the 256 hidden rows */
 constexpr int XS = 52;          /* LDS row stride of the input tile (cols 40..51 zero) */
+constexpr int IN1 = 48;         /* layer-1 depth: IN rounded up to a multiple of 16 */
 constexpr int HS = 260;         /* LDS row stride of hidden tiles */
 constexpr int OS = 17;          /* LDS row stride of the output tile */
 constexpr int LDS_FLOATS = TR * XS + 2 * TR * HS + TR * OS;
@@ -92,6 +94,74 @@ __device__ __forceinline__ void gemm(floatx4 (&acc)[MT][NT], int K, int r0, int 
     }
 }
 
+/* The same product with K a multiple of 16 and k permuted inside each block of 16: in
+ * MFMA step t of the block at k0, lane l supplies k = k0 + 4(l/16) + t for both operands
+ * (only the order of the additions changes).  A lane's four k values are then
+ * consecutive, so an operand stored k-contiguous arrives in one 16-byte load.
+ * A4(i, kb) / B4(kb, j) return the operand at k = kb .. kb+3; one block is prefetched. */
+template <int MT, int NT, class FA, class FB>
+__device__ __forceinline__ void gemm16(floatx4 (&acc)[MT][NT], int K, int r0, int c0, FA A4, FB B4) {
+    const int l = (int)(threadIdx.x & 63);
+    const int li = l & 15, kq = 4 * (l >> 4);
+    floatx4 a[MT], b[NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) a[m] = A4(r0 + 16 * m + li, kq);
+#pragma unroll
+    for (int n = 0; n < NT; ++n) b[n] = B4(kq, c0 + 16 * n + li);
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const int kn = min(k0 + 16, K - 16) + kq; /* past the end: the last block again */
+        floatx4 an[MT], bn[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) an[m] = A4(r0 + 16 * m + li, kn);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) bn[n] = B4(kn, c0 + 16 * n + li);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int n = 0; n < NT; ++n) acc[m][n] = mfma(a[m][t], b[n][t], acc[m][n]);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) a[m] = an[m];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) b[n] = bn[n];
+    }
+}
+
+/* acc[m][n] += A[rows][0..K) * B[0..K)[c0+16n ..] for the 64 rows from r0 with the rows of
+ * the four tiles interleaved: row li of tile m is r0 + 4 li + m.  The four tiles' A
+ * operands at one k are then consecutive, so an A stored row-contiguous arrives in one
+ * 16-byte load: A4(i0, k) returns A(i0 .. i0+3, k).  Two steps are prefetched. */
+template <int NT, class FA, class FB>
+__device__ __forceinline__ void gemm_rows4(floatx4 (&acc)[4][NT], int K, int r0, int c0, FA A4, FB B) {
+    const int l = (int)(threadIdx.x & 63);
+    const int li = l & 15, lk = l >> 4;
+    const int kl = K - 4;
+    floatx4 a[2];
+    float b[2][NT];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        a[s] = A4(r0 + 4 * li, 4 * s + lk);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) b[s][n] = B(4 * s + lk, c0 + 16 * n + li);
+    }
+    for (int k0 = 0; k0 < K; k0 += 8) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < NT; ++n) acc[m][n] = mfma(a[s][m], b[s][n], acc[m][n]);
+            const int kn = min(k0 + 4 * s + 8, kl) + lk;
+            a[s] = A4(r0 + 4 * li, kn);
+#pragma unroll
+            for (int n = 0; n < NT; ++n) b[s][n] = B(kn, c0 + 16 * n + li);
+        }
+    }
+}
+
+__device__ __forceinline__ floatx4 lds4(const float *p) { return *(const floatx4 *)p; }
+
 /* row / column of accumulator element i of a 16x16 tile held by this lane */
 __device__ __forceinline__ int acc_row(int i) { return 4 * ((int)(threadIdx.x & 63) >> 4) + i; }
 __device__ __forceinline__ int acc_col() { return (int)(threadIdx.x & 15); }
@@ -113,8 +183,14 @@ __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const 
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
-        gemm<4, CT>(acc, IN, 0, CW * wave, [&](int i, int k) { return X[i * XS + k]; },
-                    [&](int k, int j) { return P[O_W1 + k * HID + j]; });
+        /* K = 48: X columns 40..47 are zero and the W1 rows past 40 read as zero */
+        gemm16<4, CT>(acc, IN1, 0, CW * wave, [&](int i, int kb) { return lds4(X + i * XS + kb); },
+                      [&](int kb, int j) {
+                          floatx4 v;
+#pragma unroll
+                          for (int t = 0; t < 4; ++t) v[t] = kb + t < IN ? P[O_W1 + (kb + t) * HID + j] : 0.f;
+                          return v;
+                      });
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -133,8 +209,13 @@ __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const 
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
-        gemm<4, CT>(acc, HID, 0, CW * wave, [&](int i, int k) { return H1[i * HS + k]; },
-                    [&](int k, int j) { return P[O_W2 + k * HID + j]; });
+        gemm16<4, CT>(acc, HID, 0, CW * wave, [&](int i, int kb) { return lds4(H1 + i * HS + kb); },
+                      [&](int kb, int j) {
+                          floatx4 v;
+#pragma unroll
+                          for (int t = 0; t < 4; ++t) v[t] = P[O_W2 + (kb + t) * HID + j];
+                          return v;
+                      });
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -146,15 +227,28 @@ __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const 
                 }
     }
     __syncthreads();
-    /* layer 3: wave w < 4 computes rows 16w..16w+15, cols 0..15 */
+    /* layer 3: wave w < 4 computes rows 16w..16w+15, cols 0..15, k permuted in blocks of
+     * 16 as in gemm16.  The lane's whole W3 column is loaded first, so the weight loads
+     * (from L2) wait once rather than once per block. */
     if (wave < TR / 16) {
-        floatx4 acc[1][1] = {{zero4()}};
-        gemm<1, 1>(acc, HID, 16 * wave, 0, [&](int i, int k) { return H2[i * HS + k]; },
-                   [&](int k, int j) { return j < OUT ? P[O_W3 + k * OUT + j] : 0.f; });
+        const int li = tid & 15, kq = 4 * ((tid & 63) >> 4);
+        floatx4 bw[HID / 16];
+#pragma unroll
+        for (int s = 0; s < HID / 16; ++s)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) bw[s][t] = li < OUT ? P[O_W3 + (16 * s + kq + t) * OUT + li] : 0.f;
+        floatx4 acc = zero4();
+        const float *hr = H2 + (16 * wave + li) * HS + kq;
+#pragma unroll
+        for (int s = 0; s < HID / 16; ++s) {
+            const floatx4 av = lds4(hr + 16 * s);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc = mfma(av[t], bw[s][t], acc);
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 16 * wave + acc_row(i), c = acc_col();
-            O[r * OS + c] = c < OUT ? acc[0][0][i] + P[O_B3 + c] : 0.f;
+            O[r * OS + c] = c < OUT ? acc[i] + P[O_B3 + c] : 0.f;
         }
     }
     __syncthreads();
@@ -348,8 +442,19 @@ __global__ void __launch_bounds__(NTH) k_ppo_fwd_bwd(PpoArgs a) {
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
-        gemm<4, CT>(acc, OUTP, 0, CW * wave, [&](int i, int k) { return O[i * OS + k]; },
-                    [&](int k, int j) { return k < OUT ? P[O_W3 + j * OUT + k] : 0.f; });
+        gemm16<4, CT>(acc, OUTP, 0, CW * wave,
+                      [&](int i, int kb) {
+                          floatx4 v;
+#pragma unroll
+                          for (int t = 0; t < 4; ++t) v[t] = O[i * OS + kb + t];
+                          return v;
+                      },
+                      [&](int kb, int j) {
+                          floatx4 v;
+#pragma unroll
+                          for (int t = 0; t < 4; ++t) v[t] = kb + t < OUT ? P[O_W3 + j * OUT + kb + t] : 0.f;
+                          return v;
+                      });
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -370,15 +475,15 @@ __global__ void __launch_bounds__(NTH) k_ppo_fwd_bwd(PpoArgs a) {
 #pragma unroll
             for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
         const int r0 = 64 * pass, c0 = CW * wave;
-        gemm<4, CT>(acc, TR, r0, c0, [&](int i, int k) { return H1[k * HS + i]; },
-                    [&](int k, int j) { return H2[k * HS + j]; });
+        gemm_rows4<CT>(acc, TR, r0, c0, [&](int i0, int k) { return lds4(H1 + k * HS + i0); },
+                       [&](int k, int j) { return H2[k * HS + j]; });
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int n = 0; n < CT; ++n)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int r = r0 + 16 * m + acc_row(i), c = c0 + 16 * n + acc_col();
+                    const int r = r0 + 4 * acc_row(i) + m, c = c0 + 16 * n + acc_col();
                     G[O_W2 + r * HID + c] = acc[m][n][i];
                 }
     }
@@ -395,8 +500,10 @@ __global__ void __launch_bounds__(NTH) k_ppo_fwd_bwd(PpoArgs a) {
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
-        gemm<4, CT>(acc, HID, 0, CW * wave, [&](int i, int k) { return H2[i * HS + k]; },
-                    [&](int k, int j) { return P[O_W2 + j * HID + k]; });
+        /* W2 read transposed: a lane's four k values are consecutive in memory (the
+         * parameters are 16-byte aligned) */
+        gemm16<4, CT>(acc, HID, 0, CW * wave, [&](int i, int kb) { return lds4(H2 + i * HS + kb); },
+                      [&](int kb, int j) { return *(const floatx4 *)(P + O_W2 + j * HID + kb); });
         /* each element of H1 is read and rewritten by the lane that owns it */
 #pragma unroll
         for (int m = 0; m < 4; ++m)
@@ -527,7 +634,7 @@ int lob_gae(const float *reward, const float *value, const uint8_t *done, const 
 int64_t lob_ppo_workspace_bytes(int32_t m) {
     if (m <= 0) return LOB_EINVAL;
     const int64_t nwg = (m + TR - 1) / TR, nch = (nwg + RCH - 1) / RCH;
-    return (nwg + nch) * PW * 4;
+    return (nwg + nch) * PW * 4 + PARAM_COPY_BYTES;
 }
 
 int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, const float *logp_old,
@@ -539,13 +646,22 @@ int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, c
     if (m <= 0 || n_actions < 1 || n_actions > 9 || !(clip > 0.f)) return LOB_EINVAL;
     const int nwg = (m + TR - 1) / TR;
     const int nch = (nwg + RCH - 1) / RCH;
-    if (workspace_bytes < (int64_t)(nwg + nch) * PW * 4) return LOB_EINVAL;
+    const int64_t part_bytes = (int64_t)(nwg + nch) * PW * 4;
+    if (workspace_bytes < part_bytes + PARAM_COPY_BYTES) return LOB_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    /* the kernel reads W2 in 16-byte loads: parameters that are not 16-byte aligned (a
+     * row of a [networks][LOB_PPO_PARAMS] array) are first copied into the workspace */
+    if ((uintptr_t)params & 15) {
+        float *copy = (float *)(((uintptr_t)workspace + part_bytes + 15) & ~(uintptr_t)15);
+        if (hipMemcpyAsync(copy, params, (size_t)NPARAM * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return LOB_EHIP;
+        params = copy;
+    }
     PpoArgs a;
     a.params = params; a.obs = obs; a.act = act; a.logp_old = logp_old; a.adv = adv; a.ret = ret; a.v_old = v_old;
     a.m = m; a.n_act = n_actions; a.clip = clip; a.c_v = c_v; a.c_e = c_e; a.scale = 1.0f / (float)m;
     a.partial = workspace;
     if (!lds_opt_in()) return LOB_EHIP;
-    hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_ppo_fwd_bwd, dim3((unsigned)nwg), dim3(NTH), LDS_FLOATS * 4, st, a);
     float *sums = workspace + (int64_t)nwg * PW;
     hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((PW + 255) / 256), (unsigned)nch), dim3(256), 0, st,

@@ -139,6 +139,27 @@ def test_fused_ppo_loss_and_gradient(m, n_act, big):
     assert np.array_equal(grad2.cpu().numpy().astype(np.float64), grad)
 
 
+def test_fused_ppo_with_unaligned_parameters():
+    """The second network of a [2][78858] array starts 315,432 bytes in (not a multiple of
+    16): the call copies it to aligned workspace first and must give the same loss and
+    gradient, bit for bit, as the same values in their own allocation."""
+    ippo = _ippo()
+    rng = np.random.default_rng(21)
+    P2 = rand_params(21, 2)
+    obs, act, lpo, adv, ret, vo = batch(rng, 150, 9, P2[1].astype(np.float64))
+    args = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (obs, act.astype(np.int32), lpo, adv, ret, vo)]
+    both = torch.from_numpy(P2).cuda()
+    row = both[1]
+    assert row.data_ptr() % 16 != 0
+    loss_a, grad_a = ippo.ppo_fwd_bwd(row, *args, 9)
+    loss_b, grad_b = ippo.ppo_fwd_bwd(row.clone(), *args, 9)
+    assert torch.equal(loss_a, loss_b) and torch.equal(grad_a, grad_b)
+    assert torch.equal(both[1], torch.from_numpy(P2[1]).cuda())  # the input is not modified
+    ref_loss, ref_grad = R.ppo_loss_and_grad(P2[1].astype(np.float64), obs, act, lpo, adv, ret, vo, 9)
+    err = np.linalg.norm(grad_a.cpu().numpy().astype(np.float64) - ref_grad) / np.linalg.norm(ref_grad)
+    assert err <= 1e-5, err
+
+
 def test_autograd_function_and_optimizer_step():
     ippo = _ippo()
     rng = np.random.default_rng(9)
