@@ -263,8 +263,10 @@ int64_t lob_ppo_workspace_bytes(int32_t m);
  * clip) - R)^2)), entropy = mean of the policy entropy.  Writes loss [4] = the sums over
  * the minibatch of the per-sample total, policy, value and entropy terms (divide by m for
  * the means) and grad [LOB_PPO_PARAMS] = gradient of the mean total loss (device).
- * workspace: device, >= lob_ppo_workspace_bytes(m); params that are not 16-byte aligned
- * are copied into it first (stream-ordered).  Deterministic (fixed reduction order). */
+ * workspace: device, 16-byte aligned, >= lob_ppo_workspace_bytes(m) (LOB_EINVAL otherwise);
+ * params that are not 16-byte aligned are copied into it first (stream-ordered).
+ * Deterministic: 256 workgroups each sum a fixed set of 64-sample tiles in order, and
+ * their partials are summed in a fixed order. */
 int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, const float *logp_old,
                     const float *adv, const float *ret, const float *v_old, int32_t m, int32_t n_actions, float clip,
                     float c_v, float c_e, float *workspace, int64_t workspace_bytes, float *loss, float *grad,

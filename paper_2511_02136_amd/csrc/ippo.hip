@@ -13,6 +13,7 @@
  */
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 
@@ -32,7 +33,9 @@ constexpr int IN = LOB_OBS_DIM, HID = 256, OUT = 10, OUTP = 16;
 constexpr int O_W1 = 0, O_B1 = O_W1 + IN * HID, O_W2 = O_B1 + HID, O_B2 = O_W2 + HID * HID, O_W3 = O_B2 + HID,
               O_B3 = O_W3 + HID * OUT, NPARAM = O_B3 + OUT;
 static_assert(NPARAM == 78858, "parameter count");
-constexpr int PW = NPARAM + 4; /* per-workgroup partial: gradient, then the 4 loss sums */
+constexpr int PW = NPARAM + 6; /* per-workgroup partial: gradient, the 4 loss sums, 2 floats of padding
+                                  (a multiple of 4 floats: partials are summed in 16-byte loads) */
+constexpr int PPO_WGS = 256; /* workgroups of the fused PPO kernel */
 constexpr int64_t PARAM_COPY_BYTES = NPARAM * 4 + 16; /* workspace room for an aligned parameter copy */
 
 constexpr int TR = 64;          /* samples per workgroup tile */
@@ -161,6 +164,9 @@ __device__ __forceinline__ void gemm_rows4(floatx4 (&acc)[4][NT], int K, int r0,
 }
 
 __device__ __forceinline__ floatx4 lds4(const float *p) { return *(const floatx4 *)p; }
+
+#define GLOBAL __attribute__((address_space(1)))
+#define LOCAL __attribute__((address_space(3)))
 
 /* row / column of accumulator element i of a 16x16 tile held by this lane */
 __device__ __forceinline__ int acc_row(int i) { return 4 * ((int)(threadIdx.x & 63) >> 4) + i; }
@@ -329,9 +335,12 @@ __global__ void k_gae(const float *__restrict__ r, const float *__restrict__ v, 
 
 /* ------------------------------------------------------------------------------
  * Fused clipped-PPO loss forward + backward for one minibatch of one network.
- * Each workgroup recomputes the forward of its TR samples in LDS, forms the per-sample
- * gradient of the loss w.r.t. the outputs, back-propagates through the MLP in LDS and
- * writes its parameter-gradient partial (NPARAM floats) and its loss sums.
+ * For each tile of TR samples, a workgroup recomputes the forward in LDS, forms the
+ * per-sample gradient of the loss w.r.t. the outputs and back-propagates through the MLP
+ * in LDS.  A fixed grid of PPO_WGS workgroups (one per compute unit) strides over the
+ * tiles, each summing its tiles' parameter gradients and loss sums into one partial of
+ * PW floats: 256 partials (80 MB, within the last-level cache) for any minibatch size,
+ * rather than one per tile.
  * ---------------------------------------------------------------------------- */
 struct PpoArgs {
     const float *params;
@@ -343,230 +352,259 @@ struct PpoArgs {
     float *partial;              /* [grid][PW]: gradient, then loss sums (total, policy, value, entropy) */
 };
 
-__global__ void __launch_bounds__(NTH) k_ppo_fwd_bwd(PpoArgs a) {
-    extern __shared__ float sm[];
-    float *X = sm, *H1 = X + TR * XS, *H2 = H1 + TR * HS, *O = H2 + TR * HS;
-    const int row0 = (int)blockIdx.x * TR;
-    const int rows = min(TR, a.m - row0);
-    const float *P = a.params;
-    float *G = a.partial + (int64_t)blockIdx.x * PW;
+/* One tile of the fused kernel.  first: write the partial G, else add to it (each element
+ * is read and rewritten by the lane that wrote it).  A function of its own, not inlined:
+ * inside the kernel's tile loop the compiler keeps the per-lane LDS addresses of every
+ * unrolled load live across tiles and spills. */
+__device__ __noinline__ void ppo_tile(const PpoArgs &a, const GLOBAL float *Pg, GLOBAL float *Gg, const GLOBAL float *obs_g,
+                                      LOCAL float *sm, int tile, bool first) {
+    /* pointers to global memory and LDS arrive as such (a generic pointer parameter would
+     * make every access a flat one, which waits on both the memory and the LDS counter) */
+    const float *__restrict__ P = (const float *)Pg;
+    float *__restrict__ G = (float *)Gg;
+    float *X = (float *)sm, *H1 = X + TR * XS, *H2 = H1 + TR * HS, *O = H2 + TR * HS;
     const int tid = (int)threadIdx.x, wave = tid >> 6;
-    forward_tile(P, a.obs + (int64_t)row0 * IN, rows, X, H1, H2, O);
+    {
+        const int row0 = tile * TR;
+        const int rows = min(TR, a.m - row0);
+        auto put = [&](int i, float v) { G[i] = first ? v : G[i] + v; };
+        forward_tile(P, (const float *)obs_g + (int64_t)row0 * IN, rows, X, H1, H2, O);
 
-    /* per-sample loss and its gradient w.r.t. the 10 outputs (scaled by 1/m) */
-    float lsum[4] = {0.f, 0.f, 0.f, 0.f};
-    if (tid < TR) {
-        float *z = O + tid * OS;
-        float dz[OUT];
+        /* per-sample loss and its gradient w.r.t. the 10 outputs (scaled by 1/m) */
+        float lsum[4] = {0.f, 0.f, 0.f, 0.f};
+        if (tid < TR) {
+            float *z = O + tid * OS;
+            float dz[OUT];
 #pragma unroll
-        for (int j = 0; j < OUT; ++j) dz[j] = 0.f;
-        if (tid < rows) {
-            const int s = row0 + tid;
-            const int nact = a.n_act;
-            float mx = z[0];
-            for (int j = 1; j < nact; ++j) mx = fmaxf(mx, z[j]);
-            float se = 0.f;
-            for (int j = 0; j < nact; ++j) se += expf(z[j] - mx);
-            const float lse = mx + logf(se);
-            float H = 0.f;
-            for (int j = 0; j < nact; ++j) {
-                const float lp = z[j] - lse;
-                H -= expf(lp) * lp;
+            for (int j = 0; j < OUT; ++j) dz[j] = 0.f;
+            if (tid < rows) {
+                const int s = row0 + tid;
+                const int nact = a.n_act;
+                float mx = z[0];
+                for (int j = 1; j < nact; ++j) mx = fmaxf(mx, z[j]);
+                float se = 0.f;
+                for (int j = 0; j < nact; ++j) se += expf(z[j] - mx);
+                const float lse = mx + logf(se);
+                float H = 0.f;
+                for (int j = 0; j < nact; ++j) {
+                    const float lp = z[j] - lse;
+                    H -= expf(lp) * lp;
+                }
+                const int act = a.act[s];
+                const float logp = z[act] - lse;
+                const float ratio = expf(logp - a.logp_old[s]);
+                const float A = a.adv[s];
+                const float s1 = ratio * A;
+                const float rc = fminf(fmaxf(ratio, 1.f - a.clip), 1.f + a.clip);
+                const float s2 = rc * A;
+                const float pol = -fminf(s1, s2);
+                const float dlogp = s1 <= s2 ? -A * ratio : 0.f;
+                const float v = z[9], R = a.ret[s], vo = a.v_old[s];
+                const float dvv = v - vo;
+                const float vc = vo + fminf(fmaxf(dvv, -a.clip), a.clip);
+                const float l1 = (v - R) * (v - R), l2 = (vc - R) * (vc - R);
+                const float val = 0.5f * fmaxf(l1, l2);
+                const float dval = l1 >= l2 ? (v - R) : (fabsf(dvv) < a.clip ? (vc - R) : 0.f);
+                for (int j = 0; j < nact; ++j) {
+                    const float lp = z[j] - lse;
+                    const float p = expf(lp);
+                    const float dlp = (j == act ? 1.f : 0.f) - p;
+                    dz[j] = a.scale * (dlogp * dlp + a.c_e * p * (lp + H));
+                }
+                dz[9] = a.scale * a.c_v * dval;
+                lsum[0] = pol + a.c_v * val - a.c_e * H;
+                lsum[1] = pol;
+                lsum[2] = val;
+                lsum[3] = H;
             }
-            const int act = a.act[s];
-            const float logp = z[act] - lse;
-            const float ratio = expf(logp - a.logp_old[s]);
-            const float A = a.adv[s];
-            const float s1 = ratio * A;
-            const float rc = fminf(fmaxf(ratio, 1.f - a.clip), 1.f + a.clip);
-            const float s2 = rc * A;
-            const float pol = -fminf(s1, s2);
-            const float dlogp = s1 <= s2 ? -A * ratio : 0.f;
-            const float v = z[9], R = a.ret[s], vo = a.v_old[s];
-            const float dvv = v - vo;
-            const float vc = vo + fminf(fmaxf(dvv, -a.clip), a.clip);
-            const float l1 = (v - R) * (v - R), l2 = (vc - R) * (vc - R);
-            const float val = 0.5f * fmaxf(l1, l2);
-            const float dval = l1 >= l2 ? (v - R) : (fabsf(dvv) < a.clip ? (vc - R) : 0.f);
-            for (int j = 0; j < nact; ++j) {
-                const float lp = z[j] - lse;
-                const float p = expf(lp);
-                const float dlp = (j == act ? 1.f : 0.f) - p;
-                dz[j] = a.scale * (dlogp * dlp + a.c_e * p * (lp + H));
-            }
-            dz[9] = a.scale * a.c_v * dval;
-            lsum[0] = pol + a.c_v * val - a.c_e * H;
-            lsum[1] = pol;
-            lsum[2] = val;
-            lsum[3] = H;
+            /* the output tile now holds dOut (cols 10..15 stay zero) */
+            for (int j = 0; j < OUT; ++j) z[j] = dz[j];
         }
-        /* the output tile now holds dOut (cols 10..15 stay zero) */
-        for (int j = 0; j < OUT; ++j) z[j] = dz[j];
-    }
-    /* loss sums of the tile: wave 0 reduces its 64 lanes */
-    if (wave == 0) {
+        /* loss sums of the tile: wave 0 reduces its 64 lanes */
+        if (wave == 0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            float v = lsum[q];
-            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-            if (tid == 0) G[NPARAM + q] = v;
+            for (int q = 0; q < 4; ++q) {
+                float v = lsum[q];
+                for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+                if (tid == 0) put(NPARAM + q, v);
+            }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    /* dW3 = H2^T dOut (256 x 16, cols < 10 kept), db3 = column sums of dOut */
-    {
-        floatx4 acc[RT][1];
+        /* dW3 = H2^T dOut (256 x 16, cols < 10 kept), db3 = column sums of dOut */
+        {
+            floatx4 acc[RT][1];
 #pragma unroll
-        for (int m = 0; m < RT; ++m) acc[m][0] = zero4();
-        gemm<RT, 1>(acc, TR, CW * wave, 0, [&](int i, int k) { return H2[k * HS + i]; },
-                    [&](int k, int j) { return O[k * OS + j]; });
+            for (int m = 0; m < RT; ++m) acc[m][0] = zero4();
+            gemm<RT, 1>(acc, TR, CW * wave, 0, [&](int i, int k) { return H2[k * HS + i]; },
+                        [&](int k, int j) { return O[k * OS + j]; });
 #pragma unroll
-        for (int m = 0; m < RT; ++m)
+            for (int m = 0; m < RT; ++m)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = CW * wave + 16 * m + acc_row(i), c = acc_col();
-                if (c < OUT) G[O_W3 + r * OUT + c] = acc[m][0][i];
+                for (int i = 0; i < 4; ++i) {
+                    const int r = CW * wave + 16 * m + acc_row(i), c = acc_col();
+                    if (c < OUT) put(O_W3 + r * OUT + c, acc[m][0][i]);
+                }
+            if (tid < OUT) {
+                float s = 0.f;
+                for (int r = 0; r < TR; ++r) s += O[r * OS + tid];
+                put(O_B3 + tid, s);
             }
-        if (tid < OUT) {
-            float s = 0.f;
-            for (int r = 0; r < TR; ++r) s += O[r * OS + tid];
-            G[O_B3 + tid] = s;
         }
-    }
-    __syncthreads();
-    /* dH2 = (dOut W3^T) * (1 - H2^2), in place of H2 */
-    {
-        floatx4 acc[4][CT];
+        __syncthreads();
+        /* dH2 = (dOut W3^T) * (1 - H2^2), in place of H2 */
+        {
+            floatx4 acc[4][CT];
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+            for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
-        gemm16<4, CT>(acc, OUTP, 0, CW * wave,
-                      [&](int i, int kb) {
-                          floatx4 v;
+                for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
+            gemm16<4, CT>(acc, OUTP, 0, CW * wave,
+                          [&](int i, int kb) {
+                              floatx4 v;
 #pragma unroll
-                          for (int t = 0; t < 4; ++t) v[t] = O[i * OS + kb + t];
-                          return v;
-                      },
-                      [&](int kb, int j) {
-                          floatx4 v;
+                              for (int t = 0; t < 4; ++t) v[t] = O[i * OS + kb + t];
+                              return v;
+                          },
+                          [&](int kb, int j) {
+                              floatx4 v;
 #pragma unroll
-                          for (int t = 0; t < 4; ++t) v[t] = kb + t < OUT ? P[O_W3 + j * OUT + kb + t] : 0.f;
-                          return v;
-                      });
+                              for (int t = 0; t < 4; ++t) v[t] = kb + t < OUT ? P[O_W3 + j * OUT + kb + t] : 0.f;
+                              return v;
+                          });
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+            for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < CT; ++n)
+                for (int n = 0; n < CT; ++n)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * m + acc_row(i), c = CW * wave + 16 * n + acc_col();
-                    const float h = H2[r * HS + c];
-                    H2[r * HS + c] = acc[m][n][i] * (1.f - h * h);
-                }
-    }
-    __syncthreads();
-    /* dW2 = H1^T dH2 (256 x 256) in four passes of 64 x CW per wave; db2 */
-    for (int pass = 0; pass < 4; ++pass) {
-        floatx4 acc[4][CT];
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = 16 * m + acc_row(i), c = CW * wave + 16 * n + acc_col();
+                        const float h = H2[r * HS + c];
+                        H2[r * HS + c] = acc[m][n][i] * (1.f - h * h);
+                    }
+        }
+        __syncthreads();
+        /* dW2 = H1^T dH2 (256 x 256) in four passes of 64 x CW per wave; db2 */
+        for (int pass = 0; pass < 4; ++pass) {
+            floatx4 acc[4][CT];
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+            for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
-        const int r0 = 64 * pass, c0 = CW * wave;
-        gemm_rows4<CT>(acc, TR, r0, c0, [&](int i0, int k) { return lds4(H1 + k * HS + i0); },
-                       [&](int k, int j) { return H2[k * HS + j]; });
+                for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
+            const int r0 = 64 * pass, c0 = CW * wave;
+            /* the partial of the earlier tiles, loaded before the product so that the
+             * MFMAs cover the load latency */
+            float prev[4][CT][4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+            for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < CT; ++n)
+                for (int n = 0; n < CT; ++n)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = r0 + 4 * acc_row(i) + m, c = c0 + 16 * n + acc_col();
-                    G[O_W2 + r * HID + c] = acc[m][n][i];
-                }
-    }
-    if (tid < HID) {
-        float s = 0.f;
-        for (int r = 0; r < TR; ++r) s += H2[r * HS + tid];
-        G[O_B2 + tid] = s;
-    }
-    __syncthreads();
-    /* dH1 = (dH2 W2^T) * (1 - H1^2), in place of H1 */
-    {
-        floatx4 acc[4][CT];
+                    for (int i = 0; i < 4; ++i)
+                        prev[m][n][i] = first ? 0.f : G[O_W2 + (r0 + 4 * acc_row(i) + m) * HID + c0 + 16 * n + acc_col()];
+            gemm_rows4<CT>(acc, TR, r0, c0, [&](int i0, int k) { return lds4(H1 + k * HS + i0); },
+                           [&](int k, int j) { return H2[k * HS + j]; });
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+            for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
-        /* W2 read transposed: a lane's four k values are consecutive in memory (the
-         * parameters are 16-byte aligned) */
-        gemm16<4, CT>(acc, HID, 0, CW * wave, [&](int i, int kb) { return lds4(H2 + i * HS + kb); },
-                      [&](int kb, int j) { return *(const floatx4 *)(P + O_W2 + j * HID + kb); });
-        /* each element of H1 is read and rewritten by the lane that owns it */
+                for (int n = 0; n < CT; ++n)
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int n = 0; n < CT; ++n)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * m + acc_row(i), c = CW * wave + 16 * n + acc_col();
-                    const float h = H1[r * HS + c];
-                    H1[r * HS + c] = acc[m][n][i] * (1.f - h * h);
-                }
-    }
-    __syncthreads();
-    /* dW1 = X^T dH1 (40 x 256, computed as 48 x 256 with zero rows), db1 */
-    {
-        floatx4 acc[3][CT];
-#pragma unroll
-        for (int m = 0; m < 3; ++m)
-#pragma unroll
-            for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
-        gemm<3, CT>(acc, TR, 0, CW * wave, [&](int i, int k) { return X[k * XS + i]; },
-                    [&](int k, int j) { return H1[k * HS + j]; });
-#pragma unroll
-        for (int m = 0; m < 3; ++m)
-#pragma unroll
-            for (int n = 0; n < CT; ++n)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * m + acc_row(i), c = CW * wave + 16 * n + acc_col();
-                    if (r < IN) G[O_W1 + r * HID + c] = acc[m][n][i];
-                }
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = r0 + 4 * acc_row(i) + m, c = c0 + 16 * n + acc_col();
+                        G[O_W2 + r * HID + c] = first ? acc[m][n][i] : prev[m][n][i] + acc[m][n][i];
+                    }
+        }
         if (tid < HID) {
             float s = 0.f;
-            for (int r = 0; r < TR; ++r) s += H1[r * HS + tid];
-            G[O_B1 + tid] = s;
+            for (int r = 0; r < TR; ++r) s += H2[r * HS + tid];
+            put(O_B2 + tid, s);
         }
+        __syncthreads();
+        /* dH1 = (dH2 W2^T) * (1 - H1^2), in place of H1 */
+        {
+            floatx4 acc[4][CT];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
+            /* W2 read transposed: a lane's four k values are consecutive in memory (the
+             * parameters are 16-byte aligned) */
+            gemm16<4, CT>(acc, HID, 0, CW * wave, [&](int i, int kb) { return lds4(H2 + i * HS + kb); },
+                          [&](int kb, int j) { return *(const floatx4 *)(P + O_W2 + j * HID + kb); });
+            /* each element of H1 is read and rewritten by the lane that owns it */
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < CT; ++n)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = 16 * m + acc_row(i), c = CW * wave + 16 * n + acc_col();
+                        const float h = H1[r * HS + c];
+                        H1[r * HS + c] = acc[m][n][i] * (1.f - h * h);
+                    }
+        }
+        __syncthreads();
+        /* dW1 = X^T dH1 (40 x 256, computed as 48 x 256 with zero rows), db1 */
+        {
+            floatx4 acc[3][CT];
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+#pragma unroll
+                for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
+            gemm<3, CT>(acc, TR, 0, CW * wave, [&](int i, int k) { return X[k * XS + i]; },
+                        [&](int k, int j) { return H1[k * HS + j]; });
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+#pragma unroll
+                for (int n = 0; n < CT; ++n)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = 16 * m + acc_row(i), c = CW * wave + 16 * n + acc_col();
+                        if (r < IN) put(O_W1 + r * HID + c, acc[m][n][i]);
+                    }
+            if (tid < HID) {
+                float s = 0.f;
+                for (int r = 0; r < TR; ++r) s += H1[r * HS + tid];
+                put(O_B1 + tid, s);
+            }
+        }
+        __syncthreads(); /* the next tile's forward overwrites the LDS tiles */
     }
+}
+
+__global__ void __launch_bounds__(NTH) k_ppo_fwd_bwd(PpoArgs a) {
+    extern __shared__ float sm[];
+    float *G = a.partial + (int64_t)blockIdx.x * PW;
+    const int ntile = (a.m + TR - 1) / TR;
+    for (int tile = (int)blockIdx.x; tile < ntile; tile += (int)gridDim.x)
+        ppo_tile(a, (const GLOBAL float *)a.params, (GLOBAL float *)G, (const GLOBAL float *)a.obs, (LOCAL float *)sm,
+                 tile, tile == (int)blockIdx.x);
 }
 
 /* Sum of the per-workgroup partials in a fixed order (deterministic), in two levels:
  * chunk c of RCH consecutive workgroups is summed in workgroup order into sums[c], then
  * the chunk sums in chunk order.  Level 1 keeps 8 loads in flight per thread. */
 constexpr int RCH = 64;
-__global__ void k_reduce_chunks(const float *__restrict__ partial, int nwg, int width, float *__restrict__ sums) {
+__global__ void k_reduce_chunks(const floatx4 *__restrict__ partial, int nwg, int width4, floatx4 *__restrict__ sums) {
     const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (j >= width) return;
+    if (j >= width4) return;
     const int w0 = (int)blockIdx.y * RCH, w1 = min(nwg, w0 + RCH);
-    float s = 0.f;
+    floatx4 s = zero4();
     int w = w0;
     for (; w + 8 <= w1; w += 8) {
-        float v[8];
+        floatx4 v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(w + u) * width + j];
+        for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(w + u) * width4 + j];
 #pragma unroll
         for (int u = 0; u < 8; ++u) s += v[u];
     }
-    for (; w < w1; ++w) s += partial[(int64_t)w * width + j];
-    sums[(int64_t)blockIdx.y * width + j] = s;
+    for (; w < w1; ++w) s += partial[(int64_t)w * width4 + j];
+    sums[(int64_t)blockIdx.y * width4 + j] = s;
 }
-/* columns [0, NPARAM) go to grad, the last 4 to loss */
+/* columns [0, NPARAM) go to grad, the next 4 to loss (the padding is not summed) */
 __global__ void k_reduce_final(const float *__restrict__ sums, int nch, float *grad, float *loss) {
     const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (j >= PW) return;
+    if (j >= NPARAM + 4) return;
     float s = 0.f;
     for (int c = 0; c < nch; ++c) s += sums[(int64_t)c * PW + j];
     if (j < NPARAM) grad[j] = s;
@@ -633,7 +671,7 @@ int lob_gae(const float *reward, const float *value, const uint8_t *done, const 
 
 int64_t lob_ppo_workspace_bytes(int32_t m) {
     if (m <= 0) return LOB_EINVAL;
-    const int64_t nwg = (m + TR - 1) / TR, nch = (nwg + RCH - 1) / RCH;
+    const int64_t nwg = std::min<int64_t>((m + TR - 1) / TR, PPO_WGS), nch = (nwg + RCH - 1) / RCH;
     return (nwg + nch) * PW * 4 + PARAM_COPY_BYTES;
 }
 
@@ -644,10 +682,10 @@ int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, c
     if (!params || !obs || !act || !logp_old || !adv || !ret || !v_old || !workspace || !loss || !grad)
         return LOB_EINVAL;
     if (m <= 0 || n_actions < 1 || n_actions > 9 || !(clip > 0.f)) return LOB_EINVAL;
-    const int nwg = (m + TR - 1) / TR;
+    const int nwg = std::min((m + TR - 1) / TR, PPO_WGS);
     const int nch = (nwg + RCH - 1) / RCH;
     const int64_t part_bytes = (int64_t)(nwg + nch) * PW * 4;
-    if (workspace_bytes < part_bytes + PARAM_COPY_BYTES) return LOB_EINVAL;
+    if (workspace_bytes < part_bytes + PARAM_COPY_BYTES || ((uintptr_t)workspace & 15)) return LOB_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     /* the kernel reads W2 in 16-byte loads: parameters that are not 16-byte aligned (a
      * row of a [networks][LOB_PPO_PARAMS] array) are first copied into the workspace */
@@ -664,8 +702,8 @@ int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, c
     if (!lds_opt_in()) return LOB_EHIP;
     hipLaunchKernelGGL(k_ppo_fwd_bwd, dim3((unsigned)nwg), dim3(NTH), LDS_FLOATS * 4, st, a);
     float *sums = workspace + (int64_t)nwg * PW;
-    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((PW + 255) / 256), (unsigned)nch), dim3(256), 0, st,
-                       (const float *)a.partial, nwg, PW, sums);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((PW / 4 + 255) / 256), (unsigned)nch), dim3(256), 0, st,
+                       (const floatx4 *)a.partial, nwg, PW / 4, (floatx4 *)sums);
     hipLaunchKernelGGL(k_reduce_final, dim3((unsigned)((PW + 255) / 256)), dim3(256), 0, st, (const float *)sums, nch,
                        grad, loss);
     return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
