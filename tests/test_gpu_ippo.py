@@ -105,7 +105,10 @@ def test_gae_matches_fp64():
     assert np.abs(ret.cpu().numpy() - rr).max() <= 1e-5 * (np.abs(rr).max() + 1)
 
 
-@pytest.mark.parametrize("m,n_act,big", [(200, 9, False), (130, 3, True), (64, 9, True)])
+# 16,401 samples: more 64-sample tiles (257) than the kernel's 256 workgroups, the last
+# tile ragged and summed by workgroup 0 after its first; 1 sample: one ragged tile
+@pytest.mark.parametrize("m,n_act,big", [(200, 9, False), (130, 3, True), (64, 9, True), (1, 9, False),
+                                         (16401, 5, False)])
 def test_fused_ppo_loss_and_gradient(m, n_act, big):
     ippo = _ippo()
     rng = np.random.default_rng(m + n_act)

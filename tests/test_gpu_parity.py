@@ -91,10 +91,16 @@ SMALL = [
     # replayed executions of named orders (some of agents' orders) and ignored messages
     synth.Workload("executions", n_envs=48, n_steps=12, msgs_range=(20, 300), cap_choices=(50, 100, 200),
                    agents=("exec", "mm"), seed=38, exec_pct=12, ignored_pct=4),
+    # envs that replay no message at all beside envs with one or two per step: empty
+    # steps, agents acting alone on the reset book
+    synth.Workload("empty_steps", n_envs=40, n_steps=16, msgs_range=(0, 2), cap_choices=(3, 50, 100),
+                   agents=("exec", "mm", "dir"), seed=39),
     # the largest capacity the library accepts (16 rows of 64 orders per side), books full
     # from the start: the last row, evictions and the time lookup of every row
     synth.Workload("max_cap", n_envs=8, n_steps=6, msgs_per_step=400, cap=1024, agents=("exec", "mm"),
                    seed=37, snapshot_fill_pct=100),
+    # one env alone: a plan and a queue of one
+    synth.Workload("single_env", n_envs=1, n_steps=24, msgs_per_step=150, cap=50, agents=("exec", "mm"), seed=40),
 ]
 
 

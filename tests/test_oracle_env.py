@@ -266,6 +266,23 @@ def test_oracle_matches_naive_env_with_executions_and_ignored(agents):
     assert o.state()["counters"][:, 10].sum() == (t == 6).sum()
 
 
+def test_oracle_matches_naive_env_with_empty_steps():
+    """Envs that replay no message at all (0 per step) beside envs with one or two: the
+    agents still act on the reset book, their orders take the reset time, and no mid
+    statistic is formed where a step processes nothing."""
+    agents = ("exec", "mm", "dir")
+    w = synth.Workload("t", n_envs=9, n_steps=12, msgs_range=(0, 2), cap_choices=(3, 6, 12),
+                       agents=agents, seed=141, mid0=1000, snapshot_fill_pct=50)
+    s = synth.generate(w, threads=2)
+    per_env = s.off[:, -1] - s.off[:, 0]
+    assert (per_env == 0).any() and (per_env > 0).any()
+    o = OracleEnvs(s.caps, w.max_cap, synth.agent_kinds(agents), w.ep_len, w.seed, exec_task=60, exec_q0=4)
+    o.reset(s.book)
+    out = o.step(s, n_steps=12)
+    envs, outs = run_naive(s, w, 12, None, exec_task=60, q0=4)
+    compare(o, out, envs, outs, 12, len(agents))
+
+
 def test_buysell_market_maker_matches_naive_env():
     """The market maker rewarded by the buy-sell PnL (Eq. 4) and the quadratic inventory
     penalty: same actions as the Spooner market maker, its own reward."""
