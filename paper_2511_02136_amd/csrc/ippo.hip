@@ -51,6 +51,8 @@ constexpr int IN1 = 48;         /* layer-1 depth: IN rounded up to a multiple of
 constexpr int HS = 260;         /* LDS row stride of hidden tiles */
 constexpr int OS = 17;          /* LDS row stride of the output tile */
 constexpr int LDS_FLOATS = TR * XS + 2 * TR * HS + TR * OS;
+constexpr int TRP = 32;         /* samples per workgroup tile of the policy forward */
+constexpr int LDS_FLOATS_P = TRP * XS + 2 * TRP * HS + TRP * OS;
 constexpr uint64_t DOM_POLICY = 0x504F4C4943ULL; /* "POLIC" */
 
 __device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
@@ -172,25 +174,27 @@ __device__ __forceinline__ floatx4 lds4(const float *p) { return *(const floatx4
 __device__ __forceinline__ int acc_row(int i) { return 4 * ((int)(threadIdx.x & 63) >> 4) + i; }
 __device__ __forceinline__ int acc_col() { return (int)(threadIdx.x & 15); }
 
-/* ---- forward of a tile of TR samples into LDS: X, H1 = tanh(X W1 + b1),
- * H2 = tanh(H1 W2 + b2), O = H2 W3 + b3 (O cols 10..15 zero) ---- */
+/* ---- forward of a tile of R samples (R a multiple of 16, at most 64) into LDS: X,
+ * H1 = tanh(X W1 + b1), H2 = tanh(H1 W2 + b2), O = H2 W3 + b3 (O cols 10..15 zero) ---- */
+template <int R>
 __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const float *__restrict__ obs, int rows,
                                              float *X, float *H1, float *H2, float *O) {
+    constexpr int MT = R / 16; /* 16-row tiles per wave */
     const int tid = (int)threadIdx.x, wave = tid >> 6;
-    for (int i = tid; i < TR * XS; i += blockDim.x) {
+    for (int i = tid; i < R * XS; i += blockDim.x) {
         const int r = i / XS, c = i % XS;
         X[i] = (r < rows && c < IN) ? obs[(int64_t)r * IN + c] : 0.f;
     }
     __syncthreads();
-    /* layer 1: each wave computes 64 rows x CW cols */
+    /* layer 1: each wave computes R rows x CW cols */
     {
-        floatx4 acc[4][CT];
+        floatx4 acc[MT][CT];
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
         /* K = 48: X columns 40..47 are zero and the W1 rows past 40 read as zero */
-        gemm16<4, CT>(acc, IN1, 0, CW * wave, [&](int i, int kb) { return lds4(X + i * XS + kb); },
+        gemm16<MT, CT>(acc, IN1, 0, CW * wave, [&](int i, int kb) { return lds4(X + i * XS + kb); },
                       [&](int kb, int j) {
                           floatx4 v;
 #pragma unroll
@@ -198,7 +202,7 @@ __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const 
                           return v;
                       });
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int n = 0; n < CT; ++n)
 #pragma unroll
@@ -210,12 +214,12 @@ __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const 
     __syncthreads();
     /* layer 2 */
     {
-        floatx4 acc[4][CT];
+        floatx4 acc[MT][CT];
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
-        gemm16<4, CT>(acc, HID, 0, CW * wave, [&](int i, int kb) { return lds4(H1 + i * HS + kb); },
+        gemm16<MT, CT>(acc, HID, 0, CW * wave, [&](int i, int kb) { return lds4(H1 + i * HS + kb); },
                       [&](int kb, int j) {
                           floatx4 v;
 #pragma unroll
@@ -223,7 +227,7 @@ __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const 
                           return v;
                       });
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int n = 0; n < CT; ++n)
 #pragma unroll
@@ -233,10 +237,10 @@ __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const 
                 }
     }
     __syncthreads();
-    /* layer 3: wave w < 4 computes rows 16w..16w+15, cols 0..15, k permuted in blocks of
-     * 16 as in gemm16.  The lane's whole W3 column is loaded first, so the weight loads
+    /* layer 3: wave w < R/16 computes rows 16w..16w+15, cols 0..15, k permuted in blocks
+     * of 16 as in gemm16.  The lane's whole W3 column is loaded first, so the weight loads
      * (from L2) wait once rather than once per block. */
-    if (wave < TR / 16) {
+    if (wave < R / 16) {
         const int li = tid & 15, kq = 4 * ((tid & 63) >> 4);
         floatx4 bw[HID / 16];
 #pragma unroll
@@ -262,7 +266,9 @@ __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const 
 
 /* ------------------------------------------------------------------------------
  * Policy forward for the rollout: logits, value, a sampled action (Gumbel-max on a
- * counter hash) and its log-probability.  grid (ceil(n/TR), n_agents), NTH threads.
+ * counter hash) and its log-probability.  grid (ceil(n/TRP), n_agents), NTH threads.
+ * Tiles of 32 samples: the rollout's 4096 envs x 2 agents then give 256 workgroups, one
+ * per CU (64-sample tiles left half of the CUs idle).
  * ---------------------------------------------------------------------------- */
 struct FwdArgs {
     const float *params; /* [A][NPARAM] */
@@ -279,12 +285,12 @@ struct FwdArgs {
 
 __global__ void __launch_bounds__(NTH) k_policy_forward(FwdArgs a) {
     extern __shared__ float sm[];
-    float *X = sm, *H1 = X + TR * XS, *H2 = H1 + TR * HS, *O = H2 + TR * HS;
+    float *X = sm, *H1 = X + TRP * XS, *H2 = H1 + TRP * HS, *O = H2 + TRP * HS;
     const int ag = (int)blockIdx.y;
-    const int row0 = (int)blockIdx.x * TR;
-    const int rows = min(TR, a.n - row0);
+    const int row0 = (int)blockIdx.x * TRP;
+    const int rows = min(TRP, a.n - row0);
     const float *P = a.params + (int64_t)ag * NPARAM;
-    forward_tile(P, a.obs + ((int64_t)ag * a.n + row0) * IN, rows, X, H1, H2, O);
+    forward_tile<TRP>(P, a.obs + ((int64_t)ag * a.n + row0) * IN, rows, X, H1, H2, O);
     const int tid = (int)threadIdx.x;
     if (tid < rows) {
         const int nact = a.n_act[ag];
@@ -368,7 +374,7 @@ __device__ __noinline__ void ppo_tile(const PpoArgs &a, const GLOBAL float *Pg, 
         const int row0 = tile * TR;
         const int rows = min(TR, a.m - row0);
         auto put = [&](int i, float v) { G[i] = first ? v : G[i] + v; };
-        forward_tile(P, (const float *)obs_g + (int64_t)row0 * IN, rows, X, H1, H2, O);
+        forward_tile<TR>(P, (const float *)obs_g + (int64_t)row0 * IN, rows, X, H1, H2, O);
 
         /* per-sample loss and its gradient w.r.t. the 10 outputs (scaled by 1/m) */
         float lsum[4] = {0.f, 0.f, 0.f, 0.f};
@@ -624,7 +630,7 @@ bool lds_opt_in() {
     static bool done = false;
     if (!done) {
         if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_policy_forward),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, LDS_FLOATS * 4) != hipSuccess ||
+                                hipFuncAttributeMaxDynamicSharedMemorySize, LDS_FLOATS_P * 4) != hipSuccess ||
             hipFuncSetAttribute(reinterpret_cast<const void *>(k_ppo_fwd_bwd),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, LDS_FLOATS * 4) != hipSuccess)
             return false;
@@ -650,8 +656,8 @@ int lob_policy_forward(const float *params, const float *obs, int32_t n_agents, 
     }
     a.seed = seed; a.epoch = epoch; a.t = t; a.logits = logits; a.actions = actions; a.logp = logp; a.value = value;
     if (!lds_opt_in()) return LOB_EHIP;
-    const dim3 grid((unsigned)((n + TR - 1) / TR), (unsigned)n_agents);
-    hipLaunchKernelGGL(k_policy_forward, grid, dim3(NTH), LDS_FLOATS * 4, (hipStream_t)stream, a);
+    const dim3 grid((unsigned)((n + TRP - 1) / TRP), (unsigned)n_agents);
+    hipLaunchKernelGGL(k_policy_forward, grid, dim3(NTH), LDS_FLOATS_P * 4, (hipStream_t)stream, a);
     return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
 }
 
