@@ -49,3 +49,46 @@ def test_host_side_argument_checks():
     assert lib.lob_rollout(None, None, 1, None, None, None) == -1
     lib.lob_destroy.argtypes = [ctypes.c_void_p]
     assert lib.lob_destroy(None) == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblob.so not built")
+def test_host_side_checks_of_the_actor_critic():
+    """Argument checks of the actor-critic entry points, all taken before any device call
+    (the pointers passed where a check must fail first are never dereferenced), and the
+    workspace size of the fused PPO call: 256 workgroup partials at most, plus one partial
+    per 64 of them for the first reduction level, of 78,864 floats each (78,858 parameters,
+    4 loss sums, 2 of padding), plus room for an aligned copy of the parameters."""
+    lib = ctypes.CDLL(LIB)
+    p, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
+    lib.lob_ppo_workspace_bytes.argtypes = [i32]
+    lib.lob_ppo_workspace_bytes.restype = ctypes.c_int64
+    pw, copy = 78864 * 4, 78858 * 4 + 16
+    assert lib.lob_ppo_workspace_bytes(0) == -1 and lib.lob_ppo_workspace_bytes(-3) == -1
+    assert lib.lob_ppo_workspace_bytes(1) == (1 + 1) * pw + copy
+    assert lib.lob_ppo_workspace_bytes(64 * 100 + 1) == (101 + 2) * pw + copy
+    assert lib.lob_ppo_workspace_bytes(131072) == (256 + 4) * pw + copy
+    assert lib.lob_ppo_workspace_bytes(1 << 30) == (256 + 4) * pw + copy
+    lib.lob_ppo_fwd_bwd.argtypes = [p] * 7 + [i32, i32, f32, f32, f32, p, ctypes.c_int64, p, p, p]
+    d = [p(0x1000 + 16 * k) for k in range(7)]
+    ws, big = p(0x20000), 1 << 40
+
+    def call(m=64, n_act=9, clip=0.2, w=ws, wb=big, ptrs=d):
+        return lib.lob_ppo_fwd_bwd(*ptrs, m, n_act, clip, 0.5, 0.01, w, wb, p(0x3000), p(0x4000), None)
+    assert lib.lob_ppo_fwd_bwd(*([None] * 7), 64, 9, 0.2, 0.5, 0.01, None, 0, None, None, None) == -1
+    assert call(ptrs=[None] + d[1:]) == -1
+    assert call(m=0) == -1 and call(n_act=0) == -1 and call(n_act=10) == -1 and call(clip=0.0) == -1
+    assert call(wb=lib.lob_ppo_workspace_bytes(64) - 1) == -1   # too small
+    assert call(w=p(0x20004)) == -1                              # not 16-byte aligned
+    lib.lob_gae.argtypes = [p, p, p, p, i32, i32, f32, f32, p, p, p]
+    assert lib.lob_gae(None, None, None, None, 4, 4, 0.99, 0.95, None, None, None) == -1
+    assert lib.lob_gae(*d[:4], 0, 4, 0.99, 0.95, d[4], d[5], None) == -1
+    assert lib.lob_gae(*d[:4], 4, 0, 0.99, 0.95, d[4], d[5], None) == -1
+    lib.lob_policy_forward.argtypes = [p, p, i32, i32, p, ctypes.c_uint64, p, i32, p, p, p, p, p]
+    assert lib.lob_policy_forward(None, None, 1, 8, None, 0, None, 0, None, None, None, None, None) == -1
+    n_act = (i32 * 2)(9, 9)
+    assert lib.lob_policy_forward(d[0], d[1], 0, 8, n_act, 0, None, 0, None, d[2], d[3], d[4], None) == -1
+    assert lib.lob_policy_forward(d[0], d[1], 2, 0, n_act, 0, None, 0, None, d[2], d[3], d[4], None) == -1
+    bad = (i32 * 2)(9, 10)
+    assert lib.lob_policy_forward(d[0], d[1], 2, 8, bad, 0, None, 0, None, d[2], d[3], d[4], None) == -1
+    lib.lob_counter_bump.argtypes = [p, p]
+    assert lib.lob_counter_bump(None, None) == -1
