@@ -250,7 +250,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the env step shards by env "
-              "with no exchange, and this build measures one GPU's share.", file=sys.stderr)
+              "with no exchange, and this benchmark measures one GPU's share.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -53,7 +53,7 @@ enum {
     LOB_ENOMEM = -2,       /* device allocation failed */
     LOB_EHIP = -3,         /* a HIP runtime call failed */
     LOB_ESTATE = -4,       /* call order: no reset yet, or the episode/stream is exhausted */
-    LOB_EUNSUPPORTED = -5  /* a configuration this build does not support */
+    LOB_EUNSUPPORTED = -5  /* a configuration the library does not support */
 };
 
 #define LOB_LIMIT 1

@@ -405,7 +405,7 @@ void reset_env(Env &env, const Oracle &O, int e, const int32_t *const *f, const 
 /* Observation of agent i after the last step (40 features, all integer-valued,
  * converted to float with round-to-nearest-even).  Reading: the paper's observations
  * are "statistics related to the agents' task, such as the size of their current
- * inventory" (Sec. 4.1.1); the feature list is this build's choice. */
+ * inventory" (Sec. 4.1.1); the feature list is a reading of that passage. */
 void observe(const Oracle &O, const Env &env, int i, float *out) {
     int64_t f[OBS_DIM] = {};
     const int32_t bb = env.last_bb, ba = env.last_ba;
