@@ -349,6 +349,23 @@ def main():
     except AssertionError as ex:
         parity = f"MISMATCH: {ex}"
 
+    # context only, not the value: the same rollouts each started on an idle GPU (host
+    # synchronised before each).  Rollouts queued back to back, as timed above, run in
+    # one of two modes from one rollout to the next; from an idle GPU they do not.
+    # (a context leg like the per-step forms: skipped with --no-plain, as in profiling runs)
+    from_idle = []
+    if not args.no_plain:
+        print("[bench] rollouts started from an idle GPU (context)", file=sys.stderr, flush=True)
+        for _ in range(args.steps):
+            env.reset(book)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            env.rollout(ds, w.n_steps, out=out)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            from_idle.append(e0.elapsed_time(e1))
+
     copy_gbs = copy_bandwidth()
     traffic = measured_traffic(w.name)
 
@@ -434,6 +451,8 @@ def main():
         "env_steps_per_s": steps_per_s,
         "all_msgs_per_s": all_msgs / (ms_step / 1e3),
         "median_ms_per_step": median_ms,
+        "rollout_ms_timed": [round(mids[k].elapsed_time(ends[k]), 2) for k in range(args.steps)],
+        "rollout_ms_from_idle": [round(t, 2) for t in from_idle],
         "trades": n_trades,
         "parity": parity,
         "schedule": schedule,
