@@ -1238,6 +1238,13 @@ __global__ void k_export_agents(ExportArgs a) {
     }
 }
 
+/* Holds its stream for `ticks` of the 100 MHz real-time clock (one wave, sleeping
+ * between reads: the wait is bounded by the clock). */
+__global__ void k_hold(int64_t ticks) {
+    const int64_t t0 = (int64_t)wall_clock64();
+    while ((int64_t)wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(16);
+}
+
 __global__ void k_fill_i32(int32_t *p, int32_t n, int32_t v) {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i < n) p[i] = v;
@@ -1262,6 +1269,7 @@ struct CapClass {
 
 constexpr int MAX_CLASSES = LOB_MAX_CAP / 64; /* one class per row count */
 constexpr size_t LDS_PER_CU = 160 * 1024;  /* gfx950 */
+constexpr int64_t LANE_GAP = 1000; /* 10 us of the 100 MHz clock between class starts */
 constexpr int CONC_LANES = 3;               /* concurrent class launches (see launch_env) */
 constexpr int WAVES_PER_CU = 24;            /* 6 per SIMD at the env kernel's register use */
 constexpr int BALANCE_DEFAULT = 880;        /* permille of the LDS (measured best on uneven books) */
@@ -1421,8 +1429,14 @@ int launch_env(lob_ctx *c, KArgs a, hipStream_t st) {
     const int nc = (int)c->classes.size();
     const int lanes = std::min(nc, CONC_LANES);
     if (lanes > 1 && !hip_ok(hipEventRecord(c->ev_fork, st))) return LOB_EHIP;
-    for (int l = 1; l < lanes; ++l)
+    for (int l = 1; l < lanes; ++l) {
         if (!hip_ok(hipStreamWaitEvent(c->streams[l], c->ev_fork, 0))) return LOB_EHIP;
+        /* In a rollout the classes start one after another, largest books first, LANE_GAP
+         * apart: started at the same instant, the workgroups of two classes interleave
+         * differently from run to run, and one of them could be left slower than planned
+         * for the whole rollout. */
+        if (a.n_steps > 1) hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, c->streams[l], (int64_t)(LANE_GAP * l));
+    }
     for (int i = 0; i < nc; ++i) {
         const int k = nc - 1 - i; /* largest books first */
         const int l = i % lanes;
