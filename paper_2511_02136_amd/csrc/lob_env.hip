@@ -1269,7 +1269,7 @@ struct CapClass {
 
 constexpr int MAX_CLASSES = LOB_MAX_CAP / 64; /* one class per row count */
 constexpr size_t LDS_PER_CU = 160 * 1024;  /* gfx950 */
-constexpr int64_t LANE_GAP = 1000; /* 10 us of the 100 MHz clock between class starts */
+constexpr int64_t LANE_GAP = 5000; /* 50 us of the 100 MHz clock between class starts */
 constexpr int CONC_LANES = 3;               /* concurrent class launches (see launch_env) */
 constexpr int WAVES_PER_CU = 24;            /* 6 per SIMD at the env kernel's register use */
 constexpr int BALANCE_DEFAULT = 880;        /* permille of the LDS (measured best on uneven books) */
@@ -1434,7 +1434,8 @@ int launch_env(lob_ctx *c, KArgs a, hipStream_t st) {
         /* In a rollout the classes start one after another, largest books first, LANE_GAP
          * apart: started at the same instant, the workgroups of two classes interleave
          * differently from run to run, and one of them could be left slower than planned
-         * for the whole rollout. */
+         * for the whole rollout (3 us apart still did; smallest books first took twice as
+         * long: the large workgroups then find no room). */
         if (a.n_steps > 1) hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, c->streams[l], (int64_t)(LANE_GAP * l));
     }
     for (int i = 0; i < nc; ++i) {
