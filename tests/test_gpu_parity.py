@@ -323,6 +323,44 @@ def test_plain_and_persistent_forms_identical_full_size():
         assert torch.equal(ba[k], bb[k]), k
 
 
+def test_rollout_captured_in_a_graph():
+    """A rollout of several capacity classes (concurrent launches on forked streams,
+    staggered starts, queue counters cleared by a kernel) captured in a HIP graph: every
+    replay, with eager work and synchronisation between the replays, equals the oracle."""
+    w = SMALL[2]  # uneven: 96 envs, books of 50..400 orders, execution + market-making agent
+    n = w.n_steps
+    print(f"\n[graph] {w.name} envs={w.n_envs} steps={n}", flush=True)
+    _, DeviceStream = _lob()
+    s = synth.generate(w)
+    o = oracle_for(s, s.book, s.caps, w.max_cap, w.agents, w.ep_len, w.seed)
+    ref = o.step(s, n_steps=n)
+    env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+    assert len(env.schedule()) > 1
+    ds = DeviceStream.from_host(s)
+    toff = torch.from_numpy(ref["trade_off"]).cuda()
+    book = {k: torch.from_numpy(v).cuda() for k, v in s.book.items()}
+    out = env._alloc_out(n, True, True, toff, ds)
+    env.plan(ds, n)
+    env.rollout(ds, n, out=out)  # eager first: streams, events and plan in place
+    torch.cuda.synchronize()
+    assert_same_outputs(out, ref, n, what="eager")
+    g = torch.cuda.CUDAGraph()
+    env.reset(book)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        env.rollout(ds, n, out=out)
+    for rep in range(3):
+        for k in ("n_trades", "fills", "reward", "obs", "done", "trades"):
+            if out.get(k) is not None:
+                out[k].fill_(7)
+        env.reset(book)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert_same_outputs(out, ref, n, what=f"graph replay {rep}")
+        assert_same_books(env.books(), o.books(), what=f"graph replay {rep}")
+
+
 def test_schedule_independence():
     """Every schedule the autotuner can pick, and the padded single-class grouping,
     give identical outputs and books."""
