@@ -1269,7 +1269,8 @@ struct CapClass {
 
 constexpr int MAX_CLASSES = LOB_MAX_CAP / 64; /* one class per row count */
 constexpr size_t LDS_PER_CU = 160 * 1024;  /* gfx950 */
-constexpr int64_t LANE_GAP = 5000; /* 50 us of the 100 MHz clock between class starts */
+constexpr int64_t LANE_GAP = 5000;      /* 50 us of the 100 MHz clock between class starts */
+constexpr int64_t LANE_GAP_STEP = 1000; /* 10 us between class starts in a one-step launch */
 constexpr int CONC_LANES = 3;               /* concurrent class launches (see launch_env) */
 constexpr int WAVES_PER_CU = 24;            /* 6 per SIMD at the env kernel's register use */
 constexpr int BALANCE_DEFAULT = 880;        /* permille of the LDS (measured best on uneven books) */
@@ -1431,12 +1432,14 @@ int launch_env(lob_ctx *c, KArgs a, hipStream_t st) {
     if (lanes > 1 && !hip_ok(hipEventRecord(c->ev_fork, st))) return LOB_EHIP;
     for (int l = 1; l < lanes; ++l) {
         if (!hip_ok(hipStreamWaitEvent(c->streams[l], c->ev_fork, 0))) return LOB_EHIP;
-        /* In a rollout the classes start one after another, largest books first, LANE_GAP
-         * apart: started at the same instant, the workgroups of two classes interleave
-         * differently from run to run, and one of them could be left slower than planned
-         * for the whole rollout (3 us apart still did; smallest books first took twice as
-         * long: the large workgroups then find no room). */
-        if (a.n_steps > 1) hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, c->streams[l], (int64_t)(LANE_GAP * l));
+        /* The classes start one after another, largest books first, LANE_GAP apart (a
+         * single step: LANE_GAP_STEP, which it pays every step): started at the same
+         * instant, the workgroups of two classes interleave differently from run to run,
+         * and one of them could be left slower than planned for the whole launch (3 us
+         * apart still did; smallest books first took twice as long: the large workgroups
+         * then find no room). */
+        hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, c->streams[l],
+                           (int64_t)((a.n_steps > 1 ? LANE_GAP : LANE_GAP_STEP) * l));
     }
     for (int i = 0; i < nc; ++i) {
         const int k = nc - 1 - i; /* largest books first */
