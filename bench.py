@@ -4,7 +4,9 @@ Workload: 8192 envs with uneven shapes (per-side book capacity uniform in
 {50,100,200,400}, messages per step uniform in 1..400 per env), execution + market-making
 agent under the in-kernel random policy, 128-step episodes; synthetic MBO streams.
 One benchmark step = reset + one 128-step rollout of every env (persistent form: books
-LDS-resident for all steps), all outputs written (trades, fills, rewards, observations).
+LDS-resident for all steps, the schedule picked by the autotuner before timing, the
+rollout captured once in a HIP graph and replayed), all outputs written (trades, fills,
+rewards, observations).
 
 Prints one JSON line.  value = replayed MBO messages per second (whole job); the line
 also carries env-steps/s, the plain per-step form's throughput for comparison, the
@@ -240,11 +242,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-step form")
     ap.add_argument("--no-ippo", action="store_true", help="skip the IPPO rollout/update figures")
-    ap.add_argument("--configs", default="",
-                    help="comma-separated extra workloads to report (e.g. replay1,uniform4096,large16384)")
+    ap.add_argument("--configs", default="replay1",
+                    help="comma-separated extra workloads to report (default replay1; also uniform4096, large16384)")
     ap.add_argument("--ippo-only", action="store_true",
                     help="only the IPPO figures (profiling aid; prints them as one JSON object)")
-    ap.add_argument("--tune", action="store_true", help="run the schedule autotuner before timing")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the schedule autotuner (the default plan and balance share instead)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager rollouts instead of replays of the captured HIP graph")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -277,19 +282,36 @@ def main():
     out = env._alloc_out(w.n_steps, True, True, toff, ds)
     stream = torch.cuda.current_stream()
     env.reset(book)
-    if args.tune:
+    if not args.no_tune:
+        # the tuner times schedules on this rollout (state restored), outside the timed region
         print("[bench] autotune", file=sys.stderr, flush=True)
         env.autotune(ds, w.n_steps, out=out)
     else:
         env.plan(ds, w.n_steps)
     schedule = env.schedule()
     torch.cuda.synchronize()
+    graph = None
+    if not args.eager:
+        # the rollout (every class launch, the staggered starts, the queue counters cleared by a
+        # kernel) captured once in a HIP graph; the reset before each replay stays eager
+        env.reset(book)
+        env.rollout(ds, w.n_steps, out=out)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        env.reset(book)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph):
+            env.rollout(ds, w.n_steps, out=out)
+        torch.cuda.synchronize()
 
     def one_rollout(ev=None):
         env.reset(book)
         if ev is not None:
             ev.record(stream)
-        env.rollout(ds, w.n_steps, out=out)
+        if graph is not None:
+            graph.replay()
+        else:
+            env.rollout(ds, w.n_steps, out=out)
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -447,7 +469,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.n_envs} envs, cap U{{50,100,200,400}}, msgs/step U{{1..400}}, "
                                f"{w.n_steps} steps, agents exec+mm, random policy",
-                   "n_envs": w.n_envs, "n_steps": w.n_steps, "n_msgs": n_msgs},
+                   "n_envs": w.n_envs, "n_steps": w.n_steps, "n_msgs": n_msgs,
+                   "form": "eager rollout" if graph is None else "replay of the captured HIP graph",
+                   "schedule": "default plan" if args.no_tune else "autotuned before timing"},
         "env_steps_per_s": steps_per_s,
         "all_msgs_per_s": all_msgs / (ms_step / 1e3),
         "median_ms_per_step": median_ms,

@@ -63,8 +63,8 @@ enum {
 #define LOB_OBS_DIM 40
 #define LOB_TRADE_WORDS 8
 #define LOB_N_COUNTERS 11
-#define LOB_ENV_STATE_WORDS 8
-#define LOB_AGENT_STATE_WORDS 4
+#define LOB_ENV_STATE_WORDS 12
+#define LOB_AGENT_STATE_WORDS 6
 #define LOB_MAX_AGENTS 4
 #define LOB_MAX_CAP 1024
 
@@ -132,18 +132,26 @@ typedef struct {
     int32_t *actions;         /* device [n_steps][n_agents][n_envs]: actions taken, or NULL */
 } lob_out;
 
-/* Create a context: validates cfg, allocates the books and per-env state on the current
- * device.  Returns LOB_EINVAL / LOB_EUNSUPPORTED / LOB_ENOMEM / LOB_EHIP on failure. */
+/* Create a context (the environment configuration: book capacity of Table 2, agent types
+ * of Sec. 4.1, order sizes and reward weights of Table 2 / Eq. 2-4): validates cfg,
+ * allocates the books and per-env state on the current device.  Host-synchronous: it
+ * allocates and uploads with blocking calls and launches no kernel, so it takes no
+ * stream; the context is ready for any stream when it returns.  *out is NULL on failure.
+ * Returns LOB_EINVAL / LOB_EUNSUPPORTED / LOB_ENOMEM / LOB_EHIP on failure. */
 int lob_init(const lob_config *cfg, lob_ctx **out);
 
-/* Load every env's book from `snapshot` (canonical layout, priority order, n <= cap;
- * counts above an env's cap are clamped) and start a new episode: step 0, agents flat,
- * the execution agent's task at exec_task, reference prices from the best prices (an
- * empty side falls back to one tick beyond the other side, 0 if both are empty). */
+/* Start a new episode from a book state (Sec. 4, third paragraph: the book is initialised
+ * from the state at the episode's start).  Loads every env's book from `snapshot`
+ * (canonical layout, priority order, n <= cap; counts above an env's cap are clamped):
+ * step 0, agents flat, the execution agent's task at exec_task, reference prices from
+ * the best prices (the paper is silent on empty sides; reading: an empty side falls back
+ * to one tick beyond the other side, 0 if both are empty).  Asynchronous on stream. */
 int lob_reset(lob_ctx *ctx, const lob_books *snapshot, void *stream);
 
-/* One env-step of every env (the plain per-step form: one launch, books loaded from
- * and stored to device memory).  Messages of step t = the context's step counter are
+/* One env-step of every env, Sec. 4 steps 1-5 (action conversion with cancels, shuffle,
+ * concatenation [cancels, orders, replay], book processing with trades recorded,
+ * outcomes), in the plain per-step form: one launch, books loaded from and stored to
+ * device memory.  Messages of step t = the context's step counter are
  * read from `msgs`.  actions: device int32 [n_agents][n_envs], or NULL for the uniform
  * random policy drawn in-kernel from the counter hash.  Out-of-range actions act as 0
  * (no quotes: every resting order of that agent is cancelled).  Outputs for 1 step.
@@ -151,19 +159,25 @@ int lob_reset(lob_ctx *ctx, const lob_books *snapshot, void *stream);
 int lob_step(lob_ctx *ctx, const lob_msgs *msgs, const int32_t *actions, const lob_out *out,
              void *stream);
 
-/* n_steps env-steps of every env in one persistent launch per capacity class, books
- * resident in LDS for all steps, envs pulled from a work queue (longest first).
+/* n_steps env-steps (Sec. 4 steps 1-5) of every env in one persistent launch per
+ * capacity class (the batched form; the paper batches episodes by vectorising the step
+ * over them, Sec. 4 and Fig. 1), books resident in LDS for all steps, envs pulled from a
+ * work queue (longest first).
  * actions: device int32 [n_steps][n_agents][n_envs] or NULL (random policy).  Results
  * are identical to n_steps calls of lob_step. */
 int lob_rollout(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps, const int32_t *actions,
                 const lob_out *out, void *stream);
 
-/* Schedule plan for the next n_steps from the current step: orders each capacity
+/* Scheduling (this call, lob_schedule_get/set/balance, lob_set_padded and lob_autotune)
+ * is the library's own: the paper is silent on it (it vectorises the step over
+ * equal-shape episodes, Sec. 4 and Fig. 1).
+ * Schedule plan for the next n_steps from the current step: orders each capacity
  * class's envs by decreasing message count (longest first), so that the envs that bound
  * the runtime start first; with several classes and a balance share set (the default,
  * see lob_schedule_balance), it also sizes each class's work queue.  Reads the CSR
- * offsets back to the host (synchronous).  Used by lob_step and lob_rollout until the
- * next plan; results never depend on it. */
+ * offsets back to the host (synchronous: it first waits for the device, so that no launch
+ * still reading the previous plan's env list is running when the list is rewritten).
+ * Used by lob_step and lob_rollout until the next plan; results never depend on it. */
 int lob_plan(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps);
 
 /* The launch schedule, one record of 5 int32 per capacity class (host array):
@@ -204,19 +218,24 @@ int lob_set_padded(lob_ctx *ctx, int32_t padded);
  * temporary device memory for the state copy. */
 int lob_autotune(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps, const lob_out *out, void *stream);
 
-/* Observation of the current state, device float [n_agents][n_envs][40] (equal to the
- * last step's observation; after reset, the step statistics are zero). */
+/* Observation of the current state (Sec. 4 step 5; Sec. 4.1.1: statistics of the agent's
+ * task such as its inventory; the 40 features are a reading), device float
+ * [n_agents][n_envs][40], equal to the last step's observation (after reset the step
+ * statistics are zero).  Asynchronous on stream. */
 int lob_observe(lob_ctx *ctx, float *obs, void *stream);
 
-/* Copy the books out in canonical layout (unused slots zero). */
+/* Copy the books out in canonical layout: each side in price-time priority order
+ * (Sec. 2.1), best first, unused slots zero.  Asynchronous on stream. */
 int lob_export_books(lob_ctx *ctx, const lob_books *out, void *stream);
 
-/* Copy the state out (device arrays):
- *   env_state [n_envs][8]: last best bid, last best ask, mid2 (bid+ask) at the last step
+/* Copy the state out (device arrays), with lob_export_books everything an episode
+ * continues from (lob_import_state; Sec. 4, third paragraph):
+ *   env_state [n_envs][12]: last best bid, last best ask, mid2 (bid+ask) at the last step
  *     end, mid2 at reset, time of the last processed message (s, ns), steps since reset,
- *     mid2 change over the last step;
- *   agent_state [n_envs][n_agents][4]: inventory, cash (ticks x shares), execution
- *     remaining, order-id counter;
+ *     mid2 change over the last step, then the last step's statistics (buyer- and
+ *     seller-initiated volume, trades, last trade price);
+ *   agent_state [n_envs][n_agents][6]: inventory, cash (ticks x shares), execution
+ *     remaining, order-id counter, quantity bought and sold in the last step;
  *   counters [n_envs][11]: messages, trades, cancel and execution misses, evictions,
  *     evicted qty, drops, dropped qty, unfilled market qty, bad messages, trade records
  *     not written, ignored messages.
@@ -224,13 +243,29 @@ int lob_export_books(lob_ctx *ctx, const lob_books *out, void *stream);
 int lob_export_state(lob_ctx *ctx, int64_t *env_state, int64_t *agent_state, int64_t *counters,
                      void *stream);
 
+/* Continue every env from a given state (Sec. 4, third paragraph: an episode starts from
+ * a book state; here any state exported by lob_export_books + lob_export_state, possibly
+ * from another context or process, or edited): books in canonical layout (priority
+ * order; counts clamped to each env's capacity), env_state / agent_state / counters in
+ * the layouts of lob_export_state (device arrays; counters may be NULL = zero;
+ * agent_state may be NULL only without agents).  `step` (0..episode_len) becomes the
+ * step counter: the next step reads the messages of step `step` and is done at
+ * episode_len; it replaces word 6 of every env's env_state.  The following steps then
+ * give exactly what the exported context's following steps give.  Trade cursors are the
+ * caller's.  Asynchronous on stream (the inputs must stay valid until it has run);
+ * LOB_EINVAL for NULL books or state or a step out of range. */
+int lob_import_state(lob_ctx *ctx, const lob_books *books, const int64_t *env_state, const int64_t *agent_state,
+                     const int64_t *counters, int32_t step, void *stream);
+
 /* ---- IPPO actor-critic (Sec. 4.2: independent PPO, separate weights per agent type) ----
  * Network per agent type: MLP 40 -> 256 -> 256 -> (9 policy logits + 1 value), tanh,
- * fp32, flat parameters W1 [40][256] (input-major), b1 [256], W2 [256][256], b2 [256],
+ * fp32 (the paper trains a recurrent network, Sec. 5.2.1; this feed-forward network is
+ * the one the throughput workload fixes), flat parameters W1 [40][256] (input-major), b1 [256], W2 [256][256], b2 [256],
  * W3 [256][10], b3 [10]: LOB_PPO_PARAMS floats.  Products run on MFMA. */
 #define LOB_PPO_PARAMS 78858
 
-/* Policy forward for the rollout.  params: device [n_agents][LOB_PPO_PARAMS];
+/* Policy forward for the rollout (Sec. 4.2: each agent type acts with its own network;
+ * sampling by Gumbel-max is a reading, the paper is silent).  params: device [n_agents][LOB_PPO_PARAMS];
  * obs: device [n_agents][n][40]; n_actions: host [n_agents] (1..9, the first n_actions
  * logits are the policy).  Samples one action per row by Gumbel-max with noise from the
  * counter hash of (seed', agent, action, t, row), seed' = seed + golden * (*epoch) when
@@ -242,21 +277,27 @@ int lob_policy_forward(const float *params, const float *obs, int32_t n_agents, 
                        uint64_t seed, const uint64_t *epoch, int32_t t, float *logits, int32_t *actions, float *logp,
                        float *value, void *stream);
 
-/* Add one to a device uint64 counter (a kernel, so it can be captured in a graph). */
+/* Add one to a device uint64 counter (a kernel, so it can be captured in a graph; the
+ * sampling epoch of lob_policy_forward).  Library plumbing, no passage of the paper. */
 int lob_counter_bump(uint64_t *counter, void *stream);
 
-/* Generalised advantage estimation over a rollout, all arrays device [T][n] (column =
- * env x agent): delta_t = r_t + gamma V_{t+1} (1 - d_t) - V_t with V_T = last_value [n],
+/* Generalised advantage estimation over a rollout (the paper names IPPO, Sec. 4.2, and is
+ * silent on the estimator; reading: GAE as in PPO, gamma and lambda from the caller, 0.99
+ * and 0.95 in the IPPO workload), all arrays device [T][n] (column = env x agent): delta_t = r_t + gamma V_{t+1} (1 - d_t) - V_t with V_T = last_value [n],
  * A_t = delta_t + gamma lam (1 - d_t) A_{t+1}, ret = A + V.  done: uint8 (1 = the episode
  * ended at step t). */
 int lob_gae(const float *reward, const float *value, const uint8_t *done, const float *last_value, int32_t T,
             int32_t n, float gamma, float lam, float *adv, float *ret, void *stream);
 
-/* Bytes of device workspace lob_ppo_fwd_bwd needs for a minibatch of m samples. */
+/* Bytes of device workspace lob_ppo_fwd_bwd needs for a minibatch of m samples
+ * (LOB_EINVAL for m <= 0). */
 int64_t lob_ppo_workspace_bytes(int32_t m);
 
-/* Fused clipped-PPO loss and its gradient for one minibatch of one network, with the
- * activations recomputed from obs (none stored between rollout and update).
+/* Fused clipped-PPO loss and its gradient for one minibatch of one network (Sec. 4.2:
+ * PPO per agent type; the clipped surrogate, value and entropy terms are PPO's, their
+ * weights c_v, c_e the caller's since the paper is silent), with the activations
+ * recomputed from obs (none stored between rollout and update).  An action outside
+ * [0, n_actions) counts as action 0, as the env step takes it.
  * obs [m][40], act [m] int32, logp_old, adv, ret, v_old [m] (device).  Loss =
  * policy + c_v value - c_e entropy with policy = -mean(min(r A, clip(r, 1-clip, 1+clip) A)),
  * r = exp(logp - logp_old), value = 0.5 mean(max((V-R)^2, (V_old + clip(V - V_old, -clip,
@@ -272,13 +313,13 @@ int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, c
                     float c_v, float c_e, float *workspace, int64_t workspace_bytes, float *loss, float *grad,
                     void *stream);
 
-/* Steps taken since the last reset (host-side counter). */
+/* Steps taken since the last reset or import (host-side counter; library plumbing). */
 int lob_current_step(const lob_ctx *ctx);
 
-/* Free the context (synchronises the device first).  NULL is a no-op. */
+/* Free the context (synchronises the device first).  NULL is a no-op.  Library plumbing. */
 int lob_destroy(lob_ctx *ctx);
 
-/* Static message for an error code. */
+/* Static message for an error code (library plumbing). */
 const char *lob_strerror(int code);
 
 #ifdef __cplusplus

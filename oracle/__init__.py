@@ -27,8 +27,10 @@ N_COUNTERS = 11
 COUNTER_NAMES = ("msgs", "trades", "miss", "evict", "evicted_qty", "drop", "dropped_qty",
                  "market_unfilled", "bad", "trade_overflow", "ignored")
 ENV_STATE_NAMES = ("last_bb", "last_ba", "mid2_prev", "p_init2", "last_tsec", "last_tns", "t",
-                   "last_dmid2")
-AGENT_STATE_NAMES = ("inventory", "cash", "remaining", "order_counter")
+                   "last_dmid2", "step_buy_vol", "step_sell_vol", "step_trades", "step_last_price")
+AGENT_STATE_NAMES = ("inventory", "cash", "remaining", "order_counter", "step_bought", "step_sold")
+ENV_STATE_WORDS = len(ENV_STATE_NAMES)
+AGENT_STATE_WORDS = len(AGENT_STATE_NAMES)
 N_ACTIONS = {0: 9, 1: 9, 2: 3}
 
 
@@ -81,6 +83,8 @@ def _load():
         lib.oe_export_books.restype = i32
         lib.oe_export_state.argtypes = [p, p, p, p]
         lib.oe_export_state.restype = i32
+        lib.oe_import_state.argtypes = [p] * 11 + [i32]
+        lib.oe_import_state.restype = i32
         lib.oe_hash.argtypes = [u64] * 5
         lib.oe_hash.restype = u64
         lib.oe_mix.argtypes = [u64]
@@ -228,11 +232,26 @@ class OracleEnvs:
 
     def state(self) -> dict:
         N, A = self.n_envs, self.n_agents
-        es = np.zeros((N, 8), dtype=np.int64)
-        ag = np.zeros((N, max(A, 1), 4), dtype=np.int64)
+        es = np.zeros((N, ENV_STATE_WORDS), dtype=np.int64)
+        ag = np.zeros((N, max(A, 1), AGENT_STATE_WORDS), dtype=np.int64)
         ct = np.zeros((N, N_COUNTERS), dtype=np.int64)
         self._lib.oe_export_state(self._h, _ptr(es), _ptr(ag), _ptr(ct))
         return {"env": es, "agents": ag[:, :A], "counters": ct}
+
+    def import_state(self, book: dict, state: dict, step: int) -> None:
+        """Continue every env from ``book`` (canonical layout) and ``state`` (the layouts
+        of ``state()``; counters optional) with its step counter at ``step``."""
+        N, A = self.n_envs, self.n_agents
+        arrs = [np.ascontiguousarray(book[k], dtype=np.int32)
+                for k in ("price", "qty", "oid", "tid", "tsec", "tns", "n")]
+        es = np.ascontiguousarray(state["env"], dtype=np.int64).reshape(N, ENV_STATE_WORDS)
+        ag = np.ascontiguousarray(np.asarray(state["agents"], dtype=np.int64).reshape(N, A, AGENT_STATE_WORDS)) \
+            if A else np.zeros((N, 1, AGENT_STATE_WORDS), dtype=np.int64)
+        ct = state.get("counters")
+        ct = None if ct is None else np.ascontiguousarray(ct, dtype=np.int64).reshape(N, N_COUNTERS)
+        rc = self._lib.oe_import_state(self._h, *[_ptr(a) for a in arrs], _ptr(es), _ptr(ag), _ptr(ct), int(step))
+        if rc != 0:
+            raise RuntimeError(f"oe_import_state: {rc}")
 
 
 def trade_bound_offsets(stream, caps: np.ndarray, t0: np.ndarray, n_steps: int, n_agents: int) -> np.ndarray:

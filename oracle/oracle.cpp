@@ -33,6 +33,8 @@ enum { C_MSGS, C_TRADES, C_MISS, C_EVICT, C_EVICTED_QTY, C_DROP, C_DROPPED_QTY,
        C_MARKET_UNFILLED, C_BAD, C_TRADE_OVERFLOW, C_IGNORED, N_COUNTERS };
 constexpr int OBS_DIM = 40;
 constexpr int TRADE_WORDS = 8;
+constexpr int ENV_WORDS = 12;   /* exported env state words per env */
+constexpr int AGENT_WORDS = 6; /* exported agent state words per agent */
 
 /* ------------------------------------------------------------------------------
  * Counter hash: SplitMix64's output function (Steele, Lea, Flood, "Fast splittable
@@ -822,24 +824,67 @@ int32_t oe_export_books(void *o, int32_t *price, int32_t *qty, int32_t *oid, int
     return 0;
 }
 
-/* env_state [n_envs][8]: last_bb, last_ba, mid2_prev, p_init2, last_tsec, last_tns, t,
- * last_dmid2.  agent_state [n_envs][n_agents][4]: inventory, cash, remaining, order
- * counter.  counters [n_envs][10]. */
+/* env_state [n_envs][12]: last_bb, last_ba, mid2_prev, p_init2, last_tsec, last_tns, t,
+ * last_dmid2, then the last step's statistics (buyer- and seller-initiated volume, trades,
+ * last trade price).  agent_state [n_envs][n_agents][6]: inventory, cash, remaining,
+ * order counter, bought and sold in the last step.  counters [n_envs][11]. */
 int32_t oe_export_state(void *o, int64_t *env_state, int64_t *agent_state, int64_t *counters) {
     Oracle &O = *static_cast<Oracle *>(o);
     const int32_t A = O.cfg.n_agents;
     for (int32_t e = 0; e < O.cfg.n_envs; ++e) {
         const Env &v = O.envs[(size_t)e];
-        int64_t *es = env_state + (int64_t)e * 8;
+        int64_t *es = env_state + (int64_t)e * ENV_WORDS;
         es[0] = v.last_bb; es[1] = v.last_ba; es[2] = v.mid2_prev; es[3] = v.p_init2;
         es[4] = v.last_tsec; es[5] = v.last_tns; es[6] = v.t; es[7] = v.last_dmid2;
+        es[8] = v.st_buy_vol; es[9] = v.st_sell_vol; es[10] = v.st_trades; es[11] = v.st_last_price;
         for (int32_t i = 0; i < A; ++i) {
-            int64_t *as = agent_state + ((int64_t)e * A + i) * 4;
+            int64_t *as = agent_state + ((int64_t)e * A + i) * AGENT_WORDS;
             const Agent &g = v.agents[(size_t)i];
             as[0] = g.inv; as[1] = g.cash; as[2] = g.rem; as[3] = g.ctr;
+            as[4] = g.step_bq; as[5] = g.step_sq;
         }
         for (int k = 0; k < N_COUNTERS; ++k) counters[(int64_t)e * N_COUNTERS + k] = v.counters[k];
     }
+    return 0;
+}
+
+/* The inverse of oe_export_books + oe_export_state: every env continues from the given
+ * books (canonical layout, counts clamped to the capacity) and state, as if it had been
+ * stepped there (Sec. 4: an episode starts from a book state).  The step counter of every
+ * env is set to `step`; counters may be NULL (zero). */
+int32_t oe_import_state(void *o, const int32_t *price, const int32_t *qty, const int32_t *oid,
+                        const int32_t *tid, const int32_t *tsec, const int32_t *tns, const int32_t *n,
+                        const int64_t *env_state, const int64_t *agent_state, const int64_t *counters,
+                        int32_t step) {
+    Oracle &O = *static_cast<Oracle *>(o);
+    if (step < 0 || step > O.cfg.episode_len) return -1;
+    const int32_t A = O.cfg.n_agents, mc = O.cfg.max_cap;
+    const int32_t *f[6] = {price, qty, oid, tid, tsec, tns};
+    for (int32_t e = 0; e < O.cfg.n_envs; ++e) {
+        Env &v = O.envs[(size_t)e];
+        for (int s = 0; s < 2; ++s) {
+            const int32_t cnt = std::min(std::max(n[e * 2 + s], 0), v.book.cap);
+            std::vector<Order> list;
+            const int64_t base = ((int64_t)e * 2 + s) * mc;
+            for (int32_t j = 0; j < cnt; ++j)
+                list.push_back(Order{f[0][base + j], f[1][base + j], f[2][base + j], f[3][base + j],
+                                     f[4][base + j], f[5][base + j]});
+            v.book.side(s).load(list);
+        }
+        const int64_t *es = env_state + (int64_t)e * ENV_WORDS;
+        v.last_bb = (int32_t)es[0]; v.last_ba = (int32_t)es[1]; v.mid2_prev = es[2]; v.p_init2 = es[3];
+        v.last_tsec = (int32_t)es[4]; v.last_tns = (int32_t)es[5]; v.t = step; v.last_dmid2 = es[7];
+        v.st_buy_vol = es[8]; v.st_sell_vol = es[9]; v.st_trades = es[10]; v.st_last_price = (int32_t)es[11];
+        v.agents.assign((size_t)A, Agent{});
+        for (int32_t i = 0; i < A; ++i) {
+            const int64_t *as = agent_state + ((int64_t)e * A + i) * AGENT_WORDS;
+            Agent &g = v.agents[(size_t)i];
+            g.inv = as[0]; g.cash = as[1]; g.rem = as[2]; g.ctr = as[3];
+            g.step_bq = as[4]; g.step_sq = as[5];
+        }
+        for (int k = 0; k < N_COUNTERS; ++k) v.counters[k] = counters ? counters[(int64_t)e * N_COUNTERS + k] : 0;
+    }
+    O.was_reset = true;
     return 0;
 }
 

@@ -75,7 +75,14 @@ int32_t oe_step(void *o, int32_t n_steps,
 int32_t oe_observe(void *o, float *obs);
 int32_t oe_export_books(void *o, int32_t *price, int32_t *qty, int32_t *oid, int32_t *tid,
                         int32_t *tsec, int32_t *tns, int32_t *n);
+/* env_state [n_envs][12], agent_state [n_envs][n_agents][6], counters [n_envs][11]. */
 int32_t oe_export_state(void *o, int64_t *env_state, int64_t *agent_state, int64_t *counters);
+/* Continue every env from the given books and state (the exported layouts); every env's
+ * step counter becomes `step`; counters may be NULL (zero). */
+int32_t oe_import_state(void *o, const int32_t *price, const int32_t *qty, const int32_t *oid,
+                        const int32_t *tid, const int32_t *tsec, const int32_t *tns, const int32_t *n,
+                        const int64_t *env_state, const int64_t *agent_state, const int64_t *counters,
+                        int32_t step);
 
 /* The method's counter hash (SplitMix64 output function applied in a chain). */
 uint64_t oe_hash(uint64_t seed, uint64_t dom, uint64_t a, uint64_t b, uint64_t c);

@@ -77,6 +77,14 @@ def gae(rewards, values, dones, last_value, gamma, lam):
     return adv, adv + v
 
 
+def action_index(actions, n_actions):
+    """The action a sample's log-probability is taken at.  Reading (the paper is silent):
+    an action outside [0, n_actions) counts as action 0, the action the env step takes
+    for it."""
+    a = np.asarray(actions, dtype=np.int64)
+    return np.where((a < 0) | (a >= n_actions), 0, a)
+
+
 def ppo_loss_parts(params, obs, actions, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01):
     """Clipped PPO objective on one minibatch, float64: returns (total, policy, value, entropy).
 
@@ -85,7 +93,7 @@ def ppo_loss_parts(params, obs, actions, logp_old, adv, ret, v_old, n_actions, c
     entropy = mean(-sum_a p log p); total = policy + c_v value - c_e entropy."""
     logits, value = mlp_forward(params, obs)
     lp = log_softmax(logits, n_actions)
-    a = np.asarray(actions, dtype=np.int64)
+    a = action_index(actions, n_actions)
     logp = lp[np.arange(len(a)), a]
     ratio = np.exp(logp - np.asarray(logp_old, dtype=np.float64))
     A = np.asarray(adv, dtype=np.float64)
@@ -108,7 +116,7 @@ def ppo_loss_and_grad(params, obs, actions, logp_old, adv, ret, v_old, n_actions
     h2 = torch.tanh(h1 @ P["W2"] + P["b2"])
     out = h2 @ P["W3"] + P["b3"]
     lp = torch.log_softmax(out[:, :n_actions], dim=1)
-    a = torch.tensor(np.asarray(actions, dtype=np.int64))
+    a = torch.tensor(action_index(actions, n_actions))
     logp = lp[torch.arange(len(a)), a]
     ratio = torch.exp(logp - torch.tensor(np.asarray(logp_old, dtype=np.float64)))
     A = torch.tensor(np.asarray(adv, dtype=np.float64))

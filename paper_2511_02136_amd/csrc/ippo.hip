@@ -407,7 +407,9 @@ __device__ __noinline__ void ppo_tile(const PpoArgs &a, const GLOBAL float *Pg, 
                     const float lp = z[j] - lse;
                     H -= expf(lp) * lp;
                 }
-                const int act = a.act[s];
+                /* an action outside [0, nact) counts as action 0, as the env step takes it */
+                int act = a.act[s];
+                if ((unsigned)act >= (unsigned)nact) act = 0;
                 const float logp = z[act] - lse;
                 const float ratio = expf(logp - a.logp_old[s]);
                 const float A = a.adv[s];

@@ -50,6 +50,9 @@ constexpr int MAXA = LOB_MAX_AGENTS;
 constexpr int MAXLV = 8;          /* desired price levels per agent per step */
 constexpr int AGW = 8;            /* internal agent words: inv, cash, rem, ctr, step_bq, step_sq */
 constexpr int STW = 4;            /* step statistics: buy vol, sell vol, trades, last price */
+constexpr int ENVW = 8;           /* internal env state words (the exported state adds the STW statistics) */
+static_assert(ENVW + STW == LOB_ENV_STATE_WORDS, "exported env state = internal env state + step statistics");
+static_assert(LOB_AGENT_STATE_WORDS <= AGW, "exported agent words");
 
 /* Per-wave LDS layout after the book (int32 word offsets), for A agents (at most 8 new
  * orders per agent per step):
@@ -843,7 +846,7 @@ struct Run {
             }
         }
         /* env state, statistics and agent state into LDS, counters into lanes */
-        if (lane < LOB_ENV_STATE_WORDS) ENV()[lane] = a.env_state[(int64_t)e * LOB_ENV_STATE_WORDS + lane];
+        if (lane < ENVW) ENV()[lane] = a.env_state[(int64_t)e * ENVW + lane];
         if (lane < STW) X64(xl().st)[lane] = a.stats[(int64_t)e * STW + lane];
         if (lane < A * AGW) AG(0)[lane] = a.agent_state[(int64_t)e * A * AGW + lane];
         ctr = lane < NCTR ? a.counters[(int64_t)e * LOB_N_COUNTERS + lane] : 0;
@@ -918,7 +921,7 @@ struct Run {
             a.bk_n[gb] = n0;
             a.bk_n[gb + 1] = n1;
         }
-        if (lane < LOB_ENV_STATE_WORDS) a.env_state[(int64_t)e * LOB_ENV_STATE_WORDS + lane] = ENV()[lane];
+        if (lane < ENVW) a.env_state[(int64_t)e * ENVW + lane] = ENV()[lane];
         if (lane < NCTR) a.counters[(int64_t)e * LOB_N_COUNTERS + lane] = ctr;
         if (lane < STW) a.stats[(int64_t)e * STW + lane] = X64(xl().st)[lane];
         if (lane < A * AGW) a.agent_state[(int64_t)e * A * AGW + lane] = AG(0)[lane];
@@ -1197,7 +1200,7 @@ __global__ void __launch_bounds__(256) k_reset(ResetArgs a) {
     case 5: v = (int32_t)((uint32_t)tkey ^ 0x80000000u); break;
     default: v = 0; break;
     }
-    if (lane < LOB_ENV_STATE_WORDS) a.env_state[(int64_t)e * LOB_ENV_STATE_WORDS + lane] = v;
+    if (lane < ENVW) a.env_state[(int64_t)e * ENVW + lane] = v;
     if (lane < LOB_N_COUNTERS) a.counters[(int64_t)e * LOB_N_COUNTERS + lane] = 0;
     if (lane < STW) a.stats[(int64_t)e * STW + lane] = 0;
     if (lane < a.n_agents * AGW) {
@@ -1215,6 +1218,8 @@ struct ExportArgs {
     int32_t *dst_n;
     const int64_t *agent_src;
     int64_t *agent_dst;
+    const int64_t *env_src, *stats_src;
+    int64_t *env_dst;
 };
 
 __global__ void k_export_books(ExportArgs a) {
@@ -1235,6 +1240,56 @@ __global__ void k_export_agents(ExportArgs a) {
         const int64_t ea = g / LOB_AGENT_STATE_WORDS;
         const int w = (int)(g - ea * LOB_AGENT_STATE_WORDS);
         a.agent_dst[g] = a.agent_src[ea * AGW + w];
+    }
+}
+
+/* exported env state: the internal words, then the last step's statistics */
+__global__ void k_export_env(ExportArgs a) {
+    const int64_t total = (int64_t)a.n_envs * LOB_ENV_STATE_WORDS;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = g / LOB_ENV_STATE_WORDS;
+        const int w = (int)(g - e * LOB_ENV_STATE_WORDS);
+        a.env_dst[g] = w < ENVW ? a.env_src[e * ENVW + w] : a.stats_src[e * STW + (w - ENVW)];
+    }
+}
+
+/* The inverse of the exports: books in canonical layout (counts clamped to each env's
+ * capacity, unused slots ignored) and the exported state, with every env's step counter
+ * set to `step`; counters may be absent (zero). */
+struct ImportArgs {
+    int32_t n_envs, n_agents, max_cap, step;
+    const int32_t *caps;
+    const int32_t *src[NF];
+    const int32_t *src_n;
+    const int64_t *env_src, *agent_src, *ctr_src;
+    int32_t *dst[NF];
+    int32_t *dst_n;
+    int64_t *env_state, *agent_state, *counters, *stats;
+};
+
+__global__ void __launch_bounds__(256) k_import(ImportArgs a) {
+    const int wave = (int)(threadIdx.x >> 6), waves = (int)(blockDim.x >> 6);
+    const int e = (int)blockIdx.x * waves + wave;
+    if (e >= a.n_envs) return;
+    const int lane = lane_id();
+    const int cap = a.caps[e];
+    for (int s = 0; s < 2; ++s) {
+        const int n = min(max(a.src_n[e * 2 + s], 0), cap);
+        const int64_t off = ((int64_t)e * 2 + s) * a.max_cap;
+        for (int i = lane; i < n; i += WAVE) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) a.dst[f][off + i] = a.src[f][off + i];
+        }
+        if (lane == 0) a.dst_n[e * 2 + s] = n;
+    }
+    const int64_t *es = a.env_src + (int64_t)e * LOB_ENV_STATE_WORDS;
+    if (lane < ENVW) a.env_state[(int64_t)e * ENVW + lane] = lane == 6 ? (int64_t)a.step : es[lane];
+    if (lane < STW) a.stats[(int64_t)e * STW + lane] = es[ENVW + lane];
+    if (lane < NCTR) a.counters[(int64_t)e * LOB_N_COUNTERS + lane] = a.ctr_src ? a.ctr_src[(int64_t)e * LOB_N_COUNTERS + lane] : 0;
+    if (lane < a.n_agents * AGW) {
+        const int i = lane / AGW, w = lane % AGW;
+        a.agent_state[(int64_t)e * a.n_agents * AGW + lane] =
+            w < LOB_AGENT_STATE_WORDS ? a.agent_src[((int64_t)e * a.n_agents + i) * LOB_AGENT_STATE_WORDS + w] : 0;
     }
 }
 
@@ -1292,7 +1347,8 @@ struct lob_ctx {
     hipEvent_t ev_fork = nullptr, ev_join[MAX_CLASSES] = {};
     /* the plan: which (stream offsets, first step, steps) the env order was made for */
     const int64_t *plan_off = nullptr;
-    int plan_t0 = -1, plan_steps = -1;
+    int64_t plan_n_msgs = -1;
+    int plan_t0 = -1, plan_steps = -1, plan_rows = -1;
     int device = 0;
     int n_cu = 256;
     int t = 0;
@@ -1430,8 +1486,16 @@ int launch_env(lob_ctx *c, KArgs a, hipStream_t st) {
     const int nc = (int)c->classes.size();
     const int lanes = std::min(nc, CONC_LANES);
     if (lanes > 1 && !hip_ok(hipEventRecord(c->ev_fork, st))) return LOB_EHIP;
-    for (int l = 1; l < lanes; ++l) {
-        if (!hip_ok(hipStreamWaitEvent(c->streams[l], c->ev_fork, 0))) return LOB_EHIP;
+    /* lanes forked from the caller's stream so far: every one of them is joined back
+     * below, also when a launch fails (an unjoined fork would invalidate a stream
+     * capture, and the caller's stream would not wait for work already queued) */
+    int forked = 1, rc = LOB_OK;
+    for (int l = 1; l < lanes && rc == LOB_OK; ++l) {
+        if (!hip_ok(hipStreamWaitEvent(c->streams[l], c->ev_fork, 0))) {
+            rc = LOB_EHIP;
+            break;
+        }
+        forked = l + 1;
         /* The classes start one after another, largest books first, LANE_GAP apart (a
          * single step: LANE_GAP_STEP, which it pays every step): started at the same
          * instant, the workgroups of two classes interleave differently from run to run,
@@ -1440,19 +1504,19 @@ int launch_env(lob_ctx *c, KArgs a, hipStream_t st) {
          * then find no room). */
         hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, c->streams[l],
                            (int64_t)((a.n_steps > 1 ? LANE_GAP : LANE_GAP_STEP) * l));
+        if (hipGetLastError() != hipSuccess) rc = LOB_EHIP;
     }
-    for (int i = 0; i < nc; ++i) {
+    for (int i = 0; i < nc && rc == LOB_OK; ++i) {
         const int k = nc - 1 - i; /* largest books first */
         const int l = i % lanes;
-        const int rc = launch_class(c, (size_t)k, a, l == 0 ? st : c->streams[l]);
-        if (rc != LOB_OK) return rc;
+        rc = launch_class(c, (size_t)k, a, l == 0 ? st : c->streams[l]);
     }
-    for (int l = 1; l < lanes; ++l) {
+    for (int l = 1; l < forked; ++l) {
         if (!hip_ok(hipEventRecord(c->ev_join[l], c->streams[l])) ||
             !hip_ok(hipStreamWaitEvent(st, c->ev_join[l], 0)))
-            return LOB_EHIP;
+            rc = rc != LOB_OK ? rc : LOB_EHIP;
     }
-    return LOB_OK;
+    return rc;
 }
 
 /* Default waves (envs) per workgroup for a class: the most resident envs per CU, LDS
@@ -1568,7 +1632,15 @@ void balance_classes(lob_ctx *c, const std::vector<int64_t> &a0, const std::vect
  * balance share set, size their work queues (balance_classes).  Reads two columns of
  * the CSR offsets back to the host (synchronous). */
 int make_plan(lob_ctx *c, const lob_msgs *m, int t0, int n) {
-    if (c->plan_off == m->off && c->plan_t0 == t0 && c->plan_steps == n) return LOB_OK;
+    /* the plan is kept while the stream (offsets array, its size and step rows) and the
+     * steps are the same */
+    if (c->plan_off == m->off && c->plan_n_msgs == m->n_msgs && c->plan_rows == m->n_steps && c->plan_t0 == t0 &&
+        c->plan_steps == n)
+        return LOB_OK;
+    /* a launch still running (on the caller's stream or the class streams, which do not
+     * synchronise with the null stream) may be reading the env list and the schedule
+     * about to be rewritten: wait for the device first */
+    if (!hip_ok(hipDeviceSynchronize())) return LOB_EHIP;
     const int N = c->cfg.n_envs;
     const size_t pitch = (size_t)(m->n_steps + 1) * sizeof(int64_t);
     std::vector<int64_t> a0((size_t)N), a1((size_t)N);
@@ -1585,6 +1657,8 @@ int make_plan(lob_ctx *c, const lob_msgs *m, int t0, int n) {
     if (!hip_ok(hipMemcpy(c->d_env_list, c->env_list.data(), (size_t)N * 4, hipMemcpyHostToDevice)))
         return LOB_EHIP;
     c->plan_off = m->off;
+    c->plan_n_msgs = m->n_msgs;
+    c->plan_rows = m->n_steps;
     c->plan_t0 = t0;
     c->plan_steps = n;
     return LOB_OK;
@@ -1638,7 +1712,7 @@ int lob_init(const lob_config *cfg, lob_ctx **out) {
     rc |= dalloc(&c->d_caps, (size_t)N);
     for (int f = 0; f < NF; ++f) rc |= dalloc(&c->d_bk[f], slots);
     rc |= dalloc(&c->d_bk_n, (size_t)N * 2);
-    rc |= dalloc(&c->d_env, (size_t)N * LOB_ENV_STATE_WORDS);
+    rc |= dalloc(&c->d_env, (size_t)N * ENVW);
     rc |= dalloc(&c->d_agent, (size_t)(N * std::max<int64_t>(A, 1) * AGW));
     rc |= dalloc(&c->d_ctr, (size_t)N * LOB_N_COUNTERS);
     rc |= dalloc(&c->d_stats, (size_t)N * STW);
@@ -1805,7 +1879,7 @@ int lob_autotune(lob_ctx *c, const lob_msgs *m, int32_t n_steps, const lob_out *
     std::vector<Buf> bufs;
     for (int f = 0; f < NF; ++f) bufs.push_back({nullptr, c->d_bk[f], slots * 4});
     bufs.push_back({nullptr, c->d_bk_n, N * 2 * 4});
-    bufs.push_back({nullptr, c->d_env, N * LOB_ENV_STATE_WORDS * 8});
+    bufs.push_back({nullptr, c->d_env, N * ENVW * 8});
     bufs.push_back({nullptr, c->d_agent, N * A * AGW * 8});
     bufs.push_back({nullptr, c->d_ctr, N * LOB_N_COUNTERS * 8});
     bufs.push_back({nullptr, c->d_stats, N * STW * 8});
@@ -1925,20 +1999,57 @@ int lob_export_state(lob_ctx *c, int64_t *env_state, int64_t *agent_state, int64
     if (!c->reset_done) return LOB_ESTATE;
     hipStream_t st = (hipStream_t)stream;
     const size_t N = (size_t)c->cfg.n_envs;
-    if (env_state && !hip_ok(hipMemcpyAsync(env_state, c->d_env, N * LOB_ENV_STATE_WORDS * 8, hipMemcpyDeviceToDevice, st)))
-        return LOB_EHIP;
+    ExportArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n_envs = c->cfg.n_envs;
+    a.n_agents = c->cfg.n_agents;
+    a.agent_src = c->d_agent;
+    a.agent_dst = agent_state;
+    a.env_src = c->d_env;
+    a.stats_src = c->d_stats;
+    a.env_dst = env_state;
+    if (env_state) {
+        hipLaunchKernelGGL(k_export_env, dim3(64), dim3(256), 0, st, a);
+        if (hipGetLastError() != hipSuccess) return LOB_EHIP;
+    }
     if (counters && !hip_ok(hipMemcpyAsync(counters, c->d_ctr, N * LOB_N_COUNTERS * 8, hipMemcpyDeviceToDevice, st)))
         return LOB_EHIP;
     if (agent_state && c->cfg.n_agents > 0) {
-        ExportArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.n_envs = c->cfg.n_envs;
-        a.n_agents = c->cfg.n_agents;
-        a.agent_src = c->d_agent;
-        a.agent_dst = agent_state;
         hipLaunchKernelGGL(k_export_agents, dim3(256), dim3(256), 0, st, a);
         if (hipGetLastError() != hipSuccess) return LOB_EHIP;
     }
+    return LOB_OK;
+}
+
+int lob_import_state(lob_ctx *c, const lob_books *books, const int64_t *env_state, const int64_t *agent_state,
+                     const int64_t *counters, int32_t step, void *stream) {
+    if (!c || !books || !books->price || !books->qty || !books->oid || !books->tid || !books->tsec || !books->tns ||
+        !books->n || !env_state || (c->cfg.n_agents > 0 && !agent_state))
+        return LOB_EINVAL;
+    if (step < 0 || step > c->cfg.episode_len) return LOB_EINVAL;
+    ImportArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n_envs = c->cfg.n_envs;
+    a.n_agents = c->cfg.n_agents;
+    a.max_cap = c->cfg.max_cap;
+    a.step = step;
+    a.caps = c->d_caps;
+    const int32_t *src[NF] = {books->price, books->qty, books->oid, books->tid, books->tsec, books->tns};
+    for (int f = 0; f < NF; ++f) { a.src[f] = src[f]; a.dst[f] = c->d_bk[f]; }
+    a.src_n = books->n;
+    a.env_src = env_state;
+    a.agent_src = agent_state;
+    a.ctr_src = counters;
+    a.dst_n = c->d_bk_n;
+    a.env_state = c->d_env;
+    a.agent_state = c->d_agent;
+    a.counters = c->d_ctr;
+    a.stats = c->d_stats;
+    const int waves = 4;
+    hipLaunchKernelGGL(k_import, dim3((c->cfg.n_envs + waves - 1) / waves), dim3(64 * waves), 0, (hipStream_t)stream, a);
+    if (hipGetLastError() != hipSuccess) return LOB_EHIP;
+    c->t = step;
+    c->reset_done = true;
     return LOB_OK;
 }
 

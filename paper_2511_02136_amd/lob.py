@@ -20,8 +20,8 @@ _lib = None
 OBS_DIM = 40
 TRADE_WORDS = 8
 N_COUNTERS = 11
-ENV_STATE_WORDS = 8
-AGENT_STATE_WORDS = 4
+ENV_STATE_WORDS = 12
+AGENT_STATE_WORDS = 6
 BOOK_FIELDS = ("price", "qty", "oid", "tid", "tsec", "tns")
 AGENT_KINDS = {"exec": 0, "mm": 1, "dir": 2, "mm_buysell": 3}
 
@@ -69,6 +69,7 @@ def lib():
         L.lob_observe.argtypes = [p, p, p]
         L.lob_export_books.argtypes = [p, ctypes.POINTER(_Books), p]
         L.lob_export_state.argtypes = [p, p, p, p, p]
+        L.lob_import_state.argtypes = [p, ctypes.POINTER(_Books), p, p, p, i32, p]
         L.lob_current_step.argtypes = [p]
         L.lob_plan.argtypes = [p, ctypes.POINTER(_Msgs), i32]
         L.lob_schedule_get.argtypes = [p, p, i32]
@@ -80,7 +81,7 @@ def lib():
         L.lob_strerror.argtypes = [ctypes.c_int]
         L.lob_strerror.restype = ctypes.c_char_p
         for f in ("lob_init", "lob_reset", "lob_step", "lob_rollout", "lob_observe", "lob_export_books",
-                  "lob_export_state", "lob_current_step", "lob_destroy", "lob_plan", "lob_schedule_get",
+                  "lob_export_state", "lob_import_state", "lob_current_step", "lob_destroy", "lob_plan", "lob_schedule_get",
                   "lob_schedule_set", "lob_set_padded", "lob_schedule_balance", "lob_autotune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -316,3 +317,33 @@ class LobEnv:
         _check(self._lib.lob_export_state(self._h, _p(es), _p(ag) if A else None, _p(ct), _stream()),
                "lob_export_state")
         return {"env": es, "agents": ag[:, :A], "counters": ct}
+
+    def import_state(self, books: dict, state: dict, step: int):
+        """Continue every env from ``books`` (canonical layout, as ``books()`` returns) and
+        ``state`` (the layouts of ``state()``; counters optional) with the step counter at
+        ``step`` (see lob_import_state)."""
+        N, A, dev = self.n_envs, self.n_agents, self.device
+        bt = {k: torch.as_tensor(books[k]).to(dev, torch.int32).contiguous() for k in BOOK_FIELDS + ("n",)}
+        for k in BOOK_FIELDS:
+            if tuple(bt[k].shape) != (N, 2, self.max_cap):
+                raise LobError(f"books field {k} must be [{N}, 2, {self.max_cap}]")
+        if tuple(bt["n"].shape) != (N, 2):
+            raise LobError("books n must be [n_envs, 2]")
+        es = torch.as_tensor(state["env"]).to(dev, torch.int64).contiguous()
+        if tuple(es.shape) != (N, ENV_STATE_WORDS):
+            raise LobError(f"env state must be [{N}, {ENV_STATE_WORDS}]")
+        ag = None
+        if A:
+            ag = torch.as_tensor(state["agents"]).to(dev, torch.int64).contiguous()
+            if tuple(ag.shape) != (N, A, AGENT_STATE_WORDS):
+                raise LobError(f"agent state must be [{N}, {A}, {AGENT_STATE_WORDS}]")
+        ct = state.get("counters")
+        if ct is not None:
+            ct = torch.as_tensor(ct).to(dev, torch.int64).contiguous()
+            if tuple(ct.shape) != (N, N_COUNTERS):
+                raise LobError(f"counters must be [{N}, {N_COUNTERS}]")
+        b = _Books(*[bt[k].data_ptr() for k in BOOK_FIELDS + ("n",)])
+        _check(self._lib.lob_import_state(self._h, ctypes.byref(b), _p(es), _p(ag), _p(ct), int(step), _stream()),
+               "lob_import_state")
+        self._keep = (bt, es, ag, ct)  # alive until the stream has consumed them
+        return self

@@ -92,3 +92,13 @@ def test_host_side_checks_of_the_actor_critic():
     assert lib.lob_policy_forward(d[0], d[1], 2, 8, bad, 0, None, 0, None, d[2], d[3], d[4], None) == -1
     lib.lob_counter_bump.argtypes = [p, p]
     assert lib.lob_counter_bump(None, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblob.so not built")
+def test_host_side_checks_of_the_state_import():
+    """lob_import_state rejects a NULL context, NULL books and NULL state before any
+    device call."""
+    lib = ctypes.CDLL(LIB)
+    p = ctypes.c_void_p
+    lib.lob_import_state.argtypes = [p, p, p, p, p, ctypes.c_int32, p]
+    assert lib.lob_import_state(None, None, None, None, None, 0, None) == -1

@@ -452,3 +452,67 @@ def test_lobster_format_day_parity(tmp_path, agents, mode):
     assert_same_state(env.state(), o.state(), what=name)
     ct = o.state()["counters"]
     assert ct[:, 10].sum() > 0 and ct[:, 1].sum() > 0  # ignored messages and trades occurred
+
+
+def test_import_state_continues_in_a_fresh_context():
+    """64 steps, export of the books and state, import into a fresh context, 64 more
+    steps: every output, the books and the state equal the oracle's uninterrupted
+    128-step run, and the observation right after the import equals the exporting
+    context's.  The oracle's own state at step 64, imported into a third context and
+    run in the per-step form, continues the same way."""
+    LobEnv, DeviceStream = _lob()
+    w = synth.Workload("import", n_envs=160, n_steps=128, msgs_range=(1, 200), cap_choices=(50, 100, 200, 400),
+                       agents=("exec", "mm"), seed=42)
+    print(f"\n[import] envs={w.n_envs} steps=64+64", flush=True)
+    s = synth.generate(w)
+    o = oracle_for(s, s.book, s.caps, w.max_cap, w.agents, w.ep_len, w.seed)
+    ref1 = o.step(s, n_steps=64)
+    o_books, o_state, o_obs = o.books(), o.state(), o.observe()
+    ref2 = o.step(s, n_steps=64)
+    ds = DeviceStream.from_host(s)
+    env1 = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+    g1 = env1.rollout(ds, 64, trade_off=torch.from_numpy(ref1["trade_off"]).cuda())
+    books, state = env1.books(), env1.state()
+    obs1 = env1.observe()
+    torch.cuda.synchronize()
+    assert_same_outputs(g1, ref1, 64, what="import/first")
+    env1.close()
+    env2 = LobEnv(s.caps, w.max_cap, w.agents, w.ep_len, w.seed)
+    env2.import_state(books, state, 64)
+    assert env2.t == 64
+    assert torch.equal(env2.observe(), obs1)
+    assert np.array_equal(obs1.cpu().numpy().view(np.int32), o_obs.view(np.int32))
+    g2 = env2.rollout(ds, 64, trade_off=torch.from_numpy(ref2["trade_off"]).cuda())
+    torch.cuda.synchronize()
+    assert_same_outputs(g2, ref2, 64, what="import/second")
+    assert_same_books(env2.books(), o.books(), what="import")
+    assert_same_state(env2.state(), o.state(), what="import")
+    # the oracle's state imported
+    env3 = LobEnv(s.caps, w.max_cap, w.agents, w.ep_len, w.seed)
+    env3.import_state({k: torch.from_numpy(v) for k, v in o_books.items()},
+                      {k: torch.from_numpy(v) for k, v in o_state.items()}, 64)
+    g3 = run_steps(env3, ds, 64, None, torch.from_numpy(ref2["trade_off"]).cuda())
+    torch.cuda.synchronize()
+    assert_same_outputs(g3, ref2, 64, what="import/oracle state")
+    assert_same_books(env3.books(), o.books(), what="import/oracle state")
+    assert_same_state(env3.state(), o.state(), what="import/oracle state")
+
+
+def test_replay1_full_size_parity():
+    """The single-env replay workload at full size (10^6 messages in 10,000 steps of 100,
+    no agents) in one persistent launch: every step's trade count and every trade
+    record, the final book and the state equal the oracle's."""
+    _, DeviceStream = _lob()
+    w = synth.WORKLOADS["replay1"]
+    print(f"\n[parity] full-size {w.name}", flush=True)
+    s = synth.generate(w)
+    o = oracle_for(s, s.book, s.caps, w.max_cap, w.agents, w.ep_len, w.seed)
+    ref = o.step(s, n_steps=w.n_steps)
+    env = gpu_env(s.caps, w.max_cap, w.agents, w.ep_len, w.seed, s.book)
+    got = env.rollout(DeviceStream.from_host(s), w.n_steps, trade_off=torch.from_numpy(ref["trade_off"]).cuda())
+    torch.cuda.synchronize()
+    assert int(ref["n_trades"].sum()) > 100_000
+    assert_same_outputs(got, ref, w.n_steps, what=w.name)
+    assert_same_books(env.books(), o.books(), what=w.name)
+    assert_same_state(env.state(), o.state(), what=w.name)
+    assert int(o.state()["counters"][0, 0]) == 1_000_000

@@ -86,3 +86,35 @@ def test_update_runs_and_changes_the_policy():
     assert st["minibatches"] == tr.epochs * tr.minibatches
     assert not torch.equal(before, tr.params.detach())
     assert torch.isfinite(tr.params).all()
+
+
+def test_full_size_learned_policy_rollout_parity():
+    """The IPPO workload's rollout at full size (4096 envs x 128 steps, actions sampled by
+    the policy kernel) in the form the benchmark times, a replay of the captured HIP
+    graph: 48 sampled envs replayed by the oracle with the recorded actions are
+    bit-exact (trades, fills, rewards, observations, done)."""
+    w, s, tr = make_trainer(n_envs=4096, n_steps=128, seed=9)
+    assert w == synth.WORKLOADS["ippo4096"]
+    print("\n[parity] full-size ippo4096 learned-policy rollout", flush=True)
+    tr.rollout(use_graph=True)
+    tr.rollout(use_graph=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    sample = np.sort(rng.choice(w.n_envs, size=48, replace=False))
+    hs, book, caps = subset_stream(s, sample)
+    acts = np.ascontiguousarray(tr.pol["actions"].cpu().numpy()[:, :, sample])
+    assert acts.min() >= 0 and acts.max() <= 8
+    o = OracleEnvs(caps, w.max_cap, synth.agent_kinds(w.agents), w.ep_len, w.seed, env_ids=sample)
+    o.reset(book)
+    ref = o.step(hs, n_steps=w.n_steps, actions=acts)
+    got = {k: tr.out[k] for k in ("n_trades", "fills", "reward", "obs", "done")}
+    got["actions"] = None
+    r = dict(ref)
+    r["trades"] = None
+    assert_same_outputs(got, r, w.n_steps, envs=sample, what="ippo4096")
+    goff = tr.out["trade_off"].cpu().numpy()
+    for j, e in enumerate(sample):
+        cnt = int(ref["n_trades"][:, j].sum())
+        a = tr.out["trades"][goff[e]: goff[e] + cnt].cpu().numpy()
+        b = ref["trades"][ref["trade_off"][j]: ref["trade_off"][j] + cnt]
+        assert np.array_equal(a, b), e

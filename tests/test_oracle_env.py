@@ -109,8 +109,10 @@ def test_two_agent_scenario_step_by_step():
     assert bids == [[103, 3, 51, 0, 2, 10], [99, 10, 1, 0, 1, 0]]
     assert asks == []
     st = o.state()
-    assert st["env"][0].tolist() == [103, 103, 206, 200, 2, 10, 2, 4]
-    assert st["agents"][0].tolist() == [[-6, 610, 0, 2], [-1, 103, 0, 2]]
+    # the last words: step 1's buyer-initiated volume 2, seller-initiated 0, one trade, at 103
+    assert st["env"][0].tolist() == [103, 103, 206, 200, 2, 10, 2, 4, 2, 0, 1, 103]
+    # inventory, cash, remaining, order counter, bought and sold in step 1
+    assert st["agents"][0].tolist() == [[-6, 610, 0, 2, 0, 2], [-1, 103, 0, 2, 0, 0]]
     assert st["counters"][0].tolist() == [8, 4, 0, 0, 0, 0, 0, 0, 0, 0, 0]
     # observations after step 0
     ob = out["obs"][0, :, 0]
@@ -154,7 +156,7 @@ def test_execution_net_to_target_partial_cancels_newest_first():
     bids, asks = book_lists(o.books(), 0)
     assert [a[:4] for a in asks] == [[102, 2, E0, 1], [102, 2, E0 + 1, 1]]
     st = o.state()
-    assert st["agents"][0].tolist() == [[-2, 204, 98, 2]]
+    assert st["agents"][0].tolist() == [[-2, 204, 98, 2, 0, 0]]
     assert st["counters"][0, 2] == 0  # no cancel missed
     assert out["reward"][1, 0, 0] == f32(204.0 - 101.0 * 2)
     pen = float(np.float32(0.01))
@@ -180,7 +182,7 @@ def test_market_maker_ladder_keep_and_clamp():
     assert [b[:4] for b in bids] == [[99, 10, E0 + 8, 1]]
     assert [a[:4] for a in asks] == [[101, 10, E0 + 9, 1], [101, 3, 61, 0], [102, 5, 2, 0]]
     st = o.state()
-    assert st["agents"][0, 0].tolist() == [7, -700, 0, 10]
+    assert st["agents"][0, 0].tolist() == [7, -700, 0, 10, 0, 0]
 
 
 # ----------------------------------------------------------------------------------
@@ -359,3 +361,91 @@ def test_spooner_lambda_one_and_invariants():
         for e in range(16):
             if books["n"][e, 0] and books["n"][e, 1]:
                 assert books["price"][e, 0, 0] < books["price"][e, 1, 0]
+
+
+# ----------------------------------------------------------------------------------
+# state export and import (Sec. 4: an episode starts from a given book state)
+# ----------------------------------------------------------------------------------
+def _state_workload():
+    return synth.Workload("st", n_envs=6, n_steps=12, msgs_range=(1, 60), cap_choices=(3, 8, 20),
+                          agents=("exec", "mm", "dir"), seed=140, mid0=1000, snapshot_fill_pct=50)
+
+
+def test_exported_step_statistics_match_the_observation():
+    """The exported last-step statistics are the observation's step features: buyer-
+    and seller-initiated volume, trades and the last trade price (features 27-30), each
+    agent's bought and sold quantity (features 38-39); steps since reset is word 6."""
+    w = _state_workload()
+    s = synth.generate(w, threads=2)
+    o = OracleEnvs(s.caps, w.max_cap, synth.agent_kinds(w.agents), w.ep_len, w.seed, exec_task=60)
+    o.reset(s.book)
+    for t in range(w.n_steps):
+        out = o.step(s, n_steps=1)
+        st = o.state()
+        obs = out["obs"][0]
+        env = st["env"]
+        mid2 = env[:, 0] + env[:, 1]
+        assert np.array_equal(env[:, 6], np.full(w.n_envs, t + 1))
+        for i in range(len(w.agents)):
+            assert np.array_equal(obs[i, :, 27], env[:, 8].astype(np.float32))
+            assert np.array_equal(obs[i, :, 28], env[:, 9].astype(np.float32))
+            assert np.array_equal(obs[i, :, 29], env[:, 10].astype(np.float32))
+            f30 = np.where(env[:, 10] > 0, 2 * env[:, 11] - mid2, 0)
+            assert np.array_equal(obs[i, :, 30], f30.astype(np.float32))
+            assert np.array_equal(obs[i, :, 38], st["agents"][:, i, 4].astype(np.float32))
+            assert np.array_equal(obs[i, :, 39], st["agents"][:, i, 5].astype(np.float32))
+            # the step's fills are the bought / sold words
+            assert np.array_equal(out["fills"][0, i, :, 0], st["agents"][:, i, 4])
+            assert np.array_equal(out["fills"][0, i, :, 2], st["agents"][:, i, 5])
+
+
+@pytest.mark.parametrize("split", [0, 5, 11])
+def test_import_continues_a_run(split):
+    """A run split at step `split`, its books and state exported and imported into a
+    fresh set of envs, continues exactly as the unsplit run (outputs, books, state, and
+    the observation right after the import)."""
+    w = _state_workload()
+    s = synth.generate(w, threads=2)
+    kinds = synth.agent_kinds(w.agents)
+    full = OracleEnvs(s.caps, w.max_cap, kinds, w.ep_len, w.seed, exec_task=60)
+    full.reset(s.book)
+    first = full.step(s, n_steps=split) if split else None
+    ref = full.step(s, n_steps=w.n_steps - split)
+
+    part = OracleEnvs(s.caps, w.max_cap, kinds, w.ep_len, w.seed, exec_task=60)
+    part.reset(s.book)
+    if split:
+        part.step(s, n_steps=split)
+    books, state = part.books(), part.state()
+    obs_before = part.observe()
+    fresh = OracleEnvs(s.caps, w.max_cap, kinds, w.ep_len, w.seed, exec_task=60)
+    fresh.import_state(books, state, split)
+    assert np.array_equal(fresh.observe().view(np.int32), obs_before.view(np.int32))
+    got = fresh.step(s, n_steps=w.n_steps - split)
+    for k in ("n_trades", "fills", "done", "actions", "trade_off"):
+        assert np.array_equal(got[k], ref[k]), k
+    for k in ("reward", "obs"):
+        assert np.array_equal(got[k].view(np.int32), ref[k].view(np.int32)), k
+    assert np.array_equal(got["trades"], ref["trades"])
+    for k, v in full.books().items():
+        assert np.array_equal(fresh.books()[k], v), k
+    for k, v in full.state().items():
+        assert np.array_equal(fresh.state()[k], v), k
+    if first is not None:
+        assert first["n_trades"].shape[0] == split
+
+
+def test_import_without_counters_and_step_checked():
+    w = _state_workload()
+    s = synth.generate(w, threads=2)
+    kinds = synth.agent_kinds(w.agents)
+    o = OracleEnvs(s.caps, w.max_cap, kinds, w.ep_len, w.seed, exec_task=60)
+    o.reset(s.book)
+    o.step(s, n_steps=3)
+    st = dict(o.state())
+    st["counters"] = None
+    fresh = OracleEnvs(s.caps, w.max_cap, kinds, w.ep_len, w.seed, exec_task=60)
+    fresh.import_state(o.books(), st, 3)
+    assert not fresh.state()["counters"].any()
+    with pytest.raises(RuntimeError):
+        fresh.import_state(o.books(), st, w.ep_len + 1)

@@ -108,3 +108,22 @@ def test_gae_special_cases():
     adv, _ = R.gae(r, v, d, last, 1.0, 1.0)
     assert np.allclose(adv[5], r[5] - v[5], atol=1e-12)
     assert np.allclose(adv[:6], np.cumsum(r[5::-1], axis=0)[::-1] - v[:6], atol=1e-12)
+
+
+def test_out_of_range_actions_count_as_action_zero():
+    """Reading shared with the env step: an action outside [0, n_actions) is action 0,
+    in the loss and in its gradient."""
+    rng = np.random.default_rng(11)
+    p = R.xavier_init(rng)
+    obs, act, lpo, adv, ret, vo = batch(rng, 24, 9, p)
+    act = act.copy()
+    act[:6] = 0
+    bad = act.copy()
+    bad[:3] = -1
+    bad[3:6] = 9
+    a = R.ppo_loss_parts(p, obs, act, lpo, adv, ret, vo, 9)
+    b = R.ppo_loss_parts(p, obs, bad, lpo, adv, ret, vo, 9)
+    assert np.allclose(a, b, rtol=0, atol=0)
+    la, ga = R.ppo_loss_and_grad(p, obs, act, lpo, adv, ret, vo, 9)
+    lb, gb = R.ppo_loss_and_grad(p, obs, bad, lpo, adv, ret, vo, 9)
+    assert la == lb and np.array_equal(ga, gb)
