@@ -74,6 +74,29 @@ enum {
 #define LOB_AGENT_DIR 2  /* directional trading; 3 actions */
 #define LOB_AGENT_MM_BUYSELL 3 /* market making as LOB_AGENT_MM, rewarded by the buy-sell
                                 * PnL (Eq. 4) minus the quadratic inventory penalty */
+/* The market maker's other action spaces of Sec. 4.1.1 (rewarded as LOB_AGENT_MM, Eq. 3
+ * with the quadratic penalty).  The paper gives no tables; readings: */
+#define LOB_AGENT_MM_SPREADSKEW 4 /* spread-skew table, 9 actions, always two-sided: spread
+                                   * S = 1, 3, 5 ticks around the mid times skew k = -1, 0, +1
+                                   * (action 3 * (index of S) + index of k): bid =
+                                   * floor((bb + ba - S) / 2) + k, ask = ceil((bb + ba + S) / 2)
+                                   * + k, never crossing the step-start touch */
+#define LOB_AGENT_MM_AVST 5       /* Avellaneda-Stoikov quotes with the risk aversion as the
+                                   * action, 9 actions: gamma = avst_gamma * 2^(a - 4);
+                                   * reservation price mid - q gamma sigma^2 (T - t), spread
+                                   * gamma sigma^2 (T - t) + (2 / gamma) ln(1 + gamma / kappa),
+                                   * q = inventory / mm_q, T - t the steps left including the
+                                   * current one; bid = floor(r - spread / 2), ask = ceil(r +
+                                   * spread / 2), one quote of mm_q per side, never crossing the
+                                   * step-start touch; evaluated in double */
+/* The baselines the learned agents are evaluated against (Sec. 5.2.2); their action is
+ * not used (one action): */
+#define LOB_AGENT_EXEC_TWAP 6     /* execution by TWAP: each step sells the shortfall to
+                                   * ceil(exec_task (t + 1) / episode_len) executed (at most the
+                                   * remainder) with one limit order at the step-start best bid;
+                                   * rewarded as LOB_AGENT_EXEC (Eq. 2 and the end penalty) */
+#define LOB_AGENT_MM_AS 7         /* the Avellaneda-Stoikov market maker: LOB_AGENT_MM_AVST
+                                   * always at gamma = avst_gamma (action 4) */
 
 typedef struct lob_ctx lob_ctx;
 
@@ -94,6 +117,10 @@ typedef struct {
     float mm_lambda;           /* Spooner weight of positive inventory PnL (Eq. 3) */
     float mm_rho;              /* quadratic inventory penalty factor */
     uint32_t flags;            /* reserved, must be 0 */
+    /* Avellaneda-Stoikov quotes (LOB_AGENT_MM_AVST, LOB_AGENT_MM_AS; ignored otherwise):
+     * base risk aversion gamma0 > 0, price variance per step sigma^2 >= 0 (ticks^2),
+     * order-arrival decay kappa > 0 (per tick); mm_q must then be > 0 (LOB_EINVAL) */
+    float avst_gamma, avst_sigma2, avst_kappa;
 } lob_config;
 
 /* A market-by-order stream in CSR form (device arrays).  Env e's messages of step t are

@@ -31,7 +31,7 @@ ENV_STATE_NAMES = ("last_bb", "last_ba", "mid2_prev", "p_init2", "last_tsec", "l
 AGENT_STATE_NAMES = ("inventory", "cash", "remaining", "order_counter", "step_bought", "step_sold")
 ENV_STATE_WORDS = len(ENV_STATE_NAMES)
 AGENT_STATE_WORDS = len(AGENT_STATE_NAMES)
-N_ACTIONS = {0: 9, 1: 9, 2: 3}
+N_ACTIONS = {0: 9, 1: 9, 2: 3, 3: 9, 4: 9, 5: 9, 6: 1, 7: 1}
 
 
 class _OrCfg(ctypes.Structure):
@@ -52,6 +52,10 @@ class _OrCfg(ctypes.Structure):
         ("mm_rho", ctypes.c_float),
         ("pad_", ctypes.c_float),
         ("env_id", ctypes.c_void_p),
+        ("avst_gamma", ctypes.c_float),
+        ("avst_sigma2", ctypes.c_float),
+        ("avst_kappa", ctypes.c_float),
+        ("pad2_", ctypes.c_float),
     ]
 
 
@@ -148,7 +152,8 @@ class OracleEnvs:
     def __init__(self, caps: np.ndarray, max_cap: int, agent_kinds: Sequence[int], episode_len: int,
                  seed: int, exec_task: int = 500, exec_q0: int = 4, mm_q: int = 10, dir_q: int = 10,
                  exec_penalty: float = 0.01, mm_lambda: float = 0.0, mm_rho: float = 0.0,
-                 env_ids: Optional[np.ndarray] = None):
+                 env_ids: Optional[np.ndarray] = None, avst_gamma: float = 0.01, avst_sigma2: float = 10.0,
+                 avst_kappa: float = 0.5):
         self._lib = _load()
         self.caps = np.ascontiguousarray(caps, dtype=np.int32)
         self.kinds = np.ascontiguousarray(np.asarray(agent_kinds, dtype=np.int32).reshape(-1))
@@ -163,6 +168,7 @@ class OracleEnvs:
         c.seed = seed
         c.exec_task, c.exec_q0, c.mm_q, c.dir_q = exec_task, exec_q0, mm_q, dir_q
         c.exec_penalty, c.mm_lambda, c.mm_rho = exec_penalty, mm_lambda, mm_rho
+        c.avst_gamma, c.avst_sigma2, c.avst_kappa = avst_gamma, avst_sigma2, avst_kappa
         self.env_ids = None
         if env_ids is not None:
             self.env_ids = np.ascontiguousarray(np.asarray(env_ids, dtype=np.int32).reshape(-1))

@@ -17,6 +17,7 @@
 #include "oracle.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -27,7 +28,11 @@ namespace {
 
 enum { LIMIT = 1, PARTIAL_CANCEL = 2, DELETE = 3, MARKET = 4, EXECUTE = 5, IGNORED = 6 };
 enum { BUY = 0, SELL = 1 };
-enum { AG_EXEC = 0, AG_MM = 1, AG_DIR = 2, AG_MM_BUYSELL = 3 };
+enum { AG_EXEC = 0, AG_MM = 1, AG_DIR = 2, AG_MM_BUYSELL = 3, AG_MM_SPREADSKEW = 4, AG_MM_AVST = 5,
+       AG_EXEC_TWAP = 6, AG_MM_AS = 7 };
+bool is_exec(int kind) { return kind == AG_EXEC || kind == AG_EXEC_TWAP; }
+/* market makers rewarded by Eq. 3 (Spooner) */
+bool is_spooner(int kind) { return kind == AG_MM || kind == AG_MM_SPREADSKEW || kind == AG_MM_AVST || kind == AG_MM_AS; }
 /* per-env counters */
 enum { C_MSGS, C_TRADES, C_MISS, C_EVICT, C_EVICTED_QTY, C_DROP, C_DROPPED_QTY,
        C_MARKET_UNFILLED, C_BAD, C_TRADE_OVERFLOW, C_IGNORED, N_COUNTERS };
@@ -293,7 +298,15 @@ struct Desire {
     int64_t qty;
 };
 
-int n_actions(int kind) { return kind == AG_DIR ? 3 : 9; }
+int n_actions(int kind) {
+    if (kind == AG_DIR) return 3;
+    if (kind == AG_EXEC_TWAP || kind == AG_MM_AS) return 1; /* baselines: the action is not used */
+    return 9;
+}
+
+/* floor(x / 2) and ceil(x / 2) for any sign */
+int64_t floor_half(int64_t x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
+int64_t ceil_half2(int64_t x) { return -floor_half(-x); }
 
 int64_t ceil_half(int64_t x) { return x >= 0 ? (x + 1) / 2 : -((-x) / 2); }
 
@@ -352,6 +365,71 @@ void decode_mm(int a, int32_t bb, int32_t ba, int32_t q, std::vector<Desire> &li
     }
 }
 
+/* Sec. 4.1.1, market maker, Spread-Skew action space: tabular (spread, skew) pairs in
+ * place of continuous spread and skew parameters.  Reading (the paper gives no table):
+ * always two-sided (the space has no "no quote" option), spread S in {1, 3, 5} ticks
+ * around the mid and skew k in {-1, 0, +1} ticks, action a = 3 * (index of S) + (index of
+ * k): bid = floor((bb + ba - S) / 2) + k, ask = ceil((bb + ba + S) / 2) + k, then as for
+ * the fixed-quantity space bids stay below the step-start best ask and asks above the
+ * best bid. */
+void decode_spread_skew(int a, int32_t bb, int32_t ba, int32_t q, std::vector<Desire> &lim) {
+    static const int S[3] = {1, 3, 5};
+    const int spread = S[a / 3], skew = a % 3 - 1;
+    const int64_t m2 = (int64_t)bb + ba;
+    const int64_t bid = floor_half(m2 - spread) + skew;
+    const int64_t ask = ceil_half2(m2 + spread) + skew;
+    lim.push_back({BUY, (int32_t)std::min<int64_t>(bid, (int64_t)ba - 1), q});
+    lim.push_back({SELL, (int32_t)std::max<int64_t>(ask, (int64_t)bb + 1), q});
+}
+
+/* Sec. 4.1.1, market maker, AvSt action space: the Avellaneda-Stoikov quotes (reservation
+ * price r = s - q gamma sigma^2 (T - t), spread gamma sigma^2 (T - t) + (2 / gamma)
+ * ln(1 + gamma / kappa)) with the risk aversion gamma as the agent's choice.  Reading:
+ * gamma_a = gamma0 * 2^(a - 4) for a = 0..8; s the step-start mid; q the inventory in quote
+ * lots (inventory / mm_q); T - t the steps left in the episode including this one;
+ * sigma^2 in ticks^2 per step and kappa per tick from the configuration; bid = floor(r -
+ * spread / 2), ask = ceil(r + spread / 2), one quote per side of mm_q, clamped as the
+ * fixed-quantity space.  Evaluated in double left to right; the ln term depends only on
+ * the configuration and the action and is tabled once. */
+struct AvstTable { double A[9], B[9]; };
+AvstTable avst_table(const or_config &c) {
+    AvstTable t{};
+    for (int a = 0; a < 9; ++a) {
+        const double g = (double)c.avst_gamma * std::ldexp(1.0, a - 4);
+        t.A[a] = g * (double)c.avst_sigma2;
+        t.B[a] = (2.0 / g) * std::log(1.0 + g / (double)c.avst_kappa);
+    }
+    return t;
+}
+int32_t clamp_price(double x) {
+    const double lim = 1073741824.0; /* 2^30 */
+    return (int32_t)(x < -lim ? -lim : (x > lim ? lim : x));
+}
+void decode_avst(int a, int32_t bb, int32_t ba, int64_t inv, int32_t steps_left, const or_config &c,
+                 const AvstTable &tab, std::vector<Desire> &lim) {
+    const double q = (double)inv / (double)c.mm_q;
+    const double tau = (double)steps_left;
+    const double mid = (double)((int64_t)bb + ba) * 0.5;
+    const double r = mid - q * tab.A[a] * tau;
+    const double d = tab.A[a] * tau + tab.B[a];
+    const int32_t bid = clamp_price(std::floor(r - d * 0.5));
+    const int32_t ask = clamp_price(std::ceil(r + d * 0.5));
+    lim.push_back({BUY, (int32_t)std::min<int64_t>(bid, (int64_t)ba - 1), c.mm_q});
+    lim.push_back({SELL, (int32_t)std::max<int64_t>(ask, (int64_t)bb + 1), c.mm_q});
+}
+
+/* Sec. 5.2.2, the TWAP baseline of the execution task.  Reading: the sell task follows a
+ * linear schedule, ceil(task * (t + 1) / T) shares executed by the end of step t; each
+ * step the agent sells the shortfall (at most its remainder) with one limit order at the
+ * step-start best bid (aggressive: it takes the bid, and whatever does not fill rests
+ * there). */
+void decode_twap(int32_t bb, int64_t rem, int64_t task, int32_t t, int32_t T, std::vector<Desire> &lim) {
+    const int64_t target = (task * (int64_t)(t + 1) + T - 1) / T;
+    const int64_t done = task - rem;
+    const int64_t q = std::min(std::max<int64_t>(target - done, 0), rem);
+    if (q > 0) lim.push_back({SELL, bb, q});
+}
+
 /* Sec. 4.1.3, directional trading: a bid or an ask at the best price, or nothing.
  * Reading: "best price" is the opposite touch (the order takes liquidity). */
 void decode_dir(int a, int32_t bb, int32_t ba, int32_t q, std::vector<Desire> &lim) {
@@ -363,6 +441,7 @@ struct Oracle {
     or_config cfg;
     std::vector<int32_t> caps, kinds, ids;
     std::vector<Env> envs;
+    AvstTable avst{};
     bool was_reset = false;
 };
 
@@ -399,7 +478,7 @@ void reset_env(Env &env, const Oracle &O, int e, const int32_t *const *f, const 
     std::fill(std::begin(env.counters), std::end(env.counters), 0);
     env.agents.assign((size_t)O.cfg.n_agents, Agent{});
     for (int i = 0; i < O.cfg.n_agents; ++i)
-        if (O.kinds[(size_t)i] == AG_EXEC) env.agents[(size_t)i].rem = O.cfg.exec_task;
+        if (is_exec(O.kinds[(size_t)i])) env.agents[(size_t)i].rem = O.cfg.exec_task;
     env.st_buy_vol = env.st_sell_vol = env.st_trades = 0;
     env.st_last_price = 0;
 }
@@ -437,7 +516,7 @@ void observe(const Oracle &O, const Env &env, int i, float *out) {
     f[30] = env.st_trades > 0 ? 2 * (int64_t)env.st_last_price - mid2 : 0;
     f[31] = ag.inv;
     f[32] = ag.cash;
-    f[33] = O.kinds[(size_t)i] == AG_EXEC ? ag.rem : 0;
+    f[33] = is_exec(O.kinds[(size_t)i]) ? ag.rem : 0;
     f[34] = (int64_t)O.cfg.episode_len - env.t;
     f[35] = own_bid;
     f[36] = own_ask;
@@ -495,6 +574,10 @@ void env_step(Oracle &O, int e, int s, const StepIO &io, TradeSink &sink) {
         std::vector<Desire> lim, mkt;
         if (kind == AG_EXEC) decode_exec(a, bb0, ba0, ag.rem, O.cfg.exec_q0, lim, mkt);
         else if (kind == AG_MM || kind == AG_MM_BUYSELL) decode_mm(a, bb0, ba0, O.cfg.mm_q, lim);
+        else if (kind == AG_MM_SPREADSKEW) decode_spread_skew(a, bb0, ba0, O.cfg.mm_q, lim);
+        else if (kind == AG_MM_AVST) decode_avst(a, bb0, ba0, ag.inv, O.cfg.episode_len - t, O.cfg, O.avst, lim);
+        else if (kind == AG_MM_AS) decode_avst(4, bb0, ba0, ag.inv, O.cfg.episode_len - t, O.cfg, O.avst, lim);
+        else if (kind == AG_EXEC_TWAP) decode_twap(bb0, ag.rem, O.cfg.exec_task, t, O.cfg.episode_len, lim);
         else decode_dir(a, bb0, ba0, O.cfg.dir_q, lim);
         /* desired quantity per (side, price), in order of first appearance */
         std::vector<Desire> levels;
@@ -633,7 +716,7 @@ void env_step(Oracle &O, int e, int s, const StepIO &io, TradeSink &sink) {
         const int kind = O.kinds[(size_t)i];
         ag.inv += bq[(size_t)i] - sq[(size_t)i];
         ag.cash += sn[(size_t)i] - bn[(size_t)i];
-        if (kind == AG_EXEC) ag.rem -= sq[(size_t)i];
+        if (is_exec(kind)) ag.rem -= sq[(size_t)i];
         ag.step_bq = bq[(size_t)i];
         ag.step_sq = sq[(size_t)i];
         /* Rewards: one double expression per agent kind, evaluated left to right, then
@@ -644,7 +727,7 @@ void env_step(Oracle &O, int e, int s, const StepIO &io, TradeSink &sink) {
         const double psi_b = mbar * (double)bq[(size_t)i] - (double)bn[(size_t)i];
         const double psi_s = (double)sn[(size_t)i] - mbar * (double)sq[(size_t)i];
         double r;
-        if (kind == AG_MM) {
+        if (is_spooner(kind)) {
             /* Eq. 3 (Spooner): spread PnL plus inventory PnL, positive inventory PnL
              * weighted by lambda, minus the quadratic inventory penalty rho * I^2. */
             const double psi_inv = (double)ag.inv * (mt - mprev);
@@ -741,6 +824,19 @@ void *oe_new(const or_config *cfg) {
     for (int32_t c : O->caps)
         if (c < 1 || c > cfg->max_cap) { delete O; return nullptr; }
     if (cfg->n_agents > 0) O->kinds.assign(cfg->agent_kind, cfg->agent_kind + cfg->n_agents);
+    bool avst = false;
+    for (int32_t k : O->kinds) {
+        if (k < AG_EXEC || k > AG_MM_AS) { delete O; return nullptr; }
+        avst = avst || k == AG_MM_AVST || k == AG_MM_AS;
+    }
+    /* the Avellaneda-Stoikov quotes need gamma > 0, kappa > 0, sigma^2 >= 0 and a quote size */
+    if (avst && !(cfg->avst_gamma > 0.f && cfg->avst_kappa > 0.f && cfg->avst_sigma2 >= 0.f &&
+                  std::isfinite(cfg->avst_gamma) && std::isfinite(cfg->avst_kappa) && std::isfinite(cfg->avst_sigma2) &&
+                  cfg->mm_q > 0)) {
+        delete O;
+        return nullptr;
+    }
+    if (avst) O->avst = avst_table(*cfg);
     for (int32_t e = 0; e < cfg->n_envs; ++e) O->ids.push_back(cfg->env_id ? cfg->env_id[e] : e);
     O->cfg.cap = nullptr;
     O->cfg.agent_kind = nullptr;

@@ -33,7 +33,10 @@ typedef struct {
     int32_t max_cap;          /* stride of the book arrays */
     int32_t episode_len;
     const int32_t *cap;       /* [n_envs] per-side capacity, 1..max_cap */
-    const int32_t *agent_kind;/* [n_agents] 0 execution, 1 market maker, 2 directional */
+    const int32_t *agent_kind;/* [n_agents] 0 execution, 1 market maker (fixed quantity), 2 directional,
+                                 3 market maker rewarded by Eq. 4, 4 market maker (spread-skew),
+                                 5 market maker (AvSt), 6 TWAP execution baseline, 7 Avellaneda-Stoikov
+                                 market-making baseline */
     uint64_t seed;
     int32_t exec_task;        /* shares the execution agent sells per episode */
     int32_t exec_q0;          /* execution order quantity */
@@ -44,6 +47,10 @@ typedef struct {
     float mm_rho;             /* quadratic inventory penalty factor */
     float pad_;
     const int32_t *env_id;    /* [n_envs] env index used in the hash keys, or NULL (= position) */
+    float avst_gamma;         /* Avellaneda-Stoikov quotes: base risk aversion (> 0) */
+    float avst_sigma2;        /* price variance per step, ticks^2 (>= 0) */
+    float avst_kappa;         /* order-arrival decay per tick (> 0) */
+    float pad2_;
 } or_config;
 
 /* ---- single book (unit tests) ---- */

@@ -47,6 +47,24 @@
 namespace lobk {
 
 constexpr int MAXA = LOB_MAX_AGENTS;
+
+/* agent kinds by role: execution tasks (a sell task with a remainder), market makers
+ * rewarded by Eq. 3 (Spooner) */
+__host__ __device__ constexpr bool exec_kind(int k) { return k == LOB_AGENT_EXEC || k == LOB_AGENT_EXEC_TWAP; }
+__host__ __device__ constexpr bool spooner_kind(int k) {
+    return k == LOB_AGENT_MM || k == LOB_AGENT_MM_SPREADSKEW || k == LOB_AGENT_MM_AVST || k == LOB_AGENT_MM_AS;
+}
+/* actions of each kind (the baselines take none: one action, not used) */
+__host__ __device__ constexpr int kind_actions(int k) {
+    return k == LOB_AGENT_DIR ? 3 : ((k == LOB_AGENT_EXEC_TWAP || k == LOB_AGENT_MM_AS) ? 1 : 9);
+}
+/* floor(x / 2) for any sign */
+__device__ __forceinline__ int64_t floor_div2(int64_t x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
+/* a price from a double quote, limited to +-2^30 */
+__device__ __forceinline__ int quote_price(double x) {
+    const double lim = 1073741824.0;
+    return (int)(x < -lim ? -lim : (x > lim ? lim : x));
+}
 constexpr int MAXLV = 8;          /* desired price levels per agent per step */
 constexpr int AGW = 8;            /* internal agent words: inv, cash, rem, ctr, step_bq, step_sq */
 constexpr int STW = 4;            /* step statistics: buy vol, sell vol, trades, last price */
@@ -108,6 +126,9 @@ struct KArgs {
     uint64_t seed;
     int32_t exec_task, exec_q0, mm_q, dir_q;
     float pen, lam, rho;
+    /* Avellaneda-Stoikov quotes per risk-aversion choice: gamma sigma^2 and
+     * (2 / gamma) ln(1 + gamma / kappa), tabled on the host */
+    double avA[9], avB[9];
     int32_t kinds; /* 4 bits per agent */
     const int32_t *caps;
     /* messages */
@@ -703,6 +724,36 @@ struct Run {
                     }
                 }
             }
+        } else if (kind == LOB_AGENT_MM_SPREADSKEW) {
+            /* spread-skew table: always two-sided, spread 1/3/5 ticks around the mid,
+             * skew -1/0/+1; never crossing the step-start touch */
+            const int spread = act < 3 ? 1 : (act < 6 ? 3 : 5);
+            const int skew = act - 3 * (act / 3) - 1;
+            const int64_t m2 = (int64_t)bb0 + ba0;
+            const int64_t bid = floor_div2(m2 - spread) + skew;
+            const int64_t ask = -floor_div2(-(m2 + spread)) + skew;
+            add_level(i, nlv, 0, (int)min(bid, (int64_t)ba0 - 1), a.mm_q);
+            add_level(i, nlv, 1, (int)max(ask, (int64_t)bb0 + 1), a.mm_q);
+        } else if (kind == LOB_AGENT_MM_AVST || kind == LOB_AGENT_MM_AS) {
+            /* Avellaneda-Stoikov: reservation price mid - q gamma sigma^2 (T - t) and spread
+             * gamma sigma^2 (T - t) + (2 / gamma) ln(1 + gamma / kappa), q the inventory in
+             * quote lots; the baseline takes gamma0 (choice 4) */
+            const int g = kind == LOB_AGENT_MM_AS ? 4 : act;
+            const double q = (double)uni64(AG(i)[0]) / (double)a.mm_q;
+            const double tau = (double)(a.episode_len - t);
+            const double mid = (double)((int64_t)bb0 + ba0) * 0.5;
+            const double r = mid - q * a.avA[g] * tau;
+            const double d = a.avA[g] * tau + a.avB[g];
+            const int bid = quote_price(floor(r - d * 0.5));
+            const int ask = quote_price(ceil(r + d * 0.5));
+            add_level(i, nlv, 0, (int)min((int64_t)bid, (int64_t)ba0 - 1), a.mm_q);
+            add_level(i, nlv, 1, (int)max((int64_t)ask, (int64_t)bb0 + 1), a.mm_q);
+        } else if (kind == LOB_AGENT_EXEC_TWAP) {
+            /* TWAP: the shortfall to ceil(task (t + 1) / T) executed, at the best bid */
+            const int64_t task = a.exec_task, rem = uni64(AG(i)[2]);
+            const int64_t target = (task * (int64_t)(t + 1) + a.episode_len - 1) / a.episode_len;
+            const int64_t q = min(max(target - (task - rem), (int64_t)0), rem);
+            if (q > 0) add_level(i, nlv, 1, bb0, (int)q);
         } else if (kind == LOB_AGENT_MM || kind == LOB_AGENT_MM_BUYSELL) {
             /* fixed-quantity quotes: bid = bb - ob (below the best ask), ask = ba + oa
              * (above the best bid); action 8 ladders offsets 0..3 on both sides */
@@ -822,7 +873,7 @@ struct Run {
             else if (f == 30) v = strades > 0 ? 2 * S[3] - mid2 : 0;
             else if (f == 31) v = g[0];
             else if (f == 32) v = g[1];
-            else if (f == 33) v = kind == LOB_AGENT_EXEC ? g[2] : 0;
+            else if (f == 33) v = exec_kind(kind) ? g[2] : 0;
             else if (f == 34) v = (int64_t)a.episode_len - E[6];
             else if (f == 38) v = g[4];
             else if (f == 39) v = g[5];
@@ -979,7 +1030,7 @@ struct Run {
         int nact = 0;
         for (int i = 0; i < A; ++i) {
             const int kind = (a.kinds >> (4 * i)) & 15;
-            const int nacts = kind == LOB_AGENT_DIR ? 3 : 9;
+            const int nacts = kind_actions(kind);
             int act;
             if (a.actions_in) {
                 act = uni(a.actions_in[((int64_t)s_idx * A + i) * N + e]);
@@ -1066,11 +1117,11 @@ struct Run {
             int64_t *g = AG(i);
             const int64_t inv = uni64(g[0]) + bq - sq;
             const int64_t cash = uni64(g[1]) + sn - bn;
-            const int64_t rem = uni64(g[2]) - (kind == LOB_AGENT_EXEC ? sq : 0);
+            const int64_t rem = uni64(g[2]) - (exec_kind(kind) ? sq : 0);
             const double psi_b = mbar * (double)bq - (double)bn;
             const double psi_s = (double)sn - mbar * (double)sq;
             double r;
-            if (kind == LOB_AGENT_MM) {
+            if (spooner_kind(kind)) {
                 /* Eq. 3 with the quadratic inventory penalty */
                 const double psi_inv = (double)inv * (mt - mprev);
                 const double pos = psi_inv > 0.0 ? psi_inv : 0.0;
@@ -1206,7 +1257,7 @@ __global__ void __launch_bounds__(256) k_reset(ResetArgs a) {
     if (lane < a.n_agents * AGW) {
         const int i = lane / AGW, w = lane % AGW;
         const int kind = (a.kinds >> (4 * i)) & 15;
-        a.agent_state[(int64_t)e * a.n_agents * AGW + lane] = (w == 2 && kind == LOB_AGENT_EXEC) ? (int64_t)a.exec_task : 0;
+        a.agent_state[(int64_t)e * a.n_agents * AGW + lane] = (w == 2 && exec_kind(kind)) ? (int64_t)a.exec_task : 0;
     }
 }
 
@@ -1335,6 +1386,7 @@ struct lob_ctx {
     lob_config cfg;
     std::vector<int32_t> caps, kinds;
     int32_t kinds_packed = 0;
+    double avA[9] = {}, avB[9] = {}; /* Avellaneda-Stoikov quote terms per risk-aversion choice */
     int32_t *d_caps = nullptr;
     int32_t *d_bk[NF] = {};
     int32_t *d_bk_n = nullptr;
@@ -1408,6 +1460,10 @@ KArgs base_args(const lob_ctx *c) {
     a.pen = c->cfg.exec_penalty;
     a.lam = c->cfg.mm_lambda;
     a.rho = c->cfg.mm_rho;
+    for (int g = 0; g < 9; ++g) {
+        a.avA[g] = c->avA[g];
+        a.avB[g] = c->avB[g];
+    }
     a.kinds = c->kinds_packed;
     a.caps = c->d_caps;
     for (int f = 0; f < NF; ++f) a.bk[f] = c->d_bk[f];
@@ -1696,9 +1752,26 @@ int lob_init(const lob_config *cfg, lob_ctx **out) {
         if (v < 1 || v > cfg->max_cap) { delete c; return LOB_EINVAL; }
     for (int i = 0; i < cfg->n_agents; ++i) {
         const int k = cfg->agent_kind[i];
-        if (k < 0 || k > LOB_AGENT_MM_BUYSELL) { delete c; return LOB_EINVAL; }
+        if (k < 0 || k > LOB_AGENT_MM_AS) { delete c; return LOB_EINVAL; }
         c->kinds.push_back(k);
         c->kinds_packed |= k << (4 * i);
+    }
+    bool avst = false;
+    for (int32_t k : c->kinds) avst = avst || k == LOB_AGENT_MM_AVST || k == LOB_AGENT_MM_AS;
+    if (avst) {
+        /* Avellaneda-Stoikov quotes: gamma0 > 0, kappa > 0, sigma^2 >= 0 (finite), quotes of
+         * mm_q > 0; the choice g takes gamma = gamma0 2^(g - 4) */
+        const float g0 = cfg->avst_gamma, s2 = cfg->avst_sigma2, kp = cfg->avst_kappa;
+        if (!(g0 > 0.f && kp > 0.f && s2 >= 0.f && std::isfinite(g0) && std::isfinite(kp) && std::isfinite(s2) &&
+              cfg->mm_q > 0)) {
+            delete c;
+            return LOB_EINVAL;
+        }
+        for (int g = 0; g < 9; ++g) {
+            const double gamma = (double)g0 * std::ldexp(1.0, g - 4);
+            c->avA[g] = gamma * (double)s2;
+            c->avB[g] = (2.0 / gamma) * std::log(1.0 + gamma / (double)kp);
+        }
     }
     c->cfg.cap = nullptr;
     c->cfg.agent_kind = nullptr;

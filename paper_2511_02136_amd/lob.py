@@ -23,7 +23,10 @@ N_COUNTERS = 11
 ENV_STATE_WORDS = 12
 AGENT_STATE_WORDS = 6
 BOOK_FIELDS = ("price", "qty", "oid", "tid", "tsec", "tns")
-AGENT_KINDS = {"exec": 0, "mm": 1, "dir": 2, "mm_buysell": 3}
+# actions of each agent kind (directional 3; the TWAP and Avellaneda-Stoikov baselines 1)
+N_ACTIONS = {0: 9, 1: 9, 2: 3, 3: 9, 4: 9, 5: 9, 6: 1, 7: 1}
+AGENT_KINDS = {"exec": 0, "mm": 1, "dir": 2, "mm_buysell": 3, "mm_spreadskew": 4, "mm_avst": 5, "exec_twap": 6,
+               "mm_as": 7}
 
 
 class LobError(RuntimeError):
@@ -37,6 +40,7 @@ class _Config(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("exec_task", ctypes.c_int32), ("exec_q0", ctypes.c_int32),
         ("mm_q", ctypes.c_int32), ("dir_q", ctypes.c_int32), ("exec_penalty", ctypes.c_float),
         ("mm_lambda", ctypes.c_float), ("mm_rho", ctypes.c_float), ("flags", ctypes.c_uint32),
+        ("avst_gamma", ctypes.c_float), ("avst_sigma2", ctypes.c_float), ("avst_kappa", ctypes.c_float),
     ]
 
 
@@ -147,7 +151,8 @@ class LobEnv:
 
     def __init__(self, caps, max_cap: int, agents: Sequence = (), episode_len: int = 128, seed: int = 0,
                  exec_task: int = 500, exec_q0: int = 4, mm_q: int = 10, dir_q: int = 10,
-                 exec_penalty: float = 0.01, mm_lambda: float = 0.0, mm_rho: float = 0.0, device="cuda"):
+                 exec_penalty: float = 0.01, mm_lambda: float = 0.0, mm_rho: float = 0.0,
+                 avst_gamma: float = 0.01, avst_sigma2: float = 10.0, avst_kappa: float = 0.5, device="cuda"):
         self.device = _require_gpu(device)
         self._lib = lib()
         self.caps_host = np.ascontiguousarray(np.asarray(caps, dtype=np.int32).reshape(-1))
@@ -165,6 +170,7 @@ class LobEnv:
         c.seed = seed
         c.exec_task, c.exec_q0, c.mm_q, c.dir_q = exec_task, exec_q0, mm_q, dir_q
         c.exec_penalty, c.mm_lambda, c.mm_rho = exec_penalty, mm_lambda, mm_rho
+        c.avst_gamma, c.avst_sigma2, c.avst_kappa = avst_gamma, avst_sigma2, avst_kappa
         c.flags = 0
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

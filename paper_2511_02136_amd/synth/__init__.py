@@ -25,7 +25,8 @@ SEED_BASE = 2511021360
 LIMIT, PARTIAL_CANCEL, DELETE, MARKET = 1, 2, 3, 4
 BUY, SELL = 0, 1
 
-AGENT_KINDS = {"exec": 0, "mm": 1, "dir": 2, "mm_buysell": 3}
+AGENT_KINDS = {"exec": 0, "mm": 1, "dir": 2, "mm_buysell": 3, "mm_spreadskew": 4, "mm_avst": 5, "exec_twap": 6,
+               "mm_as": 7}
 
 
 class _Cfg(ctypes.Structure):

@@ -15,7 +15,7 @@ from typing import Optional
 import torch
 
 from . import ippo
-from .lob import LobEnv, DeviceStream
+from .lob import LobEnv, DeviceStream, N_ACTIONS
 
 # Fixed input scaling of the 40 observation features (part of the policy, not the env):
 # roughly the typical magnitude of each feature on the synthetic workloads.
@@ -30,7 +30,7 @@ class IppoTrainer:
                  lam: float = 0.95, clip: float = 0.2, c_v: float = 0.5, c_e: float = 0.01, record_trades: bool = True):
         self.env, self.ds, self.book, self.T = env, dstream, book, n_steps
         self.A, self.N = env.n_agents, env.n_envs
-        self.n_act = [3 if int(k) == 2 else 9 for k in env.kinds]
+        self.n_act = [N_ACTIONS[int(k)] for k in env.kinds]
         self.seed = seed
         self.epochs, self.minibatches = epochs, minibatches
         self.gamma, self.lam, self.clip, self.c_v, self.c_e = gamma, lam, clip, c_v, c_e

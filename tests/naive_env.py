@@ -11,7 +11,17 @@ from naive_book import NaiveBook, LIMIT, PARTIAL_CANCEL, DELETE, MARKET, BUY, SE
 M64 = (1 << 64) - 1
 DOM_SHUFFLE = 0x5348554646
 DOM_ACTION = 0x414354
-EXEC, MM, DIR, MM_BUYSELL = 0, 1, 2, 3
+EXEC, MM, DIR, MM_BUYSELL, MM_SPREADSKEW, MM_AVST, EXEC_TWAP, MM_AS = 0, 1, 2, 3, 4, 5, 6, 7
+EXEC_KINDS = (EXEC, EXEC_TWAP)
+SPOONER_KINDS = (MM, MM_SPREADSKEW, MM_AVST, MM_AS)
+
+
+def n_actions(kind):
+    if kind == DIR:
+        return 3
+    if kind in (EXEC_TWAP, MM_AS):
+        return 1
+    return 9
 
 
 def sm64(z):
@@ -35,12 +45,13 @@ def f32(x):
 
 class NaiveEnv:
     def __init__(self, e, cap, kinds, episode_len, seed, exec_task=500, q0=4, mm_q=10, dir_q=10,
-                 pen=0.01, lam=0.0, rho=0.0):
+                 pen=0.01, lam=0.0, rho=0.0, avst_gamma=0.01, avst_sigma2=10.0, avst_kappa=0.5):
         import numpy as np
         self.e, self.cap, self.kinds, self.T, self.seed = e, cap, list(kinds), episode_len, seed
         self.exec_task, self.q0, self.mm_q, self.dir_q = exec_task, q0, mm_q, dir_q
         # float parameters are given in single precision, used in double
         self.pen, self.lam, self.rho = (float(np.float32(v)) for v in (pen, lam, rho))
+        self.gamma0, self.sigma2, self.kappa = (float(np.float32(v)) for v in (avst_gamma, avst_sigma2, avst_kappa))
 
     def reset(self, bids, asks):
         self.book = NaiveBook(self.cap)
@@ -58,7 +69,7 @@ class NaiveEnv:
         A = len(self.kinds)
         self.inv = [0] * A
         self.cash = [0] * A
-        self.rem = [self.exec_task if k == EXEC else 0 for k in self.kinds]
+        self.rem = [self.exec_task if k in EXEC_KINDS else 0 for k in self.kinds]
         self.ctr = [0] * A
         self.step_bq = [0] * A
         self.step_sq = [0] * A
@@ -82,6 +93,33 @@ class NaiveEnv:
                         mkt.append((SELL, q))
                     else:
                         lim.append((SELL, p, q))
+        elif k == MM_SPREADSKEW:
+            # a table of (spread, skew): spread 1, 3 or 5 ticks around the mid, skew -1, 0, +1
+            spread, skew = (1, 3, 5)[a // 3], a % 3 - 1
+            m2 = bb + ba
+            bid = (m2 - spread) // 2 + skew
+            ask = -((-(m2 + spread)) // 2) + skew
+            lim.append((BUY, min(bid, ba - 1), self.mm_q))
+            lim.append((SELL, max(ask, bb + 1), self.mm_q))
+        elif k in (MM_AVST, MM_AS):
+            import math
+            g = self.gamma0 * 2.0 ** ((a if k == MM_AVST else 4) - 4)
+            A_ = g * self.sigma2
+            B_ = (2.0 / g) * math.log(1.0 + g / self.kappa)
+            q = self.inv[i] / self.mm_q
+            tau = float(self.T - self.t)
+            r = float(bb + ba) * 0.5 - q * A_ * tau
+            d = A_ * tau + B_
+            lo, hi = -float(1 << 30), float(1 << 30)
+            bid = int(min(max(math.floor(r - d * 0.5), lo), hi))
+            ask = int(min(max(math.ceil(r + d * 0.5), lo), hi))
+            lim.append((BUY, min(bid, ba - 1), self.mm_q))
+            lim.append((SELL, max(ask, bb + 1), self.mm_q))
+        elif k == EXEC_TWAP:
+            target = (self.exec_task * (self.t + 1) + self.T - 1) // self.T
+            q = min(max(target - (self.exec_task - self.rem[i]), 0), self.rem[i])
+            if q > 0:
+                lim.append((SELL, bb, q))
         elif k in (MM, MM_BUYSELL):
             offs = {1: [(BUY, 2), (SELL, 2)], 2: [(BUY, 4), (SELL, 4)], 3: [(BUY, -1), (SELL, -1)],
                     4: [(BUY, 2)], 5: [(SELL, 2)], 6: [(BUY, 5), (SELL, -1)], 7: [(BUY, -1), (SELL, 5)],
@@ -105,7 +143,7 @@ class NaiveEnv:
         tsec, tns = self.time
         cancel_msgs, new_msgs, used = [], [], []
         for i in range(A):
-            n_act = 3 if self.kinds[i] == DIR else 9
+            n_act = n_actions(self.kinds[i])
             if actions is None:
                 u = hash_chain(self.seed, DOM_ACTION, self.e, self.t, i) >> 32
                 a = (u * n_act) >> 32
@@ -197,12 +235,12 @@ class NaiveEnv:
         for i in range(A):
             self.inv[i] += bq[i] - sq[i]
             self.cash[i] += sn[i] - bn[i]
-            if self.kinds[i] == EXEC:
+            if self.kinds[i] in EXEC_KINDS:
                 self.rem[i] -= sq[i]
             mbar = S / (2.0 * n) if n > 0 else self.mid2_prev * 0.5
             psi_b = mbar * bq[i] - bn[i]
             psi_s = sn[i] - mbar * sq[i]
-            if self.kinds[i] == MM:
+            if self.kinds[i] in SPOONER_KINDS:
                 psi_inv = self.inv[i] * (mid2 * 0.5 - self.mid2_prev * 0.5)
                 r = psi_b + psi_s + psi_inv - (1.0 - self.lam) * (psi_inv if psi_inv > 0.0 else 0.0) \
                     - self.rho * (float(self.inv[i]) * float(self.inv[i]))
@@ -248,7 +286,7 @@ class NaiveEnv:
         f[27], f[28], f[29] = bvol, svol, ntr
         f[30] = 2 * lastp - mid2 if ntr > 0 else 0
         f[31], f[32] = self.inv[i], self.cash[i]
-        f[33] = self.rem[i] if self.kinds[i] == EXEC else 0
+        f[33] = self.rem[i] if self.kinds[i] in EXEC_KINDS else 0
         f[34] = self.T - self.t
         f[38], f[39] = self.step_bq[i], self.step_sq[i]
         return [f32(v) for v in f]

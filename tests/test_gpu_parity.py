@@ -516,3 +516,16 @@ def test_replay1_full_size_parity():
     assert_same_books(env.books(), o.books(), what=w.name)
     assert_same_state(env.state(), o.state(), what=w.name)
     assert int(o.state()["counters"][0, 0]) == 1_000_000
+
+
+@pytest.mark.parametrize("mode", ["step", "rollout"])
+@pytest.mark.parametrize("given", [False, True])
+def test_parity_agent_variants(mode, given):
+    """The market maker's spread-skew and AvSt action spaces and the TWAP and
+    Avellaneda-Stoikov baselines (quotes that move with inventory and steps left), next to
+    each other, in both forms, with random and given (including out-of-range) actions."""
+    w = synth.Workload("variants", n_envs=56, n_steps=14, msgs_range=(1, 250), cap_choices=(20, 64, 100, 200),
+                       agents=("mm_spreadskew", "exec_twap", "mm_avst", "mm_as"), seed=43)
+    parity_case(w, w.n_steps, mode, given_actions=given,
+                kw=dict(exec_task=120, mm_lambda=0.5, mm_rho=0.01, avst_gamma=0.02, avst_sigma2=6.0, avst_kappa=0.6),
+                name=f"variants/{mode}/{'given' if given else 'random'}")

@@ -232,7 +232,10 @@ def compare(o, out, envs, outs, n_steps, A):
 
 
 @pytest.mark.parametrize("agents,policy", [(("exec", "mm"), "random"), (("exec", "mm", "dir"), "given"),
-                                           (("dir", "mm"), "random"), ((), "random")])
+                                           (("dir", "mm"), "random"), ((), "random"),
+                                           (("mm_spreadskew", "exec_twap"), "random"),
+                                           (("mm_avst", "exec", "mm_as"), "given"),
+                                           (("exec_twap", "mm_avst", "mm_spreadskew", "mm_as"), "random")])
 def test_oracle_matches_naive_env(agents, policy):
     w = synth.Workload("t", n_envs=5, n_steps=12, msgs_range=(1, 40), cap_choices=(3, 6, 12),
                        agents=agents, seed=99 + len(agents), mid0=1000, snapshot_fill_pct=50)
@@ -243,10 +246,12 @@ def test_oracle_matches_naive_env(agents, policy):
     if policy == "given":
         rng = np.random.default_rng(4)
         acts = np.stack([rng.integers(-1, 10 if k != 2 else 4, size=(12, w.n_envs)) for k in kinds], 1).astype(np.int32)
-    o = OracleEnvs(s.caps, w.max_cap, kinds, w.ep_len, w.seed, exec_task=60, exec_q0=4)
+    # AvSt quotes that move with the inventory and the steps left within a few ticks
+    av = dict(avst_gamma=0.02, avst_sigma2=4.0, avst_kappa=0.7)
+    o = OracleEnvs(s.caps, w.max_cap, kinds, w.ep_len, w.seed, exec_task=60, exec_q0=4, **av)
     o.reset(s.book)
     out = o.step(s, n_steps=12, actions=acts)
-    envs, outs = run_naive(s, w, 12, acts, exec_task=60, q0=4)
+    envs, outs = run_naive(s, w, 12, acts, exec_task=60, q0=4, **av)
     compare(o, out, envs, outs, 12, A)
 
 
@@ -449,3 +454,108 @@ def test_import_without_counters_and_step_checked():
     assert not fresh.state()["counters"].any()
     with pytest.raises(RuntimeError):
         fresh.import_state(o.books(), st, w.ep_len + 1)
+
+
+# ----------------------------------------------------------------------------------
+# market-maker action spaces (Sec. 4.1.1) and baseline policies (Sec. 5.2.2)
+# ----------------------------------------------------------------------------------
+def _quotes(o, tid=1):
+    """The agent's resting orders, [(side, price, qty)] in book order."""
+    bids, asks = book_lists(o.books(), 0)
+    return [(0, b[0], b[1]) for b in bids if b[3] == tid] + [(1, a[0], a[1]) for a in asks if a[3] == tid]
+
+
+@pytest.mark.parametrize("book,action,expect", [
+    # bb 100, ba 103 (mid2 203): spread 3 ticks, no skew -> floor(200/2)=100, ceil(206/2)=103
+    ((100, 103), 4, [(0, 100, 10), (1, 103, 10)]),
+    # spread 1, skew -1 -> 101 - 1, 102 - 1
+    ((100, 103), 0, [(0, 100, 10), (1, 101, 10)]),
+    # spread 5, skew +1 -> 99 + 1, 104 + 1
+    ((100, 103), 8, [(0, 100, 10), (1, 105, 10)]),
+    # spread 3, skew -1 -> 99, 102
+    ((100, 103), 3, [(0, 99, 10), (1, 102, 10)]),
+    # bb 100, ba 101: spread 1, skew +1 -> 101 clamped below the ask (100), 102
+    ((100, 101), 2, [(0, 100, 10), (1, 102, 10)]),
+    # spread 5, skew -1 -> 98 - 1, 103 - 1 (mid2 201: floor(196/2)=98, ceil(206/2)=103)
+    ((100, 101), 6, [(0, 97, 10), (1, 102, 10)]),
+])
+def test_spread_skew_quotes(book, action, expect):
+    bb, ba = book
+    snap = hand_book([([[bb, 5, 1, 0, 1, 0]], [[ba, 5, 2, 0, 1, 1]])], 10)
+    o = OracleEnvs(np.array([10]), 10, [4], episode_len=2, seed=1, mm_q=10)
+    o.reset(snap)
+    o.step(hand_stream([[[]]]), n_steps=1, actions=np.array([[[action]]], dtype=np.int32))
+    assert _quotes(o) == expect
+
+
+def test_avst_quotes_with_inventory():
+    """gamma0 0.5, sigma^2 2, kappa 0.5, quote size 10, 4-step episode; book 100 / 102.
+    Step 0 (4 steps left, flat): gamma 0.5 -> A = 1, B = 4 ln 2 = 2.7726; spread 6.7726
+    around 101 -> bid floor(97.614) = 97, ask ceil(104.386) = 105.  A replayed market
+    sell of 15 takes the book's 5 at 100 and the agent's 10 at 97: inventory +10 = 1 lot.
+    Step 1 (3 steps left): reservation 101 - 1 * 1 * 3 = 98, spread 5.7726 -> bid
+    floor(95.114) = 95, ask ceil(100.886) = 101 (inside the book's 102).  With action 5
+    (gamma 1: A = 2, B = 2 ln 3) at step 0 instead: spread 10.197 -> 95 / 107."""
+    snap = hand_book([([[100, 5, 1, 0, 1, 0]], [[102, 5, 2, 0, 1, 1]])], 10)
+    kw = dict(mm_q=10, avst_gamma=0.5, avst_sigma2=2.0, avst_kappa=0.5)
+    o = OracleEnvs(np.array([10]), 10, [5], episode_len=4, seed=1, **kw)
+    o.reset(snap)
+    out = o.step(hand_stream([[[msg(MARKET, SELL, 0, 15, 50, 0, 2, 0)], []]]), n_steps=1,
+                 actions=np.array([[[4]]], dtype=np.int32))
+    assert out["trades"][:2, :4].tolist() == [[100, 5, 50, 1], [97, 10, 50, E0]]
+    assert _quotes(o) == [(1, 105, 10)]
+    assert o.state()["agents"][0, 0, 0] == 10
+    o.step(hand_stream([[[msg(MARKET, SELL, 0, 15, 50, 0, 2, 0)], []]]), n_steps=1,
+           actions=np.array([[[4]]], dtype=np.int32))
+    assert _quotes(o) == [(0, 95, 10), (1, 101, 10)]
+    o2 = OracleEnvs(np.array([10]), 10, [5], episode_len=4, seed=1, **kw)
+    o2.reset(snap)
+    o2.step(hand_stream([[[]]]), n_steps=1, actions=np.array([[[5]]], dtype=np.int32))
+    assert _quotes(o2) == [(0, 95, 10), (1, 107, 10)]
+
+
+def test_avst_baseline_is_the_avst_space_at_gamma0():
+    """The Avellaneda-Stoikov baseline agent quotes exactly as the AvSt action space with
+    action 4 (gamma = gamma0), whatever action it is given."""
+    w = synth.Workload("avb", n_envs=6, n_steps=10, msgs_range=(1, 60), cap_choices=(8, 20),
+                       agents=("mm_as", "exec"), seed=150, mid0=1000)
+    s = synth.generate(w, threads=2)
+    rng = np.random.default_rng(3)
+    acts_b = rng.integers(-2, 5, size=(10, 2, 6)).astype(np.int32)
+    acts_v = acts_b.copy()
+    acts_v[:, 0] = 4
+    kw = dict(exec_task=60, avst_gamma=0.02, avst_sigma2=6.0, avst_kappa=0.8)
+    ob = OracleEnvs(s.caps, w.max_cap, [7, 0], w.ep_len, w.seed, **kw)
+    ov = OracleEnvs(s.caps, w.max_cap, [5, 0], w.ep_len, w.seed, **kw)
+    ob.reset(s.book)
+    ov.reset(s.book)
+    rb = ob.step(s, n_steps=10, actions=acts_b)
+    rv = ov.step(s, n_steps=10, actions=acts_v)
+    for k in ("trades", "n_trades", "fills", "reward", "obs"):
+        assert np.array_equal(rb[k], rv[k]), k
+    assert rb["n_trades"].sum() > 0
+
+
+def test_twap_baseline_schedule():
+    """Task 10 over 4 steps: executed targets ceil(10 (t+1) / 4) = 3, 5, 8, 10, so a deep
+    bid takes 3, 2, 3, 2 at 100; rewards by Eq. 2 against P_init 101.5; the action is not
+    used."""
+    snap = hand_book([([[100, 100, 1, 0, 1, 0]], [[103, 100, 2, 0, 1, 1]])], 10)
+    o = OracleEnvs(np.array([10]), 10, [6], episode_len=4, seed=1, exec_task=10)
+    o.reset(snap)
+    out = o.step(hand_stream([[[], [], [], []]]), n_steps=4, actions=np.array([7, 0, 3, -1]).reshape(4, 1, 1))
+    assert out["fills"][:, 0, 0, 2].tolist() == [3, 2, 3, 2]
+    assert out["trades"][:4, :2].tolist() == [[100, 3], [100, 2], [100, 3], [100, 2]]
+    assert out["reward"][:, 0, 0].tolist() == [f32(300 - 101.5 * 3), f32(200 - 101.5 * 2),
+                                              f32(300 - 101.5 * 3), f32(200 - 101.5 * 2)]
+    assert o.state()["agents"][0, 0, 2] == 0
+    # a thin bid: the shortfall rests at the bid and is re-quoted with the next target
+    snap = hand_book([([[100, 1, 1, 0, 1, 0]], [[103, 100, 2, 0, 1, 1]])], 10)
+    o = OracleEnvs(np.array([10]), 10, [6], episode_len=4, seed=1, exec_task=10)
+    o.reset(snap)
+    out = o.step(hand_stream([[[], [msg(LIMIT, BUY, 101, 4, 60, 0, 2, 0)]]]), n_steps=2,
+                 actions=np.zeros((2, 1, 1), dtype=np.int32))
+    # step 0: 1 at 100, 2 rest at 100 (now the best ask); step 1: bb is the stale 100
+    # (bid side empty: the last known best), target 5 - 1 executed -> 4 wanted at 100: 2
+    # resting + a new order of 2; the replayed buy at 101 takes 4 of them
+    assert out["fills"][:, 0, 0, 2].tolist() == [1, 4]
