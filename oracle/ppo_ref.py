@@ -85,36 +85,31 @@ def action_index(actions, n_actions):
     return np.where((a < 0) | (a >= n_actions), 0, a)
 
 
-def ppo_loss_parts(params, obs, actions, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01):
-    """Clipped PPO objective on one minibatch, float64: returns (total, policy, value, entropy).
-
-    ratio = exp(logp - logp_old); policy = -mean(min(ratio A, clip(ratio, 1-eps, 1+eps) A));
-    value = 0.5 mean(max((V - R)^2, (V_old + clip(V - V_old, -eps, eps) - R)^2));
+def loss_terms(logits, value, actions, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01):
+    """The clipped PPO objective from the network outputs of N samples (logits [N, >=
+    n_actions], value [N]), float64: (total, policy, value, entropy), each a mean over the
+    samples.  ratio = exp(logp - logp_old); policy = -mean(min(ratio A, clip(ratio, 1-eps,
+    1+eps) A)); value = 0.5 mean(max((V - R)^2, (V_old + clip(V - V_old, -eps, eps) - R)^2));
     entropy = mean(-sum_a p log p); total = policy + c_v value - c_e entropy."""
-    logits, value = mlp_forward(params, obs)
     lp = log_softmax(logits, n_actions)
     a = action_index(actions, n_actions)
     logp = lp[np.arange(len(a)), a]
     ratio = np.exp(logp - np.asarray(logp_old, dtype=np.float64))
     A = np.asarray(adv, dtype=np.float64)
     pol = -np.mean(np.minimum(ratio * A, np.clip(ratio, 1 - clip, 1 + clip) * A))
+    v = np.asarray(value, dtype=np.float64)
     R = np.asarray(ret, dtype=np.float64)
     vo = np.asarray(v_old, dtype=np.float64)
-    vc = vo + np.clip(value - vo, -clip, clip)
-    val = 0.5 * np.mean(np.maximum((value - R) ** 2, (vc - R) ** 2))
+    vc = vo + np.clip(v - vo, -clip, clip)
+    val = 0.5 * np.mean(np.maximum((v - R) ** 2, (vc - R) ** 2))
     ent = np.mean(-(np.exp(lp) * lp).sum(axis=1))
     return pol + c_v * val - c_e * ent, pol, val, ent
 
 
-def ppo_loss_and_grad(params, obs, actions, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01):
-    """The same loss in torch float64 with its gradient by autograd: (loss, grad[78858])."""
+def loss_terms_torch(out, actions, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01):
+    """``loss_terms`` in torch float64 from the outputs out [N, 10] (logits, then value),
+    differentiable in out: the total loss (a 0-d tensor)."""
     import torch
-    p = torch.tensor(np.asarray(params, dtype=np.float64), requires_grad=True)
-    P = {k: p[a:b].reshape(s) for k, (a, b, s) in SLICES.items()}
-    x = torch.tensor(np.asarray(obs, dtype=np.float64))
-    h1 = torch.tanh(x @ P["W1"] + P["b1"])
-    h2 = torch.tanh(h1 @ P["W2"] + P["b2"])
-    out = h2 @ P["W3"] + P["b3"]
     lp = torch.log_softmax(out[:, :n_actions], dim=1)
     a = torch.tensor(action_index(actions, n_actions))
     logp = lp[torch.arange(len(a)), a]
@@ -127,6 +122,25 @@ def ppo_loss_and_grad(params, obs, actions, logp_old, adv, ret, v_old, n_actions
     vc = vo + torch.clamp(v - vo, -clip, clip)
     val = 0.5 * torch.mean(torch.maximum((v - R) ** 2, (vc - R) ** 2))
     ent = torch.mean(-(torch.exp(lp) * lp).sum(dim=1))
-    loss = pol + c_v * val - c_e * ent
+    return pol + c_v * val - c_e * ent
+
+
+def ppo_loss_parts(params, obs, actions, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01):
+    """Clipped PPO objective of the MLP on one minibatch, float64: returns (total, policy,
+    value, entropy) (see loss_terms)."""
+    logits, value = mlp_forward(params, obs)
+    return loss_terms(logits, value, actions, logp_old, adv, ret, v_old, n_actions, clip, c_v, c_e)
+
+
+def ppo_loss_and_grad(params, obs, actions, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01):
+    """The same loss in torch float64 with its gradient by autograd: (loss, grad[78858])."""
+    import torch
+    p = torch.tensor(np.asarray(params, dtype=np.float64), requires_grad=True)
+    P = {k: p[a:b].reshape(s) for k, (a, b, s) in SLICES.items()}
+    x = torch.tensor(np.asarray(obs, dtype=np.float64))
+    h1 = torch.tanh(x @ P["W1"] + P["b1"])
+    h2 = torch.tanh(h1 @ P["W2"] + P["b2"])
+    out = h2 @ P["W3"] + P["b3"]
+    loss = loss_terms_torch(out, actions, logp_old, adv, ret, v_old, n_actions, clip, c_v, c_e)
     loss.backward()
     return float(loss.detach()), p.grad.numpy().copy()
