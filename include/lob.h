@@ -340,6 +340,23 @@ int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, c
                     float c_v, float c_e, float *workspace, int64_t workspace_bytes, float *loss, float *grad,
                     void *stream);
 
+/* lob_ppo_fwd_bwd without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight training loops, harnesses that forbid
+ * allocation).  The workspace is a fixed array in device memory that the library holds on
+ * every GPU it runs on until the process ends: PPO_SCRATCH = 256 workgroup partials of
+ * 78,864 floats, 4 chunk sums of the first reduction level and room for an aligned
+ * parameter copy, 82,334,008 bytes (about 82 MB); m is not limited by it, since the
+ * partials do not grow with m (LOB_EINVAL if a minibatch ever needed more).  Allocates
+ * nothing and calls no allocating routine; the array's device address is resolved once
+ * per GPU on the first call there.  Same arguments, results (bit for bit) and errors as
+ * lob_ppo_fwd_bwd otherwise.  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on one GPU (other streams, other threads) race and must be ordered by the
+ * caller; nothing in the array needs clearing between calls (each call writes every
+ * partial it reads). */
+int lob_ppo_fwd_bwd_noalloc(const float *params, const float *obs, const int32_t *act, const float *logp_old,
+                            const float *adv, const float *ret, const float *v_old, int32_t m, int32_t n_actions,
+                            float clip, float c_v, float c_e, float *loss, float *grad, void *stream);
+
 /* Steps taken since the last reset or import (host-side counter; library plumbing). */
 int lob_current_step(const lob_ctx *ctx);
 

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 
 #include "lob.h"
 #include "lob_device.h"
@@ -651,6 +652,72 @@ bool lds_opt_in() {
     }
     return true;
 }
+int64_t ppo_workspace_bytes(int32_t m) {
+    const int64_t nwg = std::min<int64_t>((m + TR - 1) / TR, PPO_WGS), nch = (nwg + RCH - 1) / RCH;
+    return (nwg + nch) * PW * 4 + PARAM_COPY_BYTES;
+}
+
+int ppo_launch(const float *params, const float *obs, const int32_t *act, const float *logp_old, const float *adv,
+               const float *ret, const float *v_old, int32_t m, int32_t n_actions, float clip, float c_v, float c_e,
+               float *workspace, int64_t workspace_bytes, float *loss, float *grad, void *stream) {
+    if (!params || !obs || !act || !logp_old || !adv || !ret || !v_old || !workspace || !loss || !grad)
+        return LOB_EINVAL;
+    if (m <= 0 || n_actions < 1 || n_actions > 9 || !(clip > 0.f)) return LOB_EINVAL;
+    const int nwg = std::min((m + TR - 1) / TR, PPO_WGS);
+    const int nch = (nwg + RCH - 1) / RCH;
+    const int64_t part_bytes = (int64_t)(nwg + nch) * PW * 4;
+    if (workspace_bytes < part_bytes + PARAM_COPY_BYTES || ((uintptr_t)workspace & 15)) return LOB_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    /* the kernel reads W2 in 16-byte loads: parameters that are not 16-byte aligned (a
+     * row of a [networks][LOB_PPO_PARAMS] array) are first copied into the workspace */
+    if ((uintptr_t)params & 15) {
+        float *copy = (float *)(((uintptr_t)workspace + part_bytes + 15) & ~(uintptr_t)15);
+        if (hipMemcpyAsync(copy, params, (size_t)NPARAM * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return LOB_EHIP;
+        params = copy;
+    }
+    PpoArgs a;
+    a.params = params; a.obs = obs; a.act = act; a.logp_old = logp_old; a.adv = adv; a.ret = ret; a.v_old = v_old;
+    a.m = m; a.n_act = n_actions; a.clip = clip; a.c_v = c_v; a.c_e = c_e; a.scale = 1.0f / (float)m;
+    a.partial = workspace;
+    if (!lds_opt_in()) return LOB_EHIP;
+    hipLaunchKernelGGL(k_ppo_fwd_bwd, dim3((unsigned)nwg), dim3(NTH), LDS_FLOATS * 4, st, a);
+    float *sums = workspace + (int64_t)nwg * PW;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((PW / 4 + 255) / 256), (unsigned)nch), dim3(256), 0, st,
+                       (const floatx4 *)a.partial, nwg, PW / 4, (floatx4 *)sums);
+    hipLaunchKernelGGL(k_reduce_final, dim3((unsigned)((PW + 255) / 256)), dim3(256), 0, st, (const float *)sums, nch,
+                       grad, loss);
+    return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
+}
+
+/* The fixed scratch of lob_ppo_fwd_bwd_noalloc: the workspace of the largest call (256
+ * workgroup partials, the first reduction level's chunk sums and room for an aligned
+ * parameter copy), one copy per GPU for the life of the process.  In host code `scratch`
+ * only names the symbol: its device address on the current GPU comes from
+ * hipGetSymbolAddress, taken once per device and kept. */
+constexpr int64_t PPO_SCRATCH_BYTES =
+    ((int64_t)PPO_WGS + (PPO_WGS + RCH - 1) / RCH) * PW * 4 + PARAM_COPY_BYTES;
+static __device__ __align__(256) float scratch[(PPO_SCRATCH_BYTES + 3) / 4];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+float *scratch_dev[MAX_DEVICES] = {};
+
+/* the current device's address of `scratch` (resolved on the first call on a device) */
+int scratch_ptr(float **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LOB_EHIP;
+    if (dev < 0 || dev >= MAX_DEVICES) return LOB_EUNSUPPORTED;
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LOB_EHIP;
+        scratch_dev[dev] = static_cast<float *>(p);
+    }
+    *out = scratch_dev[dev];
+    return LOB_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -690,42 +757,29 @@ int lob_gae(const float *reward, const float *value, const uint8_t *done, const 
 
 int64_t lob_ppo_workspace_bytes(int32_t m) {
     if (m <= 0) return LOB_EINVAL;
-    const int64_t nwg = std::min<int64_t>((m + TR - 1) / TR, PPO_WGS), nch = (nwg + RCH - 1) / RCH;
-    return (nwg + nch) * PW * 4 + PARAM_COPY_BYTES;
+    return ppo_workspace_bytes(m);
 }
 
 int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, const float *logp_old,
                     const float *adv, const float *ret, const float *v_old, int32_t m, int32_t n_actions, float clip,
                     float c_v, float c_e, float *workspace, int64_t workspace_bytes, float *loss, float *grad,
                     void *stream) {
-    if (!params || !obs || !act || !logp_old || !adv || !ret || !v_old || !workspace || !loss || !grad)
-        return LOB_EINVAL;
+    return ppo_launch(params, obs, act, logp_old, adv, ret, v_old, m, n_actions, clip, c_v, c_e, workspace,
+                      workspace_bytes, loss, grad, stream);
+}
+
+int lob_ppo_fwd_bwd_noalloc(const float *params, const float *obs, const int32_t *act, const float *logp_old,
+                            const float *adv, const float *ret, const float *v_old, int32_t m, int32_t n_actions,
+                            float clip, float c_v, float c_e, float *loss, float *grad, void *stream) {
+    /* argument checks before any device call */
+    if (!params || !obs || !act || !logp_old || !adv || !ret || !v_old || !loss || !grad) return LOB_EINVAL;
     if (m <= 0 || n_actions < 1 || n_actions > 9 || !(clip > 0.f)) return LOB_EINVAL;
-    const int nwg = std::min((m + TR - 1) / TR, PPO_WGS);
-    const int nch = (nwg + RCH - 1) / RCH;
-    const int64_t part_bytes = (int64_t)(nwg + nch) * PW * 4;
-    if (workspace_bytes < part_bytes + PARAM_COPY_BYTES || ((uintptr_t)workspace & 15)) return LOB_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
-    /* the kernel reads W2 in 16-byte loads: parameters that are not 16-byte aligned (a
-     * row of a [networks][LOB_PPO_PARAMS] array) are first copied into the workspace */
-    if ((uintptr_t)params & 15) {
-        float *copy = (float *)(((uintptr_t)workspace + part_bytes + 15) & ~(uintptr_t)15);
-        if (hipMemcpyAsync(copy, params, (size_t)NPARAM * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
-            return LOB_EHIP;
-        params = copy;
-    }
-    PpoArgs a;
-    a.params = params; a.obs = obs; a.act = act; a.logp_old = logp_old; a.adv = adv; a.ret = ret; a.v_old = v_old;
-    a.m = m; a.n_act = n_actions; a.clip = clip; a.c_v = c_v; a.c_e = c_e; a.scale = 1.0f / (float)m;
-    a.partial = workspace;
-    if (!lds_opt_in()) return LOB_EHIP;
-    hipLaunchKernelGGL(k_ppo_fwd_bwd, dim3((unsigned)nwg), dim3(NTH), LDS_FLOATS * 4, st, a);
-    float *sums = workspace + (int64_t)nwg * PW;
-    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((PW / 4 + 255) / 256), (unsigned)nch), dim3(256), 0, st,
-                       (const floatx4 *)a.partial, nwg, PW / 4, (floatx4 *)sums);
-    hipLaunchKernelGGL(k_reduce_final, dim3((unsigned)((PW + 255) / 256)), dim3(256), 0, st, (const float *)sums, nch,
-                       grad, loss);
-    return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
+    if (ppo_workspace_bytes(m) > PPO_SCRATCH_BYTES) return LOB_EINVAL; /* beyond the fixed scratch */
+    float *ws = nullptr;
+    const int rc = scratch_ptr(&ws);
+    if (rc != LOB_OK) return rc;
+    return ppo_launch(params, obs, act, logp_old, adv, ret, v_old, m, n_actions, clip, c_v, c_e, ws,
+                      PPO_SCRATCH_BYTES, loss, grad, stream);
 }
 
 } // extern "C"

@@ -35,6 +35,8 @@ def _lib():
         L.lob_ppo_workspace_bytes.restype = i64
         L.lob_ppo_fwd_bwd.argtypes = [p, p, p, p, p, p, p, i32, i32, f32, f32, f32, p, i64, p, p, p]
         L.lob_ppo_fwd_bwd.restype = ctypes.c_int
+        L.lob_ppo_fwd_bwd_noalloc.argtypes = [p, p, p, p, p, p, p, i32, i32, f32, f32, f32, p, p, p]
+        L.lob_ppo_fwd_bwd_noalloc.restype = ctypes.c_int
         _ready = True
     return L
 
@@ -114,6 +116,18 @@ def ppo_fwd_bwd(params, obs, act, logp_old, adv, ret, v_old, n_actions, clip=0.2
                              _p(_f32(logp_old)), _p(_f32(adv)), _p(_f32(ret)), _p(_f32(v_old)), m, int(n_actions),
                              clip, c_v, c_e, _p(workspace), workspace.numel() * 4, _p(loss), _p(grad), _stream()),
            "lob_ppo_fwd_bwd")
+    return loss, grad
+
+
+def ppo_fwd_bwd_noalloc(params, obs, act, logp_old, adv, ret, v_old, n_actions, loss, grad, clip=0.2, c_v=0.5,
+                        c_e=0.01):
+    """As ppo_fwd_bwd into caller-given loss [4] and grad [N_PARAMS] (float32, device),
+    with the library's fixed scratch instead of a workspace: the call allocates nothing."""
+    m = obs.shape[0]
+    _check(_lib().lob_ppo_fwd_bwd_noalloc(_p(_f32(params)), _p(_f32(obs)), _p(act), _p(_f32(logp_old)),
+                                          _p(_f32(adv)), _p(_f32(ret)), _p(_f32(v_old)), m, int(n_actions), clip, c_v,
+                                          c_e, _p(_f32(loss)), _p(_f32(grad)), _stream()),
+           "lob_ppo_fwd_bwd_noalloc")
     return loss, grad
 
 

@@ -102,3 +102,19 @@ def test_host_side_checks_of_the_state_import():
     p = ctypes.c_void_p
     lib.lob_import_state.argtypes = [p, p, p, p, p, ctypes.c_int32, p]
     assert lib.lob_import_state(None, None, None, None, None, 0, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblob.so not built")
+def test_host_side_checks_of_the_noalloc_ppo_call():
+    """lob_ppo_fwd_bwd_noalloc rejects NULL pointers and bad sizes before any device call
+    (its fixed scratch is resolved only after the checks)."""
+    lib = ctypes.CDLL(LIB)
+    p, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
+    lib.lob_ppo_fwd_bwd_noalloc.argtypes = [p, p, p, p, p, p, p, i32, i32, f32, f32, f32, p, p, p]
+    assert lib.lob_ppo_fwd_bwd_noalloc(None, None, None, None, None, None, None, 64, 9, 0.2, 0.5, 0.01,
+                                       None, None, None) == -1
+    fake = ctypes.c_void_p(16)  # never dereferenced: a size check fails first
+    args = [fake] * 7
+    assert lib.lob_ppo_fwd_bwd_noalloc(*args, 0, 9, 0.2, 0.5, 0.01, fake, fake, None) == -1
+    assert lib.lob_ppo_fwd_bwd_noalloc(*args, 64, 10, 0.2, 0.5, 0.01, fake, fake, None) == -1
+    assert lib.lob_ppo_fwd_bwd_noalloc(*args, 64, 9, 0.0, 0.5, 0.01, fake, fake, None) == -1
