@@ -357,6 +357,47 @@ int lob_ppo_fwd_bwd_noalloc(const float *params, const float *obs, const int32_t
                             const float *adv, const float *ret, const float *v_old, int32_t m, int32_t n_actions,
                             float clip, float c_v, float c_e, float *loss, float *grad, void *stream);
 
+/* ---- Recurrent actor-critic (Sec. 5.2.1: the agents' networks are GRU-based; one per
+ * agent type, Sec. 4.2).  The paper gives no sizes; reading: e_t = tanh(x_t W_e + b_e)
+ * (40 -> 128), a gated recurrent unit of 128 (gates r, u, n: r = sigmoid(e W_ir + b_ir +
+ * h W_hr + b_hr), u likewise, n = tanh(e W_in + b_in + r (h W_hn + b_hn)), h' = (1 - u) n
+ * + u h), out_t = h_t W_o + b_o (9 logits + value); the hidden state is zeroed at an
+ * episode's first step.  Flat fp32 parameters: W_e [40][128], b_e [128], W_i [128][384]
+ * (gate columns r | u | n), b_i [384], W_h [128][384], b_h [384], W_o [128][10], b_o [10]:
+ * LOB_GRU_PARAMS floats.  Products run on MFMA. */
+#define LOB_GRU_PARAMS 105610
+#define LOB_GRU_HIDDEN 128
+
+/* One rollout step of the recurrent policy for every agent: params [n_agents][params],
+ * obs [n_agents][n][40], h_in / h_out [n_agents][n][128] (device; h_out may be h_in),
+ * start [n] uint8 (device, 1 = the episode starts at this step: h_in is taken as zero) or
+ * NULL.  Samples as lob_policy_forward (same counter hash and epoch; logits may be NULL).
+ * Asynchronous on stream. */
+int lob_gru_step(const float *params, const float *obs, const float *h_in, float *h_out, const uint8_t *start,
+                 int32_t n_agents, int32_t n, const int32_t *n_actions, uint64_t seed, const uint64_t *epoch, int32_t t,
+                 float *logits, int32_t *actions, float *logp, float *value, void *stream);
+
+/* Bytes of device workspace lob_gru_ppo_fwd_bwd needs for m sequences of T steps
+ * (LOB_EINVAL for T or m <= 0): the hidden states, the per-sample gradients of the
+ * gates, embedding and outputs and the recomputed embedding (1,168 floats per sample),
+ * plus the weight-gradient partials. */
+int64_t lob_gru_ppo_workspace_bytes(int32_t T, int32_t m);
+
+/* The clipped-PPO loss (the same per-sample terms as lob_ppo_fwd_bwd, averaged over the T
+ * m samples) of one network over a minibatch of m whole sequences, and its gradient
+ * through time.  obs [T][m][40], start [T][m] uint8, h0 [m][128] (the state before step
+ * 0), act, logp_old, adv, ret, v_old [T][m] (device).  The forward pass keeps only the
+ * hidden states; the backward pass recomputes each step's embedding, gates and outputs.
+ * Writes loss [4] (sums over the samples of the total, policy, value and entropy terms)
+ * and grad [LOB_GRU_PARAMS] (gradient of the mean total loss).  workspace: device,
+ * 16-byte aligned, >= lob_gru_ppo_workspace_bytes(T, m) (LOB_EINVAL otherwise).
+ * Deterministic (fixed tiles and summation orders).  An action outside [0, n_actions)
+ * counts as action 0. */
+int lob_gru_ppo_fwd_bwd(const float *params, const float *obs, const uint8_t *start, const float *h0,
+                        const int32_t *act, const float *logp_old, const float *adv, const float *ret,
+                        const float *v_old, int32_t T, int32_t m, int32_t n_actions, float clip, float c_v, float c_e,
+                        float *workspace, int64_t workspace_bytes, float *loss, float *grad, void *stream);
+
 /* Steps taken since the last reset or import (host-side counter; library plumbing). */
 int lob_current_step(const lob_ctx *ctx);
 

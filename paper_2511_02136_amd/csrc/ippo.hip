@@ -282,6 +282,33 @@ __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const 
  * Tiles of 32 samples: the rollout's 4096 envs x 2 agents then give 256 workgroups, one
  * per CU (64-sample tiles left half of the CUs idle).
  * ---------------------------------------------------------------------------- */
+/* One sample's head: the first nact of the outputs z are the policy logits, z[9] the
+ * value.  Samples an action by Gumbel-max with noise from the counter hash of (seed,
+ * agent, action, t, row) and writes it, its log-probability and the value (and the ten
+ * outputs when logits is given). */
+__device__ __forceinline__ void sample_head(const float *z, int nact, uint64_t seed, int ag, int t, int e,
+                                            int32_t *action, float *logp, float *value, float *logits) {
+    float m = z[0];
+    for (int j = 1; j < nact; ++j) m = fmaxf(m, z[j]);
+    float s = 0.f;
+    for (int j = 0; j < nact; ++j) s += expf(z[j] - m);
+    const float lse = m + logf(s);
+    int best = 0;
+    float bv = -INFINITY;
+    for (int j = 0; j < nact; ++j) {
+        const uint64_t h = hash4(seed, DOM_POLICY, (uint64_t)ag << 8 | (uint64_t)j, (uint64_t)t, (uint64_t)e);
+        const float u = ((float)(uint32_t)(h >> 40) + 0.5f) * (1.0f / 16777216.0f);
+        const float g = -logf(-logf(u));
+        const float v = z[j] + g;
+        if (v > bv) { bv = v; best = j; }
+    }
+    *action = best;
+    *logp = z[best] - lse;
+    *value = z[9];
+    if (logits)
+        for (int j = 0; j < OUT; ++j) logits[j] = z[j];
+}
+
 struct FwdArgs {
     const float *params; /* [A][NPARAM] */
     const float *obs;    /* [A][n][40] */
@@ -305,30 +332,10 @@ __global__ void __launch_bounds__(NTH) k_policy_forward(FwdArgs a) {
     forward_tile<TRP>(P, a.obs + ((int64_t)ag * a.n + row0) * IN, rows, X, H1, H2, O);
     const int tid = (int)threadIdx.x;
     if (tid < rows) {
-        const int nact = a.n_act[ag];
-        const int e = row0 + tid;
         const uint64_t seed = a.epoch ? a.seed + 0x9E3779B97F4A7C15ULL * a.epoch[0] : a.seed;
-        const float *z = O + tid * OS;
-        float m = z[0];
-        for (int j = 1; j < nact; ++j) m = fmaxf(m, z[j]);
-        float s = 0.f;
-        for (int j = 0; j < nact; ++j) s += expf(z[j] - m);
-        const float lse = m + logf(s);
-        int best = 0;
-        float bv = -INFINITY;
-        for (int j = 0; j < nact; ++j) {
-            const uint64_t h = hash4(seed, DOM_POLICY, (uint64_t)ag << 8 | (uint64_t)j, (uint64_t)a.t, (uint64_t)e);
-            const float u = ((float)(uint32_t)(h >> 40) + 0.5f) * (1.0f / 16777216.0f);
-            const float g = -logf(-logf(u));
-            const float v = z[j] + g;
-            if (v > bv) { bv = v; best = j; }
-        }
-        const int64_t o = (int64_t)ag * a.n + e;
-        a.actions[o] = best;
-        a.logp[o] = z[best] - lse;
-        a.value[o] = z[9];
-        if (a.logits)
-            for (int j = 0; j < OUT; ++j) a.logits[o * OUT + j] = z[j];
+        const int64_t o = (int64_t)ag * a.n + row0 + tid;
+        sample_head(O + tid * OS, a.n_act[ag], seed, ag, a.t, row0 + tid, a.actions + o, a.logp + o, a.value + o,
+                    a.logits ? a.logits + o * OUT : nullptr);
     }
 }
 
@@ -370,6 +377,51 @@ struct PpoArgs {
     float *partial;              /* [grid][PW]: gradient, then loss sums (total, policy, value, entropy) */
 };
 
+/* One sample's clipped-PPO loss terms from its ten outputs z (logits, then the value) and
+ * their gradient w.r.t. z, scaled by `scale` (1 / minibatch samples): policy -min(r A,
+ * clip(r, 1-clip, 1+clip) A) with r = exp(logp - logp_old), value 0.5 max((V-R)^2,
+ * (V_old + clip(V - V_old) - R)^2), entropy H; lsum = {total, policy, value, entropy}.
+ * An action outside [0, nact) counts as action 0, as the env step takes it. */
+__device__ __forceinline__ void loss_head(const float *z, int nact, int act, float logp_old, float A, float R,
+                                          float vo, float clip, float c_v, float c_e, float scale, float *dz,
+                                          float *lsum) {
+    float mx = z[0];
+    for (int j = 1; j < nact; ++j) mx = fmaxf(mx, z[j]);
+    float se = 0.f;
+    for (int j = 0; j < nact; ++j) se += expf(z[j] - mx);
+    const float lse = mx + logf(se);
+    float H = 0.f;
+    for (int j = 0; j < nact; ++j) {
+        const float lp = z[j] - lse;
+        H -= expf(lp) * lp;
+    }
+    if ((unsigned)act >= (unsigned)nact) act = 0;
+    const float logp = z[act] - lse;
+    const float ratio = expf(logp - logp_old);
+    const float s1 = ratio * A;
+    const float rc = fminf(fmaxf(ratio, 1.f - clip), 1.f + clip);
+    const float s2 = rc * A;
+    const float pol = -fminf(s1, s2);
+    const float dlogp = s1 <= s2 ? -A * ratio : 0.f;
+    const float v = z[9];
+    const float dvv = v - vo;
+    const float vc = vo + fminf(fmaxf(dvv, -clip), clip);
+    const float l1 = (v - R) * (v - R), l2 = (vc - R) * (vc - R);
+    const float val = 0.5f * fmaxf(l1, l2);
+    const float dval = l1 >= l2 ? (v - R) : (fabsf(dvv) < clip ? (vc - R) : 0.f);
+    for (int j = 0; j < nact; ++j) {
+        const float lp = z[j] - lse;
+        const float p = expf(lp);
+        const float dlp = (j == act ? 1.f : 0.f) - p;
+        dz[j] = scale * (dlogp * dlp + c_e * p * (lp + H));
+    }
+    dz[9] = scale * c_v * dval;
+    lsum[0] = pol + c_v * val - c_e * H;
+    lsum[1] = pol;
+    lsum[2] = val;
+    lsum[3] = H;
+}
+
 /* One tile of the fused kernel.  first: write the partial G, else add to it (each element
  * is read and rewritten by the lane that wrote it).  A function of its own, not inlined:
  * inside the kernel's tile loop the compiler keeps the per-lane LDS addresses of every
@@ -397,45 +449,8 @@ __device__ __noinline__ void ppo_tile(const PpoArgs &a, const GLOBAL float *Pg, 
             for (int j = 0; j < OUT; ++j) dz[j] = 0.f;
             if (tid < rows) {
                 const int s = row0 + tid;
-                const int nact = a.n_act;
-                float mx = z[0];
-                for (int j = 1; j < nact; ++j) mx = fmaxf(mx, z[j]);
-                float se = 0.f;
-                for (int j = 0; j < nact; ++j) se += expf(z[j] - mx);
-                const float lse = mx + logf(se);
-                float H = 0.f;
-                for (int j = 0; j < nact; ++j) {
-                    const float lp = z[j] - lse;
-                    H -= expf(lp) * lp;
-                }
-                /* an action outside [0, nact) counts as action 0, as the env step takes it */
-                int act = a.act[s];
-                if ((unsigned)act >= (unsigned)nact) act = 0;
-                const float logp = z[act] - lse;
-                const float ratio = expf(logp - a.logp_old[s]);
-                const float A = a.adv[s];
-                const float s1 = ratio * A;
-                const float rc = fminf(fmaxf(ratio, 1.f - a.clip), 1.f + a.clip);
-                const float s2 = rc * A;
-                const float pol = -fminf(s1, s2);
-                const float dlogp = s1 <= s2 ? -A * ratio : 0.f;
-                const float v = z[9], R = a.ret[s], vo = a.v_old[s];
-                const float dvv = v - vo;
-                const float vc = vo + fminf(fmaxf(dvv, -a.clip), a.clip);
-                const float l1 = (v - R) * (v - R), l2 = (vc - R) * (vc - R);
-                const float val = 0.5f * fmaxf(l1, l2);
-                const float dval = l1 >= l2 ? (v - R) : (fabsf(dvv) < a.clip ? (vc - R) : 0.f);
-                for (int j = 0; j < nact; ++j) {
-                    const float lp = z[j] - lse;
-                    const float p = expf(lp);
-                    const float dlp = (j == act ? 1.f : 0.f) - p;
-                    dz[j] = a.scale * (dlogp * dlp + a.c_e * p * (lp + H));
-                }
-                dz[9] = a.scale * a.c_v * dval;
-                lsum[0] = pol + a.c_v * val - a.c_e * H;
-                lsum[1] = pol;
-                lsum[2] = val;
-                lsum[3] = H;
+                loss_head(z, a.n_act, a.act[s], a.logp_old[s], a.adv[s], a.ret[s], a.v_old[s], a.clip, a.c_v, a.c_e,
+                          a.scale, dz, lsum);
             }
             /* the output tile now holds dOut (cols 10..15 stay zero) */
             for (int j = 0; j < OUT; ++j) z[j] = dz[j];
@@ -631,6 +646,457 @@ __global__ void k_reduce_final(const float *__restrict__ sums, int nch, float *g
     else loss[j - NPARAM] = s;
 }
 
+/* ==============================================================================
+ * Recurrent (GRU) actor-critic.  The paper trains its agents with a GRU-based network
+ * (Sec. 5.2.1), one per agent type (Sec. 4.2); the sizes are a reading:
+ *   e_t = tanh(x_t W_e + b_e)                                   40 -> 128
+ *   r_t = sigmoid(e_t W_ir + b_ir + h_{t-1} W_hr + b_hr)
+ *   u_t = sigmoid(e_t W_iz + b_iz + h_{t-1} W_hz + b_hz)
+ *   n_t = tanh(e_t W_in + b_in + r_t * (h_{t-1} W_hn + b_hn))
+ *   h_t = (1 - u_t) n_t + u_t h_{t-1}                           hidden state 128
+ *   out_t = h_t W_o + b_o                                       9 logits + value
+ * with h_{t-1} = 0 at an episode's first step.  Flat parameters: W_e [40][128], b_e,
+ * W_i [128][384] (gate columns r | u | n), b_i, W_h [128][384], b_h, W_o [128][10], b_o.
+ * Tiles of 16 rows (envs) run every product on v_mfma_f32_16x16x4f32.
+ * ============================================================================ */
+constexpr int GHD = 128, G3 = 3 * GHD, GIN = 40, GINP = 48;
+constexpr int GO_WE = 0, GO_BE = GO_WE + GIN * GHD, GO_WI = GO_BE + GHD, GO_BI = GO_WI + GHD * G3,
+              GO_WH = GO_BI + G3, GO_BH = GO_WH + GHD * G3, GO_WO = GO_BH + G3, GO_BO = GO_WO + GHD * OUT,
+              GNP = GO_BO + OUT;
+static_assert(GNP == LOB_GRU_PARAMS, "GRU parameter count");
+constexpr int GPW = GNP + 2;  /* per-workgroup gradient partial, a multiple of 4 floats */
+constexpr int TG = 16;        /* rows (envs) per tile */
+constexpr int HSG = GHD + 4;  /* LDS row strides */
+constexpr int GS = G3 + 4;
+constexpr int GRU_STEP_TH = 256, GRU_SEQ_TH = 512, GRU_DW_TH = 1024;
+constexpr int GRU_DW_WGS = 256; /* workgroups of the weight-gradient kernel */
+
+__device__ __forceinline__ float sigmoid_exp(float x) {
+    /* 1 / (1 + e^-x) on the hardware 2^x and reciprocal instructions */
+    return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(-x * 1.4426950408889634f));
+}
+
+/* e = tanh(X W_e + b_e) for a tile (X [16][XS], cols 40..47 zero) into E [16][HSG] */
+__device__ __forceinline__ void gru_embed(const float *__restrict__ P, const float *X, float *E, int wave, int nw) {
+    for (int ct = wave; ct < GHD / 16; ct += nw) {
+        floatx4 acc[1][1] = {{zero4()}};
+        gemm<1, 1>(acc, GINP, 0, 16 * ct, [&](int i, int k) { return X[i * XS + k]; },
+                   [&](int k, int j) { return k < GIN ? P[GO_WE + k * GHD + j] : 0.f; });
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = acc_row(i), c = 16 * ct + acc_col();
+            E[r * HSG + c] = tanh_exp(acc[0][0][i] + P[GO_BE + c]);
+        }
+    }
+}
+
+/* GI = E W_i + b_i and GH = HP W_h + b_h for a tile: 48 column tiles of 16 over the waves,
+ * three at a time (independent accumulators) */
+__device__ __forceinline__ void gru_gates(const float *__restrict__ P, const float *E, const float *HP, float *GI,
+                                          float *GH, int wave, int nw) {
+    const int per = 2 * (G3 / 16) / nw; /* column tiles per wave, a multiple of 3 */
+    for (int c3 = 0; c3 < per; c3 += 3) {
+        const int ct0 = wave * per + c3; /* a wave's tiles never straddle GI and GH */
+        const bool hh = ct0 >= G3 / 16;
+        const int c0 = 16 * (hh ? ct0 - G3 / 16 : ct0);
+        const float *A = hh ? HP : E;
+        const float *W = P + (hh ? GO_WH : GO_WI);
+        floatx4 acc[1][3] = {{zero4(), zero4(), zero4()}};
+        gemm<1, 3>(acc, GHD, 0, c0, [&](int i, int k) { return A[i * HSG + k]; },
+                   [&](int k, int j) { return W[k * G3 + j]; });
+        float *D = hh ? GH : GI;
+        const float *bias = P + (hh ? GO_BH : GO_BI);
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = acc_row(i), c = c0 + 16 * n + acc_col();
+                D[r * GS + c] = acc[0][n][i] + bias[c];
+            }
+    }
+}
+
+/* the gates and the new state: HN = (1 - u) n + u HP; with keep, GI's three column
+ * blocks are overwritten by r, u and n */
+__device__ __forceinline__ void gru_update(float *GI, const float *GH, const float *HP, float *HN, int tid, int nth,
+                                           bool keep) {
+    for (int i = tid; i < TG * GHD; i += nth) {
+        const int r = i / GHD, j = i % GHD;
+        const float *gi = GI + r * GS, *gh = GH + r * GS;
+        const float rr = sigmoid_exp(gi[j] + gh[j]);
+        const float u = sigmoid_exp(gi[GHD + j] + gh[GHD + j]);
+        const float nn = tanh_exp(gi[2 * GHD + j] + rr * gh[2 * GHD + j]);
+        HN[r * HSG + j] = (1.f - u) * nn + u * HP[r * HSG + j];
+        if (keep) {
+            GI[r * GS + j] = rr;
+            GI[r * GS + GHD + j] = u;
+            GI[r * GS + 2 * GHD + j] = nn;
+        }
+    }
+}
+
+/* O = HN W_o + b_o (cols 10..15 zero): one wave */
+__device__ __forceinline__ void gru_head(const float *__restrict__ P, const float *HN, float *O) {
+    floatx4 acc[1][1] = {{zero4()}};
+    gemm<1, 1>(acc, GHD, 0, 0, [&](int i, int k) { return HN[i * HSG + k]; },
+               [&](int k, int j) { return j < OUT ? P[GO_WO + k * OUT + j] : 0.f; });
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = acc_row(i), c = acc_col();
+        O[r * OS + c] = c < OUT ? acc[0][0][i] + P[GO_BO + c] : 0.f;
+    }
+}
+
+/* ---- one step of the rollout: grid (ceil(n / 16), n_agents), GRU_STEP_TH threads ---- */
+struct GruStepArgs {
+    const float *params;  /* [A][GNP] */
+    const float *obs;     /* [A][n][40] */
+    const float *h_in;    /* [A][n][128] */
+    float *h_out;         /* [A][n][128], may be h_in */
+    const uint8_t *start; /* [n] or null: 1 = the episode starts at this step (h_{t-1} = 0) */
+    int32_t n;
+    int32_t n_act[LOB_MAX_AGENTS];
+    uint64_t seed;
+    const uint64_t *epoch;
+    int32_t t;
+    float *logits;
+    int32_t *actions;
+    float *logp, *value;
+};
+constexpr int GRU_STEP_LDS = TG * (XS + 3 * HSG + 2 * GS + OS);
+
+__global__ void __launch_bounds__(GRU_STEP_TH) k_gru_step(GruStepArgs a) {
+    extern __shared__ float sm[];
+    float *X = sm, *E = X + TG * XS, *HP = E + TG * HSG, *HN = HP + TG * HSG, *GI = HN + TG * HSG,
+          *GH = GI + TG * GS, *O = GH + TG * GS;
+    const int ag = (int)blockIdx.y, row0 = (int)blockIdx.x * TG, rows = min(TG, a.n - row0);
+    const int tid = (int)threadIdx.x, wave = tid >> 6, nw = GRU_STEP_TH / 64;
+    const float *P = a.params + (int64_t)ag * GNP;
+    const int64_t base = (int64_t)ag * a.n + row0;
+    for (int i = tid; i < TG * XS; i += GRU_STEP_TH) {
+        const int r = i / XS, c = i % XS;
+        X[i] = (r < rows && c < GIN) ? a.obs[(base + r) * GIN + c] : 0.f;
+    }
+    for (int i = tid; i < TG * GHD; i += GRU_STEP_TH) {
+        const int r = i / GHD, c = i % GHD;
+        const bool zero = r >= rows || (a.start && a.start[row0 + r]);
+        HP[r * HSG + c] = zero ? 0.f : a.h_in[(base + r) * GHD + c];
+    }
+    __syncthreads();
+    gru_embed(P, X, E, wave, nw);
+    __syncthreads();
+    gru_gates(P, E, HP, GI, GH, wave, nw);
+    __syncthreads();
+    gru_update(GI, GH, HP, HN, tid, GRU_STEP_TH, false);
+    __syncthreads();
+    for (int i = tid; i < TG * GHD; i += GRU_STEP_TH) {
+        const int r = i / GHD, c = i % GHD;
+        if (r < rows) a.h_out[(base + r) * GHD + c] = HN[r * HSG + c];
+    }
+    if (wave == 0) gru_head(P, HN, O);
+    __syncthreads();
+    if (tid < rows) {
+        const uint64_t seed = a.epoch ? a.seed + 0x9E3779B97F4A7C15ULL * a.epoch[0] : a.seed;
+        const int64_t o = base + tid;
+        sample_head(O + tid * OS, a.n_act[ag], seed, ag, a.t, row0 + tid, a.actions + o, a.logp + o, a.value + o,
+                    a.logits ? a.logits + o * OUT : nullptr);
+    }
+}
+
+/* ---- clipped-PPO loss over whole sequences, forward and backward through time ----
+ * k_gru_seq: one workgroup per tile of 16 sequences.  Forward: the recurrence over the T
+ * steps, keeping only the hidden states (HS [T+1][m][128], HS[0] = h0).  Backward, t =
+ * T-1 .. 0: the embedding, gates and outputs of step t are recomputed from x_t and
+ * h_{t-1}, the per-sample loss gradient dO is formed, and dh (carried from step t+1) is
+ * taken back through the cell; the gradients w.r.t. the gate pre-activations (DGI, DGH),
+ * the embedding pre-activation (DE), the outputs (DO) and the recomputed embedding (E) go
+ * to the workspace for the weight-gradient products, which k_gru_dw forms over all T m
+ * samples at once. */
+struct GruSeqArgs {
+    const float *params, *obs;  /* obs [T][m][40] */
+    const uint8_t *start;       /* [T][m] */
+    const float *h0;            /* [m][128] */
+    const int32_t *act;
+    const float *logp_old, *adv, *ret, *v_old; /* [T][m] */
+    int32_t T, m, n_act;
+    float clip, c_v, c_e, scale; /* scale = 1 / (T m) */
+    float *HS, *E, *DGI, *DGH, *DE, *DO, *LS; /* workspace */
+    const float *WiT, *WhT;     /* W_i and W_h transposed, [384][128] */
+};
+constexpr int GRU_SEQ_LDS = TG * (XS + 4 * HSG + 4 * GS + OS);
+
+__global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_seq(GruSeqArgs a) {
+    extern __shared__ float sm[];
+    float *X = sm, *E = X + TG * XS, *HP = E + TG * HSG, *HN = HP + TG * HSG, *DH = HN + TG * HSG, *GI = DH + TG * HSG,
+          *GH = GI + TG * GS, *DGI = GH + TG * GS, *DGH = DGI + TG * GS, *O = DGH + TG * GS;
+    const int row0 = (int)blockIdx.x * TG, rows = min(TG, a.m - row0);
+    const int tid = (int)threadIdx.x, wave = tid >> 6, nw = GRU_SEQ_TH / 64;
+    const float *__restrict__ P = a.params;
+    const int T = a.T, m = a.m;
+    auto stage_x = [&](int t) {
+        for (int i = tid; i < TG * XS; i += GRU_SEQ_TH) {
+            const int r = i / XS, c = i % XS;
+            X[i] = (r < rows && c < GIN) ? a.obs[((int64_t)t * m + row0 + r) * GIN + c] : 0.f;
+        }
+    };
+    /* forward: h0, then the recurrence; HS[t] is h_{t-1} as stored (before an episode
+     * start zeroes it) */
+    for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
+        const int r = i / GHD, c = i % GHD;
+        const float v = r < rows ? a.h0[(int64_t)(row0 + r) * GHD + c] : 0.f;
+        HN[r * HSG + c] = v;
+        if (r < rows) a.HS[(int64_t)(row0 + r) * GHD + c] = v;
+    }
+    for (int t = 0; t < T; ++t) {
+        stage_x(t);
+        for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
+            const int r = i / GHD, c = i % GHD;
+            const bool zero = r >= rows || a.start[(int64_t)t * m + row0 + r];
+            HP[r * HSG + c] = zero ? 0.f : HN[r * HSG + c];
+        }
+        __syncthreads();
+        gru_embed(P, X, E, wave, nw);
+        __syncthreads();
+        gru_gates(P, E, HP, GI, GH, wave, nw);
+        __syncthreads();
+        gru_update(GI, GH, HP, HN, tid, GRU_SEQ_TH, false);
+        __syncthreads();
+        for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
+            const int r = i / GHD, c = i % GHD;
+            if (r < rows) a.HS[((int64_t)(t + 1) * m + row0 + r) * GHD + c] = HN[r * HSG + c];
+        }
+    }
+    /* backward */
+    for (int i = tid; i < TG * HSG; i += GRU_SEQ_TH) DH[i] = 0.f;
+    float lsum[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int t = T - 1; t >= 0; --t) {
+        __syncthreads();
+        stage_x(t);
+        for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
+            const int r = i / GHD, c = i % GHD;
+            const bool zero = r >= rows || a.start[(int64_t)t * m + row0 + r];
+            HP[r * HSG + c] = zero ? 0.f : a.HS[((int64_t)t * m + row0 + r) * GHD + c];
+        }
+        __syncthreads();
+        gru_embed(P, X, E, wave, nw);
+        __syncthreads();
+        gru_gates(P, E, HP, GI, GH, wave, nw);
+        __syncthreads();
+        gru_update(GI, GH, HP, HN, tid, GRU_SEQ_TH, true);
+        __syncthreads();
+        if (wave == 0) gru_head(P, HN, O);
+        __syncthreads();
+        /* per-sample loss terms and dO (scaled by 1 / (T m)) */
+        if (tid < TG) {
+            float *z = O + tid * OS;
+            float dz[OUT];
+#pragma unroll
+            for (int j = 0; j < OUT; ++j) dz[j] = 0.f;
+            if (tid < rows) {
+                const int64_t s = (int64_t)t * m + row0 + tid;
+                float ls[4];
+                loss_head(z, a.n_act, a.act[s], a.logp_old[s], a.adv[s], a.ret[s], a.v_old[s], a.clip, a.c_v, a.c_e,
+                          a.scale, dz, ls);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) lsum[q] += ls[q];
+            }
+            for (int j = 0; j < OUT; ++j) z[j] = dz[j];
+            if (tid < rows) {
+                const int64_t s = (int64_t)t * m + row0 + tid;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) a.DO[s * 16 + j] = j < OUT ? dz[j] : 0.f;
+            }
+        }
+        /* the recomputed embedding for the weight products */
+        for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
+            const int r = i / GHD, c = i % GHD;
+            if (r < rows) a.E[((int64_t)t * m + row0 + r) * GHD + c] = E[r * HSG + c];
+        }
+        __syncthreads();
+        /* dh += dO W_o^T (K = 16, rows 10..15 of W_o^T zero) */
+        if (wave < GHD / 16) {
+            floatx4 acc[1][1] = {{zero4()}};
+            gemm<1, 1>(acc, 16, 0, 16 * wave, [&](int i, int k) { return O[i * OS + k]; },
+                       [&](int k, int j) { return k < OUT ? P[GO_WO + j * OUT + k] : 0.f; });
+#pragma unroll
+            for (int i = 0; i < 4; ++i) DH[acc_row(i) * HSG + 16 * wave + acc_col()] += acc[0][0][i];
+        }
+        __syncthreads();
+        /* back through the cell: gate pre-activation gradients; DH keeps the direct part
+         * u dh of dh_{t-1} */
+        for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
+            const int r = i / GHD, j = i % GHD;
+            const float dh = DH[r * HSG + j];
+            const float rr = GI[r * GS + j], u = GI[r * GS + GHD + j], nn = GI[r * GS + 2 * GHD + j];
+            const float hp = HP[r * HSG + j], ghn = GH[r * GS + 2 * GHD + j];
+            const float dnp = dh * (1.f - u) * (1.f - nn * nn);
+            const float dup = dh * (hp - nn) * u * (1.f - u);
+            const float drp = dnp * ghn * rr * (1.f - rr);
+            DGI[r * GS + j] = drp;
+            DGI[r * GS + GHD + j] = dup;
+            DGI[r * GS + 2 * GHD + j] = dnp;
+            DGH[r * GS + j] = drp;
+            DGH[r * GS + GHD + j] = dup;
+            DGH[r * GS + 2 * GHD + j] = dnp * rr;
+            DH[r * HSG + j] = dh * u;
+        }
+        __syncthreads();
+        for (int i = tid; i < TG * G3; i += GRU_SEQ_TH) {
+            const int r = i / G3, c = i % G3;
+            if (r < rows) {
+                const int64_t s = (int64_t)t * m + row0 + r;
+                a.DGI[s * G3 + c] = DGI[r * GS + c];
+                a.DGH[s * G3 + c] = DGH[r * GS + c];
+            }
+        }
+        /* dh_{t-1} += DGH W_h^T and de = (DGI W_i^T) (1 - e^2), K = 384: one column tile of
+         * each per wave */
+        {
+            floatx4 acc[1][1] = {{zero4()}}, acd[1][1] = {{zero4()}};
+            gemm<1, 1>(acc, G3, 0, 16 * wave, [&](int i, int k) { return DGH[i * GS + k]; },
+                       [&](int k, int j) { return a.WhT[k * GHD + j]; });
+            gemm<1, 1>(acd, G3, 0, 16 * wave, [&](int i, int k) { return DGI[i * GS + k]; },
+                       [&](int k, int j) { return a.WiT[k * GHD + j]; });
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = acc_row(i), c = 16 * wave + acc_col();
+                const bool stop = r >= rows || a.start[(int64_t)t * m + row0 + r];
+                DH[r * HSG + c] = stop ? 0.f : DH[r * HSG + c] + acc[0][0][i];
+                const float e = E[r * HSG + c];
+                if (r < rows) a.DE[((int64_t)t * m + row0 + r) * GHD + c] = acd[0][0][i] * (1.f - e * e);
+            }
+        }
+    }
+    /* loss sums of the tile in row order */
+    __syncthreads();
+    if (tid < TG)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) O[tid * OS + q] = lsum[q];
+    __syncthreads();
+    if (tid < 4) {
+        float v = 0.f;
+        for (int r = 0; r < TG; ++r) v += O[r * OS + tid];
+        a.LS[(int64_t)blockIdx.x * 4 + tid] = v;
+    }
+}
+
+/* W_i and W_h transposed into the workspace ([384][128] each) */
+__global__ void k_gru_transpose(const float *__restrict__ P, float *WiT, float *WhT) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= GHD * G3) return;
+    const int k = i / GHD, j = i % GHD; /* destination row k (gate column), column j */
+    WiT[i] = P[GO_WI + j * G3 + k];
+    WhT[i] = P[GO_WH + j * G3 + k];
+}
+
+/* ---- weight gradients over all T m samples: workgroup w takes a contiguous range of
+ * samples (s = t m + env) and writes one partial of every parameter; the partials are
+ * then summed in a fixed order ---- */
+struct GruDwArgs {
+    const float *obs;          /* [S][40] */
+    const uint8_t *start;      /* [S] */
+    const float *HS, *E, *DGI, *DGH, *DE, *DO;
+    int64_t S, m;
+    float *partial;            /* [grid][GPW] */
+};
+
+template <int NT, class FA, class FB>
+__device__ __forceinline__ void dw_tiles(floatx4 (&acc)[1][NT], int len, int r0, int c0, FA A, FB B) {
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[0][n] = zero4();
+    gemm<1, NT>(acc, (len + 3) & ~3, r0, c0, [&](int i, int k) { return k < len ? A(i, k) : 0.f; },
+                [&](int k, int j) { return k < len ? B(k, j) : 0.f; });
+}
+
+__global__ void __launch_bounds__(GRU_DW_TH) k_gru_dw(GruDwArgs a) {
+    const int64_t s0 = a.S * (int64_t)blockIdx.x / gridDim.x, s1 = a.S * (int64_t)(blockIdx.x + 1) / gridDim.x;
+    const int len = (int)(s1 - s0);
+    float *G = a.partial + (int64_t)blockIdx.x * GPW;
+    const int tid = (int)threadIdx.x, wave = tid >> 6;
+    const float *Eb = a.E + s0 * GHD, *DGIb = a.DGI + s0 * G3, *DGHb = a.DGH + s0 * G3, *DEb = a.DE + s0 * GHD;
+    const float *HPb = a.HS + s0 * GHD, *HNb = a.HS + (s0 + a.m) * GHD, *DOb = a.DO + s0 * 16;
+    const float *Xb = a.obs + s0 * GIN;
+    const uint8_t *Sb = a.start + s0;
+    /* dW_i = E^T DGI and dW_h = HP^T DGH (HP zero at an episode start): 8 x 24 tiles each,
+     * a wave takes one row tile and 12 column tiles, three at a time */
+    const int rt = wave & 7, cb = (wave >> 3) * 12;
+    for (int c3 = 0; c3 < 12; c3 += 3) {
+        floatx4 acc[1][3];
+        dw_tiles<3>(acc, len, 16 * rt, 16 * (cb + c3), [&](int i, int k) { return Eb[(int64_t)k * GHD + i]; },
+                    [&](int k, int j) { return DGIb[(int64_t)k * G3 + j]; });
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                G[GO_WI + (16 * rt + acc_row(i)) * G3 + 16 * (cb + c3 + n) + acc_col()] = acc[0][n][i];
+        dw_tiles<3>(acc, len, 16 * rt, 16 * (cb + c3),
+                    [&](int i, int k) { return Sb[k] ? 0.f : HPb[(int64_t)k * GHD + i]; },
+                    [&](int k, int j) { return DGHb[(int64_t)k * G3 + j]; });
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                G[GO_WH + (16 * rt + acc_row(i)) * G3 + 16 * (cb + c3 + n) + acc_col()] = acc[0][n][i];
+    }
+    /* dW_e = X^T DE (3 x 8 tiles, rows 40..47 dropped) and dW_o = HN^T DO (8 tiles) */
+    for (int tt = wave; tt < 24 + 8; tt += GRU_DW_TH / 64) {
+        floatx4 acc[1][1];
+        if (tt < 24) {
+            const int r0 = 16 * (tt / 8), c0 = 16 * (tt % 8);
+            dw_tiles<1>(acc, len, r0, c0, [&](int i, int k) { return i < GIN ? Xb[(int64_t)k * GIN + i] : 0.f; },
+                        [&](int k, int j) { return DEb[(int64_t)k * GHD + j]; });
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = r0 + acc_row(i);
+                if (r < GIN) G[GO_WE + r * GHD + c0 + acc_col()] = acc[0][0][i];
+            }
+        } else {
+            const int r0 = 16 * (tt - 24);
+            dw_tiles<1>(acc, len, r0, 0, [&](int i, int k) { return HNb[(int64_t)k * GHD + i]; },
+                        [&](int k, int j) { return DOb[(int64_t)k * 16 + j]; });
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (acc_col() < OUT) G[GO_WO + (r0 + acc_row(i)) * OUT + acc_col()] = acc[0][0][i];
+        }
+    }
+    /* biases: column sums in sample order */
+    for (int c = tid; c < G3 + G3 + GHD + OUT; c += GRU_DW_TH) {
+        float v = 0.f;
+        if (c < G3) {
+            for (int k = 0; k < len; ++k) v += DGIb[(int64_t)k * G3 + c];
+            G[GO_BI + c] = v;
+        } else if (c < 2 * G3) {
+            for (int k = 0; k < len; ++k) v += DGHb[(int64_t)k * G3 + c - G3];
+            G[GO_BH + c - G3] = v;
+        } else if (c < 2 * G3 + GHD) {
+            for (int k = 0; k < len; ++k) v += DEb[(int64_t)k * GHD + c - 2 * G3];
+            G[GO_BE + c - 2 * G3] = v;
+        } else {
+            for (int k = 0; k < len; ++k) v += DOb[(int64_t)k * 16 + c - 2 * G3 - GHD];
+            G[GO_BO + c - 2 * G3 - GHD] = v;
+        }
+    }
+    if (tid < GPW - GNP) G[GNP + tid] = 0.f;
+}
+
+/* columns [0, width) of the chunk sums summed in chunk order into out */
+__global__ void k_reduce_out(const float *__restrict__ sums, int nch, int pitch, int width, float *out) {
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= width) return;
+    float s = 0.f;
+    for (int c = 0; c < nch; ++c) s += sums[(int64_t)c * pitch + j];
+    out[j] = s;
+}
+
+/* the tiles' loss sums in tile order */
+__global__ void k_gru_loss(const float *__restrict__ LS, int ntile, float *loss) {
+    const int q = (int)threadIdx.x;
+    if (q >= 4) return;
+    float s = 0.f;
+    for (int i = 0; i < ntile; ++i) s += LS[(int64_t)i * 4 + q];
+    loss[q] = s;
+}
+
 __global__ void k_bump(uint64_t *c) {
     if (threadIdx.x == 0 && blockIdx.x == 0) c[0] += 1;
 }
@@ -646,12 +1112,43 @@ bool lds_opt_in() {
         if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_policy_forward),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, LDS_FLOATS_P * 4) != hipSuccess ||
             hipFuncSetAttribute(reinterpret_cast<const void *>(k_ppo_fwd_bwd),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, LDS_FLOATS * 4) != hipSuccess)
+                                hipFuncAttributeMaxDynamicSharedMemorySize, LDS_FLOATS * 4) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(k_gru_step),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, GRU_STEP_LDS * 4) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(k_gru_seq),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, GRU_SEQ_LDS * 4) != hipSuccess)
             return false;
         done = true;
     }
     return true;
 }
+/* the GRU loss workspace, in floats from its start (every part a multiple of 4 floats) */
+struct GruWs {
+    int64_t hs, e, dgi, dgh, de, dout, ls, wit, wht, part, sums, total;
+    int ntile, nwg, nch;
+};
+GruWs gru_ws(int32_t T, int32_t m) {
+    GruWs w{};
+    const int64_t S = (int64_t)T * m;
+    w.ntile = (m + TG - 1) / TG;
+    w.nwg = (int)std::min<int64_t>(GRU_DW_WGS, (S + 63) / 64);
+    w.nch = (w.nwg + RCH - 1) / RCH;
+    int64_t o = 0;
+    w.hs = o; o += (int64_t)(T + 1) * m * GHD;
+    w.e = o; o += S * GHD;
+    w.dgi = o; o += S * G3;
+    w.dgh = o; o += S * G3;
+    w.de = o; o += S * GHD;
+    w.dout = o; o += S * 16;
+    w.ls = o; o += (int64_t)w.ntile * 4;
+    w.wit = o; o += (int64_t)GHD * G3;
+    w.wht = o; o += (int64_t)GHD * G3;
+    w.part = o; o += (int64_t)w.nwg * GPW;
+    w.sums = o; o += (int64_t)w.nch * GPW;
+    w.total = o;
+    return w;
+}
+
 int64_t ppo_workspace_bytes(int32_t m) {
     const int64_t nwg = std::min<int64_t>((m + TR - 1) / TR, PPO_WGS), nch = (nwg + RCH - 1) / RCH;
     return (nwg + nch) * PW * 4 + PARAM_COPY_BYTES;
@@ -738,6 +1235,63 @@ int lob_policy_forward(const float *params, const float *obs, int32_t n_agents, 
     if (!lds_opt_in()) return LOB_EHIP;
     const dim3 grid((unsigned)((n + TRP - 1) / TRP), (unsigned)n_agents);
     hipLaunchKernelGGL(k_policy_forward, grid, dim3(NTH), LDS_FLOATS_P * 4, (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
+}
+
+int lob_gru_step(const float *params, const float *obs, const float *h_in, float *h_out, const uint8_t *start,
+                 int32_t n_agents, int32_t n, const int32_t *n_actions, uint64_t seed, const uint64_t *epoch, int32_t t,
+                 float *logits, int32_t *actions, float *logp, float *value, void *stream) {
+    if (!params || !obs || !h_in || !h_out || !n_actions || !actions || !logp || !value) return LOB_EINVAL;
+    if (n_agents < 1 || n_agents > LOB_MAX_AGENTS || n <= 0) return LOB_EINVAL;
+    GruStepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.params = params; a.obs = obs; a.h_in = h_in; a.h_out = h_out; a.start = start; a.n = n;
+    for (int i = 0; i < n_agents; ++i) {
+        if (n_actions[i] < 1 || n_actions[i] > 9) return LOB_EINVAL;
+        a.n_act[i] = n_actions[i];
+    }
+    a.seed = seed; a.epoch = epoch; a.t = t; a.logits = logits; a.actions = actions; a.logp = logp; a.value = value;
+    if (!lds_opt_in()) return LOB_EHIP;
+    hipLaunchKernelGGL(k_gru_step, dim3((unsigned)((n + TG - 1) / TG), (unsigned)n_agents), dim3(GRU_STEP_TH),
+                       GRU_STEP_LDS * 4, (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
+}
+
+int64_t lob_gru_ppo_workspace_bytes(int32_t T, int32_t m) {
+    if (T <= 0 || m <= 0) return LOB_EINVAL;
+    return gru_ws(T, m).total * 4;
+}
+
+int lob_gru_ppo_fwd_bwd(const float *params, const float *obs, const uint8_t *start, const float *h0,
+                        const int32_t *act, const float *logp_old, const float *adv, const float *ret,
+                        const float *v_old, int32_t T, int32_t m, int32_t n_actions, float clip, float c_v, float c_e,
+                        float *workspace, int64_t workspace_bytes, float *loss, float *grad, void *stream) {
+    if (!params || !obs || !start || !h0 || !act || !logp_old || !adv || !ret || !v_old || !workspace || !loss || !grad)
+        return LOB_EINVAL;
+    if (T <= 0 || m <= 0 || n_actions < 1 || n_actions > 9 || !(clip > 0.f)) return LOB_EINVAL;
+    if ((int64_t)T * m > ((int64_t)1 << 31) / G3) return LOB_EUNSUPPORTED;
+    const GruWs w = gru_ws(T, m);
+    if (workspace_bytes < w.total * 4 || ((uintptr_t)workspace & 15)) return LOB_EINVAL;
+    if (!lds_opt_in()) return LOB_EHIP;
+    hipStream_t st = (hipStream_t)stream;
+    float *ws = workspace;
+    hipLaunchKernelGGL(k_gru_transpose, dim3((GHD * G3 + 255) / 256), dim3(256), 0, st, params, ws + w.wit, ws + w.wht);
+    GruSeqArgs a;
+    a.params = params; a.obs = obs; a.start = start; a.h0 = h0; a.act = act; a.logp_old = logp_old; a.adv = adv;
+    a.ret = ret; a.v_old = v_old; a.T = T; a.m = m; a.n_act = n_actions; a.clip = clip; a.c_v = c_v; a.c_e = c_e;
+    a.scale = 1.0f / (float)((int64_t)T * m);
+    a.HS = ws + w.hs; a.E = ws + w.e; a.DGI = ws + w.dgi; a.DGH = ws + w.dgh; a.DE = ws + w.de; a.DO = ws + w.dout;
+    a.LS = ws + w.ls; a.WiT = ws + w.wit; a.WhT = ws + w.wht;
+    hipLaunchKernelGGL(k_gru_seq, dim3((unsigned)w.ntile), dim3(GRU_SEQ_TH), GRU_SEQ_LDS * 4, st, a);
+    GruDwArgs d;
+    d.obs = obs; d.start = start; d.HS = a.HS; d.E = a.E; d.DGI = a.DGI; d.DGH = a.DGH; d.DE = a.DE; d.DO = a.DO;
+    d.S = (int64_t)T * m; d.m = m; d.partial = ws + w.part;
+    hipLaunchKernelGGL(k_gru_dw, dim3((unsigned)w.nwg), dim3(GRU_DW_TH), 0, st, d);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((GPW / 4 + 255) / 256), (unsigned)w.nch), dim3(256), 0, st,
+                       (const floatx4 *)(ws + w.part), w.nwg, GPW / 4, (floatx4 *)(ws + w.sums));
+    hipLaunchKernelGGL(k_reduce_out, dim3((unsigned)((GNP + 255) / 256)), dim3(256), 0, st, (const float *)(ws + w.sums),
+                       w.nch, GPW, GNP, grad);
+    hipLaunchKernelGGL(k_gru_loss, dim3(1), dim3(64), 0, st, (const float *)(ws + w.ls), w.ntile, loss);
     return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
 }
 

@@ -15,6 +15,8 @@ import torch
 from .lob import lib, _check, _p, _stream, LobError
 
 N_PARAMS = 78858
+GRU_PARAMS = 105610
+GRU_HIDDEN = 128
 OBS_DIM = 40
 
 _ready = False
@@ -37,6 +39,12 @@ def _lib():
         L.lob_ppo_fwd_bwd.restype = ctypes.c_int
         L.lob_ppo_fwd_bwd_noalloc.argtypes = [p, p, p, p, p, p, p, i32, i32, f32, f32, f32, p, p, p]
         L.lob_ppo_fwd_bwd_noalloc.restype = ctypes.c_int
+        L.lob_gru_step.argtypes = [p, p, p, p, p, i32, i32, p, u64, p, i32, p, p, p, p, p]
+        L.lob_gru_step.restype = ctypes.c_int
+        L.lob_gru_ppo_workspace_bytes.argtypes = [i32, i32]
+        L.lob_gru_ppo_workspace_bytes.restype = i64
+        L.lob_gru_ppo_fwd_bwd.argtypes = [p, p, p, p, p, p, p, p, p, i32, i32, i32, f32, f32, f32, p, i64, p, p, p]
+        L.lob_gru_ppo_fwd_bwd.restype = ctypes.c_int
         _ready = True
     return L
 
@@ -129,6 +137,88 @@ def ppo_fwd_bwd_noalloc(params, obs, act, logp_old, adv, ret, v_old, n_actions, 
                                           c_e, _p(_f32(loss)), _p(_f32(grad)), _stream()),
            "lob_ppo_fwd_bwd_noalloc")
     return loss, grad
+
+
+def gru_init_params(n_agents: int, seed: int, device="cuda") -> torch.Tensor:
+    """Glorot-uniform matrices and zero biases for n_agents recurrent networks,
+    [n_agents, GRU_PARAMS]."""
+    g = torch.Generator().manual_seed(seed)
+    out = torch.zeros(n_agents, GRU_PARAMS, dtype=torch.float32)
+    shapes = ((40, 128), (128,), (128, 384), (384,), (128, 384), (384,), (128, 10), (10,))
+    for a in range(n_agents):
+        o = 0
+        for sh in shapes:
+            n = int(np.prod(sh))
+            if len(sh) == 2:
+                lim = float(np.sqrt(6.0 / (sh[0] + sh[1])))
+                out[a, o:o + n] = (torch.rand(n, generator=g) * 2 - 1) * lim
+            o += n
+    return out.to(device)
+
+
+def gru_step(params: torch.Tensor, obs: torch.Tensor, h: torch.Tensor, n_actions: Sequence[int], seed: int, t: int,
+             start: torch.Tensor = None, h_out: torch.Tensor = None, want_logits: bool = False,
+             epoch: torch.Tensor = None, out: dict = None) -> dict:
+    """One recurrent policy step: params [A, GRU_PARAMS], obs [A, n, 40], h [A, n, 128]
+    (float32, device), start [n] uint8 or None -> actions, logp, value [A, n] and the new
+    state in out["h"] (h_out, or h itself: updated in place)."""
+    A, n = obs.shape[0], obs.shape[1]
+    dev = obs.device
+    if out is None:
+        out = {"actions": torch.empty((A, n), dtype=torch.int32, device=dev),
+               "logp": torch.empty((A, n), dtype=torch.float32, device=dev),
+               "value": torch.empty((A, n), dtype=torch.float32, device=dev),
+               "logits": torch.empty((A, n, 10), dtype=torch.float32, device=dev) if want_logits else None}
+    ho = h if h_out is None else h_out
+    na = (ctypes.c_int32 * A)(*[int(x) for x in n_actions])
+    _check(_lib().lob_gru_step(_p(_f32(params)), _p(_f32(obs)), _p(_f32(h)), _p(_f32(ho)),
+                               _p(None if start is None else start.to(torch.uint8).contiguous()), A, n, na, seed,
+                               _p(epoch), t, _p(out.get("logits")), _p(out["actions"]), _p(out["logp"]),
+                               _p(out["value"]), _stream()), "lob_gru_step")
+    out["h"] = ho
+    return out
+
+
+def gru_workspace_bytes(T: int, m: int) -> int:
+    return int(_lib().lob_gru_ppo_workspace_bytes(int(T), int(m)))
+
+
+def gru_ppo_fwd_bwd(params, obs, start, h0, act, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01,
+                    workspace=None):
+    """Loss sums [4] and the gradient of the mean loss of m sequences of T steps:
+    obs [T, m, 40], start [T, m] uint8, h0 [m, 128], act/logp_old/adv/ret/v_old [T, m]."""
+    T, m = obs.shape[0], obs.shape[1]
+    L = _lib()
+    need = int(L.lob_gru_ppo_workspace_bytes(T, m))
+    if workspace is None or workspace.numel() * 4 < need:
+        workspace = torch.empty((need + 3) // 4, dtype=torch.float32, device=obs.device)
+    loss = torch.empty(4, dtype=torch.float32, device=obs.device)
+    grad = torch.empty(GRU_PARAMS, dtype=torch.float32, device=obs.device)
+    _check(L.lob_gru_ppo_fwd_bwd(_p(_f32(params)), _p(_f32(obs)), _p(start.to(torch.uint8).contiguous()),
+                                 _p(_f32(h0)), _p(act.to(torch.int32).contiguous()), _p(_f32(logp_old)),
+                                 _p(_f32(adv)), _p(_f32(ret)), _p(_f32(v_old)), T, m, int(n_actions), clip, c_v, c_e,
+                                 _p(workspace), workspace.numel() * 4, _p(loss), _p(grad), _stream()),
+           "lob_gru_ppo_fwd_bwd")
+    return loss, grad
+
+
+class FusedGruPPOLoss(torch.autograd.Function):
+    """Mean clipped-PPO loss of m whole sequences for the recurrent network; forward runs
+    the fused recurrent kernels (forward through time keeping only the hidden states,
+    backward through time recomputing the rest), which also produce the parameter
+    gradient; backward scales it by the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, params, obs, start, h0, act, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01):
+        loss, grad = gru_ppo_fwd_bwd(params.detach().contiguous(), obs, start, h0, act, logp_old, adv, ret, v_old,
+                                     n_actions, clip, c_v, c_e)
+        ctx.save_for_backward(grad)
+        return loss[0] / (obs.shape[0] * obs.shape[1])
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return (g * grad,) + (None,) * 12
 
 
 class FusedPPOLoss(torch.autograd.Function):

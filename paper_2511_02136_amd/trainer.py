@@ -1,7 +1,9 @@
 """IPPO on the batched LOB environment: learned-policy rollouts and PPO updates.
 
 One independent actor-critic per agent (Sec. 4.2 of the paper: separate networks, no
-shared weights).  A rollout step is the policy forward (MFMA kernel, sampling
+shared weights): the feed-forward MLP, or the recurrent (GRU) network the paper trains
+(Sec. 5.2.1), whose update runs over whole sequences (minibatches of envs) with the loss
+taken back through time.  A rollout step is the policy forward (MFMA kernel, sampling
 in-kernel) followed by one env step with the sampled actions; the whole T-step rollout
 (reset included) can be captured once in a HIP graph and replayed, with a device counter
 giving every replay fresh sampling noise.  The update runs GAE and, per agent, epochs of
@@ -27,7 +29,8 @@ assert len(OBS_SCALE) == 40
 class IppoTrainer:
     def __init__(self, env: LobEnv, dstream: DeviceStream, book: dict, n_steps: int, seed: int = 0,
                  param_seed: int = 0, lr: float = 3e-4, epochs: int = 4, minibatches: int = 4, gamma: float = 0.99,
-                 lam: float = 0.95, clip: float = 0.2, c_v: float = 0.5, c_e: float = 0.01, record_trades: bool = True):
+                 lam: float = 0.95, clip: float = 0.2, c_v: float = 0.5, c_e: float = 0.01, record_trades: bool = True,
+                 network: str = "mlp"):
         self.env, self.ds, self.book, self.T = env, dstream, book, n_steps
         self.A, self.N = env.n_agents, env.n_envs
         self.n_act = [N_ACTIONS[int(k)] for k in env.kinds]
@@ -35,7 +38,11 @@ class IppoTrainer:
         self.epochs, self.minibatches = epochs, minibatches
         self.gamma, self.lam, self.clip, self.c_v, self.c_e = gamma, lam, clip, c_v, c_e
         dev = env.device
-        self.params = torch.nn.Parameter(ippo.xavier_params(self.A, param_seed, device=dev))
+        if network not in ("mlp", "gru"):
+            raise ValueError("network must be 'mlp' or 'gru'")
+        self.network = network
+        init = ippo.xavier_params if network == "mlp" else ippo.gru_init_params
+        self.params = torch.nn.Parameter(init(self.A, param_seed, device=dev))
         self.opt = torch.optim.Adam([self.params], lr=lr)
         self.inv_scale = (1.0 / torch.tensor(OBS_SCALE, dtype=torch.float32)).to(dev)
         T, A, N = n_steps, self.A, self.N
@@ -46,6 +53,8 @@ class IppoTrainer:
         self.out = env._alloc_out(T, True, record_trades, None, dstream, actions_out=False)
         self.cursor = torch.zeros(N, dtype=torch.int64, device=dev)
         self.epoch = torch.zeros(1, dtype=torch.int64, device=dev)
+        # recurrent state of the GRU policy during the rollout (zero at the episode start)
+        self.h = torch.zeros((A, N, ippo.GRU_HIDDEN), dtype=torch.float32, device=dev) if network == "gru" else None
         self.graph: Optional[torch.cuda.CUDAGraph] = None
 
     # ---- rollout ----
@@ -55,9 +64,16 @@ class IppoTrainer:
         env.reset(self.book)
         self.cursor.zero_()
         torch.mul(env.observe(), self.inv_scale, out=self.obs[0])
+        if self.h is not None:
+            self.h.zero_()
         for t in range(T):
             pf = {k: v[t] for k, v in self.pol.items()}
-            ippo.policy_forward(self.params.detach(), self.obs[t], self.n_act, self.seed, t, epoch=self.epoch, out=pf)
+            if self.h is None:
+                ippo.policy_forward(self.params.detach(), self.obs[t], self.n_act, self.seed, t, epoch=self.epoch,
+                                    out=pf)
+            else:
+                ippo.gru_step(self.params.detach(), self.obs[t], self.h, self.n_act, self.seed, t, epoch=self.epoch,
+                              out=pf)
             view = {k: (v[t:t + 1] if k not in ("trades", "trade_off") and v is not None else v)
                     for k, v in self.out.items()}
             env.step(self.ds, pf["actions"], out=view, cursor=self.cursor)
@@ -91,6 +107,8 @@ class IppoTrainer:
         adv, ret = ippo.gae(rew.contiguous(), val.contiguous(), done, torch.zeros(A * N, device=rew.device),
                             self.gamma, self.lam)
         adv, ret = adv.reshape(T, A, N), ret.reshape(T, A, N)
+        if self.network == "gru":
+            return self._update_gru(adv, ret)
         M = T * N
         mb = M // self.minibatches
         stats = {"loss": 0.0, "minibatches": 0}
@@ -109,6 +127,38 @@ class IppoTrainer:
                     vo = self.pol["value"][:, a].reshape(M)[idx].contiguous()
                     loss = ippo.FusedPPOLoss.apply(self.params[a], obs, act, lpo, ad, rt, vo, self.n_act[a],
                                                    self.clip, self.c_v, self.c_e)
+                    total = total + loss
+                total.backward()
+                self.opt.step()
+                stats["loss"] += float(total.detach())
+                stats["minibatches"] += 1
+        stats["loss"] /= max(1, stats["minibatches"])
+        return stats
+
+    def _update_gru(self, adv, ret) -> dict:
+        """Epochs of minibatches of whole sequences (envs), the loss back through time."""
+        T, A, N = self.T, self.A, self.N
+        dev = adv.device
+        mb = N // self.minibatches
+        start = torch.zeros((T, mb), dtype=torch.uint8, device=dev)
+        start[0] = 1  # the rollout is one episode from its reset
+        h0 = torch.zeros((mb, ippo.GRU_HIDDEN), dtype=torch.float32, device=dev)
+        stats = {"loss": 0.0, "minibatches": 0}
+        for _ in range(self.epochs):
+            perms = [torch.randperm(N, device=dev) for _ in range(A)]
+            for k in range(self.minibatches):
+                self.opt.zero_grad(set_to_none=True)
+                total = 0.0
+                for a in range(A):
+                    idx = perms[a][k * mb:(k + 1) * mb]
+                    obs = self.obs[:T, a][:, idx].contiguous()
+                    act = self.pol["actions"][:, a][:, idx].contiguous()
+                    lpo = self.pol["logp"][:, a][:, idx].contiguous()
+                    ad = adv[:, a][:, idx].contiguous()
+                    rt = ret[:, a][:, idx].contiguous()
+                    vo = self.pol["value"][:, a][:, idx].contiguous()
+                    loss = ippo.FusedGruPPOLoss.apply(self.params[a], obs, start, h0, act, lpo, ad, rt, vo,
+                                                      self.n_act[a], self.clip, self.c_v, self.c_e)
                     total = total + loss
                 total.backward()
                 self.opt.step()
