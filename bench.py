@@ -171,6 +171,76 @@ def cpu_baseline(w, stream, budget_s=15.0, threads=None):
 # and 3 (none for the observation); 2 FLOP per MAC
 PPO_FLOP_PER_SAMPLE = 2 * ((40 * 256 + 256 * 256 + 256 * 10) * 2 + 256 * 256 + 256 * 10)
 FP32_MFMA_PEAK_TFLOPS = 157.3
+# recurrent network per sample: forward 40x128 + 128x384 + 128x384 + 128x10 MACs (embedding,
+# input and recurrent gate products, head); backward the input gradients of the head, the
+# recurrent and the gate products (none for the observation) and every weight gradient;
+# 2 FLOP per MAC.  The forward pass the kernel runs a second time (recomputation) is not
+# counted.
+GRU_FWD_MACS = 40 * 128 + 2 * 128 * 384 + 128 * 10
+GRU_FLOP_PER_SAMPLE = 2 * (GRU_FWD_MACS + (128 * 10 + 2 * 128 * 384) + GRU_FWD_MACS)
+
+
+def gru_bench(reps: int = 3):
+    """ippo4096 with the recurrent (GRU) actor-critic: graph-captured learned-policy rollout,
+    one update over whole sequences (4 epochs x 4 minibatches of 1024 envs x 128 steps per
+    agent) and one fused GRU loss call on a full minibatch, with its MFMA roofline."""
+    import torch
+    from paper_2511_02136_amd import synth, ippo
+    from paper_2511_02136_amd.lob import LobEnv, DeviceStream
+    from paper_2511_02136_amd.trainer import IppoTrainer
+    w = synth.WORKLOADS["ippo4096"]
+    s = synth.generate(w)
+    ds = DeviceStream.from_host(s)
+    env = LobEnv(s.caps, w.max_cap, w.agents, w.ep_len, w.seed)
+    book = {k: torch.from_numpy(v).cuda() for k, v in s.book.items()}
+    tr = IppoTrainer(env, ds, book, w.n_steps, seed=w.seed, network="gru")
+    tr.rollout(use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        tr.rollout(use_graph=True)
+    torch.cuda.synchronize()
+    roll_ms = (time.perf_counter() - t0) * 1e3 / reps
+    tr.update()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr.update()
+    torch.cuda.synchronize()
+    upd_ms = (time.perf_counter() - t0) * 1e3
+    T, N = w.n_steps, w.n_envs
+    m = N // tr.minibatches
+    obs = tr.obs[:T, 0][:, :m].contiguous()
+    start = torch.zeros((T, m), dtype=torch.uint8, device="cuda")
+    start[0] = 1
+    h0 = torch.zeros((m, ippo.GRU_HIDDEN), dtype=torch.float32, device="cuda")
+    act = tr.pol["actions"][:, 0][:, :m].contiguous()
+    lpo = tr.pol["logp"][:, 0][:, :m].contiguous()
+    val = tr.pol["value"][:, 0][:, :m].contiguous()
+    adv = torch.randn((T, m), device="cuda")
+    ret = val + 0.1 * torch.randn((T, m), device="cuda")
+    prm = tr.params.detach()[0].contiguous()
+    ws = torch.empty((ippo.gru_workspace_bytes(T, m) + 3) // 4, dtype=torch.float32, device="cuda")
+    args = (prm, obs, start, h0, act, lpo, adv, ret, val, tr.n_act[0])
+    ippo.gru_ppo_fwd_bwd(*args, workspace=ws, obs_scale=tr.inv_scale)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_calls = 5
+    e0.record(st)
+    for _ in range(n_calls):
+        ippo.gru_ppo_fwd_bwd(*args, workspace=ws, obs_scale=tr.inv_scale)
+    e1.record(st)
+    torch.cuda.synchronize()
+    call_ms = e0.elapsed_time(e1) / n_calls
+    tflops = T * m * GRU_FLOP_PER_SAMPLE / (call_ms / 1e3) / 1e12
+    return {"workload": f"ippo4096: {N} envs x {T} steps, 2 agents, GRU 40-128-GRU(128)-(9+1) fp32",
+            "rollout_ms": roll_ms, "rollout_env_steps_per_s": N * T / (roll_ms / 1e3), "update_ms": upd_ms,
+            "update": "GAE + 4 epochs x 4 minibatches (1024 sequences of 128 steps) x 2 agents + Adam",
+            "gru_ppo_fwd_bwd_call": {"sequences": m, "steps": T, "samples": T * m, "ms": call_ms,
+                                     "flop_per_sample": GRU_FLOP_PER_SAMPLE,
+                                     "launches": "k_gru_transpose, k_gru_seq, k_gru_dw, k_reduce_chunks, "
+                                                 "k_reduce_out, k_gru_loss",
+                                     "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
+                                                  "unit": "TFLOP/s", "frac": tflops / FP32_MFMA_PEAK_TFLOPS}}}
 
 
 def ippo_bench(reps: int = 3):
@@ -212,13 +282,13 @@ def ippo_bench(reps: int = 3):
     ret = val + 0.1 * torch.randn(m, device="cuda")
     prm = tr.params.detach()[0].contiguous()
     ws = torch.empty((ippo.workspace_bytes(m) + 3) // 4, dtype=torch.float32, device="cuda")
-    ippo.ppo_fwd_bwd(prm, obs, act, lpo, adv, ret, val, tr.n_act[0], workspace=ws)
+    ippo.ppo_fwd_bwd(prm, obs, act, lpo, adv, ret, val, tr.n_act[0], workspace=ws, obs_scale=tr.inv_scale)
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     n_calls = 10
     e0.record(st)
     for _ in range(n_calls):
-        ippo.ppo_fwd_bwd(prm, obs, act, lpo, adv, ret, val, tr.n_act[0], workspace=ws)
+        ippo.ppo_fwd_bwd(prm, obs, act, lpo, adv, ret, val, tr.n_act[0], workspace=ws, obs_scale=tr.inv_scale)
     e1.record(st)
     torch.cuda.synchronize()
     ppo_ms = e0.elapsed_time(e1) / n_calls
@@ -246,6 +316,8 @@ def main():
                     help="comma-separated extra workloads to report (default replay1; also uniform4096, large16384)")
     ap.add_argument("--ippo-only", action="store_true",
                     help="only the IPPO figures (profiling aid; prints them as one JSON object)")
+    ap.add_argument("--gru-only", action="store_true",
+                    help="only the recurrent actor-critic figures (profiling aid; one JSON object)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the schedule autotuner (the default plan and balance share instead)")
     ap.add_argument("--eager", action="store_true",
@@ -271,6 +343,9 @@ def main():
         del src, dst
     if args.ippo_only:
         print(json.dumps({"ippo": ippo_bench()}), flush=True)
+        return
+    if args.gru_only:
+        print(json.dumps({"ippo_gru": gru_bench()}), flush=True)
         return
     w = synth.WORKLOADS[args.workload]
     print(f"[bench] generating {w.name}", file=sys.stderr, flush=True)
@@ -437,6 +512,9 @@ def main():
         del out, env, ds
         torch.cuda.empty_cache()
         ippo_res = ippo_bench()
+        torch.cuda.empty_cache()
+        print("[bench] ippo4096 with the recurrent network", file=sys.stderr, flush=True)
+        ippo_res["gru"] = gru_bench()
 
     cpu = None
     if not args.no_cpu:

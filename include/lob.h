@@ -293,14 +293,17 @@ int lob_import_state(lob_ctx *ctx, const lob_books *books, const int64_t *env_st
 
 /* Policy forward for the rollout (Sec. 4.2: each agent type acts with its own network;
  * sampling by Gumbel-max is a reading, the paper is silent).  params: device [n_agents][LOB_PPO_PARAMS];
- * obs: device [n_agents][n][40]; n_actions: host [n_agents] (1..9, the first n_actions
+ * obs: device [n_agents][n][40], the env's observations as written; obs_scale: device
+ * [40] or NULL, the policy's input scaling (feature c enters the network as obs * obs_scale[c];
+ * the same argument of the PPO calls must match it); n_actions: host [n_agents] (1..9, the first n_actions
  * logits are the policy).  Samples one action per row by Gumbel-max with noise from the
  * counter hash of (seed', agent, action, t, row), seed' = seed + golden * (*epoch) when
  * epoch (a device uint64 counter, so that a captured graph draws new noise on each replay)
  * is given, else seed.  Outputs (device): logits [n_agents][n][10] (may be NULL), actions
  * [n_agents][n] int32, logp [n_agents][n] (log-probability of the sampled action), value
  * [n_agents][n].  Asynchronous on stream. */
-int lob_policy_forward(const float *params, const float *obs, int32_t n_agents, int32_t n, const int32_t *n_actions,
+int lob_policy_forward(const float *params, const float *obs, const float *obs_scale, int32_t n_agents, int32_t n,
+                       const int32_t *n_actions,
                        uint64_t seed, const uint64_t *epoch, int32_t t, float *logits, int32_t *actions, float *logp,
                        float *value, void *stream);
 
@@ -323,7 +326,8 @@ int64_t lob_ppo_workspace_bytes(int32_t m);
 /* Fused clipped-PPO loss and its gradient for one minibatch of one network (Sec. 4.2:
  * PPO per agent type; the clipped surrogate, value and entropy terms are PPO's, their
  * weights c_v, c_e the caller's since the paper is silent), with the activations
- * recomputed from obs (none stored between rollout and update).  An action outside
+ * recomputed from obs (none stored between rollout and update; obs_scale as for
+ * lob_policy_forward).  An action outside
  * [0, n_actions) counts as action 0, as the env step takes it.
  * obs [m][40], act [m] int32, logp_old, adv, ret, v_old [m] (device).  Loss =
  * policy + c_v value - c_e entropy with policy = -mean(min(r A, clip(r, 1-clip, 1+clip) A)),
@@ -335,7 +339,8 @@ int64_t lob_ppo_workspace_bytes(int32_t m);
  * params that are not 16-byte aligned are copied into it first (stream-ordered).
  * Deterministic: 256 workgroups each sum a fixed set of 64-sample tiles in order, and
  * their partials are summed in a fixed order. */
-int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, const float *logp_old,
+int lob_ppo_fwd_bwd(const float *params, const float *obs, const float *obs_scale, const int32_t *act,
+                    const float *logp_old,
                     const float *adv, const float *ret, const float *v_old, int32_t m, int32_t n_actions, float clip,
                     float c_v, float c_e, float *workspace, int64_t workspace_bytes, float *loss, float *grad,
                     void *stream);
@@ -353,7 +358,8 @@ int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, c
  * overlap on one GPU (other streams, other threads) race and must be ordered by the
  * caller; nothing in the array needs clearing between calls (each call writes every
  * partial it reads). */
-int lob_ppo_fwd_bwd_noalloc(const float *params, const float *obs, const int32_t *act, const float *logp_old,
+int lob_ppo_fwd_bwd_noalloc(const float *params, const float *obs, const float *obs_scale, const int32_t *act,
+                            const float *logp_old,
                             const float *adv, const float *ret, const float *v_old, int32_t m, int32_t n_actions,
                             float clip, float c_v, float c_e, float *loss, float *grad, void *stream);
 
@@ -369,11 +375,12 @@ int lob_ppo_fwd_bwd_noalloc(const float *params, const float *obs, const int32_t
 #define LOB_GRU_HIDDEN 128
 
 /* One rollout step of the recurrent policy for every agent: params [n_agents][params],
- * obs [n_agents][n][40], h_in / h_out [n_agents][n][128] (device; h_out may be h_in),
+ * obs [n_agents][n][40] (obs_scale as for lob_policy_forward), h_in / h_out [n_agents][n][128] (device; h_out may be h_in),
  * start [n] uint8 (device, 1 = the episode starts at this step: h_in is taken as zero) or
  * NULL.  Samples as lob_policy_forward (same counter hash and epoch; logits may be NULL).
  * Asynchronous on stream. */
-int lob_gru_step(const float *params, const float *obs, const float *h_in, float *h_out, const uint8_t *start,
+int lob_gru_step(const float *params, const float *obs, const float *obs_scale, const float *h_in, float *h_out,
+                 const uint8_t *start,
                  int32_t n_agents, int32_t n, const int32_t *n_actions, uint64_t seed, const uint64_t *epoch, int32_t t,
                  float *logits, int32_t *actions, float *logp, float *value, void *stream);
 
@@ -385,7 +392,7 @@ int64_t lob_gru_ppo_workspace_bytes(int32_t T, int32_t m);
 
 /* The clipped-PPO loss (the same per-sample terms as lob_ppo_fwd_bwd, averaged over the T
  * m samples) of one network over a minibatch of m whole sequences, and its gradient
- * through time.  obs [T][m][40], start [T][m] uint8, h0 [m][128] (the state before step
+ * through time.  obs [T][m][40] (obs_scale as for lob_policy_forward), start [T][m] uint8, h0 [m][128] (the state before step
  * 0), act, logp_old, adv, ret, v_old [T][m] (device).  The forward pass keeps only the
  * hidden states; the backward pass recomputes each step's embedding, gates and outputs.
  * Writes loss [4] (sums over the samples of the total, policy, value and entropy terms)
@@ -393,7 +400,8 @@ int64_t lob_gru_ppo_workspace_bytes(int32_t T, int32_t m);
  * 16-byte aligned, >= lob_gru_ppo_workspace_bytes(T, m) (LOB_EINVAL otherwise).
  * Deterministic (fixed tiles and summation orders).  An action outside [0, n_actions)
  * counts as action 0. */
-int lob_gru_ppo_fwd_bwd(const float *params, const float *obs, const uint8_t *start, const float *h0,
+int lob_gru_ppo_fwd_bwd(const float *params, const float *obs, const float *obs_scale, const uint8_t *start,
+                        const float *h0,
                         const int32_t *act, const float *logp_old, const float *adv, const float *ret,
                         const float *v_old, int32_t T, int32_t m, int32_t n_actions, float clip, float c_v, float c_e,
                         float *workspace, int64_t workspace_bytes, float *loss, float *grad, void *stream);

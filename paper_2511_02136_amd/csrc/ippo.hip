@@ -186,16 +186,23 @@ __device__ __forceinline__ float tanh_exp(float x) {
 __device__ __forceinline__ int acc_row(int i) { return 4 * ((int)(threadIdx.x & 63) >> 4) + i; }
 __device__ __forceinline__ int acc_col() { return (int)(threadIdx.x & 15); }
 
-/* ---- forward of a tile of R samples (R a multiple of 16, at most 64) into LDS: X,
- * H1 = tanh(X W1 + b1), H2 = tanh(H1 W2 + b2), O = H2 W3 + b3 (O cols 10..15 zero) ---- */
+/* the policy's input scaling of observation feature c (xs null: none) */
+__device__ __forceinline__ float obs_in(const float *__restrict__ obs, const float *__restrict__ xs, int64_t i, int c) {
+    return xs ? obs[i] * xs[c] : obs[i];
+}
+
+/* ---- forward of a tile of R samples (R a multiple of 16, at most 64) into LDS: X (the
+ * observations times the input scales xs, when given), H1 = tanh(X W1 + b1),
+ * H2 = tanh(H1 W2 + b2), O = H2 W3 + b3 (O cols 10..15 zero) ---- */
 template <int R>
-__device__ __forceinline__ void forward_tile(const float *__restrict__ P, const float *__restrict__ obs, int rows,
-                                             float *X, float *H1, float *H2, float *O) {
+__device__ __forceinline__ void forward_tile(const float *__restrict__ P, const float *__restrict__ obs,
+                                             const float *__restrict__ xs, int rows, float *X, float *H1, float *H2,
+                                             float *O) {
     constexpr int MT = R / 16; /* 16-row tiles per wave */
     const int tid = (int)threadIdx.x, wave = tid >> 6;
     for (int i = tid; i < R * XS; i += blockDim.x) {
         const int r = i / XS, c = i % XS;
-        X[i] = (r < rows && c < IN) ? obs[(int64_t)r * IN + c] : 0.f;
+        X[i] = (r < rows && c < IN) ? obs_in(obs, xs, (int64_t)r * IN + c, c) : 0.f;
     }
     __syncthreads();
     /* layer 1: each wave computes R rows x CW cols */
@@ -312,6 +319,7 @@ __device__ __forceinline__ void sample_head(const float *z, int nact, uint64_t s
 struct FwdArgs {
     const float *params; /* [A][NPARAM] */
     const float *obs;    /* [A][n][40] */
+    const float *obs_scale; /* [40] or null */
     int32_t n, n_agents;
     int32_t n_act[LOB_MAX_AGENTS];
     uint64_t seed;
@@ -329,7 +337,7 @@ __global__ void __launch_bounds__(NTH) k_policy_forward(FwdArgs a) {
     const int row0 = (int)blockIdx.x * TRP;
     const int rows = min(TRP, a.n - row0);
     const float *P = a.params + (int64_t)ag * NPARAM;
-    forward_tile<TRP>(P, a.obs + ((int64_t)ag * a.n + row0) * IN, rows, X, H1, H2, O);
+    forward_tile<TRP>(P, a.obs + ((int64_t)ag * a.n + row0) * IN, a.obs_scale, rows, X, H1, H2, O);
     const int tid = (int)threadIdx.x;
     if (tid < rows) {
         const uint64_t seed = a.epoch ? a.seed + 0x9E3779B97F4A7C15ULL * a.epoch[0] : a.seed;
@@ -370,6 +378,7 @@ __global__ void k_gae(const float *__restrict__ r, const float *__restrict__ v, 
 struct PpoArgs {
     const float *params;
     const float *obs;
+    const float *obs_scale; /* [40] or null */
     const int32_t *act;
     const float *logp_old, *adv, *ret, *v_old;
     int32_t m, n_act;
@@ -438,7 +447,7 @@ __device__ __noinline__ void ppo_tile(const PpoArgs &a, const GLOBAL float *Pg, 
         const int row0 = tile * TR;
         const int rows = min(TR, a.m - row0);
         auto put = [&](int i, float v) { G[i] = first ? v : G[i] + v; };
-        forward_tile<TR>(P, (const float *)obs_g + (int64_t)row0 * IN, rows, X, H1, H2, O);
+        forward_tile<TR>(P, (const float *)obs_g + (int64_t)row0 * IN, a.obs_scale, rows, X, H1, H2, O);
 
         /* per-sample loss and its gradient w.r.t. the 10 outputs (scaled by 1/m) */
         float lsum[4] = {0.f, 0.f, 0.f, 0.f};
@@ -751,6 +760,7 @@ __device__ __forceinline__ void gru_head(const float *__restrict__ P, const floa
 struct GruStepArgs {
     const float *params;  /* [A][GNP] */
     const float *obs;     /* [A][n][40] */
+    const float *obs_scale; /* [40] or null */
     const float *h_in;    /* [A][n][128] */
     float *h_out;         /* [A][n][128], may be h_in */
     const uint8_t *start; /* [n] or null: 1 = the episode starts at this step (h_{t-1} = 0) */
@@ -775,7 +785,7 @@ __global__ void __launch_bounds__(GRU_STEP_TH) k_gru_step(GruStepArgs a) {
     const int64_t base = (int64_t)ag * a.n + row0;
     for (int i = tid; i < TG * XS; i += GRU_STEP_TH) {
         const int r = i / XS, c = i % XS;
-        X[i] = (r < rows && c < GIN) ? a.obs[(base + r) * GIN + c] : 0.f;
+        X[i] = (r < rows && c < GIN) ? obs_in(a.obs, a.obs_scale, (base + r) * GIN + c, c) : 0.f;
     }
     for (int i = tid; i < TG * GHD; i += GRU_STEP_TH) {
         const int r = i / GHD, c = i % GHD;
@@ -814,6 +824,7 @@ __global__ void __launch_bounds__(GRU_STEP_TH) k_gru_step(GruStepArgs a) {
  * samples at once. */
 struct GruSeqArgs {
     const float *params, *obs;  /* obs [T][m][40] */
+    const float *obs_scale;     /* [40] or null */
     const uint8_t *start;       /* [T][m] */
     const float *h0;            /* [m][128] */
     const int32_t *act;
@@ -836,7 +847,7 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_seq(GruSeqArgs a) {
     auto stage_x = [&](int t) {
         for (int i = tid; i < TG * XS; i += GRU_SEQ_TH) {
             const int r = i / XS, c = i % XS;
-            X[i] = (r < rows && c < GIN) ? a.obs[((int64_t)t * m + row0 + r) * GIN + c] : 0.f;
+            X[i] = (r < rows && c < GIN) ? obs_in(a.obs, a.obs_scale, ((int64_t)t * m + row0 + r) * GIN + c, c) : 0.f;
         }
     };
     /* forward: h0, then the recurrence; HS[t] is h_{t-1} as stored (before an episode
@@ -994,6 +1005,7 @@ __global__ void k_gru_transpose(const float *__restrict__ P, float *WiT, float *
  * then summed in a fixed order ---- */
 struct GruDwArgs {
     const float *obs;          /* [S][40] */
+    const float *obs_scale;    /* [40] or null */
     const uint8_t *start;      /* [S] */
     const float *HS, *E, *DGI, *DGH, *DE, *DO;
     int64_t S, m;
@@ -1043,7 +1055,8 @@ __global__ void __launch_bounds__(GRU_DW_TH) k_gru_dw(GruDwArgs a) {
         floatx4 acc[1][1];
         if (tt < 24) {
             const int r0 = 16 * (tt / 8), c0 = 16 * (tt % 8);
-            dw_tiles<1>(acc, len, r0, c0, [&](int i, int k) { return i < GIN ? Xb[(int64_t)k * GIN + i] : 0.f; },
+            dw_tiles<1>(acc, len, r0, c0,
+                        [&](int i, int k) { return i < GIN ? obs_in(Xb, a.obs_scale, (int64_t)k * GIN + i, i) : 0.f; },
                         [&](int k, int j) { return DEb[(int64_t)k * GHD + j]; });
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -1154,7 +1167,8 @@ int64_t ppo_workspace_bytes(int32_t m) {
     return (nwg + nch) * PW * 4 + PARAM_COPY_BYTES;
 }
 
-int ppo_launch(const float *params, const float *obs, const int32_t *act, const float *logp_old, const float *adv,
+int ppo_launch(const float *params, const float *obs, const float *obs_scale, const int32_t *act, const float *logp_old,
+               const float *adv,
                const float *ret, const float *v_old, int32_t m, int32_t n_actions, float clip, float c_v, float c_e,
                float *workspace, int64_t workspace_bytes, float *loss, float *grad, void *stream) {
     if (!params || !obs || !act || !logp_old || !adv || !ret || !v_old || !workspace || !loss || !grad)
@@ -1174,7 +1188,8 @@ int ppo_launch(const float *params, const float *obs, const int32_t *act, const 
         params = copy;
     }
     PpoArgs a;
-    a.params = params; a.obs = obs; a.act = act; a.logp_old = logp_old; a.adv = adv; a.ret = ret; a.v_old = v_old;
+    a.params = params; a.obs = obs; a.obs_scale = obs_scale; a.act = act; a.logp_old = logp_old; a.adv = adv;
+    a.ret = ret; a.v_old = v_old;
     a.m = m; a.n_act = n_actions; a.clip = clip; a.c_v = c_v; a.c_e = c_e; a.scale = 1.0f / (float)m;
     a.partial = workspace;
     if (!lds_opt_in()) return LOB_EHIP;
@@ -1219,14 +1234,15 @@ int scratch_ptr(float **out) {
 
 extern "C" {
 
-int lob_policy_forward(const float *params, const float *obs, int32_t n_agents, int32_t n, const int32_t *n_actions,
+int lob_policy_forward(const float *params, const float *obs, const float *obs_scale, int32_t n_agents, int32_t n,
+                       const int32_t *n_actions,
                        uint64_t seed, const uint64_t *epoch, int32_t t, float *logits, int32_t *actions, float *logp,
                        float *value, void *stream) {
     if (!params || !obs || !n_actions || !actions || !logp || !value) return LOB_EINVAL;
     if (n_agents < 1 || n_agents > LOB_MAX_AGENTS || n <= 0) return LOB_EINVAL;
     FwdArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.params = params; a.obs = obs; a.n = n; a.n_agents = n_agents;
+    a.params = params; a.obs = obs; a.obs_scale = obs_scale; a.n = n; a.n_agents = n_agents;
     for (int i = 0; i < n_agents; ++i) {
         if (n_actions[i] < 1 || n_actions[i] > 9) return LOB_EINVAL;
         a.n_act[i] = n_actions[i];
@@ -1238,14 +1254,15 @@ int lob_policy_forward(const float *params, const float *obs, int32_t n_agents, 
     return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
 }
 
-int lob_gru_step(const float *params, const float *obs, const float *h_in, float *h_out, const uint8_t *start,
+int lob_gru_step(const float *params, const float *obs, const float *obs_scale, const float *h_in, float *h_out,
+                 const uint8_t *start,
                  int32_t n_agents, int32_t n, const int32_t *n_actions, uint64_t seed, const uint64_t *epoch, int32_t t,
                  float *logits, int32_t *actions, float *logp, float *value, void *stream) {
     if (!params || !obs || !h_in || !h_out || !n_actions || !actions || !logp || !value) return LOB_EINVAL;
     if (n_agents < 1 || n_agents > LOB_MAX_AGENTS || n <= 0) return LOB_EINVAL;
     GruStepArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.params = params; a.obs = obs; a.h_in = h_in; a.h_out = h_out; a.start = start; a.n = n;
+    a.params = params; a.obs = obs; a.obs_scale = obs_scale; a.h_in = h_in; a.h_out = h_out; a.start = start; a.n = n;
     for (int i = 0; i < n_agents; ++i) {
         if (n_actions[i] < 1 || n_actions[i] > 9) return LOB_EINVAL;
         a.n_act[i] = n_actions[i];
@@ -1262,7 +1279,8 @@ int64_t lob_gru_ppo_workspace_bytes(int32_t T, int32_t m) {
     return gru_ws(T, m).total * 4;
 }
 
-int lob_gru_ppo_fwd_bwd(const float *params, const float *obs, const uint8_t *start, const float *h0,
+int lob_gru_ppo_fwd_bwd(const float *params, const float *obs, const float *obs_scale, const uint8_t *start,
+                        const float *h0,
                         const int32_t *act, const float *logp_old, const float *adv, const float *ret,
                         const float *v_old, int32_t T, int32_t m, int32_t n_actions, float clip, float c_v, float c_e,
                         float *workspace, int64_t workspace_bytes, float *loss, float *grad, void *stream) {
@@ -1277,14 +1295,14 @@ int lob_gru_ppo_fwd_bwd(const float *params, const float *obs, const uint8_t *st
     float *ws = workspace;
     hipLaunchKernelGGL(k_gru_transpose, dim3((GHD * G3 + 255) / 256), dim3(256), 0, st, params, ws + w.wit, ws + w.wht);
     GruSeqArgs a;
-    a.params = params; a.obs = obs; a.start = start; a.h0 = h0; a.act = act; a.logp_old = logp_old; a.adv = adv;
+    a.params = params; a.obs = obs; a.obs_scale = obs_scale; a.start = start; a.h0 = h0; a.act = act; a.logp_old = logp_old; a.adv = adv;
     a.ret = ret; a.v_old = v_old; a.T = T; a.m = m; a.n_act = n_actions; a.clip = clip; a.c_v = c_v; a.c_e = c_e;
     a.scale = 1.0f / (float)((int64_t)T * m);
     a.HS = ws + w.hs; a.E = ws + w.e; a.DGI = ws + w.dgi; a.DGH = ws + w.dgh; a.DE = ws + w.de; a.DO = ws + w.dout;
     a.LS = ws + w.ls; a.WiT = ws + w.wit; a.WhT = ws + w.wht;
     hipLaunchKernelGGL(k_gru_seq, dim3((unsigned)w.ntile), dim3(GRU_SEQ_TH), GRU_SEQ_LDS * 4, st, a);
     GruDwArgs d;
-    d.obs = obs; d.start = start; d.HS = a.HS; d.E = a.E; d.DGI = a.DGI; d.DGH = a.DGH; d.DE = a.DE; d.DO = a.DO;
+    d.obs = obs; d.obs_scale = obs_scale; d.start = start; d.HS = a.HS; d.E = a.E; d.DGI = a.DGI; d.DGH = a.DGH; d.DE = a.DE; d.DO = a.DO;
     d.S = (int64_t)T * m; d.m = m; d.partial = ws + w.part;
     hipLaunchKernelGGL(k_gru_dw, dim3((unsigned)w.nwg), dim3(GRU_DW_TH), 0, st, d);
     hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((GPW / 4 + 255) / 256), (unsigned)w.nch), dim3(256), 0, st,
@@ -1314,15 +1332,17 @@ int64_t lob_ppo_workspace_bytes(int32_t m) {
     return ppo_workspace_bytes(m);
 }
 
-int lob_ppo_fwd_bwd(const float *params, const float *obs, const int32_t *act, const float *logp_old,
+int lob_ppo_fwd_bwd(const float *params, const float *obs, const float *obs_scale, const int32_t *act,
+                    const float *logp_old,
                     const float *adv, const float *ret, const float *v_old, int32_t m, int32_t n_actions, float clip,
                     float c_v, float c_e, float *workspace, int64_t workspace_bytes, float *loss, float *grad,
                     void *stream) {
-    return ppo_launch(params, obs, act, logp_old, adv, ret, v_old, m, n_actions, clip, c_v, c_e, workspace,
+    return ppo_launch(params, obs, obs_scale, act, logp_old, adv, ret, v_old, m, n_actions, clip, c_v, c_e, workspace,
                       workspace_bytes, loss, grad, stream);
 }
 
-int lob_ppo_fwd_bwd_noalloc(const float *params, const float *obs, const int32_t *act, const float *logp_old,
+int lob_ppo_fwd_bwd_noalloc(const float *params, const float *obs, const float *obs_scale, const int32_t *act,
+                            const float *logp_old,
                             const float *adv, const float *ret, const float *v_old, int32_t m, int32_t n_actions,
                             float clip, float c_v, float c_e, float *loss, float *grad, void *stream) {
     /* argument checks before any device call */
@@ -1332,7 +1352,7 @@ int lob_ppo_fwd_bwd_noalloc(const float *params, const float *obs, const int32_t
     float *ws = nullptr;
     const int rc = scratch_ptr(&ws);
     if (rc != LOB_OK) return rc;
-    return ppo_launch(params, obs, act, logp_old, adv, ret, v_old, m, n_actions, clip, c_v, c_e, ws,
+    return ppo_launch(params, obs, obs_scale, act, logp_old, adv, ret, v_old, m, n_actions, clip, c_v, c_e, ws,
                       PPO_SCRATCH_BYTES, loss, grad, stream);
 }
 

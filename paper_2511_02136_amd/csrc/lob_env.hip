@@ -47,6 +47,7 @@
 namespace lobk {
 
 constexpr int MAXA = LOB_MAX_AGENTS;
+constexpr int FIND_ROWS = 4; /* rows an order-id search loads per LDS round trip */
 
 /* agent kinds by role: execution tasks (a sell task with a remainder), market makers
  * rewarded by Eq. 3 (Spooner) */
@@ -300,11 +301,22 @@ struct Run {
      * this is the first order with that id in priority order */
     template <int S> __device__ __forceinline__ int find_top(int f, int hi, int v) {
         const int32_t *col = reinterpret_cast<const int32_t *>(RS<S>(0)) + f;
-        for (int r = hi >> 6; r >= 0; --r) {
-            const int j = (r << 6) + lane;
-            const int x = col[min(j, hi) * (2 * REC)];
-            const uint64_t m = lanes_eq(x, v) & lanes_le(j, hi);
-            if (m) return (r << 6) + 63 - __builtin_clzll(m);
+        /* FIND_ROWS rows per LDS round trip (their loads are issued together): a cancel
+         * whose order is gone (a quarter of the replayed messages) searches every row */
+        for (int r = hi >> 6; r >= 0; r -= FIND_ROWS) {
+            int x[FIND_ROWS];
+#pragma unroll
+            for (int k = 0; k < FIND_ROWS; ++k) {
+                const int j = (max(r - k, 0) << 6) + lane;
+                x[k] = col[min(j, hi) * (2 * REC)];
+            }
+#pragma unroll
+            for (int k = 0; k < FIND_ROWS; ++k) {
+                if (r - k < 0) return -1;
+                const int j = ((r - k) << 6) + lane;
+                const uint64_t m = lanes_eq(x[k], v) & lanes_le(j, hi);
+                if (m) return ((r - k) << 6) + 63 - __builtin_clzll(m);
+            }
         }
         return -1;
     }
@@ -1344,7 +1356,7 @@ __global__ void __launch_bounds__(256) k_import(ImportArgs a) {
     }
 }
 
-/* Holds its stream for `ticks` of the 100 MHz real-time clock (one wave, sleeping
+/* Holds its stream for `ticks` of the constant-rate wall clock (one wave, sleeping
  * between reads: the wait is bounded by the clock). */
 __global__ void k_hold(int64_t ticks) {
     const int64_t t0 = (int64_t)wall_clock64();
@@ -1375,8 +1387,8 @@ struct CapClass {
 
 constexpr int MAX_CLASSES = LOB_MAX_CAP / 64; /* one class per row count */
 constexpr size_t LDS_PER_CU = 160 * 1024;  /* gfx950 */
-constexpr int64_t LANE_GAP = 5000;      /* 50 us of the 100 MHz clock between class starts */
-constexpr int64_t LANE_GAP_STEP = 1000; /* 10 us between class starts in a one-step launch */
+constexpr int64_t LANE_GAP_US = 50;      /* between class starts in a rollout */
+constexpr int64_t LANE_GAP_STEP_US = 10; /* between class starts in a one-step launch */
 constexpr int CONC_LANES = 3;               /* concurrent class launches (see launch_env) */
 constexpr int WAVES_PER_CU = 24;            /* 6 per SIMD at the env kernel's register use */
 constexpr int BALANCE_DEFAULT = 880;        /* permille of the LDS (measured best on uneven books) */
@@ -1403,6 +1415,7 @@ struct lob_ctx {
     int plan_t0 = -1, plan_steps = -1, plan_rows = -1;
     int device = 0;
     int n_cu = 256;
+    int64_t ticks_per_us = 100; /* of the device's wall clock (its rate is read at init) */
     int t = 0;
     bool reset_done = false;
     bool padded = false;
@@ -1552,14 +1565,14 @@ int launch_env(lob_ctx *c, KArgs a, hipStream_t st) {
             break;
         }
         forked = l + 1;
-        /* The classes start one after another, largest books first, LANE_GAP apart (a
-         * single step: LANE_GAP_STEP, which it pays every step): started at the same
+        /* The classes start one after another, largest books first, LANE_GAP_US apart (a
+         * single step: LANE_GAP_STEP_US, which it pays every step): started at the same
          * instant, the workgroups of two classes interleave differently from run to run,
          * and one of them could be left slower than planned for the whole launch (3 us
          * apart still did; smallest books first took twice as long: the large workgroups
          * then find no room). */
         hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, c->streams[l],
-                           (int64_t)((a.n_steps > 1 ? LANE_GAP : LANE_GAP_STEP) * l));
+                           (int64_t)((a.n_steps > 1 ? LANE_GAP_US : LANE_GAP_STEP_US) * c->ticks_per_us * l));
         if (hipGetLastError() != hipSuccess) rc = LOB_EHIP;
     }
     for (int i = 0; i < nc && rc == LOB_OK; ++i) {
@@ -1778,6 +1791,11 @@ int lob_init(const lob_config *cfg, lob_ctx **out) {
     if (!hip_ok(hipGetDevice(&c->device))) { delete c; return LOB_EHIP; }
     hipDeviceProp_t prop;
     if (hip_ok(hipGetDeviceProperties(&prop, c->device))) c->n_cu = prop.multiProcessorCount;
+    /* the wall clock's rate differs between boxes (100 MHz on some, 30 MHz on others): the
+     * class-start gaps are set in microseconds */
+    int wall_khz = 0;
+    if (hip_ok(hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, c->device)) && wall_khz >= 1000)
+        c->ticks_per_us = wall_khz / 1000;
 
     const int64_t N = cfg->n_envs, A = cfg->n_agents;
     const size_t slots = (size_t)N * 2 * cfg->max_cap;

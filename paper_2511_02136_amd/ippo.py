@@ -27,7 +27,7 @@ def _lib():
     L = lib()
     if not _ready:
         p, i32, i64, f32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_uint64
-        L.lob_policy_forward.argtypes = [p, p, i32, i32, p, u64, p, i32, p, p, p, p, p]
+        L.lob_policy_forward.argtypes = [p, p, p, i32, i32, p, u64, p, i32, p, p, p, p, p]
         L.lob_counter_bump.argtypes = [p, p]
         L.lob_counter_bump.restype = ctypes.c_int
         L.lob_policy_forward.restype = ctypes.c_int
@@ -35,15 +35,15 @@ def _lib():
         L.lob_gae.restype = ctypes.c_int
         L.lob_ppo_workspace_bytes.argtypes = [i32]
         L.lob_ppo_workspace_bytes.restype = i64
-        L.lob_ppo_fwd_bwd.argtypes = [p, p, p, p, p, p, p, i32, i32, f32, f32, f32, p, i64, p, p, p]
+        L.lob_ppo_fwd_bwd.argtypes = [p, p, p, p, p, p, p, p, i32, i32, f32, f32, f32, p, i64, p, p, p]
         L.lob_ppo_fwd_bwd.restype = ctypes.c_int
-        L.lob_ppo_fwd_bwd_noalloc.argtypes = [p, p, p, p, p, p, p, i32, i32, f32, f32, f32, p, p, p]
+        L.lob_ppo_fwd_bwd_noalloc.argtypes = [p, p, p, p, p, p, p, p, i32, i32, f32, f32, f32, p, p, p]
         L.lob_ppo_fwd_bwd_noalloc.restype = ctypes.c_int
-        L.lob_gru_step.argtypes = [p, p, p, p, p, i32, i32, p, u64, p, i32, p, p, p, p, p]
+        L.lob_gru_step.argtypes = [p, p, p, p, p, p, i32, i32, p, u64, p, i32, p, p, p, p, p]
         L.lob_gru_step.restype = ctypes.c_int
         L.lob_gru_ppo_workspace_bytes.argtypes = [i32, i32]
         L.lob_gru_ppo_workspace_bytes.restype = i64
-        L.lob_gru_ppo_fwd_bwd.argtypes = [p, p, p, p, p, p, p, p, p, i32, i32, i32, f32, f32, f32, p, i64, p, p, p]
+        L.lob_gru_ppo_fwd_bwd.argtypes = [p, p, p, p, p, p, p, p, p, p, i32, i32, i32, f32, f32, f32, p, i64, p, p, p]
         L.lob_gru_ppo_fwd_bwd.restype = ctypes.c_int
         _ready = True
     return L
@@ -76,9 +76,15 @@ def counter_bump(counter: torch.Tensor):
     _check(_lib().lob_counter_bump(_p(counter), _stream()), "lob_counter_bump")
 
 
+def _scale(obs_scale):
+    return None if obs_scale is None else _f32(obs_scale)
+
+
 def policy_forward(params: torch.Tensor, obs: torch.Tensor, n_actions: Sequence[int], seed: int, t: int,
-                   want_logits: bool = False, epoch: torch.Tensor = None, out: dict = None) -> dict:
-    """params [A, N_PARAMS], obs [A, n, 40] (float32, device) -> actions, logp, value [A, n]."""
+                   want_logits: bool = False, epoch: torch.Tensor = None, out: dict = None,
+                   obs_scale: torch.Tensor = None) -> dict:
+    """params [A, N_PARAMS], obs [A, n, 40] (float32, device; scaled by obs_scale [40]
+    in the kernel when given) -> actions, logp, value [A, n]."""
     A, n = obs.shape[0], obs.shape[1]
     dev = obs.device
     if out is None:
@@ -87,7 +93,8 @@ def policy_forward(params: torch.Tensor, obs: torch.Tensor, n_actions: Sequence[
                "value": torch.empty((A, n), dtype=torch.float32, device=dev),
                "logits": torch.empty((A, n, 10), dtype=torch.float32, device=dev) if want_logits else None}
     na = (ctypes.c_int32 * A)(*[int(x) for x in n_actions])
-    _check(_lib().lob_policy_forward(_p(_f32(params)), _p(_f32(obs)), A, n, na, seed, _p(epoch), t,
+    _check(_lib().lob_policy_forward(_p(_f32(params)), _p(_f32(obs)), _p(_scale(obs_scale)), A, n, na, seed,
+                                     _p(epoch), t,
                                      _p(out.get("logits")), _p(out["actions"]), _p(out["logp"]), _p(out["value"]),
                                      _stream()), "lob_policy_forward")
     return out
@@ -111,7 +118,7 @@ def workspace_bytes(m: int) -> int:
 
 
 def ppo_fwd_bwd(params, obs, act, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01,
-                workspace=None):
+                workspace=None, obs_scale=None):
     """Loss sums [4] (total, policy, value, entropy) and the gradient of the mean loss."""
     m = obs.shape[0]
     L = _lib()
@@ -120,7 +127,8 @@ def ppo_fwd_bwd(params, obs, act, logp_old, adv, ret, v_old, n_actions, clip=0.2
         workspace = torch.empty((need + 3) // 4, dtype=torch.float32, device=obs.device)
     loss = torch.empty(4, dtype=torch.float32, device=obs.device)
     grad = torch.empty(N_PARAMS, dtype=torch.float32, device=obs.device)
-    _check(L.lob_ppo_fwd_bwd(_p(_f32(params)), _p(_f32(obs)), _p(act.to(torch.int32).contiguous()),
+    _check(L.lob_ppo_fwd_bwd(_p(_f32(params)), _p(_f32(obs)), _p(_scale(obs_scale)),
+                             _p(act.to(torch.int32).contiguous()),
                              _p(_f32(logp_old)), _p(_f32(adv)), _p(_f32(ret)), _p(_f32(v_old)), m, int(n_actions),
                              clip, c_v, c_e, _p(workspace), workspace.numel() * 4, _p(loss), _p(grad), _stream()),
            "lob_ppo_fwd_bwd")
@@ -128,11 +136,12 @@ def ppo_fwd_bwd(params, obs, act, logp_old, adv, ret, v_old, n_actions, clip=0.2
 
 
 def ppo_fwd_bwd_noalloc(params, obs, act, logp_old, adv, ret, v_old, n_actions, loss, grad, clip=0.2, c_v=0.5,
-                        c_e=0.01):
+                        c_e=0.01, obs_scale=None):
     """As ppo_fwd_bwd into caller-given loss [4] and grad [N_PARAMS] (float32, device),
     with the library's fixed scratch instead of a workspace: the call allocates nothing."""
     m = obs.shape[0]
-    _check(_lib().lob_ppo_fwd_bwd_noalloc(_p(_f32(params)), _p(_f32(obs)), _p(act), _p(_f32(logp_old)),
+    _check(_lib().lob_ppo_fwd_bwd_noalloc(_p(_f32(params)), _p(_f32(obs)), _p(_scale(obs_scale)), _p(act),
+                                          _p(_f32(logp_old)),
                                           _p(_f32(adv)), _p(_f32(ret)), _p(_f32(v_old)), m, int(n_actions), clip, c_v,
                                           c_e, _p(_f32(loss)), _p(_f32(grad)), _stream()),
            "lob_ppo_fwd_bwd_noalloc")
@@ -158,7 +167,7 @@ def gru_init_params(n_agents: int, seed: int, device="cuda") -> torch.Tensor:
 
 def gru_step(params: torch.Tensor, obs: torch.Tensor, h: torch.Tensor, n_actions: Sequence[int], seed: int, t: int,
              start: torch.Tensor = None, h_out: torch.Tensor = None, want_logits: bool = False,
-             epoch: torch.Tensor = None, out: dict = None) -> dict:
+             epoch: torch.Tensor = None, out: dict = None, obs_scale: torch.Tensor = None) -> dict:
     """One recurrent policy step: params [A, GRU_PARAMS], obs [A, n, 40], h [A, n, 128]
     (float32, device), start [n] uint8 or None -> actions, logp, value [A, n] and the new
     state in out["h"] (h_out, or h itself: updated in place)."""
@@ -171,7 +180,7 @@ def gru_step(params: torch.Tensor, obs: torch.Tensor, h: torch.Tensor, n_actions
                "logits": torch.empty((A, n, 10), dtype=torch.float32, device=dev) if want_logits else None}
     ho = h if h_out is None else h_out
     na = (ctypes.c_int32 * A)(*[int(x) for x in n_actions])
-    _check(_lib().lob_gru_step(_p(_f32(params)), _p(_f32(obs)), _p(_f32(h)), _p(_f32(ho)),
+    _check(_lib().lob_gru_step(_p(_f32(params)), _p(_f32(obs)), _p(_scale(obs_scale)), _p(_f32(h)), _p(_f32(ho)),
                                _p(None if start is None else start.to(torch.uint8).contiguous()), A, n, na, seed,
                                _p(epoch), t, _p(out.get("logits")), _p(out["actions"]), _p(out["logp"]),
                                _p(out["value"]), _stream()), "lob_gru_step")
@@ -184,7 +193,7 @@ def gru_workspace_bytes(T: int, m: int) -> int:
 
 
 def gru_ppo_fwd_bwd(params, obs, start, h0, act, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01,
-                    workspace=None):
+                    workspace=None, obs_scale=None):
     """Loss sums [4] and the gradient of the mean loss of m sequences of T steps:
     obs [T, m, 40], start [T, m] uint8, h0 [m, 128], act/logp_old/adv/ret/v_old [T, m]."""
     T, m = obs.shape[0], obs.shape[1]
@@ -194,7 +203,8 @@ def gru_ppo_fwd_bwd(params, obs, start, h0, act, logp_old, adv, ret, v_old, n_ac
         workspace = torch.empty((need + 3) // 4, dtype=torch.float32, device=obs.device)
     loss = torch.empty(4, dtype=torch.float32, device=obs.device)
     grad = torch.empty(GRU_PARAMS, dtype=torch.float32, device=obs.device)
-    _check(L.lob_gru_ppo_fwd_bwd(_p(_f32(params)), _p(_f32(obs)), _p(start.to(torch.uint8).contiguous()),
+    _check(L.lob_gru_ppo_fwd_bwd(_p(_f32(params)), _p(_f32(obs)), _p(_scale(obs_scale)),
+                                 _p(start.to(torch.uint8).contiguous()),
                                  _p(_f32(h0)), _p(act.to(torch.int32).contiguous()), _p(_f32(logp_old)),
                                  _p(_f32(adv)), _p(_f32(ret)), _p(_f32(v_old)), T, m, int(n_actions), clip, c_v, c_e,
                                  _p(workspace), workspace.numel() * 4, _p(loss), _p(grad), _stream()),
@@ -209,16 +219,17 @@ class FusedGruPPOLoss(torch.autograd.Function):
     gradient; backward scales it by the incoming gradient."""
 
     @staticmethod
-    def forward(ctx, params, obs, start, h0, act, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01):
+    def forward(ctx, params, obs, start, h0, act, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01,
+                obs_scale=None):
         loss, grad = gru_ppo_fwd_bwd(params.detach().contiguous(), obs, start, h0, act, logp_old, adv, ret, v_old,
-                                     n_actions, clip, c_v, c_e)
+                                     n_actions, clip, c_v, c_e, obs_scale=obs_scale)
         ctx.save_for_backward(grad)
         return loss[0] / (obs.shape[0] * obs.shape[1])
 
     @staticmethod
     def backward(ctx, g):
         (grad,) = ctx.saved_tensors
-        return (g * grad,) + (None,) * 12
+        return (g * grad,) + (None,) * 13
 
 
 class FusedPPOLoss(torch.autograd.Function):
@@ -227,13 +238,14 @@ class FusedPPOLoss(torch.autograd.Function):
     scales that gradient by the incoming gradient."""
 
     @staticmethod
-    def forward(ctx, params, obs, act, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01):
+    def forward(ctx, params, obs, act, logp_old, adv, ret, v_old, n_actions, clip=0.2, c_v=0.5, c_e=0.01,
+                obs_scale=None):
         loss, grad = ppo_fwd_bwd(params.detach().contiguous(), obs, act, logp_old, adv, ret, v_old, n_actions,
-                                 clip, c_v, c_e)
+                                 clip, c_v, c_e, obs_scale=obs_scale)
         ctx.save_for_backward(grad)
         return loss[0] / obs.shape[0]
 
     @staticmethod
     def backward(ctx, g):
         (grad,) = ctx.saved_tensors
-        return (g * grad,) + (None,) * 10
+        return (g * grad,) + (None,) * 11

@@ -44,13 +44,16 @@ class IppoTrainer:
         init = ippo.xavier_params if network == "mlp" else ippo.gru_init_params
         self.params = torch.nn.Parameter(init(self.A, param_seed, device=dev))
         self.opt = torch.optim.Adam([self.params], lr=lr)
+        # the policy's input scaling, applied inside the policy and loss kernels
         self.inv_scale = (1.0 / torch.tensor(OBS_SCALE, dtype=torch.float32)).to(dev)
         T, A, N = n_steps, self.A, self.N
+        # raw observations: [0] from the reset, [t + 1] written by the env step t itself
         self.obs = torch.empty((T + 1, A, N, 40), dtype=torch.float32, device=dev)
         self.pol = {"actions": torch.empty((T, A, N), dtype=torch.int32, device=dev),
                     "logp": torch.empty((T, A, N), dtype=torch.float32, device=dev),
                     "value": torch.empty((T, A, N), dtype=torch.float32, device=dev)}
-        self.out = env._alloc_out(T, True, record_trades, None, dstream, actions_out=False)
+        self.out = env._alloc_out(T, False, record_trades, None, dstream, actions_out=False)
+        self.out["obs"] = self.obs[1:]
         self.cursor = torch.zeros(N, dtype=torch.int64, device=dev)
         self.epoch = torch.zeros(1, dtype=torch.int64, device=dev)
         # recurrent state of the GRU policy during the rollout (zero at the episode start)
@@ -63,21 +66,20 @@ class IppoTrainer:
         ippo.counter_bump(self.epoch)
         env.reset(self.book)
         self.cursor.zero_()
-        torch.mul(env.observe(), self.inv_scale, out=self.obs[0])
+        self.obs[0].copy_(env.observe())
         if self.h is not None:
             self.h.zero_()
         for t in range(T):
             pf = {k: v[t] for k, v in self.pol.items()}
             if self.h is None:
                 ippo.policy_forward(self.params.detach(), self.obs[t], self.n_act, self.seed, t, epoch=self.epoch,
-                                    out=pf)
+                                    out=pf, obs_scale=self.inv_scale)
             else:
                 ippo.gru_step(self.params.detach(), self.obs[t], self.h, self.n_act, self.seed, t, epoch=self.epoch,
-                              out=pf)
+                              out=pf, obs_scale=self.inv_scale)
             view = {k: (v[t:t + 1] if k not in ("trades", "trade_off") and v is not None else v)
                     for k, v in self.out.items()}
             env.step(self.ds, pf["actions"], out=view, cursor=self.cursor)
-            torch.mul(view["obs"][0], self.inv_scale, out=self.obs[t + 1])
 
     def rollout(self, use_graph: bool = False):
         """Reset and run T steps with the current policy; results stay in the buffers."""
@@ -126,7 +128,7 @@ class IppoTrainer:
                     rt = ret[:, a].reshape(M)[idx].contiguous()
                     vo = self.pol["value"][:, a].reshape(M)[idx].contiguous()
                     loss = ippo.FusedPPOLoss.apply(self.params[a], obs, act, lpo, ad, rt, vo, self.n_act[a],
-                                                   self.clip, self.c_v, self.c_e)
+                                                   self.clip, self.c_v, self.c_e, self.inv_scale)
                     total = total + loss
                 total.backward()
                 self.opt.step()
@@ -158,7 +160,7 @@ class IppoTrainer:
                     rt = ret[:, a][:, idx].contiguous()
                     vo = self.pol["value"][:, a][:, idx].contiguous()
                     loss = ippo.FusedGruPPOLoss.apply(self.params[a], obs, start, h0, act, lpo, ad, rt, vo,
-                                                      self.n_act[a], self.clip, self.c_v, self.c_e)
+                                                      self.n_act[a], self.clip, self.c_v, self.c_e, self.inv_scale)
                     total = total + loss
                 total.backward()
                 self.opt.step()

@@ -68,13 +68,15 @@ def test_host_side_checks_of_the_actor_critic():
     assert lib.lob_ppo_workspace_bytes(64 * 100 + 1) == (101 + 2) * pw + copy
     assert lib.lob_ppo_workspace_bytes(131072) == (256 + 4) * pw + copy
     assert lib.lob_ppo_workspace_bytes(1 << 30) == (256 + 4) * pw + copy
-    lib.lob_ppo_fwd_bwd.argtypes = [p] * 7 + [i32, i32, f32, f32, f32, p, ctypes.c_int64, p, p, p]
+    lib.lob_ppo_fwd_bwd.argtypes = [p] * 8 + [i32, i32, f32, f32, f32, p, ctypes.c_int64, p, p, p]
     d = [p(0x1000 + 16 * k) for k in range(7)]
     ws, big = p(0x20000), 1 << 40
 
     def call(m=64, n_act=9, clip=0.2, w=ws, wb=big, ptrs=d):
-        return lib.lob_ppo_fwd_bwd(*ptrs, m, n_act, clip, 0.5, 0.01, w, wb, p(0x3000), p(0x4000), None)
-    assert lib.lob_ppo_fwd_bwd(*([None] * 7), 64, 9, 0.2, 0.5, 0.01, None, 0, None, None, None) == -1
+        # the observation scale (third argument) is optional
+        return lib.lob_ppo_fwd_bwd(*ptrs[:2], None, *ptrs[2:], m, n_act, clip, 0.5, 0.01, w, wb, p(0x3000), p(0x4000),
+                                   None)
+    assert lib.lob_ppo_fwd_bwd(*([None] * 8), 64, 9, 0.2, 0.5, 0.01, None, 0, None, None, None) == -1
     assert call(ptrs=[None] + d[1:]) == -1
     assert call(m=0) == -1 and call(n_act=0) == -1 and call(n_act=10) == -1 and call(clip=0.0) == -1
     assert call(wb=lib.lob_ppo_workspace_bytes(64) - 1) == -1   # too small
@@ -83,13 +85,13 @@ def test_host_side_checks_of_the_actor_critic():
     assert lib.lob_gae(None, None, None, None, 4, 4, 0.99, 0.95, None, None, None) == -1
     assert lib.lob_gae(*d[:4], 0, 4, 0.99, 0.95, d[4], d[5], None) == -1
     assert lib.lob_gae(*d[:4], 4, 0, 0.99, 0.95, d[4], d[5], None) == -1
-    lib.lob_policy_forward.argtypes = [p, p, i32, i32, p, ctypes.c_uint64, p, i32, p, p, p, p, p]
-    assert lib.lob_policy_forward(None, None, 1, 8, None, 0, None, 0, None, None, None, None, None) == -1
+    lib.lob_policy_forward.argtypes = [p, p, p, i32, i32, p, ctypes.c_uint64, p, i32, p, p, p, p, p]
+    assert lib.lob_policy_forward(None, None, None, 1, 8, None, 0, None, 0, None, None, None, None, None) == -1
     n_act = (i32 * 2)(9, 9)
-    assert lib.lob_policy_forward(d[0], d[1], 0, 8, n_act, 0, None, 0, None, d[2], d[3], d[4], None) == -1
-    assert lib.lob_policy_forward(d[0], d[1], 2, 0, n_act, 0, None, 0, None, d[2], d[3], d[4], None) == -1
+    assert lib.lob_policy_forward(d[0], d[1], None, 0, 8, n_act, 0, None, 0, None, d[2], d[3], d[4], None) == -1
+    assert lib.lob_policy_forward(d[0], d[1], None, 2, 0, n_act, 0, None, 0, None, d[2], d[3], d[4], None) == -1
     bad = (i32 * 2)(9, 10)
-    assert lib.lob_policy_forward(d[0], d[1], 2, 8, bad, 0, None, 0, None, d[2], d[3], d[4], None) == -1
+    assert lib.lob_policy_forward(d[0], d[1], None, 2, 8, bad, 0, None, 0, None, d[2], d[3], d[4], None) == -1
     lib.lob_counter_bump.argtypes = [p, p]
     assert lib.lob_counter_bump(None, None) == -1
 
@@ -110,11 +112,50 @@ def test_host_side_checks_of_the_noalloc_ppo_call():
     (its fixed scratch is resolved only after the checks)."""
     lib = ctypes.CDLL(LIB)
     p, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
-    lib.lob_ppo_fwd_bwd_noalloc.argtypes = [p, p, p, p, p, p, p, i32, i32, f32, f32, f32, p, p, p]
-    assert lib.lob_ppo_fwd_bwd_noalloc(None, None, None, None, None, None, None, 64, 9, 0.2, 0.5, 0.01,
+    lib.lob_ppo_fwd_bwd_noalloc.argtypes = [p, p, p, p, p, p, p, p, i32, i32, f32, f32, f32, p, p, p]
+    assert lib.lob_ppo_fwd_bwd_noalloc(None, None, None, None, None, None, None, None, 64, 9, 0.2, 0.5, 0.01,
                                        None, None, None) == -1
     fake = ctypes.c_void_p(16)  # never dereferenced: a size check fails first
-    args = [fake] * 7
+    args = [fake, fake, None] + [fake] * 5
     assert lib.lob_ppo_fwd_bwd_noalloc(*args, 0, 9, 0.2, 0.5, 0.01, fake, fake, None) == -1
     assert lib.lob_ppo_fwd_bwd_noalloc(*args, 64, 10, 0.2, 0.5, 0.01, fake, fake, None) == -1
     assert lib.lob_ppo_fwd_bwd_noalloc(*args, 64, 9, 0.0, 0.5, 0.01, fake, fake, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblob.so not built")
+def test_host_side_checks_of_the_recurrent_actor_critic():
+    """Workspace size of the recurrent loss (per sample: hidden state, embedding, gate,
+    embedding and output gradients = 128 + 128 + 384 + 384 + 128 + 16 floats; one more
+    hidden state per sequence; loss sums per 16-sequence tile; the two transposed weight
+    matrices; weight-gradient partials of 105,612 floats for one workgroup per 64
+    samples, at most 256, and the first reduction level's chunk sums) and argument
+    checks before any device call."""
+    lib = ctypes.CDLL(LIB)
+    p, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
+    lib.lob_gru_ppo_workspace_bytes.argtypes = [i32, i32]
+    lib.lob_gru_ppo_workspace_bytes.restype = ctypes.c_int64
+
+    def expect(T, m):
+        S = T * m
+        nwg = min(256, (S + 63) // 64)
+        nch = (nwg + 63) // 64
+        return 4 * ((T + 1) * m * 128 + S * (128 + 384 + 384 + 128 + 16) + ((m + 15) // 16) * 4 + 2 * 128 * 384
+                    + (nwg + nch) * 105612)
+    assert lib.lob_gru_ppo_workspace_bytes(0, 5) == -1 and lib.lob_gru_ppo_workspace_bytes(5, 0) == -1
+    for T, m in ((1, 1), (8, 20), (128, 1024)):
+        assert lib.lob_gru_ppo_workspace_bytes(T, m) == expect(T, m), (T, m)
+    lib.lob_gru_ppo_fwd_bwd.argtypes = [p] * 10 + [i32, i32, i32, f32, f32, f32, p, ctypes.c_int64, p, p, p]
+    d = [p(0x1000 + 16 * k) for k in range(10)]
+    d[2] = None  # the observation scale is optional
+
+    def call(T=8, m=20, n_act=9, clip=0.2, w=p(0x40000), wb=1 << 40, ptrs=d):
+        return lib.lob_gru_ppo_fwd_bwd(*ptrs, T, m, n_act, clip, 0.5, 0.01, w, wb, p(0x3000), p(0x4000), None)
+    assert call(ptrs=[None] + d[1:]) == -1
+    assert call(T=0) == -1 and call(m=0) == -1 and call(n_act=10) == -1 and call(clip=0.0) == -1
+    assert call(wb=lib.lob_gru_ppo_workspace_bytes(8, 20) - 1) == -1
+    assert call(w=p(0x40008)) == -1
+    lib.lob_gru_step.argtypes = [p] * 6 + [i32, i32, p, ctypes.c_uint64, p, i32, p, p, p, p, p]
+    n_act = (i32 * 2)(9, 3)
+    assert lib.lob_gru_step(None, *d[1:6], 2, 8, n_act, 0, None, 0, None, d[6], d[7], d[8], None) == -1
+    assert lib.lob_gru_step(*d[:6], 0, 8, n_act, 0, None, 0, None, d[6], d[7], d[8], None) == -1
+    assert lib.lob_gru_step(*d[:6], 2, 0, n_act, 0, None, 0, None, d[6], d[7], d[8], None) == -1

@@ -216,3 +216,23 @@ def test_gru_trainer_rollout_parity_and_update():
     torch.cuda.synchronize()
     assert np.isfinite(st["loss"]) and st["minibatches"] == tr.epochs * tr.minibatches
     assert not torch.equal(before, tr.params.detach()) and torch.isfinite(tr.params).all()
+
+
+def test_gru_observation_scale_inside_the_kernels():
+    ippo = _ippo()
+    rng = np.random.default_rng(43)
+    P = gru_params(43)[0]
+    b = list(_seq_batch(rng, 6, 20, P.astype(np.float64), 9))
+    sc = rng.uniform(0.01, 0.5, size=40).astype(np.float32)
+    raw = (b[0] / sc).astype(np.float32)
+    dev_s = [torch.from_numpy(np.ascontiguousarray(v)).cuda() for v in [P] + b]
+    scaled = (torch.from_numpy(raw).cuda() * torch.from_numpy(sc).cuda()).contiguous()
+    la, ga = ippo.gru_ppo_fwd_bwd(dev_s[0], torch.from_numpy(raw).cuda(), *dev_s[2:], 9,
+                                  obs_scale=torch.from_numpy(sc).cuda())
+    lb, gb = ippo.gru_ppo_fwd_bwd(dev_s[0], scaled, *dev_s[2:], 9)
+    assert torch.equal(la, lb) and torch.equal(ga, gb)
+    h = torch.zeros((1, 20, 128), device="cuda")
+    sa = ippo.gru_step(dev_s[0][None], torch.from_numpy(raw[0][None]).cuda(), h, [9], seed=1, t=0,
+                       h_out=torch.empty_like(h), obs_scale=torch.from_numpy(sc).cuda())
+    sb = ippo.gru_step(dev_s[0][None], scaled[0][None].contiguous(), h, [9], seed=1, t=0, h_out=torch.empty_like(h))
+    assert torch.equal(sa["h"], sb["h"]) and torch.equal(sa["actions"], sb["actions"])

@@ -207,3 +207,26 @@ def test_full_size_minibatch_gradient(m):
     assert abs(float(loss[0]) / m - ref_loss) <= 2e-5 * (abs(ref_loss) + 1e-3)
     err = np.linalg.norm(grad.cpu().numpy().astype(np.float64) - ref_grad) / np.linalg.norm(ref_grad)
     assert err <= 1e-5, err
+
+
+def test_observation_scale_inside_the_kernels():
+    """The policy's input scaling given to the kernels equals scaling the observations
+    first: policy forward bit for bit (the kernel multiplies as torch does), the PPO loss
+    and gradient bit for bit."""
+    ippo = _ippo()
+    rng = np.random.default_rng(41)
+    P = torch.from_numpy(rand_params(41, 2)).cuda()
+    obs = torch.from_numpy(rng.normal(0, 50, size=(2, 96, 40)).astype(np.float32)).cuda()
+    sc = torch.from_numpy(rng.uniform(0.001, 0.5, size=40).astype(np.float32)).cuda()
+    a = ippo.policy_forward(P, obs, [9, 3], seed=3, t=1, want_logits=True, obs_scale=sc)
+    b = ippo.policy_forward(P, (obs * sc).contiguous(), [9, 3], seed=3, t=1, want_logits=True)
+    for k in ("actions", "logp", "value", "logits"):
+        assert torch.equal(a[k], b[k]), k
+    m = 130
+    o = obs[0, :96].contiguous()
+    o = torch.cat([o, o[:34]]).contiguous()
+    act = torch.from_numpy(rng.integers(0, 9, size=m).astype(np.int32)).cuda()
+    lpo, adv, ret, vo = (torch.from_numpy(rng.normal(0, 1, size=m).astype(np.float32)).cuda() for _ in range(4))
+    la, ga = ippo.ppo_fwd_bwd(P[0].contiguous(), o, act, lpo, adv, ret, vo, 9, obs_scale=sc)
+    lb, gb = ippo.ppo_fwd_bwd(P[0].contiguous(), (o * sc).contiguous(), act, lpo, adv, ret, vo, 9)
+    assert torch.equal(la, lb) and torch.equal(ga, gb)
