@@ -134,6 +134,44 @@ __device__ __forceinline__ void gemm16(floatx4 (&acc)[MT][NT], int K, int r0, in
     }
 }
 
+/* gemm16 with PF blocks of 16 k in flight: a lane's operands for the next PF blocks are
+ * loaded while the current block's MFMAs run, so a weight operand read from L2 (the
+ * recurrent network's per-step products) waits once per PF blocks rather than once per
+ * block.  K a multiple of 16. */
+template <int MT, int NT, int PF, class FA, class FB>
+__device__ __forceinline__ void gemm16p(floatx4 (&acc)[MT][NT], int K, int r0, int c0, FA A4, FB B4) {
+    const int l = (int)(threadIdx.x & 63);
+    const int li = l & 15, kq = 4 * (l >> 4);
+    const int nb = K / 16;
+    floatx4 a[PF][MT], b[PF][NT];
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+        const int kb = 16 * min(s, nb - 1) + kq;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) a[s][m] = A4(r0 + 16 * m + li, kb);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) b[s][n] = B4(kb, c0 + 16 * n + li);
+    }
+    for (int blk = 0; blk < nb; blk += PF) {
+#pragma unroll
+        for (int s = 0; s < PF; ++s) {
+            if (blk + s < nb) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+#pragma unroll
+                        for (int n = 0; n < NT; ++n) acc[m][n] = mfma(a[s][m][t], b[s][n][t], acc[m][n]);
+                const int kn = 16 * min(blk + s + PF, nb - 1) + kq; /* past the end: the last block again */
+#pragma unroll
+                for (int m = 0; m < MT; ++m) a[s][m] = A4(r0 + 16 * m + li, kn);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) b[s][n] = B4(kn, c0 + 16 * n + li);
+            }
+        }
+    }
+}
+
 /* acc[m][n] += A[rows][0..K) * B[0..K)[c0+16n ..] for the 64 rows from r0 with the rows of
  * the four tiles interleaved: row li of tile m is r0 + 4 li + m.  The four tiles' A
  * operands at one k are then consecutive, so an A stored row-contiguous arrives in one
@@ -756,6 +794,91 @@ __device__ __forceinline__ void gru_head(const float *__restrict__ P, const floa
     }
 }
 
+/* The sequence kernel's weights, prepared in its workspace so that every product reads
+ * its weight operand k-contiguous in 16-byte loads: W_e^T [128][48] (k >= 40 zero),
+ * W_i^T and W_h^T [384][128] (the gate products), W_i and W_h [128][384] (the backward
+ * products, 16-byte aligned copies), W_o^T [16][128] and W_o [128][16] (cols >= 10 zero). */
+struct GruW {
+    const float *WeT, *WiT, *WhT, *Wi, *Wh, *WoT, *WoP;
+};
+constexpr int GW_WET = 0, GW_WIT = GW_WET + GHD * GINP, GW_WHT = GW_WIT + G3 * GHD, GW_WI = GW_WHT + G3 * GHD,
+              GW_WH = GW_WI + GHD * G3, GW_WOT = GW_WH + GHD * G3, GW_WOP = GW_WOT + 16 * GHD,
+              GW_FLOATS = GW_WOP + GHD * 16;
+static_assert(GW_FLOATS % 4 == 0, "prepared weights keep 16-byte alignment");
+
+__global__ void k_gru_prep(const float *__restrict__ P, float *W) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < GHD * GINP) {
+        const int j = i / GINP, k = i % GINP;
+        W[GW_WET + i] = k < GIN ? P[GO_WE + k * GHD + j] : 0.f;
+    }
+    if (i < G3 * GHD) {
+        const int g = i / GHD, e = i % GHD; /* W^T[g][e] = W[e][g] */
+        W[GW_WIT + i] = P[GO_WI + e * G3 + g];
+        W[GW_WHT + i] = P[GO_WH + e * G3 + g];
+        W[GW_WI + i] = P[GO_WI + i];
+        W[GW_WH + i] = P[GO_WH + i];
+    }
+    if (i < 16 * GHD) {
+        const int j = i / GHD, k = i % GHD;
+        W[GW_WOT + i] = j < OUT ? P[GO_WO + k * OUT + j] : 0.f;
+        const int jj = i / 16, kk = i % 16;
+        W[GW_WOP + i] = kk < OUT ? P[GO_WO + jj * OUT + kk] : 0.f;
+    }
+}
+
+constexpr int GPF = 4; /* 16-k blocks in flight in the sequence kernel's products */
+
+__device__ __forceinline__ floatx4 gload4(const float *p) { return *(const floatx4 *)p; }
+
+/* the products of the sequence kernel on the prepared weights (biases from P) */
+__device__ __forceinline__ void gru_embed_w(const float *__restrict__ P, const GruW &w, const float *X, float *E, int wave,
+                                            int nw) {
+    for (int ct = wave; ct < GHD / 16; ct += nw) {
+        floatx4 acc[1][1] = {{zero4()}};
+        gemm16p<1, 1, 3>(acc, GINP, 0, 16 * ct, [&](int i, int kb) { return lds4(X + i * XS + kb); },
+                         [&](int kb, int j) { return gload4(w.WeT + j * GINP + kb); });
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = acc_row(i), c = 16 * ct + acc_col();
+            E[r * HSG + c] = tanh_exp(acc[0][0][i] + P[GO_BE + c]);
+        }
+    }
+}
+__device__ __forceinline__ void gru_gates_w(const float *__restrict__ P, const GruW &w, const float *E, const float *HP,
+                                            float *GI, float *GH, int wave, int nw) {
+    const int per = 2 * (G3 / 16) / nw;
+    for (int c3 = 0; c3 < per; c3 += 3) {
+        const int ct0 = wave * per + c3;
+        const bool hh = ct0 >= G3 / 16;
+        const int c0 = 16 * (hh ? ct0 - G3 / 16 : ct0);
+        const float *A = hh ? HP : E;
+        const float *WT = hh ? w.WhT : w.WiT;
+        floatx4 acc[1][3] = {{zero4(), zero4(), zero4()}};
+        gemm16p<1, 3, GPF>(acc, GHD, 0, c0, [&](int i, int kb) { return lds4(A + i * HSG + kb); },
+                           [&](int kb, int j) { return gload4(WT + j * GHD + kb); });
+        float *D = hh ? GH : GI;
+        const float *bias = P + (hh ? GO_BH : GO_BI);
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = acc_row(i), c = c0 + 16 * n + acc_col();
+                D[r * GS + c] = acc[0][n][i] + bias[c];
+            }
+    }
+}
+__device__ __forceinline__ void gru_head_w(const float *__restrict__ P, const GruW &w, const float *HN, float *O) {
+    floatx4 acc[1][1] = {{zero4()}};
+    gemm16p<1, 1, GPF>(acc, GHD, 0, 0, [&](int i, int kb) { return lds4(HN + i * HSG + kb); },
+                       [&](int kb, int j) { return gload4(w.WoT + j * GHD + kb); });
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = acc_row(i), c = acc_col();
+        O[r * OS + c] = c < OUT ? acc[0][0][i] + P[GO_BO + c] : 0.f;
+    }
+}
+
 /* ---- one step of the rollout: grid (ceil(n / 16), n_agents), GRU_STEP_TH threads ---- */
 struct GruStepArgs {
     const float *params;  /* [A][GNP] */
@@ -832,22 +955,46 @@ struct GruSeqArgs {
     int32_t T, m, n_act;
     float clip, c_v, c_e, scale; /* scale = 1 / (T m) */
     float *HS, *E, *DGI, *DGH, *DE, *DO, *LS; /* workspace */
-    const float *WiT, *WhT;     /* W_i and W_h transposed, [384][128] */
+    GruW w;                     /* prepared weights (workspace) */
 };
-constexpr int GRU_SEQ_LDS = TG * (XS + 4 * HSG + 4 * GS + OS);
+constexpr int GRU_SEQ_LDS = TG * (XS + 4 * HSG + 4 * GS + OS) + TG;
 
 __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_seq(GruSeqArgs a) {
     extern __shared__ float sm[];
     float *X = sm, *E = X + TG * XS, *HP = E + TG * HSG, *HN = HP + TG * HSG, *DH = HN + TG * HSG, *GI = DH + TG * HSG,
           *GH = GI + TG * GS, *DGI = GH + TG * GS, *DGH = DGI + TG * GS, *O = DGH + TG * GS;
+    float *ST = O + TG * OS; /* the step's episode-start flag of each row (backward pass) */
     const int row0 = (int)blockIdx.x * TG, rows = min(TG, a.m - row0);
     const int tid = (int)threadIdx.x, wave = tid >> 6, nw = GRU_SEQ_TH / 64;
     const float *__restrict__ P = a.params;
     const int T = a.T, m = a.m;
-    auto stage_x = [&](int t) {
-        for (int i = tid; i < TG * XS; i += GRU_SEQ_TH) {
-            const int r = i / XS, c = i % XS;
-            X[i] = (r < rows && c < GIN) ? obs_in(a.obs, a.obs_scale, ((int64_t)t * m + row0 + r) * GIN + c, c) : 0.f;
+    /* A step's inputs (its observation tile, the episode-start flags of the rows a thread
+     * handles, in the backward pass the stored state h_{t-1} and the per-sample PPO inputs)
+     * are loaded into registers one step ahead, so that no step waits on device memory. */
+    constexpr int XE = (TG * XS + GRU_SEQ_TH - 1) / GRU_SEQ_TH, HE = TG * GHD / GRU_SEQ_TH;
+    static_assert(TG * GHD % GRU_SEQ_TH == 0, "state elements per thread");
+    float xv[XE], hv[HE];
+    uint8_t sv[HE];
+    auto load_x = [&](int t) {
+#pragma unroll
+        for (int k = 0; k < XE; ++k) {
+            const int i = tid + k * GRU_SEQ_TH, r = i / XS, c = i % XS;
+            xv[k] = (i < TG * XS && r < rows && c < GIN)
+                        ? obs_in(a.obs, a.obs_scale, ((int64_t)t * m + row0 + r) * GIN + c, c) : 0.f;
+        }
+    };
+    auto store_x = [&]() {
+#pragma unroll
+        for (int k = 0; k < XE; ++k) {
+            const int i = tid + k * GRU_SEQ_TH;
+            if (i < TG * XS) X[i] = xv[k];
+        }
+    };
+    auto load_start = [&](int t) {
+#pragma unroll
+        for (int k = 0; k < HE; ++k) {
+            const int r = (tid + k * GRU_SEQ_TH) / GHD;
+            sv[k] = r < rows ? a.start[(int64_t)t * m + row0 + r] : 1;
         }
     };
     /* forward: h0, then the recurrence; HS[t] is h_{t-1} as stored (before an episode
@@ -858,17 +1005,23 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_seq(GruSeqArgs a) {
         HN[r * HSG + c] = v;
         if (r < rows) a.HS[(int64_t)(row0 + r) * GHD + c] = v;
     }
+    load_x(0);
+    load_start(0);
     for (int t = 0; t < T; ++t) {
-        stage_x(t);
-        for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
-            const int r = i / GHD, c = i % GHD;
-            const bool zero = r >= rows || a.start[(int64_t)t * m + row0 + r];
-            HP[r * HSG + c] = zero ? 0.f : HN[r * HSG + c];
+        store_x();
+#pragma unroll
+        for (int k = 0; k < HE; ++k) {
+            const int i = tid + k * GRU_SEQ_TH, r = i / GHD, c = i % GHD;
+            HP[r * HSG + c] = sv[k] ? 0.f : HN[r * HSG + c];
+        }
+        if (t + 1 < T) {
+            load_x(t + 1);
+            load_start(t + 1);
         }
         __syncthreads();
-        gru_embed(P, X, E, wave, nw);
+        gru_embed_w(P, a.w, X, E, wave, nw);
         __syncthreads();
-        gru_gates(P, E, HP, GI, GH, wave, nw);
+        gru_gates_w(P, a.w, E, HP, GI, GH, wave, nw);
         __syncthreads();
         gru_update(GI, GH, HP, HN, tid, GRU_SEQ_TH, false);
         __syncthreads();
@@ -880,22 +1033,51 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_seq(GruSeqArgs a) {
     /* backward */
     for (int i = tid; i < TG * HSG; i += GRU_SEQ_TH) DH[i] = 0.f;
     float lsum[4] = {0.f, 0.f, 0.f, 0.f};
+    auto load_h = [&](int t) {
+#pragma unroll
+        for (int k = 0; k < HE; ++k) {
+            const int i = tid + k * GRU_SEQ_TH, r = i / GHD, c = i % GHD;
+            hv[k] = r < rows ? a.HS[((int64_t)t * m + row0 + r) * GHD + c] : 0.f;
+        }
+    };
+    /* the per-sample PPO inputs of row tid (threads below 16) */
+    int pa = 0;
+    float plo = 0.f, pad = 0.f, pre = 0.f, pvo = 0.f;
+    auto load_ppo = [&](int t) {
+        if (tid < rows) {
+            const int64_t s = (int64_t)t * m + row0 + tid;
+            pa = a.act[s]; plo = a.logp_old[s]; pad = a.adv[s]; pre = a.ret[s]; pvo = a.v_old[s];
+        }
+    };
+    load_x(T - 1);
+    load_start(T - 1);
+    load_h(T - 1);
+    load_ppo(T - 1);
     for (int t = T - 1; t >= 0; --t) {
         __syncthreads();
-        stage_x(t);
-        for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
-            const int r = i / GHD, c = i % GHD;
-            const bool zero = r >= rows || a.start[(int64_t)t * m + row0 + r];
-            HP[r * HSG + c] = zero ? 0.f : a.HS[((int64_t)t * m + row0 + r) * GHD + c];
+        store_x();
+#pragma unroll
+        for (int k = 0; k < HE; ++k) {
+            const int i = tid + k * GRU_SEQ_TH, r = i / GHD, c = i % GHD;
+            HP[r * HSG + c] = sv[k] ? 0.f : hv[k];
+            if (c == 0) ST[r] = sv[k] ? 1.f : 0.f;
+        }
+        const int cur_a = pa;
+        const float cur_lo = plo, cur_ad = pad, cur_re = pre, cur_vo = pvo;
+        if (t > 0) {
+            load_x(t - 1);
+            load_start(t - 1);
+            load_h(t - 1);
+            load_ppo(t - 1);
         }
         __syncthreads();
-        gru_embed(P, X, E, wave, nw);
+        gru_embed_w(P, a.w, X, E, wave, nw);
         __syncthreads();
-        gru_gates(P, E, HP, GI, GH, wave, nw);
+        gru_gates_w(P, a.w, E, HP, GI, GH, wave, nw);
         __syncthreads();
         gru_update(GI, GH, HP, HN, tid, GRU_SEQ_TH, true);
         __syncthreads();
-        if (wave == 0) gru_head(P, HN, O);
+        if (wave == 0) gru_head_w(P, a.w, HN, O);
         __syncthreads();
         /* per-sample loss terms and dO (scaled by 1 / (T m)) */
         if (tid < TG) {
@@ -904,10 +1086,8 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_seq(GruSeqArgs a) {
 #pragma unroll
             for (int j = 0; j < OUT; ++j) dz[j] = 0.f;
             if (tid < rows) {
-                const int64_t s = (int64_t)t * m + row0 + tid;
                 float ls[4];
-                loss_head(z, a.n_act, a.act[s], a.logp_old[s], a.adv[s], a.ret[s], a.v_old[s], a.clip, a.c_v, a.c_e,
-                          a.scale, dz, ls);
+                loss_head(z, a.n_act, cur_a, cur_lo, cur_ad, cur_re, cur_vo, a.clip, a.c_v, a.c_e, a.scale, dz, ls);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) lsum[q] += ls[q];
             }
@@ -927,8 +1107,11 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_seq(GruSeqArgs a) {
         /* dh += dO W_o^T (K = 16, rows 10..15 of W_o^T zero) */
         if (wave < GHD / 16) {
             floatx4 acc[1][1] = {{zero4()}};
-            gemm<1, 1>(acc, 16, 0, 16 * wave, [&](int i, int k) { return O[i * OS + k]; },
-                       [&](int k, int j) { return k < OUT ? P[GO_WO + j * OUT + k] : 0.f; });
+            gemm16p<1, 1, 1>(acc, 16, 0, 16 * wave,
+                             [&](int i, int kb) {
+                                 return floatx4{O[i * OS + kb], O[i * OS + kb + 1], O[i * OS + kb + 2], O[i * OS + kb + 3]};
+                             },
+                             [&](int kb, int j) { return gload4(a.w.WoP + j * 16 + kb); });
 #pragma unroll
             for (int i = 0; i < 4; ++i) DH[acc_row(i) * HSG + 16 * wave + acc_col()] += acc[0][0][i];
         }
@@ -964,14 +1147,14 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_seq(GruSeqArgs a) {
          * each per wave */
         {
             floatx4 acc[1][1] = {{zero4()}}, acd[1][1] = {{zero4()}};
-            gemm<1, 1>(acc, G3, 0, 16 * wave, [&](int i, int k) { return DGH[i * GS + k]; },
-                       [&](int k, int j) { return a.WhT[k * GHD + j]; });
-            gemm<1, 1>(acd, G3, 0, 16 * wave, [&](int i, int k) { return DGI[i * GS + k]; },
-                       [&](int k, int j) { return a.WiT[k * GHD + j]; });
+            gemm16p<1, 1, 2 * GPF>(acc, G3, 0, 16 * wave, [&](int i, int kb) { return lds4(DGH + i * GS + kb); },
+                                   [&](int kb, int j) { return gload4(a.w.Wh + j * G3 + kb); });
+            gemm16p<1, 1, 2 * GPF>(acd, G3, 0, 16 * wave, [&](int i, int kb) { return lds4(DGI + i * GS + kb); },
+                                   [&](int kb, int j) { return gload4(a.w.Wi + j * G3 + kb); });
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = acc_row(i), c = 16 * wave + acc_col();
-                const bool stop = r >= rows || a.start[(int64_t)t * m + row0 + r];
+                const bool stop = ST[r] != 0.f; /* also set for rows past the last sequence */
                 DH[r * HSG + c] = stop ? 0.f : DH[r * HSG + c] + acc[0][0][i];
                 const float e = E[r * HSG + c];
                 if (r < rows) a.DE[((int64_t)t * m + row0 + r) * GHD + c] = acd[0][0][i] * (1.f - e * e);
@@ -989,15 +1172,6 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_seq(GruSeqArgs a) {
         for (int r = 0; r < TG; ++r) v += O[r * OS + tid];
         a.LS[(int64_t)blockIdx.x * 4 + tid] = v;
     }
-}
-
-/* W_i and W_h transposed into the workspace ([384][128] each) */
-__global__ void k_gru_transpose(const float *__restrict__ P, float *WiT, float *WhT) {
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i >= GHD * G3) return;
-    const int k = i / GHD, j = i % GHD; /* destination row k (gate column), column j */
-    WiT[i] = P[GO_WI + j * G3 + k];
-    WhT[i] = P[GO_WH + j * G3 + k];
 }
 
 /* ---- weight gradients over all T m samples: workgroup w takes a contiguous range of
@@ -1137,7 +1311,7 @@ bool lds_opt_in() {
 }
 /* the GRU loss workspace, in floats from its start (every part a multiple of 4 floats) */
 struct GruWs {
-    int64_t hs, e, dgi, dgh, de, dout, ls, wit, wht, part, sums, total;
+    int64_t hs, e, dgi, dgh, de, dout, ls, wts, part, sums, total;
     int ntile, nwg, nch;
 };
 GruWs gru_ws(int32_t T, int32_t m) {
@@ -1154,8 +1328,7 @@ GruWs gru_ws(int32_t T, int32_t m) {
     w.de = o; o += S * GHD;
     w.dout = o; o += S * 16;
     w.ls = o; o += (int64_t)w.ntile * 4;
-    w.wit = o; o += (int64_t)GHD * G3;
-    w.wht = o; o += (int64_t)GHD * G3;
+    w.wts = o; o += GW_FLOATS;
     w.part = o; o += (int64_t)w.nwg * GPW;
     w.sums = o; o += (int64_t)w.nch * GPW;
     w.total = o;
@@ -1293,13 +1466,15 @@ int lob_gru_ppo_fwd_bwd(const float *params, const float *obs, const float *obs_
     if (!lds_opt_in()) return LOB_EHIP;
     hipStream_t st = (hipStream_t)stream;
     float *ws = workspace;
-    hipLaunchKernelGGL(k_gru_transpose, dim3((GHD * G3 + 255) / 256), dim3(256), 0, st, params, ws + w.wit, ws + w.wht);
+    hipLaunchKernelGGL(k_gru_prep, dim3((GHD * G3 + 255) / 256), dim3(256), 0, st, params, ws + w.wts);
     GruSeqArgs a;
     a.params = params; a.obs = obs; a.obs_scale = obs_scale; a.start = start; a.h0 = h0; a.act = act; a.logp_old = logp_old; a.adv = adv;
     a.ret = ret; a.v_old = v_old; a.T = T; a.m = m; a.n_act = n_actions; a.clip = clip; a.c_v = c_v; a.c_e = c_e;
     a.scale = 1.0f / (float)((int64_t)T * m);
     a.HS = ws + w.hs; a.E = ws + w.e; a.DGI = ws + w.dgi; a.DGH = ws + w.dgh; a.DE = ws + w.de; a.DO = ws + w.dout;
-    a.LS = ws + w.ls; a.WiT = ws + w.wit; a.WhT = ws + w.wht;
+    a.LS = ws + w.ls;
+    const float *W = ws + w.wts;
+    a.w = GruW{W + GW_WET, W + GW_WIT, W + GW_WHT, W + GW_WI, W + GW_WH, W + GW_WOT, W + GW_WOP};
     hipLaunchKernelGGL(k_gru_seq, dim3((unsigned)w.ntile), dim3(GRU_SEQ_TH), GRU_SEQ_LDS * 4, st, a);
     GruDwArgs d;
     d.obs = obs; d.obs_scale = obs_scale; d.start = start; d.HS = a.HS; d.E = a.E; d.DGI = a.DGI; d.DGH = a.DGH; d.DE = a.DE; d.DO = a.DO;
