@@ -237,7 +237,7 @@ def gru_bench(reps: int = 3):
             "update": "GAE + 4 epochs x 4 minibatches (1024 sequences of 128 steps) x 2 agents + Adam",
             "gru_ppo_fwd_bwd_call": {"sequences": m, "steps": T, "samples": T * m, "ms": call_ms,
                                      "flop_per_sample": GRU_FLOP_PER_SAMPLE,
-                                     "launches": "k_gru_transpose, k_gru_seq, k_gru_dw, k_reduce_chunks, "
+                                     "launches": "k_gru_prep, k_gru_seq, k_gru_dw, k_reduce_chunks, "
                                                  "k_reduce_out, k_gru_loss",
                                      "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
                                                   "unit": "TFLOP/s", "frac": tflops / FP32_MFMA_PEAK_TFLOPS}}}
@@ -323,7 +323,8 @@ def main():
     ap.add_argument("--eager", action="store_true",
                     help="time eager rollouts instead of replays of the captured HIP graph")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="first copy 256 MiB device-to-device (calibrates HBM byte counters)")
+                    help="first copy 256 MiB device-to-device, by the blit copy and by an elementwise kernel "
+                         "(calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the env step shards by env "
@@ -335,10 +336,14 @@ def main():
     from paper_2511_02136_amd.lob import LobEnv, DeviceStream
 
     if args.copy_probe:
+        # HBM byte-counter calibration: 256 MiB read and 256 MiB written, once by the
+        # runtime's blit copy and once by an ordinary elementwise kernel (x * 1)
         src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1, out=dst)
         torch.cuda.synchronize()
         del src, dst
     if args.ippo_only:

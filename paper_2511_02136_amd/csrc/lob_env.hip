@@ -127,9 +127,10 @@ struct KArgs {
     uint64_t seed;
     int32_t exec_task, exec_q0, mm_q, dir_q;
     float pen, lam, rho;
-    /* Avellaneda-Stoikov quotes per risk-aversion choice: gamma sigma^2 and
-     * (2 / gamma) ln(1 + gamma / kappa), tabled on the host */
-    double avA[9], avB[9];
+    /* Avellaneda-Stoikov quote terms per risk-aversion choice g, tabled on the host in
+     * device memory: [g] = gamma sigma^2, [9 + g] = (2 / gamma) ln(1 + gamma / kappa)
+     * (a kernel-argument array indexed at run time would be copied to scratch) */
+    const double *avst;
     int32_t kinds; /* 4 bits per agent */
     const int32_t *caps;
     /* messages */
@@ -754,8 +755,9 @@ struct Run {
             const double q = (double)uni64(AG(i)[0]) / (double)a.mm_q;
             const double tau = (double)(a.episode_len - t);
             const double mid = (double)((int64_t)bb0 + ba0) * 0.5;
-            const double r = mid - q * a.avA[g] * tau;
-            const double d = a.avA[g] * tau + a.avB[g];
+            const double avA = a.avst[g], avB = a.avst[9 + g];
+            const double r = mid - q * avA * tau;
+            const double d = avA * tau + avB;
             const int bid = quote_price(floor(r - d * 0.5));
             const int ask = quote_price(ceil(r + d * 0.5));
             add_level(i, nlv, 0, (int)min((int64_t)bid, (int64_t)ba0 - 1), a.mm_q);
@@ -1398,7 +1400,8 @@ struct lob_ctx {
     lob_config cfg;
     std::vector<int32_t> caps, kinds;
     int32_t kinds_packed = 0;
-    double avA[9] = {}, avB[9] = {}; /* Avellaneda-Stoikov quote terms per risk-aversion choice */
+    double avst[18] = {};            /* Avellaneda-Stoikov quote terms per risk-aversion choice */
+    double *d_avst = nullptr;        /* the same on the device */
     int32_t *d_caps = nullptr;
     int32_t *d_bk[NF] = {};
     int32_t *d_bk_n = nullptr;
@@ -1450,6 +1453,7 @@ void free_ctx(lob_ctx *c) {
     (void)hipFree(c->d_stats);
     (void)hipFree(c->d_env_list);
     (void)hipFree(c->d_work);
+    (void)hipFree(c->d_avst);
     for (int k = 0; k < MAX_CLASSES; ++k) {
         if (c->streams[k]) (void)hipStreamDestroy(c->streams[k]);
         if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
@@ -1473,10 +1477,7 @@ KArgs base_args(const lob_ctx *c) {
     a.pen = c->cfg.exec_penalty;
     a.lam = c->cfg.mm_lambda;
     a.rho = c->cfg.mm_rho;
-    for (int g = 0; g < 9; ++g) {
-        a.avA[g] = c->avA[g];
-        a.avB[g] = c->avB[g];
-    }
+    a.avst = c->d_avst;
     a.kinds = c->kinds_packed;
     a.caps = c->d_caps;
     for (int f = 0; f < NF; ++f) a.bk[f] = c->d_bk[f];
@@ -1782,8 +1783,8 @@ int lob_init(const lob_config *cfg, lob_ctx **out) {
         }
         for (int g = 0; g < 9; ++g) {
             const double gamma = (double)g0 * std::ldexp(1.0, g - 4);
-            c->avA[g] = gamma * (double)s2;
-            c->avB[g] = (2.0 / gamma) * std::log(1.0 + gamma / (double)kp);
+            c->avst[g] = gamma * (double)s2;
+            c->avst[9 + g] = (2.0 / gamma) * std::log(1.0 + gamma / (double)kp);
         }
     }
     c->cfg.cap = nullptr;
@@ -1809,11 +1810,13 @@ int lob_init(const lob_config *cfg, lob_ctx **out) {
     rc |= dalloc(&c->d_stats, (size_t)N * STW);
     rc |= dalloc(&c->d_env_list, (size_t)N);
     rc |= dalloc(&c->d_work, 64);
+    rc |= dalloc(&c->d_avst, 18);
     if (rc != LOB_OK) { free_ctx(c); return LOB_ENOMEM; }
 
     if ((rc = build_classes(c, false)) != LOB_OK) { free_ctx(c); return rc; }
     if (!hip_ok(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) ||
-        !hip_ok(hipMemcpy(c->d_caps, c->caps.data(), (size_t)N * 4, hipMemcpyHostToDevice))) {
+        !hip_ok(hipMemcpy(c->d_caps, c->caps.data(), (size_t)N * 4, hipMemcpyHostToDevice)) ||
+        !hip_ok(hipMemcpy(c->d_avst, c->avst, sizeof(c->avst), hipMemcpyHostToDevice))) {
         free_ctx(c);
         return LOB_EHIP;
     }

@@ -30,7 +30,7 @@ class IppoTrainer:
     def __init__(self, env: LobEnv, dstream: DeviceStream, book: dict, n_steps: int, seed: int = 0,
                  param_seed: int = 0, lr: float = 3e-4, epochs: int = 4, minibatches: int = 4, gamma: float = 0.99,
                  lam: float = 0.95, clip: float = 0.2, c_v: float = 0.5, c_e: float = 0.01, record_trades: bool = True,
-                 network: str = "mlp"):
+                 network: str = "mlp", agent_streams: bool = True):
         self.env, self.ds, self.book, self.T = env, dstream, book, n_steps
         self.A, self.N = env.n_agents, env.n_envs
         self.n_act = [N_ACTIONS[int(k)] for k in env.kinds]
@@ -58,6 +58,9 @@ class IppoTrainer:
         self.epoch = torch.zeros(1, dtype=torch.int64, device=dev)
         # recurrent state of the GRU policy during the rollout (zero at the episode start)
         self.h = torch.zeros((A, N, ippo.GRU_HIDDEN), dtype=torch.float32, device=dev) if network == "gru" else None
+        # issue each agent's loss calls on a stream of its own (False: all on the current one)
+        self.agent_streams = agent_streams
+        self._streams = None
         self.graph: Optional[torch.cuda.CUDAGraph] = None
 
     # ---- rollout ----
@@ -113,23 +116,51 @@ class IppoTrainer:
             return self._update_gru(adv, ret)
         M = T * N
         mb = M // self.minibatches
+
+        def agent_loss(a, idx):
+            obs = self.obs[:T, a].reshape(M, 40)[idx].contiguous()
+            act = self.pol["actions"][:, a].reshape(M)[idx].contiguous()
+            lpo = self.pol["logp"][:, a].reshape(M)[idx].contiguous()
+            ad = adv[:, a].reshape(M)[idx].contiguous()
+            rt = ret[:, a].reshape(M)[idx].contiguous()
+            vo = self.pol["value"][:, a].reshape(M)[idx].contiguous()
+            return ippo.FusedPPOLoss.apply(self.params[a], obs, act, lpo, ad, rt, vo, self.n_act[a],
+                                           self.clip, self.c_v, self.c_e, self.inv_scale)
+        return self._epochs(M, mb, agent_loss)
+
+    def _agent_streams(self):
+        """One stream per agent (default priority): the agents' networks are independent,
+        so their loss kernels of one minibatch may run side by side."""
+        if self._streams is None:
+            self._streams = [torch.cuda.Stream(device=self.env.device) for _ in range(self.A)]
+        return self._streams
+
+    def _epochs(self, n_items, mb, agent_loss) -> dict:
+        """Epochs of shuffled minibatches; per minibatch every agent's fused loss call is
+        issued on its own stream (forward and, by autograd's stream rule, backward), the
+        losses summed on the current stream, then one Adam step over all networks."""
+        dev = self.params.device
+        streams = self._agent_streams() if self.agent_streams else None
         stats = {"loss": 0.0, "minibatches": 0}
         for _ in range(self.epochs):
-            perms = [torch.randperm(M, device=rew.device) for _ in range(A)]
+            perms = [torch.randperm(n_items, device=dev) for _ in range(self.A)]
             for k in range(self.minibatches):
                 self.opt.zero_grad(set_to_none=True)
-                total = 0.0
-                for a in range(A):
+                main = torch.cuda.current_stream(dev)
+                losses = []
+                for a in range(self.A):
                     idx = perms[a][k * mb:(k + 1) * mb]
-                    obs = self.obs[:T, a].reshape(M, 40)[idx].contiguous()
-                    act = self.pol["actions"][:, a].reshape(M)[idx].contiguous()
-                    lpo = self.pol["logp"][:, a].reshape(M)[idx].contiguous()
-                    ad = adv[:, a].reshape(M)[idx].contiguous()
-                    rt = ret[:, a].reshape(M)[idx].contiguous()
-                    vo = self.pol["value"][:, a].reshape(M)[idx].contiguous()
-                    loss = ippo.FusedPPOLoss.apply(self.params[a], obs, act, lpo, ad, rt, vo, self.n_act[a],
-                                                   self.clip, self.c_v, self.c_e, self.inv_scale)
-                    total = total + loss
+                    if streams is None:
+                        losses.append(agent_loss(a, idx))
+                        continue
+                    streams[a].wait_stream(main)
+                    with torch.cuda.stream(streams[a]):
+                        losses.append(agent_loss(a, idx))
+                for st in streams or ():
+                    main.wait_stream(st)
+                total = losses[0]
+                for l in losses[1:]:
+                    total = total + l
                 total.backward()
                 self.opt.step()
                 stats["loss"] += float(total.detach())
@@ -139,32 +170,20 @@ class IppoTrainer:
 
     def _update_gru(self, adv, ret) -> dict:
         """Epochs of minibatches of whole sequences (envs), the loss back through time."""
-        T, A, N = self.T, self.A, self.N
+        T, N = self.T, self.N
         dev = adv.device
         mb = N // self.minibatches
         start = torch.zeros((T, mb), dtype=torch.uint8, device=dev)
         start[0] = 1  # the rollout is one episode from its reset
         h0 = torch.zeros((mb, ippo.GRU_HIDDEN), dtype=torch.float32, device=dev)
-        stats = {"loss": 0.0, "minibatches": 0}
-        for _ in range(self.epochs):
-            perms = [torch.randperm(N, device=dev) for _ in range(A)]
-            for k in range(self.minibatches):
-                self.opt.zero_grad(set_to_none=True)
-                total = 0.0
-                for a in range(A):
-                    idx = perms[a][k * mb:(k + 1) * mb]
-                    obs = self.obs[:T, a][:, idx].contiguous()
-                    act = self.pol["actions"][:, a][:, idx].contiguous()
-                    lpo = self.pol["logp"][:, a][:, idx].contiguous()
-                    ad = adv[:, a][:, idx].contiguous()
-                    rt = ret[:, a][:, idx].contiguous()
-                    vo = self.pol["value"][:, a][:, idx].contiguous()
-                    loss = ippo.FusedGruPPOLoss.apply(self.params[a], obs, start, h0, act, lpo, ad, rt, vo,
-                                                      self.n_act[a], self.clip, self.c_v, self.c_e, self.inv_scale)
-                    total = total + loss
-                total.backward()
-                self.opt.step()
-                stats["loss"] += float(total.detach())
-                stats["minibatches"] += 1
-        stats["loss"] /= max(1, stats["minibatches"])
-        return stats
+
+        def agent_loss(a, idx):
+            obs = self.obs[:T, a][:, idx].contiguous()
+            act = self.pol["actions"][:, a][:, idx].contiguous()
+            lpo = self.pol["logp"][:, a][:, idx].contiguous()
+            ad = adv[:, a][:, idx].contiguous()
+            rt = ret[:, a][:, idx].contiguous()
+            vo = self.pol["value"][:, a][:, idx].contiguous()
+            return ippo.FusedGruPPOLoss.apply(self.params[a], obs, start, h0, act, lpo, ad, rt, vo,
+                                              self.n_act[a], self.clip, self.c_v, self.c_e, self.inv_scale)
+        return self._epochs(N, mb, agent_loss)

@@ -12,7 +12,7 @@ from gpu_compare import assert_same_outputs
 pytestmark = pytest.mark.gpu
 
 
-def make_trainer(n_envs=256, n_steps=16, seed=3):
+def make_trainer(n_envs=256, n_steps=16, seed=3, **kw):
     from paper_2511_02136_amd.lob import LobEnv, DeviceStream
     from paper_2511_02136_amd.trainer import IppoTrainer
     w = synth.WORKLOADS["ippo4096"].scaled(n_envs=n_envs, n_steps=n_steps)
@@ -20,7 +20,7 @@ def make_trainer(n_envs=256, n_steps=16, seed=3):
     env = LobEnv(s.caps, w.max_cap, w.agents, w.ep_len, w.seed)
     ds = DeviceStream.from_host(s)
     book = {k: torch.from_numpy(v).cuda() for k, v in s.book.items()}
-    return w, s, IppoTrainer(env, ds, book, n_steps, seed=seed, param_seed=seed)
+    return w, s, IppoTrainer(env, ds, book, n_steps, seed=seed, param_seed=seed, **kw)
 
 
 def snapshot(tr):
@@ -86,6 +86,23 @@ def test_update_runs_and_changes_the_policy():
     assert st["minibatches"] == tr.epochs * tr.minibatches
     assert not torch.equal(before, tr.params.detach())
     assert torch.isfinite(tr.params).all()
+
+
+@pytest.mark.parametrize("network", ["mlp", "gru"])
+def test_update_on_agent_streams_equals_one_stream(network):
+    """The update issues each agent's fused loss calls on a stream of its own; with the
+    same rollout and the same minibatch shuffles the parameters after the update are
+    bit-identical to an update with every call on the current stream."""
+    res = []
+    for concurrent in (True, False):
+        w, s, tr = make_trainer(n_envs=128, n_steps=16, seed=11, network=network, agent_streams=concurrent)
+        tr.rollout(use_graph=False)
+        torch.manual_seed(5)
+        st = tr.update()
+        torch.cuda.synchronize()
+        res.append((st["loss"], tr.params.detach().clone()))
+    assert res[0][0] == res[1][0]
+    assert torch.equal(res[0][1], res[1][1])
 
 
 def test_full_size_learned_policy_rollout_parity():
