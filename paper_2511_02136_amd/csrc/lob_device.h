@@ -46,6 +46,26 @@ __device__ __forceinline__ uint64_t lanes_le(int a, int b) { return __builtin_am
 __device__ __forceinline__ int shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
 __device__ __forceinline__ int2 shl1(int2 v) { return make_int2(shl1(v.x), shl1(v.y)); }
 
+/* lane l takes lane l - 1's value (lane 0 takes 0) */
+__device__ __forceinline__ int shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+
+/* inclusive prefix sum over the 64 lanes, saturating at 2^31 - 1: shifts within each row
+ * of 16 lanes, then the broadcasts of lane 15 into rows 1 and 3 and of lane 31 into rows
+ * 2 and 3 */
+__device__ __forceinline__ unsigned sat_add(unsigned a, unsigned b) {
+    const unsigned s = a + b;
+    return s > 0x7fffffffu ? 0x7fffffffu : s;
+}
+__device__ __forceinline__ unsigned scan_sat(unsigned x) {
+    x = sat_add(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true)); /* row_shr:1 */
+    x = sat_add(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true)); /* row_shr:2 */
+    x = sat_add(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true)); /* row_shr:4 */
+    x = sat_add(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true)); /* row_shr:8 */
+    x = sat_add(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false)); /* row_bcast:15 */
+    x = sat_add(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false)); /* row_bcast:31 */
+    return x;
+}
+
 __device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
 __device__ __forceinline__ int64_t rdlane64(int64_t v, int l) {

@@ -424,8 +424,10 @@ struct Run {
 
     /* ---- matching: an incoming order of side S against the opposite side while it
      * crosses (market orders cross at any price); trades at the resting price, best
-     * first, one resting order at a time from the top record down.  Returns the
-     * unmatched remainder. ---- */
+     * first.  The 64 best orders are loaded at once, lane l holding the l-th best; when
+     * the best one alone does not fill the order, an inclusive prefix sum of the crossing
+     * quantities over the lanes finds where the order is filled, and the lanes up to that
+     * one write their trade records together.  Returns the unmatched remainder. ---- */
     template <int S, bool MARKET>
     __device__ __forceinline__ int match(int p, int q, int agg_oid, int agg_tid) {
         constexpr int O = 1 - S;
@@ -435,31 +437,60 @@ struct Run {
         if (!MARKET && (bestS<O>() ^ km(O)) > kp) return q;
         int no = n_opp, rem = q, ntr = 0, last_price = 0;
         int64_t notional = 0;
-        int2 *rec = &US<O>(0, no - 1);
-        int2 pq = rec[0];
         for (;;) {
-            /* the order at the top crosses */
-            const int2 ot = rec[1];
-            const int price = uni(pq.x), qty = uni(pq.y);
-            const int poid = uni(ot.x), ptid = uni(ot.y);
-            const int x = min(rem, qty);
-            write_trade(ntr, price, x, agg_oid, poid, agg_tid, ptid, S);
-            add_fill(ptid, S != 0, x, (int64_t)x * price);
-            notional += (int64_t)x * price;
-            rem -= x;
-            ntr += 1;
-            last_price = price;
-            if (x < qty) {
-                /* partly filled: the incoming order is done */
-                if (lane == 0) rec[0].y = qty - x;
-                WAVE_SYNC();
+            /* lane l: the l-th best order of the opposite side (record no - 1 - l) */
+            const int j = no - 1 - lane;
+            const int4 r = *RQ<O>(max(j, 0));
+            const bool cross = j >= 0 && (MARKET || (r.x ^ km(O)) <= kp);
+            const uint64_t ncm = ballot(!cross);
+            if (ncm & 1) break; /* after a row of fills: the new best order does not cross */
+            int kd, kn, nt;
+            unsigned inc = 0, exc = 0;
+            if (rdlane(r.y, 0) >= rem) {
+                kd = 0; /* the best order fills the rest (the common case) */
+                kn = nt = 1;
+            } else {
+                inc = scan_sat(cross ? (unsigned)r.y : 0u);
+                exc = (unsigned)shr1((int)inc);
+                const uint64_t dm = ballot(cross && inc >= (unsigned)rem);
+                kn = ncm ? (int)__builtin_ctzll(ncm) : WAVE; /* first order that does not cross */
+                kd = dm ? (int)__builtin_ctzll(dm) : WAVE;   /* the order that fills the rest */
+                nt = min(kd + 1, kn);                       /* orders traded against */
+            }
+            const int x = lane == kd ? rem - (int)exc : r.y; /* lane l < nt trades x */
+            const int rec = tr_next + ntr + lane;
+            if (lane < nt && rec < tr_room) {
+                int4 *pt = reinterpret_cast<int4 *>(tr_base + (int64_t)rec * LOB_TRADE_WORDS);
+                pt[0] = make_int4(r.x, x, agg_oid, r.z);
+                pt[1] = make_int4(agg_tid, r.w, S | (seq << 1), t);
+            }
+            /* passive fills of agents' orders among them (rare) */
+            uint64_t am = ballot(lane < nt && (unsigned)(r.w - 1) < (unsigned)A);
+            while (am) {
+                const int l = (int)__builtin_ctzll(am);
+                am &= am - 1;
+                const int px = rdlane(x, l);
+                add_fill(rdlane(r.w, l), S != 0, px, (int64_t)px * rdlane(r.x, l));
+            }
+            for (int l = 0; l < nt; ++l) notional += (int64_t)rdlane(x, l) * rdlane(r.x, l);
+            last_price = rdlane(r.x, nt - 1);
+            ntr += nt;
+            if (kd < kn) {
+                /* filled at lane kd: that order keeps the rest of its quantity, if any */
+                const int qk = rdlane(r.y, kd), xk = rdlane(x, kd);
+                if (xk < qk) {
+                    if (lane == kd) RQ<O>(j)->y = qk - xk;
+                    WAVE_SYNC();
+                    no -= kd;
+                } else {
+                    no -= kd + 1;
+                }
+                rem = 0;
                 break;
             }
-            no -= 1;
-            if (min(rem, no) == 0) break;
-            rec = &US<O>(0, no - 1);
-            pq = rec[0];
-            if (!MARKET && (uni(pq.x) ^ km(O)) > kp) break;
+            no -= nt;
+            rem -= rdlane((int)inc, nt - 1);
+            if (kn < WAVE || no == 0) break;
         }
         add_fill(agg_tid, S == 0, q - rem, notional);
         if (no != n_opp) {

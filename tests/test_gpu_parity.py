@@ -190,6 +190,49 @@ def test_sweeps_across_rows_and_empty_sides():
         assert_same_state(env.state(), o.state(), what=f"sweeps{agents}")
 
 
+@pytest.mark.parametrize("mode", ["rollout", "step"])
+def test_sweeps_of_a_row_or_more_that_stop(mode):
+    """Incoming orders that trade against 64 or more resting orders: exactly one row of
+    crossing orders and then an order that does not cross; a row and a part; an order
+    filled exactly by the 64th order; a market order across three rows; two full rows
+    and then a price that stops the sweep (remainder rests)."""
+    _, DeviceStream = _lob()
+    B = [
+        ([], [[1000, 2, 100 + k, 0, 1, k] for k in range(64)] + [[1050, 1, 300 + k, 0, 1, k] for k in range(20)]),
+        ([], [[1000, 2, 100 + k, 0, 1, k] for k in range(80)] + [[1050, 1, 300 + k, 0, 1, k] for k in range(20)]),
+        ([[990, 3, 100 + k, 0, 1, k] for k in range(64)] + [[980, 1, 300 + k, 0, 1, k] for k in range(10)], []),
+        ([], [[1000 + k // 10, 1, 100 + k, 0, 1, k] for k in range(130)]),
+        ([], [[1000, 1, 100 + k, 0, 1, k] for k in range(128)] + [[1100, 1, 300 + k, 0, 1, k] for k in range(5)]),
+    ]
+    snap = hand_book(B, 200)
+    steps = [
+        [[msg(LIMIT, BUY, 1020, 500, 9000)], [msg(MARKET, SELL, 0, 400, 9001)]],
+        [[msg(LIMIT, BUY, 1020, 500, 9000)], [msg(LIMIT, SELL, 1000, 10, 9001)]],
+        [[msg(LIMIT, SELL, 985, 192, 9000)], [msg(LIMIT, SELL, 985, 5, 9001)]],
+        [[msg(MARKET, BUY, 0, 129, 9000)], [msg(MARKET, BUY, 0, 5, 9001)]],
+        [[msg(LIMIT, BUY, 1000, 200, 9000)], [msg(MARKET, SELL, 0, 100, 9001)]],
+    ]
+    hs = hand_stream(steps)
+    caps = np.full(len(B), 200)
+    for agents in ((), ("exec", "mm")):
+        o = oracle_for(hs, snap, caps, 200, agents, 2, 5)
+        acts = np.zeros((2, len(agents), len(B)), np.int32)
+        ref = o.step(hs, n_steps=2, actions=acts if agents else None)
+        env = gpu_env(caps, 200, agents, 2, 5, snap)
+        ds = DeviceStream.from_host(hs)
+        toff = torch.from_numpy(ref["trade_off"]).cuda()
+        a = torch.from_numpy(acts).cuda() if agents else None
+        if mode == "rollout":
+            got = env.rollout(ds, 2, actions=a, trade_off=toff)
+        else:
+            got = run_steps(env, ds, 2, a, toff)
+        assert_same_outputs(got, ref, 2, what=f"deep sweeps {agents}")
+        assert_same_books(env.books(), o.books(), what=f"deep sweeps {agents}")
+        assert_same_state(env.state(), o.state(), what=f"deep sweeps {agents}")
+    # the sweeps did trade across rows: 64, 80, 64, 129 and 128 resting orders
+    assert ref["n_trades"][0].tolist() == [64, 80, 64, 129, 128]
+
+
 def test_trade_region_overflow_is_counted():
     _, DeviceStream = _lob()
     w = synth.Workload("overflow", n_envs=16, n_steps=8, msgs_per_step=100, cap=100, agents=("exec", "mm"), seed=39)
