@@ -15,9 +15,9 @@
  *     j%64 of row j/64 (see lob_device.h);
  *   - a book message is a few wave-wide LDS instructions: a ballot search from the top
  *     row down for cancels and for the insertion rank, a one-pass shift of the rows an
- *     insertion or removal touches (usually one), and matching that walks the resting
- *     orders from the top one at a time in scalar code (fills of the best order move
- *     nothing);
+ *     insertion or removal touches (usually one), and matching on the 64 best orders at
+ *     once (a prefix sum of their quantities finds the fill point; fills of the best
+ *     order move nothing);
  *   - agent orders and replayed messages run through one loop, 64 messages per chunk
  *     staged with coalesced SoA loads;
  *   - envs are grouped by capacity class (books spanning the same number of rows), each
@@ -424,10 +424,12 @@ struct Run {
 
     /* ---- matching: an incoming order of side S against the opposite side while it
      * crosses (market orders cross at any price); trades at the resting price, best
-     * first.  The 64 best orders are loaded at once, lane l holding the l-th best; when
-     * the best one alone does not fill the order, an inclusive prefix sum of the crossing
-     * quantities over the lanes finds where the order is filled, and the lanes up to that
-     * one write their trade records together.  Returns the unmatched remainder. ---- */
+     * first.  The best order is read first (one broadcast read); when it alone does not
+     * fill the order, the 64 best orders are loaded at once, lane l holding the l-th
+     * best, an inclusive prefix sum of the crossing quantities over the lanes finds
+     * where the order is filled, and the lanes up to that one write their trade records
+     * together (a sweep beyond 64 orders takes the next 64).  Returns the unmatched
+     * remainder. ---- */
     template <int S, bool MARKET>
     __device__ __forceinline__ int match(int p, int q, int agg_oid, int agg_tid) {
         constexpr int O = 1 - S;
@@ -437,7 +439,24 @@ struct Run {
         if (!MARKET && (bestS<O>() ^ km(O)) > kp) return q;
         int no = n_opp, rem = q, ntr = 0, last_price = 0;
         int64_t notional = 0;
-        for (;;) {
+        const int4 bo = *RQ<O>(no - 1); /* the best order (a broadcast read) */
+        const int bq = uni(bo.y);
+        if (bq >= rem) {
+            /* it fills the order (the common case): one trade, no row load */
+            const int bp = uni(bo.x), bt = uni(bo.w);
+            write_trade(0, bp, rem, agg_oid, uni(bo.z), agg_tid, bt, S);
+            add_fill(bt, S != 0, rem, (int64_t)rem * bp);
+            if (rem < bq) {
+                if (lane == 0) RQ<O>(no - 1)->y = bq - rem;
+                WAVE_SYNC();
+            } else {
+                no -= 1;
+            }
+            notional = (int64_t)rem * bp;
+            last_price = bp;
+            ntr = 1;
+            rem = 0;
+        } else for (;;) {
             /* lane l: the l-th best order of the opposite side (record no - 1 - l) */
             const int j = no - 1 - lane;
             const int4 r = *RQ<O>(max(j, 0));
@@ -447,7 +466,7 @@ struct Run {
             int kd, kn, nt;
             unsigned inc = 0, exc = 0;
             if (rdlane(r.y, 0) >= rem) {
-                kd = 0; /* the best order fills the rest (the common case) */
+                kd = 0; /* the row's best order fills the rest */
                 kn = nt = 1;
             } else {
                 inc = scan_sat(cross ? (unsigned)r.y : 0u);
@@ -1213,9 +1232,10 @@ struct Run {
 /* ------------------------------------------------------------------------------
  * Kernels
  * ---------------------------------------------------------------------------- */
-/* 256 threads, at least 6 waves per SIMD: caps registers at 80 VGPRs (the few spills
- * are outside the message loop) */
-__global__ void __launch_bounds__(256, 6) k_env(KArgs a) {
+/* 256 threads, at least 4 waves per SIMD: up to 128 VGPRs (it takes 110, no spills).
+ * LDS, not registers, bounds the resident envs of the large books; capping registers at
+ * 80 for 6 waves per SIMD spilled to scratch and was 2% slower on the uneven workload. */
+__global__ void __launch_bounds__(256, 4) k_env(KArgs a) {
     extern __shared__ int32_t smem[];
     const int wave = uni((int)(threadIdx.x >> 6)), waves = (int)(blockDim.x >> 6);
     int32_t *L = smem + wave * a.lds_words;
@@ -1423,7 +1443,7 @@ constexpr size_t LDS_PER_CU = 160 * 1024;  /* gfx950 */
 constexpr int64_t LANE_GAP_US = 50;      /* between class starts in a rollout */
 constexpr int64_t LANE_GAP_STEP_US = 10; /* between class starts in a one-step launch */
 constexpr int CONC_LANES = 3;               /* concurrent class launches (see launch_env) */
-constexpr int WAVES_PER_CU = 24;            /* 6 per SIMD at the env kernel's register use */
+constexpr int WAVES_PER_CU = 16;            /* 4 per SIMD at the env kernel's register use */
 constexpr int BALANCE_DEFAULT = 880;        /* permille of the LDS (measured best on uneven books) */
 constexpr int64_t STEP_ALLOWANCE = 8;       /* fixed per-env-step work, in messages */
 
