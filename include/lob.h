@@ -202,8 +202,9 @@ int lob_rollout(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps, const int32
  * class's envs by decreasing message count (longest first), so that the envs that bound
  * the runtime start first; with several classes and a balance share set (the default,
  * see lob_schedule_balance), it also sizes each class's work queue.  Reads the CSR
- * offsets back to the host (synchronous: it first waits for the device, so that no launch
- * still reading the previous plan's env list is running when the list is rewritten).
+ * offsets back to the host (synchronous: it first waits for this context's last launch,
+ * or for the whole device once a launch of it was captured into a graph, so that no
+ * launch still reading the previous plan's env list is running when it is rewritten).
  * Used by lob_step and lob_rollout until the next plan; results never depend on it. */
 int lob_plan(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps);
 
@@ -233,8 +234,9 @@ int lob_schedule_balance(lob_ctx *ctx, int32_t permille);
 /* Batching ablation.  padded = 1 puts every env into one class whose LDS books are
  * sized for the largest capacity (uniform padding, the batching a map over envs of
  * equal shape gives); padded = 0 restores one class per book row count (the default).
- * Resets the plan and the schedules; results never depend on it.  Waits for the device
- * (host-synchronous); not callable during stream capture. */
+ * Resets the plan and the schedules; results never depend on it.  Waits for this
+ * context's launches as lob_plan does (host-synchronous); not callable during stream
+ * capture. */
 int lob_set_padded(lob_ctx *ctx, int32_t padded);
 
 /* Autotuner: times schedules on the next n_steps of msgs from the current state

@@ -1463,6 +1463,10 @@ struct lob_ctx {
     std::vector<CapClass> classes;
     hipStream_t streams[MAX_CLASSES] = {};
     hipEvent_t ev_fork = nullptr, ev_join[MAX_CLASSES] = {};
+    /* recorded on the caller's stream after each launch (lanes joined): the host waits
+     * for it before rewriting what running launches read (env list, work queues) */
+    hipEvent_t ev_done = nullptr;
+    bool launched = false, captured = false;
     /* the plan: which (stream offsets, first step, steps) the env order was made for */
     const int64_t *plan_off = nullptr;
     int64_t plan_n_msgs = -1;
@@ -1510,6 +1514,7 @@ void free_ctx(lob_ctx *c) {
         if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
     }
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_done) (void)hipEventDestroy(c->ev_done);
     delete c;
 }
 
@@ -1637,7 +1642,23 @@ int launch_env(lob_ctx *c, KArgs a, hipStream_t st) {
             !hip_ok(hipStreamWaitEvent(st, c->ev_join[l], 0)))
             rc = rc != LOB_OK ? rc : LOB_EHIP;
     }
+    /* under stream capture the launch runs when the graph is replayed, which this
+     * context does not see: later waits fall back to the whole device */
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hip_ok(hipStreamIsCapturing(st, &cs)) && cs == hipStreamCaptureStatusNone) {
+        if (!hip_ok(hipEventRecord(c->ev_done, st))) rc = rc != LOB_OK ? rc : LOB_EHIP;
+        c->launched = true;
+    } else {
+        c->captured = true;
+    }
     return rc;
+}
+
+/* Wait until no launch of this context can still be running: the last eager launch's
+ * completion event, or the whole device once a launch was captured into a graph. */
+bool wait_launches(lob_ctx *c) {
+    if (c->captured) return hip_ok(hipDeviceSynchronize());
+    return !c->launched || hip_ok(hipEventSynchronize(c->ev_done));
 }
 
 /* Default waves (envs) per workgroup for a class: the most resident envs per CU, LDS
@@ -1760,8 +1781,8 @@ int make_plan(lob_ctx *c, const lob_msgs *m, int t0, int n) {
         return LOB_OK;
     /* a launch still running (on the caller's stream or the class streams, which do not
      * synchronise with the null stream) may be reading the env list and the schedule
-     * about to be rewritten: wait for the device first */
-    if (!hip_ok(hipDeviceSynchronize())) return LOB_EHIP;
+     * about to be rewritten: wait for it first */
+    if (!wait_launches(c)) return LOB_EHIP;
     const int N = c->cfg.n_envs;
     const size_t pitch = (size_t)(m->n_steps + 1) * sizeof(int64_t);
     std::vector<int64_t> a0((size_t)N), a1((size_t)N);
@@ -1866,6 +1887,7 @@ int lob_init(const lob_config *cfg, lob_ctx **out) {
 
     if ((rc = build_classes(c, false)) != LOB_OK) { free_ctx(c); return rc; }
     if (!hip_ok(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) ||
+        !hip_ok(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming)) ||
         !hip_ok(hipMemcpy(c->d_caps, c->caps.data(), (size_t)N * 4, hipMemcpyHostToDevice)) ||
         !hip_ok(hipMemcpy(c->d_avst, c->avst, sizeof(c->avst), hipMemcpyHostToDevice))) {
         free_ctx(c);
@@ -2000,7 +2022,7 @@ int lob_schedule_balance(lob_ctx *c, int32_t permille) {
 
 int lob_set_padded(lob_ctx *c, int32_t padded) {
     if (!c || (padded != 0 && padded != 1)) return LOB_EINVAL;
-    if (hipDeviceSynchronize() != hipSuccess) return LOB_EHIP;
+    if (!wait_launches(c)) return LOB_EHIP;
     return build_classes(c, padded != 0);
 }
 
