@@ -1176,7 +1176,15 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_seq(GruSeqArgs a) {
 
 /* ---- weight gradients over all T m samples: workgroup w takes a contiguous range of
  * samples (s = t m + env) and writes one partial of every parameter; the partials are
- * then summed in a fixed order ---- */
+ * then summed in a fixed order.  The range is staged through LDS DWK samples at a time
+ * (every operand read from memory once per workgroup), in two passes:
+ *   1. dW_i = E^T DGI and dW_h = HP^T DGH (HP zero at an episode start): 8 x 24 tiles
+ *      each, in blocks of 4 x 6 tiles, one block per wave; the bias sums of DGI, DGH;
+ *   2. dW_e = X^T DE (3 x 8 tiles, rows 40..47 dropped) and dW_o = HN^T DO (8 tiles),
+ *      two tiles per wave; the bias sums of DE and DO.
+ * The sample index is the MFMA k index: lane l supplies sample k0 + l / 16 of a row
+ * tile's column l % 16.  LDS rows are padded to 16 mod 64 words, so the four sample rows
+ * one MFMA step reads fall on disjoint banks. ---- */
 struct GruDwArgs {
     const float *obs;          /* [S][40] */
     const float *obs_scale;    /* [40] or null */
@@ -1185,83 +1193,157 @@ struct GruDwArgs {
     int64_t S, m;
     float *partial;            /* [grid][GPW] */
 };
-
-template <int NT, class FA, class FB>
-__device__ __forceinline__ void dw_tiles(floatx4 (&acc)[1][NT], int len, int r0, int c0, FA A, FB B) {
-#pragma unroll
-    for (int n = 0; n < NT; ++n) acc[0][n] = zero4();
-    gemm<1, NT>(acc, (len + 3) & ~3, r0, c0, [&](int i, int k) { return k < len ? A(i, k) : 0.f; },
-                [&](int k, int j) { return k < len ? B(k, j) : 0.f; });
-}
+constexpr int DWK = 16;                                    /* samples per staged chunk */
+constexpr int DSH = GHD + 16, DSG = G3 + 16, DSX = 80, DSO = 16;
+constexpr int DW_LDS = DWK * (2 * DSH + 2 * DSG);           /* floats (pass 1; pass 2 needs less) */
+static_assert(DWK * (DSX + 2 * DSH + DSO) <= DW_LDS, "pass 2 fits in pass 1's LDS");
+static_assert(GRU_DW_TH == 1024 && DWK % 4 == 0, "16 waves: the 16 blocks of pass 1, 32 tiles of pass 2");
 
 __global__ void __launch_bounds__(GRU_DW_TH) k_gru_dw(GruDwArgs a) {
+    extern __shared__ float sm[];
     const int64_t s0 = a.S * (int64_t)blockIdx.x / gridDim.x, s1 = a.S * (int64_t)(blockIdx.x + 1) / gridDim.x;
     const int len = (int)(s1 - s0);
     float *G = a.partial + (int64_t)blockIdx.x * GPW;
-    const int tid = (int)threadIdx.x, wave = tid >> 6;
-    const float *Eb = a.E + s0 * GHD, *DGIb = a.DGI + s0 * G3, *DGHb = a.DGH + s0 * G3, *DEb = a.DE + s0 * GHD;
-    const float *HPb = a.HS + s0 * GHD, *HNb = a.HS + (s0 + a.m) * GHD, *DOb = a.DO + s0 * 16;
-    const float *Xb = a.obs + s0 * GIN;
-    const uint8_t *Sb = a.start + s0;
-    /* dW_i = E^T DGI and dW_h = HP^T DGH (HP zero at an episode start): 8 x 24 tiles each,
-     * a wave takes one row tile and 12 column tiles, three at a time */
-    const int rt = wave & 7, cb = (wave >> 3) * 12;
-    for (int c3 = 0; c3 < 12; c3 += 3) {
-        floatx4 acc[1][3];
-        dw_tiles<3>(acc, len, 16 * rt, 16 * (cb + c3), [&](int i, int k) { return Eb[(int64_t)k * GHD + i]; },
-                    [&](int k, int j) { return DGIb[(int64_t)k * G3 + j]; });
+    const int tid = (int)threadIdx.x, wave = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+
+    /* pass 1 */
+    {
+        float *sE = sm, *sHP = sE + DWK * DSH, *sGI = sHP + DWK * DSH, *sGH = sGI + DWK * DSG;
+        const bool hh = wave >= 8; /* waves 0..7: dW_i, 8..15: dW_h */
+        const int r0 = 64 * ((wave >> 2) & 1), c0 = 96 * (wave & 3);
+        const float *sA = hh ? sHP : sE, *sB = hh ? sGH : sGI;
+        floatx4 acc[4][6];
 #pragma unroll
-        for (int n = 0; n < 3; ++n)
+        for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                G[GO_WI + (16 * rt + acc_row(i)) * G3 + 16 * (cb + c3 + n) + acc_col()] = acc[0][n][i];
-        dw_tiles<3>(acc, len, 16 * rt, 16 * (cb + c3),
-                    [&](int i, int k) { return Sb[k] ? 0.f : HPb[(int64_t)k * GHD + i]; },
-                    [&](int k, int j) { return DGHb[(int64_t)k * G3 + j]; });
-#pragma unroll
-        for (int n = 0; n < 3; ++n)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                G[GO_WH + (16 * rt + acc_row(i)) * G3 + 16 * (cb + c3 + n) + acc_col()] = acc[0][n][i];
-    }
-    /* dW_e = X^T DE (3 x 8 tiles, rows 40..47 dropped) and dW_o = HN^T DO (8 tiles) */
-    for (int tt = wave; tt < 24 + 8; tt += GRU_DW_TH / 64) {
-        floatx4 acc[1][1];
-        if (tt < 24) {
-            const int r0 = 16 * (tt / 8), c0 = 16 * (tt % 8);
-            dw_tiles<1>(acc, len, r0, c0,
-                        [&](int i, int k) { return i < GIN ? obs_in(Xb, a.obs_scale, (int64_t)k * GIN + i, i) : 0.f; },
-                        [&](int k, int j) { return DEb[(int64_t)k * GHD + j]; });
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = r0 + acc_row(i);
-                if (r < GIN) G[GO_WE + r * GHD + c0 + acc_col()] = acc[0][0][i];
+            for (int n = 0; n < 6; ++n) acc[m][n] = zero4();
+        float bsum = 0.f; /* threads below 768: column tid of [DGI | DGH] */
+        for (int k0 = 0; k0 < len; k0 += DWK) {
+            const int kc = min(DWK, len - k0);
+            __syncthreads();
+            for (int q = tid; q < DWK * (GHD / 4); q += GRU_DW_TH) {
+                const int r = q / (GHD / 4), c = 4 * (q % (GHD / 4));
+                floatx4 e = zero4(), h = zero4();
+                if (r < kc) {
+                    const int64_t sa = s0 + k0 + r;
+                    e = gload4(a.E + sa * GHD + c);
+                    if (!a.start[sa]) h = gload4(a.HS + sa * GHD + c);
+                }
+                *(floatx4 *)(sE + r * DSH + c) = e;
+                *(floatx4 *)(sHP + r * DSH + c) = h;
             }
-        } else {
-            const int r0 = 16 * (tt - 24);
-            dw_tiles<1>(acc, len, r0, 0, [&](int i, int k) { return HNb[(int64_t)k * GHD + i]; },
-                        [&](int k, int j) { return DOb[(int64_t)k * 16 + j]; });
+            for (int q = tid; q < DWK * (G3 / 4); q += GRU_DW_TH) {
+                const int r = q / (G3 / 4), c = 4 * (q % (G3 / 4));
+                floatx4 gi = zero4(), gh = zero4();
+                if (r < kc) {
+                    const int64_t sa = s0 + k0 + r;
+                    gi = gload4(a.DGI + sa * G3 + c);
+                    gh = gload4(a.DGH + sa * G3 + c);
+                }
+                *(floatx4 *)(sGI + r * DSG + c) = gi;
+                *(floatx4 *)(sGH + r * DSG + c) = gh;
+            }
+            __syncthreads();
+            if (tid < 2 * G3) {
+                const float *col = tid < G3 ? sGI + tid : sGH + (tid - G3);
+                for (int r = 0; r < kc; ++r) bsum += col[r * DSG];
+            }
+            for (int kk = 0; kk < kc; kk += 4) {
+                float av[4], bv[6];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (acc_col() < OUT) G[GO_WO + (r0 + acc_row(i)) * OUT + acc_col()] = acc[0][0][i];
+                for (int m = 0; m < 4; ++m) av[m] = sA[(kk + lk) * DSH + r0 + 16 * m + li];
+#pragma unroll
+                for (int n = 0; n < 6; ++n) bv[n] = sB[(kk + lk) * DSG + c0 + 16 * n + li];
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int n = 0; n < 6; ++n) acc[m][n] = mfma(av[m], bv[n], acc[m][n]);
+            }
         }
+        float *W = G + (hh ? GO_WH : GO_WI);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 6; ++n)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    W[(r0 + 16 * m + acc_row(i)) * G3 + c0 + 16 * n + acc_col()] = acc[m][n][i];
+        if (tid < G3) G[GO_BI + tid] = bsum;
+        else if (tid < 2 * G3) G[GO_BH + tid - G3] = bsum;
     }
-    /* biases: column sums in sample order */
-    for (int c = tid; c < G3 + G3 + GHD + OUT; c += GRU_DW_TH) {
-        float v = 0.f;
-        if (c < G3) {
-            for (int k = 0; k < len; ++k) v += DGIb[(int64_t)k * G3 + c];
-            G[GO_BI + c] = v;
-        } else if (c < 2 * G3) {
-            for (int k = 0; k < len; ++k) v += DGHb[(int64_t)k * G3 + c - G3];
-            G[GO_BH + c - G3] = v;
-        } else if (c < 2 * G3 + GHD) {
-            for (int k = 0; k < len; ++k) v += DEb[(int64_t)k * GHD + c - 2 * G3];
-            G[GO_BE + c - 2 * G3] = v;
+
+    /* pass 2: waves 0..11 two dW_e tiles (row tile wave / 4, column tiles 2 (wave % 4) and
+     * the next), waves 12..15 two dW_o tiles (row tiles 2 (wave - 12) and the next) */
+    {
+        float *sX = sm, *sDE = sX + DWK * DSX, *sHN = sDE + DWK * DSH, *sDO = sHN + DWK * DSH;
+        const bool wo = wave >= 12;
+        const float *sA0, *sA1, *sB0, *sB1;
+        int sa_, sb_;
+        if (!wo) {
+            const int rt = wave >> 2, ct = 2 * (wave & 3);
+            sA0 = sA1 = sX + 16 * rt; sB0 = sDE + 16 * ct; sB1 = sDE + 16 * (ct + 1);
+            sa_ = DSX; sb_ = DSH;
         } else {
-            for (int k = 0; k < len; ++k) v += DOb[(int64_t)k * 16 + c - 2 * G3 - GHD];
-            G[GO_BO + c - 2 * G3 - GHD] = v;
+            const int rt = 2 * (wave - 12);
+            sA0 = sHN + 16 * rt; sA1 = sHN + 16 * (rt + 1); sB0 = sB1 = sDO;
+            sa_ = DSH; sb_ = DSO;
         }
+        floatx4 acc[2] = {zero4(), zero4()};
+        float bsum = 0.f; /* threads below 128 + 10: column tid of [DE | DO] */
+        for (int k0 = 0; k0 < len; k0 += DWK) {
+            const int kc = min(DWK, len - k0);
+            __syncthreads();
+            for (int q = tid; q < DWK * DSX; q += GRU_DW_TH) {
+                const int r = q / DSX, c = q % DSX;
+                sX[q] = (r < kc && c < GIN) ? obs_in(a.obs, a.obs_scale, (s0 + k0 + r) * GIN + c, c) : 0.f;
+            }
+            for (int q = tid; q < DWK * (GHD / 4); q += GRU_DW_TH) {
+                const int r = q / (GHD / 4), c = 4 * (q % (GHD / 4));
+                floatx4 d = zero4(), h = zero4();
+                if (r < kc) {
+                    const int64_t sa = s0 + k0 + r;
+                    d = gload4(a.DE + sa * GHD + c);
+                    h = gload4(a.HS + (sa + a.m) * GHD + c);
+                }
+                *(floatx4 *)(sDE + r * DSH + c) = d;
+                *(floatx4 *)(sHN + r * DSH + c) = h;
+            }
+            for (int q = tid; q < DWK * 4; q += GRU_DW_TH) {
+                const int r = q / 4, c = 4 * (q % 4);
+                *(floatx4 *)(sDO + r * DSO + c) = r < kc ? gload4(a.DO + (s0 + k0 + r) * 16 + c) : zero4();
+            }
+            __syncthreads();
+            if (tid < GHD + OUT) {
+                const float *col = tid < GHD ? sDE + tid : sDO + (tid - GHD);
+                const int st = tid < GHD ? DSH : DSO;
+                for (int r = 0; r < kc; ++r) bsum += col[r * st];
+            }
+            for (int kk = 0; kk < kc; kk += 4) {
+                const float a0 = sA0[(kk + lk) * sa_ + li], a1 = sA1[(kk + lk) * sa_ + li];
+                const float b0 = sB0[(kk + lk) * sb_ + li], b1 = sB1[(kk + lk) * sb_ + li];
+                acc[0] = mfma(a0, b0, acc[0]);
+                acc[1] = mfma(a1, b1, acc[1]);
+            }
+        }
+        if (!wo) {
+            const int rt = wave >> 2, ct = 2 * (wave & 3);
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * rt + acc_row(i);
+                    if (r < GIN) G[GO_WE + r * GHD + 16 * (ct + n) + acc_col()] = acc[n][i];
+                }
+        } else {
+            const int rt = 2 * (wave - 12);
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (acc_col() < OUT) G[GO_WO + (16 * (rt + n) + acc_row(i)) * OUT + acc_col()] = acc[n][i];
+        }
+        if (tid < GHD) G[GO_BE + tid] = bsum;
+        else if (tid < GHD + OUT) G[GO_BO + tid - GHD] = bsum;
     }
     if (tid < GPW - GNP) G[GNP + tid] = 0.f;
 }
@@ -1303,7 +1385,9 @@ bool lds_opt_in() {
             hipFuncSetAttribute(reinterpret_cast<const void *>(k_gru_step),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, GRU_STEP_LDS * 4) != hipSuccess ||
             hipFuncSetAttribute(reinterpret_cast<const void *>(k_gru_seq),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, GRU_SEQ_LDS * 4) != hipSuccess)
+                                hipFuncAttributeMaxDynamicSharedMemorySize, GRU_SEQ_LDS * 4) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(k_gru_dw),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, DW_LDS * 4) != hipSuccess)
             return false;
         done = true;
     }
@@ -1479,7 +1563,7 @@ int lob_gru_ppo_fwd_bwd(const float *params, const float *obs, const float *obs_
     GruDwArgs d;
     d.obs = obs; d.obs_scale = obs_scale; d.start = start; d.HS = a.HS; d.E = a.E; d.DGI = a.DGI; d.DGH = a.DGH; d.DE = a.DE; d.DO = a.DO;
     d.S = (int64_t)T * m; d.m = m; d.partial = ws + w.part;
-    hipLaunchKernelGGL(k_gru_dw, dim3((unsigned)w.nwg), dim3(GRU_DW_TH), 0, st, d);
+    hipLaunchKernelGGL(k_gru_dw, dim3((unsigned)w.nwg), dim3(GRU_DW_TH), DW_LDS * 4, st, d);
     hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((GPW / 4 + 255) / 256), (unsigned)w.nch), dim3(256), 0, st,
                        (const floatx4 *)(ws + w.part), w.nwg, GPW / 4, (floatx4 *)(ws + w.sums));
     hipLaunchKernelGGL(k_reduce_out, dim3((unsigned)((GNP + 255) / 256)), dim3(256), 0, st, (const float *)(ws + w.sums),
