@@ -387,16 +387,19 @@ int lob_gru_step(const float *params, const float *obs, const float *obs_scale, 
                  float *logits, int32_t *actions, float *logp, float *value, void *stream);
 
 /* Bytes of device workspace lob_gru_ppo_fwd_bwd needs for m sequences of T steps
- * (LOB_EINVAL for T or m <= 0): the hidden states, the per-sample gradients of the
- * gates, embedding and outputs and the recomputed embedding (1,168 floats per sample),
- * plus the weight-gradient partials. */
+ * (LOB_EINVAL for T or m <= 0): the hidden states, the per-sample embedding, input-gate
+ * products (then their gradients), hidden-gate gradients, embedding and output gradients
+ * (1,168 floats per sample), loss sums per 64 samples, the prepared weights and the
+ * weight-gradient partials. */
 int64_t lob_gru_ppo_workspace_bytes(int32_t T, int32_t m);
 
 /* The clipped-PPO loss (the same per-sample terms as lob_ppo_fwd_bwd, averaged over the T
  * m samples) of one network over a minibatch of m whole sequences, and its gradient
  * through time.  obs [T][m][40] (obs_scale as for lob_policy_forward), start [T][m] uint8, h0 [m][128] (the state before step
- * 0), act, logp_old, adv, ret, v_old [T][m] (device).  The forward pass keeps only the
- * hidden states; the backward pass recomputes each step's embedding, gates and outputs.
+ * 0), act, logp_old, adv, ret, v_old [T][m] (device).  The products that do not depend on
+ * the previous state (embedding, input gates, outputs and loss terms, embedding gradient,
+ * weight gradients) run batched over all samples; the forward recurrence keeps only the
+ * hidden states and the backward one recomputes each step's hidden-gate products.
  * Writes loss [4] (sums over the samples of the total, policy, value and entropy terms)
  * and grad [LOB_GRU_PARAMS] (gradient of the mean total loss).  workspace: device,
  * 16-byte aligned, >= lob_gru_ppo_workspace_bytes(T, m) (LOB_EINVAL otherwise).

@@ -831,54 +831,6 @@ constexpr int GPF = 4; /* 16-k blocks in flight in the sequence kernel's product
 
 __device__ __forceinline__ floatx4 gload4(const float *p) { return *(const floatx4 *)p; }
 
-/* the products of the sequence kernel on the prepared weights (biases from P) */
-__device__ __forceinline__ void gru_embed_w(const float *__restrict__ P, const GruW &w, const float *X, float *E, int wave,
-                                            int nw) {
-    for (int ct = wave; ct < GHD / 16; ct += nw) {
-        floatx4 acc[1][1] = {{zero4()}};
-        gemm16p<1, 1, 3>(acc, GINP, 0, 16 * ct, [&](int i, int kb) { return lds4(X + i * XS + kb); },
-                         [&](int kb, int j) { return gload4(w.WeT + j * GINP + kb); });
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = acc_row(i), c = 16 * ct + acc_col();
-            E[r * HSG + c] = tanh_exp(acc[0][0][i] + P[GO_BE + c]);
-        }
-    }
-}
-__device__ __forceinline__ void gru_gates_w(const float *__restrict__ P, const GruW &w, const float *E, const float *HP,
-                                            float *GI, float *GH, int wave, int nw) {
-    const int per = 2 * (G3 / 16) / nw;
-    for (int c3 = 0; c3 < per; c3 += 3) {
-        const int ct0 = wave * per + c3;
-        const bool hh = ct0 >= G3 / 16;
-        const int c0 = 16 * (hh ? ct0 - G3 / 16 : ct0);
-        const float *A = hh ? HP : E;
-        const float *WT = hh ? w.WhT : w.WiT;
-        floatx4 acc[1][3] = {{zero4(), zero4(), zero4()}};
-        gemm16p<1, 3, GPF>(acc, GHD, 0, c0, [&](int i, int kb) { return lds4(A + i * HSG + kb); },
-                           [&](int kb, int j) { return gload4(WT + j * GHD + kb); });
-        float *D = hh ? GH : GI;
-        const float *bias = P + (hh ? GO_BH : GO_BI);
-#pragma unroll
-        for (int n = 0; n < 3; ++n)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = acc_row(i), c = c0 + 16 * n + acc_col();
-                D[r * GS + c] = acc[0][n][i] + bias[c];
-            }
-    }
-}
-__device__ __forceinline__ void gru_head_w(const float *__restrict__ P, const GruW &w, const float *HN, float *O) {
-    floatx4 acc[1][1] = {{zero4()}};
-    gemm16p<1, 1, GPF>(acc, GHD, 0, 0, [&](int i, int kb) { return lds4(HN + i * HSG + kb); },
-                       [&](int kb, int j) { return gload4(w.WoT + j * GHD + kb); });
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = acc_row(i), c = acc_col();
-        O[r * OS + c] = c < OUT ? acc[0][0][i] + P[GO_BO + c] : 0.f;
-    }
-}
-
 /* ---- one step of the rollout: grid (ceil(n / 16), n_agents), GRU_STEP_TH threads ---- */
 struct GruStepArgs {
     const float *params;  /* [A][GNP] */
@@ -937,14 +889,19 @@ __global__ void __launch_bounds__(GRU_STEP_TH) k_gru_step(GruStepArgs a) {
 }
 
 /* ---- clipped-PPO loss over whole sequences, forward and backward through time ----
- * k_gru_seq: one workgroup per tile of 16 sequences.  Forward: the recurrence over the T
- * steps, keeping only the hidden states (HS [T+1][m][128], HS[0] = h0).  Backward, t =
- * T-1 .. 0: the embedding, gates and outputs of step t are recomputed from x_t and
- * h_{t-1}, the per-sample loss gradient dO is formed, and dh (carried from step t+1) is
- * taken back through the cell; the gradients w.r.t. the gate pre-activations (DGI, DGH),
- * the embedding pre-activation (DE), the outputs (DO) and the recomputed embedding (E) go
- * to the workspace for the weight-gradient products, which k_gru_dw forms over all T m
- * samples at once. */
+ * Only the recurrence h_{t-1} -> h_t is sequential; everything that does not depend on
+ * the previous state runs as batched products over all T m samples (s = t m + env):
+ *   k_gru_in   E = tanh(X W_e + b_e) and GI = E W_i + b_i of every sample;
+ *   k_gru_fwd  one workgroup per tile of 16 sequences: GH = h_{t-1} W_h + b_h and the
+ *              cell, t = 0 .. T-1, keeping only the hidden states (HS [T+1][m][128],
+ *              HS[0] = h0, HS[t] = h_{t-1} as stored before an episode start zeroes it);
+ *   k_gru_head the outputs h_t W_o + b_o, the per-sample loss terms and their gradient dO;
+ *   k_gru_bwd  one workgroup per tile: t = T-1 .. 0, GH recomputed from h_{t-1}, dh
+ *              (carried from step t+1, plus dO W_o^T) taken back through the cell into the
+ *              gate pre-activation gradients DGI, DGH (DGI overwrites the sample's GI),
+ *              and dh_{t-1} = u dh + DGH W_h^T;
+ *   k_gru_de   the embedding pre-activation gradient DE = (DGI W_i^T) (1 - E^2);
+ * then k_gru_dw forms the weight gradients over all samples. */
 struct GruSeqArgs {
     const float *params, *obs;  /* obs [T][m][40] */
     const float *obs_scale;     /* [40] or null */
@@ -957,71 +914,130 @@ struct GruSeqArgs {
     float *HS, *E, *DGI, *DGH, *DE, *DO, *LS; /* workspace */
     GruW w;                     /* prepared weights (workspace) */
 };
-constexpr int GRU_SEQ_LDS = TG * (XS + 4 * HSG + 4 * GS + OS) + TG;
+constexpr int TI = 64;          /* samples per workgroup of the batched kernels */
+constexpr int GRU_IN_TH = 512, GRU_HEAD_TH = 256;
+constexpr int GRU_IN_LDS = TI * (XS + HSG);                   /* X and E tiles */
+constexpr int GRU_FWD_LDS = TG * (2 * HSG + 2 * GS);           /* HP, HN, GI, GH */
+constexpr int GRU_BWD_LDS = TG * (3 * HSG + 3 * GS + 16) + TG; /* HP, DH, DHO, GI, GH, DGH, DO, ST */
+constexpr int GRU_HEAD_LDS = TI * (OS + 4);                    /* outputs, loss terms */
+static_assert(GRU_IN_TH == 512 && GRU_SEQ_TH == 512, "8 waves: 8 column tiles of 128, 24 of 384");
 
-__global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_seq(GruSeqArgs a) {
+/* E and GI of the 64 samples from s0 = 64 blockIdx.x (the last workgroup may have fewer) */
+__global__ void __launch_bounds__(GRU_IN_TH) k_gru_in(GruSeqArgs a) {
     extern __shared__ float sm[];
-    float *X = sm, *E = X + TG * XS, *HP = E + TG * HSG, *HN = HP + TG * HSG, *DH = HN + TG * HSG, *GI = DH + TG * HSG,
-          *GH = GI + TG * GS, *DGI = GH + TG * GS, *DGH = DGI + TG * GS, *O = DGH + TG * GS;
-    float *ST = O + TG * OS; /* the step's episode-start flag of each row (backward pass) */
-    const int row0 = (int)blockIdx.x * TG, rows = min(TG, a.m - row0);
-    const int tid = (int)threadIdx.x, wave = tid >> 6, nw = GRU_SEQ_TH / 64;
-    const float *__restrict__ P = a.params;
-    const int T = a.T, m = a.m;
-    /* A step's inputs (its observation tile, the episode-start flags of the rows a thread
-     * handles, in the backward pass the stored state h_{t-1} and the per-sample PPO inputs)
-     * are loaded into registers one step ahead, so that no step waits on device memory. */
-    constexpr int XE = (TG * XS + GRU_SEQ_TH - 1) / GRU_SEQ_TH, HE = TG * GHD / GRU_SEQ_TH;
-    static_assert(TG * GHD % GRU_SEQ_TH == 0, "state elements per thread");
-    float xv[XE], hv[HE];
-    uint8_t sv[HE];
-    auto load_x = [&](int t) {
+    float *X = sm, *E = X + TI * XS;
+    const int64_t S = (int64_t)a.T * a.m, s0 = (int64_t)blockIdx.x * TI;
+    const int rows = (int)min((int64_t)TI, S - s0);
+    const int tid = (int)threadIdx.x, wave = tid >> 6;
+    for (int i = tid; i < TI * XS; i += GRU_IN_TH) {
+        const int r = i / XS, c = i % XS;
+        X[i] = (r < rows && c < GIN) ? obs_in(a.obs, a.obs_scale, (s0 + r) * GIN + c, c) : 0.f;
+    }
+    __syncthreads();
+    {
+        /* E: column tile `wave` of the four row tiles */
+        floatx4 acc[4][1] = {{zero4()}, {zero4()}, {zero4()}, {zero4()}};
+        gemm16p<4, 1, 3>(acc, GINP, 0, 16 * wave, [&](int i, int kb) { return lds4(X + i * XS + kb); },
+                         [&](int kb, int j) { return gload4(a.w.WeT + j * GINP + kb); });
 #pragma unroll
-        for (int k = 0; k < XE; ++k) {
-            const int i = tid + k * GRU_SEQ_TH, r = i / XS, c = i % XS;
-            xv[k] = (i < TG * XS && r < rows && c < GIN)
-                        ? obs_in(a.obs, a.obs_scale, ((int64_t)t * m + row0 + r) * GIN + c, c) : 0.f;
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * mt + acc_row(i), c = 16 * wave + acc_col();
+                const float e = tanh_exp(acc[mt][0][i] + a.params[GO_BE + c]);
+                E[r * HSG + c] = e;
+                if (r < rows) a.E[(s0 + r) * GHD + c] = e;
+            }
+    }
+    __syncthreads();
+    {
+        /* GI: column tiles 3 wave .. 3 wave + 2 of the four row tiles */
+        floatx4 acc[4][3];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int n = 0; n < 3; ++n) acc[mt][n] = zero4();
+        gemm16p<4, 3, 2>(acc, GHD, 0, 48 * wave, [&](int i, int kb) { return lds4(E + i * HSG + kb); },
+                         [&](int kb, int j) { return gload4(a.w.WiT + j * GHD + kb); });
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int n = 0; n < 3; ++n)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * mt + acc_row(i), c = 48 * wave + 16 * n + acc_col();
+                    if (r < rows) a.DGI[(s0 + r) * G3 + c] = acc[mt][n][i] + a.params[GO_BI + c];
+                }
+    }
+}
+
+/* GH = HP W_h + b_h for a tile: column tiles 3 wave .. 3 wave + 2 */
+__device__ __forceinline__ void gru_gh(const float *__restrict__ P, const GruW &w, const float *HP, float *GH, int wave) {
+    floatx4 acc[1][3] = {{zero4(), zero4(), zero4()}};
+    gemm16p<1, 3, GPF>(acc, GHD, 0, 48 * wave, [&](int i, int kb) { return lds4(HP + i * HSG + kb); },
+                       [&](int kb, int j) { return gload4(w.WhT + j * GHD + kb); });
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = acc_row(i), c = 48 * wave + 16 * n + acc_col();
+            GH[r * GS + c] = acc[0][n][i] + P[GO_BH + c];
         }
-    };
-    auto store_x = [&]() {
+}
+
+/* A step's GI rows (three float4 per thread) and the episode-start flags of the rows a
+ * thread handles are loaded into registers one step ahead, so that no step waits on
+ * device memory. */
+constexpr int GRU_GE = TG * G3 / 4 / GRU_SEQ_TH, GRU_HE = TG * GHD / GRU_SEQ_TH;
+static_assert(TG * G3 % (4 * GRU_SEQ_TH) == 0 && TG * GHD % GRU_SEQ_TH == 0, "whole elements per thread");
+
+__global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_fwd(GruSeqArgs a) {
+    extern __shared__ float sm[];
+    float *HP = sm, *HN = HP + TG * HSG, *GI = HN + TG * HSG, *GH = GI + TG * GS;
+    const int row0 = (int)blockIdx.x * TG, rows = min(TG, a.m - row0);
+    const int tid = (int)threadIdx.x, wave = tid >> 6;
+    const int T = a.T, m = a.m;
+    floatx4 gv[GRU_GE];
+    uint8_t sv[GRU_HE];
+    auto load_gi = [&](int t) {
 #pragma unroll
-        for (int k = 0; k < XE; ++k) {
-            const int i = tid + k * GRU_SEQ_TH;
-            if (i < TG * XS) X[i] = xv[k];
+        for (int k = 0; k < GRU_GE; ++k) {
+            const int q = tid + k * GRU_SEQ_TH, r = q / (G3 / 4), c = 4 * (q % (G3 / 4));
+            gv[k] = r < rows ? gload4(a.DGI + ((int64_t)t * m + row0 + r) * G3 + c) : zero4();
         }
     };
     auto load_start = [&](int t) {
 #pragma unroll
-        for (int k = 0; k < HE; ++k) {
+        for (int k = 0; k < GRU_HE; ++k) {
             const int r = (tid + k * GRU_SEQ_TH) / GHD;
             sv[k] = r < rows ? a.start[(int64_t)t * m + row0 + r] : 1;
         }
     };
-    /* forward: h0, then the recurrence; HS[t] is h_{t-1} as stored (before an episode
-     * start zeroes it) */
     for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
         const int r = i / GHD, c = i % GHD;
         const float v = r < rows ? a.h0[(int64_t)(row0 + r) * GHD + c] : 0.f;
         HN[r * HSG + c] = v;
         if (r < rows) a.HS[(int64_t)(row0 + r) * GHD + c] = v;
     }
-    load_x(0);
+    load_gi(0);
     load_start(0);
     for (int t = 0; t < T; ++t) {
-        store_x();
 #pragma unroll
-        for (int k = 0; k < HE; ++k) {
+        for (int k = 0; k < GRU_GE; ++k) {
+            const int q = tid + k * GRU_SEQ_TH, r = q / (G3 / 4), c = 4 * (q % (G3 / 4));
+            *(floatx4 *)(GI + r * GS + c) = gv[k];
+        }
+#pragma unroll
+        for (int k = 0; k < GRU_HE; ++k) {
             const int i = tid + k * GRU_SEQ_TH, r = i / GHD, c = i % GHD;
             HP[r * HSG + c] = sv[k] ? 0.f : HN[r * HSG + c];
         }
         if (t + 1 < T) {
-            load_x(t + 1);
+            load_gi(t + 1);
             load_start(t + 1);
         }
         __syncthreads();
-        gru_embed_w(P, a.w, X, E, wave, nw);
-        __syncthreads();
-        gru_gates_w(P, a.w, E, HP, GI, GH, wave, nw);
+        gru_gh(a.params, a.w, HP, GH, wave);
         __syncthreads();
         gru_update(GI, GH, HP, HN, tid, GRU_SEQ_TH, false);
         __syncthreads();
@@ -1030,148 +1046,176 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_seq(GruSeqArgs a) {
             if (r < rows) a.HS[((int64_t)(t + 1) * m + row0 + r) * GHD + c] = HN[r * HSG + c];
         }
     }
-    /* backward */
-    for (int i = tid; i < TG * HSG; i += GRU_SEQ_TH) DH[i] = 0.f;
-    float lsum[4] = {0.f, 0.f, 0.f, 0.f};
-    auto load_h = [&](int t) {
+}
+
+/* the outputs of the 64 samples from s0 = 64 blockIdx.x (h_t of sample s is HS[s + m]),
+ * their loss terms and dO (scaled by 1 / (T m)); the workgroup's loss sums in sample
+ * order */
+__global__ void __launch_bounds__(GRU_HEAD_TH) k_gru_head(GruSeqArgs a) {
+    extern __shared__ float sm[];
+    float *O = sm, *LT = O + TI * OS;
+    const int64_t S = (int64_t)a.T * a.m, s0 = (int64_t)blockIdx.x * TI;
+    const int rows = (int)min((int64_t)TI, S - s0);
+    const int tid = (int)threadIdx.x, wave = tid >> 6;
+    {
+        /* row tile `wave` */
+        floatx4 acc[1][1] = {{zero4()}};
+        const int r0 = 16 * wave;
+        gemm16p<1, 1, GPF>(acc, GHD, 0, 0,
+                           [&](int i, int kb) {
+                               return r0 + i < rows ? gload4(a.HS + (s0 + r0 + i + a.m) * GHD + kb) : zero4();
+                           },
+                           [&](int kb, int j) { return gload4(a.w.WoT + j * GHD + kb); });
 #pragma unroll
-        for (int k = 0; k < HE; ++k) {
+        for (int i = 0; i < 4; ++i) {
+            const int r = r0 + acc_row(i), c = acc_col();
+            O[r * OS + c] = c < OUT ? acc[0][0][i] + a.params[GO_BO + c] : 0.f;
+        }
+    }
+    __syncthreads();
+    if (tid < TI) {
+        float dz[OUT], ls[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < OUT; ++j) dz[j] = 0.f;
+        if (tid < rows) {
+            const int64_t s = s0 + tid;
+            loss_head(O + tid * OS, a.n_act, a.act[s], a.logp_old[s], a.adv[s], a.ret[s], a.v_old[s], a.clip, a.c_v,
+                      a.c_e, a.scale, dz, ls);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) a.DO[s * 16 + j] = j < OUT ? dz[j] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) LT[tid * 4 + q] = ls[q];
+    }
+    __syncthreads();
+    if (tid < 4) {
+        float v = 0.f;
+        for (int r = 0; r < TI; ++r) v += LT[r * 4 + tid];
+        a.LS[(int64_t)blockIdx.x * 4 + tid] = v;
+    }
+}
+
+__global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_bwd(GruSeqArgs a) {
+    extern __shared__ float sm[];
+    float *HP = sm, *DH = HP + TG * HSG, *DHO = DH + TG * HSG, *GI = DHO + TG * HSG, *GH = GI + TG * GS,
+          *DGH = GH + TG * GS, *DOt = DGH + TG * GS;
+    float *ST = DOt + TG * 16; /* the step's episode-start flag of each row */
+    const int row0 = (int)blockIdx.x * TG, rows = min(TG, a.m - row0);
+    const int tid = (int)threadIdx.x, wave = tid >> 6;
+    const int T = a.T, m = a.m;
+    floatx4 gv[GRU_GE], dov = zero4();
+    float hv[GRU_HE];
+    uint8_t sv[GRU_HE];
+    auto load = [&](int t) {
+#pragma unroll
+        for (int k = 0; k < GRU_GE; ++k) {
+            const int q = tid + k * GRU_SEQ_TH, r = q / (G3 / 4), c = 4 * (q % (G3 / 4));
+            gv[k] = r < rows ? gload4(a.DGI + ((int64_t)t * m + row0 + r) * G3 + c) : zero4();
+        }
+#pragma unroll
+        for (int k = 0; k < GRU_HE; ++k) {
             const int i = tid + k * GRU_SEQ_TH, r = i / GHD, c = i % GHD;
+            sv[k] = r < rows ? a.start[(int64_t)t * m + row0 + r] : 1;
             hv[k] = r < rows ? a.HS[((int64_t)t * m + row0 + r) * GHD + c] : 0.f;
         }
-    };
-    /* the per-sample PPO inputs of row tid (threads below 16) */
-    int pa = 0;
-    float plo = 0.f, pad = 0.f, pre = 0.f, pvo = 0.f;
-    auto load_ppo = [&](int t) {
-        if (tid < rows) {
-            const int64_t s = (int64_t)t * m + row0 + tid;
-            pa = a.act[s]; plo = a.logp_old[s]; pad = a.adv[s]; pre = a.ret[s]; pvo = a.v_old[s];
+        if (tid < TG * 4) {
+            const int r = tid / 4, c = 4 * (tid % 4);
+            dov = r < rows ? gload4(a.DO + ((int64_t)t * m + row0 + r) * 16 + c) : zero4();
         }
     };
-    load_x(T - 1);
-    load_start(T - 1);
-    load_h(T - 1);
-    load_ppo(T - 1);
+    for (int i = tid; i < TG * HSG; i += GRU_SEQ_TH) DH[i] = 0.f;
+    load(T - 1);
     for (int t = T - 1; t >= 0; --t) {
         __syncthreads();
-        store_x();
 #pragma unroll
-        for (int k = 0; k < HE; ++k) {
+        for (int k = 0; k < GRU_GE; ++k) {
+            const int q = tid + k * GRU_SEQ_TH, r = q / (G3 / 4), c = 4 * (q % (G3 / 4));
+            *(floatx4 *)(GI + r * GS + c) = gv[k];
+        }
+#pragma unroll
+        for (int k = 0; k < GRU_HE; ++k) {
             const int i = tid + k * GRU_SEQ_TH, r = i / GHD, c = i % GHD;
             HP[r * HSG + c] = sv[k] ? 0.f : hv[k];
             if (c == 0) ST[r] = sv[k] ? 1.f : 0.f;
         }
-        const int cur_a = pa;
-        const float cur_lo = plo, cur_ad = pad, cur_re = pre, cur_vo = pvo;
-        if (t > 0) {
-            load_x(t - 1);
-            load_start(t - 1);
-            load_h(t - 1);
-            load_ppo(t - 1);
-        }
+        if (tid < TG * 4) *(floatx4 *)(DOt + (tid / 4) * 16 + 4 * (tid % 4)) = dov;
+        if (t > 0) load(t - 1);
         __syncthreads();
-        gru_embed_w(P, a.w, X, E, wave, nw);
-        __syncthreads();
-        gru_gates_w(P, a.w, E, HP, GI, GH, wave, nw);
-        __syncthreads();
-        gru_update(GI, GH, HP, HN, tid, GRU_SEQ_TH, true);
-        __syncthreads();
-        if (wave == 0) gru_head_w(P, a.w, HN, O);
-        __syncthreads();
-        /* per-sample loss terms and dO (scaled by 1 / (T m)) */
-        if (tid < TG) {
-            float *z = O + tid * OS;
-            float dz[OUT];
-#pragma unroll
-            for (int j = 0; j < OUT; ++j) dz[j] = 0.f;
-            if (tid < rows) {
-                float ls[4];
-                loss_head(z, a.n_act, cur_a, cur_lo, cur_ad, cur_re, cur_vo, a.clip, a.c_v, a.c_e, a.scale, dz, ls);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) lsum[q] += ls[q];
-            }
-            for (int j = 0; j < OUT; ++j) z[j] = dz[j];
-            if (tid < rows) {
-                const int64_t s = (int64_t)t * m + row0 + tid;
-#pragma unroll
-                for (int j = 0; j < 16; ++j) a.DO[s * 16 + j] = j < OUT ? dz[j] : 0.f;
-            }
-        }
-        /* the recomputed embedding for the weight products */
-        for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
-            const int r = i / GHD, c = i % GHD;
-            if (r < rows) a.E[((int64_t)t * m + row0 + r) * GHD + c] = E[r * HSG + c];
-        }
-        __syncthreads();
-        /* dh += dO W_o^T (K = 16, rows 10..15 of W_o^T zero) */
-        if (wave < GHD / 16) {
+        /* GH recomputed from h_{t-1}, and dO W_o^T (column tile `wave`, K = 16, rows 10..15
+         * of W_o^T zero) */
+        gru_gh(a.params, a.w, HP, GH, wave);
+        {
             floatx4 acc[1][1] = {{zero4()}};
-            gemm16p<1, 1, 1>(acc, 16, 0, 16 * wave,
-                             [&](int i, int kb) {
-                                 return floatx4{O[i * OS + kb], O[i * OS + kb + 1], O[i * OS + kb + 2], O[i * OS + kb + 3]};
-                             },
+            gemm16p<1, 1, 1>(acc, 16, 0, 16 * wave, [&](int i, int kb) { return lds4(DOt + i * 16 + kb); },
                              [&](int kb, int j) { return gload4(a.w.WoP + j * 16 + kb); });
 #pragma unroll
-            for (int i = 0; i < 4; ++i) DH[acc_row(i) * HSG + 16 * wave + acc_col()] += acc[0][0][i];
+            for (int i = 0; i < 4; ++i) DHO[acc_row(i) * HSG + 16 * wave + acc_col()] = acc[0][0][i];
         }
         __syncthreads();
-        /* back through the cell: gate pre-activation gradients; DH keeps the direct part
-         * u dh of dh_{t-1} */
+        /* the cell again and back through it: gate pre-activation gradients (to the
+         * workspace, DGI over the sample's GI); DH keeps the direct part u dh of dh_{t-1} */
         for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
             const int r = i / GHD, j = i % GHD;
-            const float dh = DH[r * HSG + j];
-            const float rr = GI[r * GS + j], u = GI[r * GS + GHD + j], nn = GI[r * GS + 2 * GHD + j];
-            const float hp = HP[r * HSG + j], ghn = GH[r * GS + 2 * GHD + j];
+            const float *gi = GI + r * GS, *gh = GH + r * GS;
+            const float rr = sigmoid_exp(gi[j] + gh[j]);
+            const float u = sigmoid_exp(gi[GHD + j] + gh[GHD + j]);
+            const float ghn = gh[2 * GHD + j];
+            const float nn = tanh_exp(gi[2 * GHD + j] + rr * ghn);
+            const float hp = HP[r * HSG + j];
+            const float dh = DH[r * HSG + j] + DHO[r * HSG + j];
             const float dnp = dh * (1.f - u) * (1.f - nn * nn);
             const float dup = dh * (hp - nn) * u * (1.f - u);
             const float drp = dnp * ghn * rr * (1.f - rr);
-            DGI[r * GS + j] = drp;
-            DGI[r * GS + GHD + j] = dup;
-            DGI[r * GS + 2 * GHD + j] = dnp;
             DGH[r * GS + j] = drp;
             DGH[r * GS + GHD + j] = dup;
             DGH[r * GS + 2 * GHD + j] = dnp * rr;
             DH[r * HSG + j] = dh * u;
-        }
-        __syncthreads();
-        for (int i = tid; i < TG * G3; i += GRU_SEQ_TH) {
-            const int r = i / G3, c = i % G3;
             if (r < rows) {
-                const int64_t s = (int64_t)t * m + row0 + r;
-                a.DGI[s * G3 + c] = DGI[r * GS + c];
-                a.DGH[s * G3 + c] = DGH[r * GS + c];
+                const int64_t s = ((int64_t)t * m + row0 + r) * G3;
+                a.DGI[s + j] = drp;
+                a.DGI[s + GHD + j] = dup;
+                a.DGI[s + 2 * GHD + j] = dnp;
+                a.DGH[s + j] = drp;
+                a.DGH[s + GHD + j] = dup;
+                a.DGH[s + 2 * GHD + j] = dnp * rr;
             }
         }
-        /* dh_{t-1} += DGH W_h^T and de = (DGI W_i^T) (1 - e^2), K = 384: one column tile of
-         * each per wave */
+        __syncthreads();
+        /* dh_{t-1} = u dh + DGH W_h^T (column tile `wave`, K = 384), zero at an episode
+         * start (also set for rows past the last sequence) */
         {
-            floatx4 acc[1][1] = {{zero4()}}, acd[1][1] = {{zero4()}};
+            floatx4 acc[1][1] = {{zero4()}};
             gemm16p<1, 1, 2 * GPF>(acc, G3, 0, 16 * wave, [&](int i, int kb) { return lds4(DGH + i * GS + kb); },
                                    [&](int kb, int j) { return gload4(a.w.Wh + j * G3 + kb); });
-            gemm16p<1, 1, 2 * GPF>(acd, G3, 0, 16 * wave, [&](int i, int kb) { return lds4(DGI + i * GS + kb); },
-                                   [&](int kb, int j) { return gload4(a.w.Wi + j * G3 + kb); });
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = acc_row(i), c = 16 * wave + acc_col();
-                const bool stop = ST[r] != 0.f; /* also set for rows past the last sequence */
-                DH[r * HSG + c] = stop ? 0.f : DH[r * HSG + c] + acc[0][0][i];
-                const float e = E[r * HSG + c];
-                if (r < rows) a.DE[((int64_t)t * m + row0 + r) * GHD + c] = acd[0][0][i] * (1.f - e * e);
+                DH[r * HSG + c] = ST[r] != 0.f ? 0.f : DH[r * HSG + c] + acc[0][0][i];
             }
         }
     }
-    /* loss sums of the tile in row order */
-    __syncthreads();
-    if (tid < TG)
+}
+
+/* DE = (DGI W_i^T) (1 - E^2) of the 64 samples from s0 = 64 blockIdx.x: column tile
+ * `wave` of the four row tiles */
+__global__ void __launch_bounds__(GRU_IN_TH) k_gru_de(GruSeqArgs a) {
+    const int64_t S = (int64_t)a.T * a.m, s0 = (int64_t)blockIdx.x * TI;
+    const int rows = (int)min((int64_t)TI, S - s0);
+    const int wave = (int)threadIdx.x >> 6;
+    floatx4 acc[4][1] = {{zero4()}, {zero4()}, {zero4()}, {zero4()}};
+    gemm16p<4, 1, GPF>(acc, G3, 0, 16 * wave,
+                       [&](int i, int kb) { return i < rows ? gload4(a.DGI + (s0 + i) * G3 + kb) : zero4(); },
+                       [&](int kb, int j) { return gload4(a.w.Wi + j * G3 + kb); });
 #pragma unroll
-        for (int q = 0; q < 4; ++q) O[tid * OS + q] = lsum[q];
-    __syncthreads();
-    if (tid < 4) {
-        float v = 0.f;
-        for (int r = 0; r < TG; ++r) v += O[r * OS + tid];
-        a.LS[(int64_t)blockIdx.x * 4 + tid] = v;
-    }
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * mt + acc_row(i), c = 16 * wave + acc_col();
+            if (r < rows) {
+                const float e = a.E[(s0 + r) * GHD + c];
+                a.DE[(s0 + r) * GHD + c] = acc[mt][0][i] * (1.f - e * e);
+            }
+        }
 }
 
 /* ---- weight gradients over all T m samples: workgroup w takes a contiguous range of
@@ -1357,7 +1401,7 @@ __global__ void k_reduce_out(const float *__restrict__ sums, int nch, int pitch,
     out[j] = s;
 }
 
-/* the tiles' loss sums in tile order */
+/* the workgroups' loss sums in workgroup (sample) order */
 __global__ void k_gru_loss(const float *__restrict__ LS, int ntile, float *loss) {
     const int q = (int)threadIdx.x;
     if (q >= 4) return;
@@ -1384,8 +1428,10 @@ bool lds_opt_in() {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, LDS_FLOATS * 4) != hipSuccess ||
             hipFuncSetAttribute(reinterpret_cast<const void *>(k_gru_step),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, GRU_STEP_LDS * 4) != hipSuccess ||
-            hipFuncSetAttribute(reinterpret_cast<const void *>(k_gru_seq),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, GRU_SEQ_LDS * 4) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(k_gru_fwd),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, GRU_FWD_LDS * 4) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(k_gru_bwd),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, GRU_BWD_LDS * 4) != hipSuccess ||
             hipFuncSetAttribute(reinterpret_cast<const void *>(k_gru_dw),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, DW_LDS * 4) != hipSuccess)
             return false;
@@ -1396,12 +1442,13 @@ bool lds_opt_in() {
 /* the GRU loss workspace, in floats from its start (every part a multiple of 4 floats) */
 struct GruWs {
     int64_t hs, e, dgi, dgh, de, dout, ls, wts, part, sums, total;
-    int ntile, nwg, nch;
+    int ntile, nin, nwg, nch;
 };
 GruWs gru_ws(int32_t T, int32_t m) {
     GruWs w{};
     const int64_t S = (int64_t)T * m;
     w.ntile = (m + TG - 1) / TG;
+    w.nin = (int)((S + TI - 1) / TI);
     w.nwg = (int)std::min<int64_t>(GRU_DW_WGS, (S + 63) / 64);
     w.nch = (w.nwg + RCH - 1) / RCH;
     int64_t o = 0;
@@ -1411,7 +1458,7 @@ GruWs gru_ws(int32_t T, int32_t m) {
     w.dgh = o; o += S * G3;
     w.de = o; o += S * GHD;
     w.dout = o; o += S * 16;
-    w.ls = o; o += (int64_t)w.ntile * 4;
+    w.ls = o; o += (int64_t)w.nin * 4;
     w.wts = o; o += GW_FLOATS;
     w.part = o; o += (int64_t)w.nwg * GPW;
     w.sums = o; o += (int64_t)w.nch * GPW;
@@ -1559,7 +1606,11 @@ int lob_gru_ppo_fwd_bwd(const float *params, const float *obs, const float *obs_
     a.LS = ws + w.ls;
     const float *W = ws + w.wts;
     a.w = GruW{W + GW_WET, W + GW_WIT, W + GW_WHT, W + GW_WI, W + GW_WH, W + GW_WOT, W + GW_WOP};
-    hipLaunchKernelGGL(k_gru_seq, dim3((unsigned)w.ntile), dim3(GRU_SEQ_TH), GRU_SEQ_LDS * 4, st, a);
+    hipLaunchKernelGGL(k_gru_in, dim3((unsigned)w.nin), dim3(GRU_IN_TH), GRU_IN_LDS * 4, st, a);
+    hipLaunchKernelGGL(k_gru_fwd, dim3((unsigned)w.ntile), dim3(GRU_SEQ_TH), GRU_FWD_LDS * 4, st, a);
+    hipLaunchKernelGGL(k_gru_head, dim3((unsigned)w.nin), dim3(GRU_HEAD_TH), GRU_HEAD_LDS * 4, st, a);
+    hipLaunchKernelGGL(k_gru_bwd, dim3((unsigned)w.ntile), dim3(GRU_SEQ_TH), GRU_BWD_LDS * 4, st, a);
+    hipLaunchKernelGGL(k_gru_de, dim3((unsigned)w.nin), dim3(GRU_IN_TH), 0, st, a);
     GruDwArgs d;
     d.obs = obs; d.obs_scale = obs_scale; d.start = start; d.HS = a.HS; d.E = a.E; d.DGI = a.DGI; d.DGH = a.DGH; d.DE = a.DE; d.DO = a.DO;
     d.S = (int64_t)T * m; d.m = m; d.partial = ws + w.part;
@@ -1568,7 +1619,7 @@ int lob_gru_ppo_fwd_bwd(const float *params, const float *obs, const float *obs_
                        (const floatx4 *)(ws + w.part), w.nwg, GPW / 4, (floatx4 *)(ws + w.sums));
     hipLaunchKernelGGL(k_reduce_out, dim3((unsigned)((GNP + 255) / 256)), dim3(256), 0, st, (const float *)(ws + w.sums),
                        w.nch, GPW, GNP, grad);
-    hipLaunchKernelGGL(k_gru_loss, dim3(1), dim3(64), 0, st, (const float *)(ws + w.ls), w.ntile, loss);
+    hipLaunchKernelGGL(k_gru_loss, dim3(1), dim3(64), 0, st, (const float *)(ws + w.ls), w.nin, loss);
     return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
 }
 

@@ -124,10 +124,11 @@ def test_host_side_checks_of_the_noalloc_ppo_call():
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="liblob.so not built")
 def test_host_side_checks_of_the_recurrent_actor_critic():
-    """Workspace size of the recurrent loss (per sample: hidden state, embedding, gate,
-    embedding and output gradients = 128 + 128 + 384 + 384 + 128 + 16 floats; one more
-    hidden state per sequence; loss sums per 16-sequence tile; the weights prepared for
-    16-byte loads (W_e^T, W_i^T, W_h^T, W_i, W_h, W_o^T and W_o padded); weight-gradient partials of 105,612 floats for one workgroup per 64
+    """Workspace size of the recurrent loss (per sample: hidden state, embedding, input
+    gates then their gradients, hidden-gate, embedding and output gradients = 128 + 128 +
+    384 + 384 + 128 + 16 floats; one more hidden state per sequence; loss sums per 64
+    samples; the weights prepared for 16-byte loads (W_e^T, W_i^T, W_h^T, W_i, W_h, W_o^T
+    and W_o padded); weight-gradient partials of 105,612 floats for one workgroup per 64
     samples, at most 256, and the first reduction level's chunk sums) and argument
     checks before any device call."""
     lib = ctypes.CDLL(LIB)
@@ -140,7 +141,7 @@ def test_host_side_checks_of_the_recurrent_actor_critic():
         nwg = min(256, (S + 63) // 64)
         nch = (nwg + 63) // 64
         weights = 128 * 48 + 4 * 384 * 128 + 2 * 16 * 128  # the sequence kernel's prepared weights
-        return 4 * ((T + 1) * m * 128 + S * (128 + 384 + 384 + 128 + 16) + ((m + 15) // 16) * 4 + weights
+        return 4 * ((T + 1) * m * 128 + S * (128 + 384 + 384 + 128 + 16) + ((S + 63) // 64) * 4 + weights
                     + (nwg + nch) * 105612)
     assert lib.lob_gru_ppo_workspace_bytes(0, 5) == -1 and lib.lob_gru_ppo_workspace_bytes(5, 0) == -1
     for T, m in ((1, 1), (8, 20), (128, 1024)):
