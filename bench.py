@@ -237,8 +237,8 @@ def gru_bench(reps: int = 3):
             "update": "GAE + 4 epochs x 4 minibatches (1024 sequences of 128 steps) x 2 agents + Adam",
             "gru_ppo_fwd_bwd_call": {"sequences": m, "steps": T, "samples": T * m, "ms": call_ms,
                                      "flop_per_sample": GRU_FLOP_PER_SAMPLE,
-                                     "launches": "k_gru_prep, k_gru_seq, k_gru_dw, k_reduce_chunks, "
-                                                 "k_reduce_out, k_gru_loss",
+                                     "launches": "k_gru_prep, k_gru_in, k_gru_fwd, k_gru_head, k_gru_bwd, "
+                                                 "k_gru_de, k_gru_dw, k_reduce_chunks, k_reduce_out, k_gru_loss",
                                      "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
                                                   "unit": "TFLOP/s", "frac": tflops / FP32_MFMA_PEAK_TFLOPS}}}
 

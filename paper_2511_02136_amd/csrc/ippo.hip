@@ -1401,13 +1401,25 @@ __global__ void k_reduce_out(const float *__restrict__ sums, int nch, int pitch,
     out[j] = s;
 }
 
-/* the workgroups' loss sums in workgroup (sample) order */
-__global__ void k_gru_loss(const float *__restrict__ LS, int ntile, float *loss) {
-    const int q = (int)threadIdx.x;
-    if (q >= 4) return;
-    float s = 0.f;
-    for (int i = 0; i < ntile; ++i) s += LS[(int64_t)i * 4 + q];
-    loss[q] = s;
+/* the workgroups' loss sums in a fixed order: thread i adds the contiguous run of entries
+ * [i n / 256, (i + 1) n / 256) in order, then those 256 sums are added in thread order */
+constexpr int GRU_LOSS_TH = 256;
+__global__ void __launch_bounds__(GRU_LOSS_TH) k_gru_loss(const float *__restrict__ LS, int n, float *loss) {
+    __shared__ float part[GRU_LOSS_TH][4];
+    const int tid = (int)threadIdx.x;
+    const int lo = (int)((int64_t)n * tid / GRU_LOSS_TH), hi = (int)((int64_t)n * (tid + 1) / GRU_LOSS_TH);
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int i = lo; i < hi; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += LS[(int64_t)i * 4 + q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[tid][q] = v[q];
+    __syncthreads();
+    if (tid < 4) {
+        float sum = 0.f;
+        for (int i = 0; i < GRU_LOSS_TH; ++i) sum += part[i][tid];
+        loss[tid] = sum;
+    }
 }
 
 __global__ void k_bump(uint64_t *c) {
@@ -1619,7 +1631,7 @@ int lob_gru_ppo_fwd_bwd(const float *params, const float *obs, const float *obs_
                        (const floatx4 *)(ws + w.part), w.nwg, GPW / 4, (floatx4 *)(ws + w.sums));
     hipLaunchKernelGGL(k_reduce_out, dim3((unsigned)((GNP + 255) / 256)), dim3(256), 0, st, (const float *)(ws + w.sums),
                        w.nch, GPW, GNP, grad);
-    hipLaunchKernelGGL(k_gru_loss, dim3(1), dim3(64), 0, st, (const float *)(ws + w.ls), w.nin, loss);
+    hipLaunchKernelGGL(k_gru_loss, dim3(1), dim3(GRU_LOSS_TH), 0, st, (const float *)(ws + w.ls), w.nin, loss);
     return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
 }
 
