@@ -715,7 +715,7 @@ constexpr int GPW = GNP + 2;  /* per-workgroup gradient partial, a multiple of 4
 constexpr int TG = 16;        /* rows (envs) per tile */
 constexpr int HSG = GHD + 4;  /* LDS row strides */
 constexpr int GS = G3 + 4;
-constexpr int GRU_STEP_TH = 256, GRU_SEQ_TH = 512, GRU_DW_TH = 1024;
+constexpr int GRU_STEP_TH = 512, GRU_SEQ_TH = 512, GRU_DW_TH = 1024;
 constexpr int GRU_DW_WGS = 256; /* workgroups of the weight-gradient kernel */
 
 __device__ __forceinline__ float sigmoid_exp(float x) {
@@ -723,51 +723,11 @@ __device__ __forceinline__ float sigmoid_exp(float x) {
     return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(-x * 1.4426950408889634f));
 }
 
-/* e = tanh(X W_e + b_e) for a tile (X [16][XS], cols 40..47 zero) into E [16][HSG] */
-__device__ __forceinline__ void gru_embed(const float *__restrict__ P, const float *X, float *E, int wave, int nw) {
-    for (int ct = wave; ct < GHD / 16; ct += nw) {
-        floatx4 acc[1][1] = {{zero4()}};
-        gemm<1, 1>(acc, GINP, 0, 16 * ct, [&](int i, int k) { return X[i * XS + k]; },
-                   [&](int k, int j) { return k < GIN ? P[GO_WE + k * GHD + j] : 0.f; });
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = acc_row(i), c = 16 * ct + acc_col();
-            E[r * HSG + c] = tanh_exp(acc[0][0][i] + P[GO_BE + c]);
-        }
-    }
-}
-
-/* GI = E W_i + b_i and GH = HP W_h + b_h for a tile: 48 column tiles of 16 over the waves,
- * three at a time (independent accumulators) */
-__device__ __forceinline__ void gru_gates(const float *__restrict__ P, const float *E, const float *HP, float *GI,
-                                          float *GH, int wave, int nw) {
-    const int per = 2 * (G3 / 16) / nw; /* column tiles per wave, a multiple of 3 */
-    for (int c3 = 0; c3 < per; c3 += 3) {
-        const int ct0 = wave * per + c3; /* a wave's tiles never straddle GI and GH */
-        const bool hh = ct0 >= G3 / 16;
-        const int c0 = 16 * (hh ? ct0 - G3 / 16 : ct0);
-        const float *A = hh ? HP : E;
-        const float *W = P + (hh ? GO_WH : GO_WI);
-        floatx4 acc[1][3] = {{zero4(), zero4(), zero4()}};
-        gemm<1, 3>(acc, GHD, 0, c0, [&](int i, int k) { return A[i * HSG + k]; },
-                   [&](int k, int j) { return W[k * G3 + j]; });
-        float *D = hh ? GH : GI;
-        const float *bias = P + (hh ? GO_BH : GO_BI);
-#pragma unroll
-        for (int n = 0; n < 3; ++n)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = acc_row(i), c = c0 + 16 * n + acc_col();
-                D[r * GS + c] = acc[0][n][i] + bias[c];
-            }
-    }
-}
-
 /* the gates and the new state: HN = (1 - u) n + u HP; with keep, GI's three column
  * blocks are overwritten by r, u and n */
 __device__ __forceinline__ void gru_update(float *GI, const float *GH, const float *HP, float *HN, int tid, int nth,
-                                           bool keep) {
-    for (int i = tid; i < TG * GHD; i += nth) {
+                                           bool keep, int nrow = TG) {
+    for (int i = tid; i < nrow * GHD; i += nth) {
         const int r = i / GHD, j = i % GHD;
         const float *gi = GI + r * GS, *gh = GH + r * GS;
         const float rr = sigmoid_exp(gi[j] + gh[j]);
@@ -779,18 +739,6 @@ __device__ __forceinline__ void gru_update(float *GI, const float *GH, const flo
             GI[r * GS + GHD + j] = u;
             GI[r * GS + 2 * GHD + j] = nn;
         }
-    }
-}
-
-/* O = HN W_o + b_o (cols 10..15 zero): one wave */
-__device__ __forceinline__ void gru_head(const float *__restrict__ P, const float *HN, float *O) {
-    floatx4 acc[1][1] = {{zero4()}};
-    gemm<1, 1>(acc, GHD, 0, 0, [&](int i, int k) { return HN[i * HSG + k]; },
-               [&](int k, int j) { return j < OUT ? P[GO_WO + k * OUT + j] : 0.f; });
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = acc_row(i), c = acc_col();
-        O[r * OS + c] = c < OUT ? acc[0][0][i] + P[GO_BO + c] : 0.f;
     }
 }
 
@@ -831,7 +779,10 @@ constexpr int GPF = 4; /* 16-k blocks in flight in the sequence kernel's product
 
 __device__ __forceinline__ floatx4 gload4(const float *p) { return *(const floatx4 *)p; }
 
-/* ---- one step of the rollout: grid (ceil(n / 16), n_agents), GRU_STEP_TH threads ---- */
+/* ---- one step of the rollout: grid (ceil(n / 32), n_agents), GRU_STEP_TH threads.  A
+ * workgroup takes 32 envs of one agent (two row tiles), so every weight it streams from
+ * the caches serves 32 rows; the state products on v_mfma_f32_16x16x4f32, the cell, the
+ * head and the sampling. ---- */
 struct GruStepArgs {
     const float *params;  /* [A][GNP] */
     const float *obs;     /* [A][n][40] */
@@ -848,37 +799,87 @@ struct GruStepArgs {
     int32_t *actions;
     float *logp, *value;
 };
-constexpr int GRU_STEP_LDS = TG * (XS + 3 * HSG + 2 * GS + OS);
+constexpr int TS = 32; /* envs per workgroup of the rollout step */
+constexpr int GRU_STEP_LDS = TS * (XS + 3 * HSG + 2 * GS + OS);
+static_assert(GRU_STEP_TH == 512, "8 waves: 8 column tiles of 128, 48 of the two gate products");
 
 __global__ void __launch_bounds__(GRU_STEP_TH) k_gru_step(GruStepArgs a) {
     extern __shared__ float sm[];
-    float *X = sm, *E = X + TG * XS, *HP = E + TG * HSG, *HN = HP + TG * HSG, *GI = HN + TG * HSG,
-          *GH = GI + TG * GS, *O = GH + TG * GS;
-    const int ag = (int)blockIdx.y, row0 = (int)blockIdx.x * TG, rows = min(TG, a.n - row0);
-    const int tid = (int)threadIdx.x, wave = tid >> 6, nw = GRU_STEP_TH / 64;
+    float *X = sm, *E = X + TS * XS, *HP = E + TS * HSG, *HN = HP + TS * HSG, *GI = HN + TS * HSG,
+          *GH = GI + TS * GS, *O = GH + TS * GS;
+    const int ag = (int)blockIdx.y, row0 = (int)blockIdx.x * TS, rows = min(TS, a.n - row0);
+    const int tid = (int)threadIdx.x, wave = tid >> 6;
     const float *P = a.params + (int64_t)ag * GNP;
     const int64_t base = (int64_t)ag * a.n + row0;
-    for (int i = tid; i < TG * XS; i += GRU_STEP_TH) {
+    for (int i = tid; i < TS * XS; i += GRU_STEP_TH) {
         const int r = i / XS, c = i % XS;
         X[i] = (r < rows && c < GIN) ? obs_in(a.obs, a.obs_scale, (base + r) * GIN + c, c) : 0.f;
     }
-    for (int i = tid; i < TG * GHD; i += GRU_STEP_TH) {
+    for (int i = tid; i < TS * GHD; i += GRU_STEP_TH) {
         const int r = i / GHD, c = i % GHD;
         const bool zero = r >= rows || (a.start && a.start[row0 + r]);
         HP[r * HSG + c] = zero ? 0.f : a.h_in[(base + r) * GHD + c];
     }
     __syncthreads();
-    gru_embed(P, X, E, wave, nw);
+    {
+        /* E = tanh(X W_e + b_e): column tile `wave` of both row tiles */
+        floatx4 acc[2][1] = {{zero4()}, {zero4()}};
+        gemm<2, 1>(acc, GINP, 0, 16 * wave, [&](int i, int k) { return X[i * XS + k]; },
+                   [&](int k, int j) { return k < GIN ? P[GO_WE + k * GHD + j] : 0.f; });
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * mt + acc_row(i), c = 16 * wave + acc_col();
+                E[r * HSG + c] = tanh_exp(acc[mt][0][i] + P[GO_BE + c]);
+            }
+    }
     __syncthreads();
-    gru_gates(P, E, HP, GI, GH, wave, nw);
+    /* GI = E W_i + b_i and GH = HP W_h + b_h: column tiles 6 wave .. 6 wave + 5 of the 48
+     * (24 of each product; a wave's tiles never straddle the two), three at a time */
+    for (int c3 = 0; c3 < 6; c3 += 3) {
+        const int ct0 = 6 * wave + c3;
+        const bool hh = ct0 >= G3 / 16;
+        const int c0 = 16 * (hh ? ct0 - G3 / 16 : ct0);
+        const float *A = hh ? HP : E;
+        const float *W = P + (hh ? GO_WH : GO_WI);
+        floatx4 acc[2][3];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int n = 0; n < 3; ++n) acc[mt][n] = zero4();
+        gemm<2, 3>(acc, GHD, 0, c0, [&](int i, int k) { return A[i * HSG + k]; },
+                   [&](int k, int j) { return W[k * G3 + j]; });
+        float *D = hh ? GH : GI;
+        const float *bias = P + (hh ? GO_BH : GO_BI);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int n = 0; n < 3; ++n)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * mt + acc_row(i), c = c0 + 16 * n + acc_col();
+                    D[r * GS + c] = acc[mt][n][i] + bias[c];
+                }
+    }
     __syncthreads();
-    gru_update(GI, GH, HP, HN, tid, GRU_STEP_TH, false);
+    gru_update(GI, GH, HP, HN, tid, GRU_STEP_TH, false, TS);
     __syncthreads();
-    for (int i = tid; i < TG * GHD; i += GRU_STEP_TH) {
+    for (int i = tid; i < TS * GHD; i += GRU_STEP_TH) {
         const int r = i / GHD, c = i % GHD;
         if (r < rows) a.h_out[(base + r) * GHD + c] = HN[r * HSG + c];
     }
-    if (wave == 0) gru_head(P, HN, O);
+    if (wave < 2) {
+        /* O = HN W_o + b_o (cols 10..15 zero): row tile `wave` */
+        floatx4 acc[1][1] = {{zero4()}};
+        gemm<1, 1>(acc, GHD, 16 * wave, 0, [&](int i, int k) { return HN[i * HSG + k]; },
+                   [&](int k, int j) { return j < OUT ? P[GO_WO + k * OUT + j] : 0.f; });
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * wave + acc_row(i), c = acc_col();
+            O[r * OS + c] = c < OUT ? acc[0][0][i] + P[GO_BO + c] : 0.f;
+        }
+    }
     __syncthreads();
     if (tid < rows) {
         const uint64_t seed = a.epoch ? a.seed + 0x9E3779B97F4A7C15ULL * a.epoch[0] : a.seed;
@@ -1585,7 +1586,7 @@ int lob_gru_step(const float *params, const float *obs, const float *obs_scale, 
     }
     a.seed = seed; a.epoch = epoch; a.t = t; a.logits = logits; a.actions = actions; a.logp = logp; a.value = value;
     if (!lds_opt_in()) return LOB_EHIP;
-    hipLaunchKernelGGL(k_gru_step, dim3((unsigned)((n + TG - 1) / TG), (unsigned)n_agents), dim3(GRU_STEP_TH),
+    hipLaunchKernelGGL(k_gru_step, dim3((unsigned)((n + TS - 1) / TS), (unsigned)n_agents), dim3(GRU_STEP_TH),
                        GRU_STEP_LDS * 4, (hipStream_t)stream, a);
     return hipGetLastError() == hipSuccess ? LOB_OK : LOB_EHIP;
 }
