@@ -918,8 +918,8 @@ struct GruSeqArgs {
 constexpr int TI = 64;          /* samples per workgroup of the batched kernels */
 constexpr int GRU_IN_TH = 512, GRU_HEAD_TH = 256;
 constexpr int GRU_IN_LDS = TI * (XS + HSG);                   /* X and E tiles */
-constexpr int GRU_FWD_LDS = TG * (2 * HSG + 2 * GS);           /* HP, HN, GI, GH */
-constexpr int GRU_BWD_LDS = TG * (3 * HSG + 3 * GS + 16) + TG; /* HP, DH, DHO, GI, GH, DGH, DO, ST */
+constexpr int GRU_FWD_LDS = TG * (HSG + 3 * GS);               /* HP, GH, two GI buffers */
+constexpr int GRU_BWD_LDS = TG * (4 * HSG + 4 * GS + 32) + 2 * TG; /* DH, DHO, GH, DGH; two of HP, GI, dO, ST */
 constexpr int GRU_HEAD_LDS = TI * (OS + 4);                    /* outputs, loss terms */
 static_assert(GRU_IN_TH == 512 && GRU_SEQ_TH == 512, "8 waves: 8 column tiles of 128, 24 of 384");
 
@@ -987,65 +987,72 @@ __device__ __forceinline__ void gru_gh(const float *__restrict__ P, const GruW &
 }
 
 /* A step's GI rows (three float4 per thread) and the episode-start flags of the rows a
- * thread handles are loaded into registers one step ahead, so that no step waits on
+ * thread handles are loaded into registers ahead of their step, so that no step waits on
  * device memory. */
 constexpr int GRU_GE = TG * G3 / 4 / GRU_SEQ_TH, GRU_HE = TG * GHD / GRU_SEQ_TH;
 static_assert(TG * G3 % (4 * GRU_SEQ_TH) == 0 && TG * GHD % GRU_SEQ_TH == 0, "whole elements per thread");
 
+/* Two barriers per step: GH = HP W_h + b_h, then the cell, which also writes the next
+ * step's input state (HP, zeroed at an episode start; each thread its own elements) and
+ * stores the next step's GI rows into the other of two GI buffers. */
 __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_fwd(GruSeqArgs a) {
     extern __shared__ float sm[];
-    float *HP = sm, *HN = HP + TG * HSG, *GI = HN + TG * HSG, *GH = GI + TG * GS;
+    float *HP = sm, *GH = HP + TG * HSG, *GIb = GH + TG * GS; /* GIb: two buffers */
     const int row0 = (int)blockIdx.x * TG, rows = min(TG, a.m - row0);
     const int tid = (int)threadIdx.x, wave = tid >> 6;
     const int T = a.T, m = a.m;
     floatx4 gv[GRU_GE];
     uint8_t sv[GRU_HE];
-    auto load_gi = [&](int t) {
+    auto load = [&](int t) {
 #pragma unroll
         for (int k = 0; k < GRU_GE; ++k) {
             const int q = tid + k * GRU_SEQ_TH, r = q / (G3 / 4), c = 4 * (q % (G3 / 4));
             gv[k] = r < rows ? gload4(a.DGI + ((int64_t)t * m + row0 + r) * G3 + c) : zero4();
         }
-    };
-    auto load_start = [&](int t) {
 #pragma unroll
         for (int k = 0; k < GRU_HE; ++k) {
             const int r = (tid + k * GRU_SEQ_TH) / GHD;
             sv[k] = r < rows ? a.start[(int64_t)t * m + row0 + r] : 1;
         }
     };
-    for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
-        const int r = i / GHD, c = i % GHD;
-        const float v = r < rows ? a.h0[(int64_t)(row0 + r) * GHD + c] : 0.f;
-        HN[r * HSG + c] = v;
-        if (r < rows) a.HS[(int64_t)(row0 + r) * GHD + c] = v;
-    }
-    load_gi(0);
-    load_start(0);
-    for (int t = 0; t < T; ++t) {
+    auto store_gi = [&](float *GI) {
 #pragma unroll
         for (int k = 0; k < GRU_GE; ++k) {
             const int q = tid + k * GRU_SEQ_TH, r = q / (G3 / 4), c = 4 * (q % (G3 / 4));
             *(floatx4 *)(GI + r * GS + c) = gv[k];
         }
+    };
+    load(0);
+    store_gi(GIb);
 #pragma unroll
-        for (int k = 0; k < GRU_HE; ++k) {
-            const int i = tid + k * GRU_SEQ_TH, r = i / GHD, c = i % GHD;
-            HP[r * HSG + c] = sv[k] ? 0.f : HN[r * HSG + c];
-        }
-        if (t + 1 < T) {
-            load_gi(t + 1);
-            load_start(t + 1);
-        }
-        __syncthreads();
+    for (int k = 0; k < GRU_HE; ++k) {
+        const int i = tid + k * GRU_SEQ_TH, r = i / GHD, c = i % GHD;
+        const float v = r < rows ? a.h0[(int64_t)(row0 + r) * GHD + c] : 0.f;
+        if (r < rows) a.HS[(int64_t)(row0 + r) * GHD + c] = v;
+        HP[r * HSG + c] = sv[k] ? 0.f : v;
+    }
+    if (T > 1) load(1);
+    __syncthreads();
+    for (int t = 0; t < T; ++t) {
         gru_gh(a.params, a.w, HP, GH, wave);
         __syncthreads();
-        gru_update(GI, GH, HP, HN, tid, GRU_SEQ_TH, false);
-        __syncthreads();
-        for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
-            const int r = i / GHD, c = i % GHD;
-            if (r < rows) a.HS[((int64_t)(t + 1) * m + row0 + r) * GHD + c] = HN[r * HSG + c];
+        const float *GI = GIb + (t & 1) * TG * GS;
+#pragma unroll
+        for (int k = 0; k < GRU_HE; ++k) {
+            const int i = tid + k * GRU_SEQ_TH, r = i / GHD, j = i % GHD;
+            const float *gi = GI + r * GS, *gh = GH + r * GS;
+            const float rr = sigmoid_exp(gi[j] + gh[j]);
+            const float u = sigmoid_exp(gi[GHD + j] + gh[GHD + j]);
+            const float nn = tanh_exp(gi[2 * GHD + j] + rr * gh[2 * GHD + j]);
+            const float hn = (1.f - u) * nn + u * HP[r * HSG + j];
+            if (r < rows) a.HS[((int64_t)(t + 1) * m + row0 + r) * GHD + j] = hn;
+            HP[r * HSG + j] = sv[k] ? 0.f : hn; /* sv: the start flags of step t + 1 */
         }
+        if (t + 1 < T) {
+            store_gi(GIb + ((t + 1) & 1) * TG * GS);
+            if (t + 2 < T) load(t + 2);
+        }
+        __syncthreads();
     }
 }
 
@@ -1096,11 +1103,18 @@ __global__ void __launch_bounds__(GRU_HEAD_TH) k_gru_head(GruSeqArgs a) {
     }
 }
 
+/* Two barriers per step, software-pipelined: the product phase after the cell of step
+ * t + 1 forms dh_t = u dh + DGH_{t+1} W_h^T together with step t's GH (recomputed from
+ * h_{t-1}) and dO_t W_o^T; then the cell of step t.  A step's inputs (GI rows, h_{t-1},
+ * start flags, dO) go into one of two buffers by the parity of t, loaded into registers
+ * two steps ahead. */
 __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_bwd(GruSeqArgs a) {
     extern __shared__ float sm[];
-    float *HP = sm, *DH = HP + TG * HSG, *DHO = DH + TG * HSG, *GI = DHO + TG * HSG, *GH = GI + TG * GS,
-          *DGH = GH + TG * GS, *DOt = DGH + TG * GS;
-    float *ST = DOt + TG * 16; /* the step's episode-start flag of each row */
+    float *DH = sm, *DHO = DH + TG * HSG, *GH = DHO + TG * HSG, *DGH = GH + TG * GS;
+    float *HPb = DGH + TG * GS;        /* [2][TG][HSG] */
+    float *GIb = HPb + 2 * TG * HSG;   /* [2][TG][GS] */
+    float *DOb = GIb + 2 * TG * GS;    /* [2][TG][16] */
+    float *STb = DOb + 2 * TG * 16;    /* [2][TG] */
     const int row0 = (int)blockIdx.x * TG, rows = min(TG, a.m - row0);
     const int tid = (int)threadIdx.x, wave = tid >> 6;
     const int T = a.T, m = a.m;
@@ -1124,10 +1138,9 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_bwd(GruSeqArgs a) {
             dov = r < rows ? gload4(a.DO + ((int64_t)t * m + row0 + r) * 16 + c) : zero4();
         }
     };
-    for (int i = tid; i < TG * HSG; i += GRU_SEQ_TH) DH[i] = 0.f;
-    load(T - 1);
-    for (int t = T - 1; t >= 0; --t) {
-        __syncthreads();
+    auto stage = [&](int t) { /* the registers (step t) into the buffers of t's parity */
+        const int p = t & 1;
+        float *GI = GIb + p * TG * GS, *HP = HPb + p * TG * HSG;
 #pragma unroll
         for (int k = 0; k < GRU_GE; ++k) {
             const int q = tid + k * GRU_SEQ_TH, r = q / (G3 / 4), c = 4 * (q % (G3 / 4));
@@ -1137,26 +1150,37 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_bwd(GruSeqArgs a) {
         for (int k = 0; k < GRU_HE; ++k) {
             const int i = tid + k * GRU_SEQ_TH, r = i / GHD, c = i % GHD;
             HP[r * HSG + c] = sv[k] ? 0.f : hv[k];
-            if (c == 0) ST[r] = sv[k] ? 1.f : 0.f;
+            if (c == 0) STb[p * TG + r] = sv[k] ? 1.f : 0.f;
         }
-        if (tid < TG * 4) *(floatx4 *)(DOt + (tid / 4) * 16 + 4 * (tid % 4)) = dov;
-        if (t > 0) load(t - 1);
-        __syncthreads();
-        /* GH recomputed from h_{t-1}, and dO W_o^T (column tile `wave`, K = 16, rows 10..15
-         * of W_o^T zero) */
-        gru_gh(a.params, a.w, HP, GH, wave);
-        {
-            floatx4 acc[1][1] = {{zero4()}};
-            gemm16p<1, 1, 1>(acc, 16, 0, 16 * wave, [&](int i, int kb) { return lds4(DOt + i * 16 + kb); },
-                             [&](int kb, int j) { return gload4(a.w.WoP + j * 16 + kb); });
+        if (tid < TG * 4) *(floatx4 *)(DOb + p * TG * 16 + (tid / 4) * 16 + 4 * (tid % 4)) = dov;
+    };
+    /* GH of step t (from h_{t-1}) and dO_t W_o^T (column tile `wave`, K = 16, rows 10..15
+     * of W_o^T zero) */
+    auto gates_and_out = [&](int t) {
+        const int p = t & 1;
+        gru_gh(a.params, a.w, HPb + p * TG * HSG, GH, wave);
+        floatx4 acc[1][1] = {{zero4()}};
+        const float *DOt = DOb + p * TG * 16;
+        gemm16p<1, 1, 1>(acc, 16, 0, 16 * wave, [&](int i, int kb) { return lds4(DOt + i * 16 + kb); },
+                         [&](int kb, int j) { return gload4(a.w.WoP + j * 16 + kb); });
 #pragma unroll
-            for (int i = 0; i < 4; ++i) DHO[acc_row(i) * HSG + 16 * wave + acc_col()] = acc[0][0][i];
-        }
-        __syncthreads();
+        for (int i = 0; i < 4; ++i) DHO[acc_row(i) * HSG + 16 * wave + acc_col()] = acc[0][0][i];
+    };
+    for (int i = tid; i < TG * HSG; i += GRU_SEQ_TH) DH[i] = 0.f;
+    load(T - 1);
+    stage(T - 1);
+    if (T > 1) load(T - 2);
+    __syncthreads();
+    gates_and_out(T - 1);
+    __syncthreads();
+    for (int t = T - 1; t >= 0; --t) {
+        const int p = t & 1;
+        const float *GI = GIb + p * TG * GS, *HP = HPb + p * TG * HSG;
         /* the cell again and back through it: gate pre-activation gradients (to the
          * workspace, DGI over the sample's GI); DH keeps the direct part u dh of dh_{t-1} */
-        for (int i = tid; i < TG * GHD; i += GRU_SEQ_TH) {
-            const int r = i / GHD, j = i % GHD;
+#pragma unroll
+        for (int k = 0; k < GRU_HE; ++k) {
+            const int i = tid + k * GRU_SEQ_TH, r = i / GHD, j = i % GHD;
             const float *gi = GI + r * GS, *gh = GH + r * GS;
             const float rr = sigmoid_exp(gi[j] + gh[j]);
             const float u = sigmoid_exp(gi[GHD + j] + gh[GHD + j]);
@@ -1181,19 +1205,27 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_bwd(GruSeqArgs a) {
                 a.DGH[s + 2 * GHD + j] = dnp * rr;
             }
         }
+        if (t == 0) break;
+        /* step t - 1's inputs into the other buffers (their step t + 1 readers are done) */
+        stage(t - 1);
+        if (t >= 2) load(t - 2);
         __syncthreads();
         /* dh_{t-1} = u dh + DGH W_h^T (column tile `wave`, K = 384), zero at an episode
-         * start (also set for rows past the last sequence) */
+         * start of step t (also set for rows past the last sequence); with step t - 1's
+         * GH and dO W_o^T */
         {
             floatx4 acc[1][1] = {{zero4()}};
             gemm16p<1, 1, 2 * GPF>(acc, G3, 0, 16 * wave, [&](int i, int kb) { return lds4(DGH + i * GS + kb); },
                                    [&](int kb, int j) { return gload4(a.w.Wh + j * G3 + kb); });
+            const float *ST = STb + p * TG;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = acc_row(i), c = 16 * wave + acc_col();
                 DH[r * HSG + c] = ST[r] != 0.f ? 0.f : DH[r * HSG + c] + acc[0][0][i];
             }
         }
+        gates_and_out(t - 1);
+        __syncthreads();
     }
 }
 
