@@ -78,13 +78,13 @@ def test_gru_step_matches_fp64_and_samples_consistently():
     assert torch.equal(out2["h"], out["h"]) and torch.equal(out2["actions"], out["actions"])
 
 
-def _seq_batch(rng, T, m, P64, n_act, starts=True):
+def _seq_batch(rng, T, m, P64, n_act, starts=True, h0_given=False):
     x = rng.normal(0, 1, size=(T, m, 40)).astype(np.float32)
     start = np.zeros((T, m), np.uint8)
-    start[0] = 1
+    start[0] = 0 if h0_given else 1
     if starts:
         start[T // 2, ::3] = 1
-    h0 = np.zeros((m, 128), np.float32)
+    h0 = (rng.normal(0, 0.3, size=(m, 128)) if h0_given else np.zeros((m, 128))).astype(np.float32)
     logits, v, _ = G.forward(P64, x, start.astype(bool), h0)
     z = logits[:, :, :n_act]
     lp = z - z.max(-1, keepdims=True)
@@ -106,15 +106,22 @@ def _run(ippo, P, b, n_act):
 
 
 # a ragged tile (m = 20: 16 + 4), episode starts mid-sequence, 3 actions; one sequence of
-# one step; more samples than the weight-gradient kernel's 256 workgroups x 64
-@pytest.mark.parametrize("T,m,n_act", [(8, 20, 9), (6, 33, 3), (1, 1, 9), (40, 450, 9)])
-def test_gru_loss_and_gradient_through_time(T, m, n_act):
+# one step; two and three steps (the recurrences' two-step-ahead loads and parity
+# buffers at their shortest); a partial last 64-sample chunk of the batched kernels
+# (T m = 3 x 17 = 51); more samples than the weight-gradient kernel's 256 workgroups x 64
+@pytest.mark.parametrize("T,m,n_act,h0_given", [(8, 20, 9, False), (6, 33, 3, False), (1, 1, 9, False),
+                                                (2, 5, 9, False), (3, 17, 9, True), (5, 21, 9, True),
+                                                (40, 450, 9, False)])
+def test_gru_loss_and_gradient_through_time(T, m, n_act, h0_given):
+    """Loss sums and the gradient through time against the float64 reference (autograd
+    and, for small sizes, central finite differences); with h0_given a nonzero state
+    before step 0 and no episode start there."""
     ippo = _ippo()
-    print(f"\n[gru] T={T} m={m}", flush=True)
+    print(f"\n[gru] T={T} m={m} h0_given={h0_given}", flush=True)
     rng = np.random.default_rng(T * 100 + m)
     P = gru_params(T + m)[0]
     P64 = P.astype(np.float64)
-    b = _seq_batch(rng, T, m, P64, n_act)
+    b = _seq_batch(rng, T, m, P64, n_act, h0_given=h0_given)
     loss, grad, dev = _run(ippo, P, b, n_act)
     S = T * m
     tot, pol, val, ent = G.ppo_loss_parts(P64, *b, n_act)
