@@ -972,18 +972,40 @@ __global__ void __launch_bounds__(GRU_IN_TH) k_gru_in(GruSeqArgs a) {
     }
 }
 
-/* GH = HP W_h + b_h for a tile: column tiles 3 wave .. 3 wave + 2 */
-__device__ __forceinline__ void gru_gh(const float *__restrict__ P, const GruW &w, const float *HP, float *GH, int wave) {
-    floatx4 acc[1][3] = {{zero4(), zero4(), zero4()}};
-    gemm16p<1, 3, GPF>(acc, GHD, 0, 48 * wave, [&](int i, int kb) { return lds4(HP + i * HSG + kb); },
-                       [&](int kb, int j) { return gload4(w.WhT + j * GHD + kb); });
+/* The weights of a wave's three GH column tiles (48 wave .. 48 wave + 47), held in
+ * registers for a whole recurrence: lane l keeps W_h^T rows 48 wave + 16 n + l % 16 at
+ * k = 16 blk + 4 (l / 16) .. + 3, the operands of every MFMA step of the product, and
+ * the three bias values of its column. */
+struct GhRegs {
+    floatx4 w[GHD / 16][3];
+    float b[3];
+};
+__device__ __forceinline__ void gh_regs_load(GhRegs &g, const float *__restrict__ P, const GruW &w, int wave) {
+    const int l = (int)(threadIdx.x & 63), li = l & 15, kq = 4 * (l >> 4);
+#pragma unroll
+    for (int blk = 0; blk < GHD / 16; ++blk)
+#pragma unroll
+        for (int n = 0; n < 3; ++n) g.w[blk][n] = gload4(w.WhT + (48 * wave + 16 * n + li) * GHD + 16 * blk + kq);
+#pragma unroll
+    for (int n = 0; n < 3; ++n) g.b[n] = P[GO_BH + 48 * wave + 16 * n + li];
+}
+/* GH = HP W_h + b_h for a tile from the register-resident weights: only HP is read */
+__device__ __forceinline__ void gru_gh_regs(const GhRegs &g, const float *HP, float *GH, int wave) {
+    const int l = (int)(threadIdx.x & 63), li = l & 15, kq = 4 * (l >> 4);
+    floatx4 av[GHD / 16];
+#pragma unroll
+    for (int blk = 0; blk < GHD / 16; ++blk) av[blk] = lds4(HP + li * HSG + 16 * blk + kq);
+    floatx4 acc[3] = {zero4(), zero4(), zero4()};
+#pragma unroll
+    for (int blk = 0; blk < GHD / 16; ++blk)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int n = 0; n < 3; ++n) acc[n] = mfma(av[blk][t], g.w[blk][n][t], acc[n]);
 #pragma unroll
     for (int n = 0; n < 3; ++n)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = acc_row(i), c = 48 * wave + 16 * n + acc_col();
-            GH[r * GS + c] = acc[0][n][i] + P[GO_BH + c];
-        }
+        for (int i = 0; i < 4; ++i) GH[acc_row(i) * GS + 48 * wave + 16 * n + acc_col()] = acc[n][i] + g.b[n];
 }
 
 /* A step's GI rows (three float4 per thread) and the episode-start flags of the rows a
@@ -1001,6 +1023,8 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_fwd(GruSeqArgs a) {
     const int row0 = (int)blockIdx.x * TG, rows = min(TG, a.m - row0);
     const int tid = (int)threadIdx.x, wave = tid >> 6;
     const int T = a.T, m = a.m;
+    GhRegs gr;
+    gh_regs_load(gr, a.params, a.w, wave);
     floatx4 gv[GRU_GE];
     uint8_t sv[GRU_HE];
     auto load = [&](int t) {
@@ -1034,7 +1058,7 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_fwd(GruSeqArgs a) {
     if (T > 1) load(1);
     __syncthreads();
     for (int t = 0; t < T; ++t) {
-        gru_gh(a.params, a.w, HP, GH, wave);
+        gru_gh_regs(gr, HP, GH, wave);
         __syncthreads();
         const float *GI = GIb + (t & 1) * TG * GS;
 #pragma unroll
@@ -1118,6 +1142,8 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_bwd(GruSeqArgs a) {
     const int row0 = (int)blockIdx.x * TG, rows = min(TG, a.m - row0);
     const int tid = (int)threadIdx.x, wave = tid >> 6;
     const int T = a.T, m = a.m;
+    GhRegs gr;
+    gh_regs_load(gr, a.params, a.w, wave);
     floatx4 gv[GRU_GE], dov = zero4();
     float hv[GRU_HE];
     uint8_t sv[GRU_HE];
@@ -1158,7 +1184,7 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_bwd(GruSeqArgs a) {
      * of W_o^T zero) */
     auto gates_and_out = [&](int t) {
         const int p = t & 1;
-        gru_gh(a.params, a.w, HPb + p * TG * HSG, GH, wave);
+        gru_gh_regs(gr, HPb + p * TG * HSG, GH, wave);
         floatx4 acc[1][1] = {{zero4()}};
         const float *DOt = DOb + p * TG * 16;
         gemm16p<1, 1, 1>(acc, 16, 0, 16 * wave, [&](int i, int kb) { return lds4(DOt + i * 16 + kb); },
