@@ -439,12 +439,16 @@ struct Run {
         if (!MARKET && (bestS<O>() ^ km(O)) > kp) return q;
         int no = n_opp, rem = q, ntr = 0, last_price = 0;
         int64_t notional = 0;
-        const int4 bo = *RQ<O>(no - 1); /* the best order (a broadcast read) */
-        const int bq = uni(bo.y);
+        /* lane 0: the best order, the other lanes the second best (clamped) */
+        const int4 bo = *RQ<O>(max(no - 1 - min(lane, 1), 0));
+        /* prices of the last rows read, lane l the order no_row - 1 - l: the new best
+         * order after the fills is among them unless a whole row was consumed */
+        int rx = bo.x, no_row = no;
+        const int bq = rdlane(bo.y, 0);
         if (bq >= rem) {
             /* it fills the order (the common case): one trade, no row load */
-            const int bp = uni(bo.x), bt = uni(bo.w);
-            write_trade(0, bp, rem, agg_oid, uni(bo.z), agg_tid, bt, S);
+            const int bp = rdlane(bo.x, 0), bt = rdlane(bo.w, 0);
+            write_trade(0, bp, rem, agg_oid, rdlane(bo.z, 0), agg_tid, bt, S);
             add_fill(bt, S != 0, rem, (int64_t)rem * bp);
             if (rem < bq) {
                 if (lane == 0) RQ<O>(no - 1)->y = bq - rem;
@@ -460,6 +464,8 @@ struct Run {
             /* lane l: the l-th best order of the opposite side (record no - 1 - l) */
             const int j = no - 1 - lane;
             const int4 r = *RQ<O>(max(j, 0));
+            rx = r.x;
+            no_row = no;
             const bool cross = j >= 0 && (MARKET || (r.x ^ km(O)) <= kp);
             const uint64_t ncm = ballot(!cross);
             if (ncm & 1) break; /* after a row of fills: the new best order does not cross */
@@ -514,7 +520,13 @@ struct Run {
         add_fill(agg_tid, S == 0, q - rem, notional);
         if (no != n_opp) {
             nS<O>() = no;
-            refresh_bestS<O>();
+            const int l = no_row - no; /* lane of the new best order in rx */
+            if (no > 0 && l < WAVE) {
+                bestS<O>() = rdlane(rx, l);
+                touch_changed();
+            } else {
+                refresh_bestS<O>();
+            }
         }
         tr_next += ntr;
         if (S == 0) st_buy += q - rem; else st_sell += q - rem;
@@ -612,8 +624,12 @@ struct Run {
         }
         const int rt = (n - 1) >> 6;
         const int j = (rt << 6) + lane;
-        const int4 o = *RQ<S>(min(j, n - 1));
-        const int ot = *TS<S>(min(j, n - 1));
+        int4 o = *RQ<S>(min(j, n - 1));
+        int ot = *TS<S>(min(j, n - 1));
+        /* the whole top row (records and time references) arrives in the one LDS round
+         * trip that the id comparison waits for anyway; a hit then moves it from
+         * registers */
+        asm volatile("" : "+v"(o.x), "+v"(o.y), "+v"(o.z), "+v"(o.w), "+v"(ot));
         const uint64_t mt = lanes_eq(o.z, oid) & lanes_lt(j, n);
         int k;
         if (mt) {
@@ -637,6 +653,18 @@ struct Run {
                 *TS<S>(j) = ut;
             }
             WAVE_SYNC();
+            nS<S>() = n - 1;
+            if (k == n - 1) {
+                /* the best order left: the next best is the record below it, in the
+                 * loaded row unless k opened the row */
+                if (k & 63) {
+                    bestS<S>() = rdlane(o.x, (k & 63) - 1);
+                    touch_changed();
+                } else {
+                    refresh_bestS<S>();
+                }
+            }
+            return;
         } else {
             k = find_top<S>(FO, (rt << 6) - 1, oid);
             if (k < 0) {
@@ -657,8 +685,8 @@ struct Run {
             }
             remove_at<S>(k, n);
         }
+        /* below the top row: the best order stays */
         nS<S>() = n - 1;
-        if (k == n - 1) refresh_bestS<S>();
     }
 
     /* ---- one message of the step sequence: m.code says which handler (the operation
