@@ -366,19 +366,30 @@ struct Run {
         }
         WAVE_SYNC();
     }
-    /* record k of side S (n live) leaves: [k+1, n) moves down by one */
-    template <int S> __device__ __forceinline__ void remove_at(int k, int n) {
-        for (int r = k >> 6; r <= (n - 2) >> 6; ++r) {
+    /* record k of side S (n live), below the top row rt = (n - 1) >> 6, leaves: [k+1, n)
+     * moves down by one, row by row from k's row up; the top row from (o, ot), that row as
+     * loaded before (lane l: record 64 rt + l) */
+    template <int S> __device__ __forceinline__ void remove_below_top(int k, int n, int4 o, int ot) {
+        const int rt = (n - 1) >> 6;
+        for (int r = k >> 6; r < rt; ++r) {
             const int j = (r << 6) + lane;
-            const int4 x = *RQ<S>(min(j + 1, n - 1));
-            const int xt = *TS<S>(min(j + 1, n - 1));
+            const int4 x = *RQ<S>(j + 1);
+            const int xt = *TS<S>(j + 1);
             WAVE_SYNC();
-            if ((unsigned)(j - k) < (unsigned)(n - 1 - k)) {
+            if (j >= k) {
                 *RQ<S>(j) = x;
                 *TS<S>(j) = xt;
             }
             WAVE_SYNC();
         }
+        const int j = (rt << 6) + lane;
+        const int4 u = make_int4(shl1(o.x), shl1(o.y), shl1(o.z), shl1(o.w));
+        const int ut = shl1(ot);
+        if (j < n - 1) {
+            *RQ<S>(j) = u;
+            *TS<S>(j) = ut;
+        }
+        WAVE_SYNC();
     }
     /* full side (n = cap): the worst order (record 0) leaves, [1, ins) moves down by one and
      * the new order takes record ins - 1 (ins >= 1) */
@@ -683,7 +694,7 @@ struct Run {
                     return;
                 }
             }
-            remove_at<S>(k, n);
+            remove_below_top<S>(k, n, o, ot);
         }
         /* below the top row: the best order stays */
         nS<S>() = n - 1;
