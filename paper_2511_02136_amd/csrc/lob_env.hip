@@ -592,6 +592,35 @@ struct Run {
                 put<S>(0, make_int4(p, q, oid, tid), m.tref());
             }
             nS<S>() = n + 1;
+        } else if (n <= WAVE) {
+            /* a full side of one row, loaded once (lane l: record l): the worst order is
+             * lane 0, the orders ahead of the new one are counted from the same load, and
+             * on an eviction lanes below ins - 1 take the record above them, lane ins - 1
+             * the new order, in one store */
+            const int4 y = *RQ<S>(min(lane, n - 1));
+            const int yt = *TS<S>(min(lane, n - 1));
+            const int wp = rdlane(y.x, 0);
+            if ((p ^ km(S)) >= (wp ^ km(S))) {
+                count(C_DROP, 1);
+                count(C_DROPPED_QTY, q);
+                return;
+            }
+            count(C_EVICT, 1);
+            count(C_EVICTED_QTY, rdlane(y.y, 0));
+            cnt = __popcll(better_eq<S>(y.x, p) & lanes_lt(lane, n));
+            const int ins = n - cnt;
+            const int tr = m.tref();
+            const bool me = lane == ins - 1;
+            const int4 u = make_int4(shl1(y.x), shl1(y.y), shl1(y.z), shl1(y.w));
+            const int ut = shl1(yt);
+            const int4 v = make_int4(me ? p : u.x, me ? q : u.y, me ? oid : u.z, me ? tid : u.w);
+            const int vt = me ? tr : ut;
+            WAVE_SYNC();
+            if (lane < ins) {
+                *RQ<S>(lane) = v;
+                *TS<S>(lane) = vt;
+            }
+            WAVE_SYNC();
         } else {
             const int2 w = *RS<S>(0);
             const int wp = uni(w.x);
