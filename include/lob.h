@@ -242,7 +242,8 @@ int lob_set_padded(lob_ctx *ctx, int32_t padded);
 /* Autotuner: times schedules on the next n_steps of msgs from the current state
  * (restored after every run) and keeps the fastest.  One class: every (waves, mode) of
  * it.  Several classes (launched concurrently): the whole launch at balance shares 0,
- * 800, 840, 880, 920 and 960 permille (lob_schedule_balance).  Makes a plan first.
+ * 800 to 920 in steps of 20, and 960 permille (lob_schedule_balance), each run twice
+ * and timed by its faster run.  Makes a plan first.
  * Synchronous; the buffers of `out` are overwritten (scratch).  Allocates and frees
  * temporary device memory for the state copy. */
 int lob_autotune(lob_ctx *ctx, const lob_msgs *msgs, int32_t n_steps, const lob_out *out, void *stream);

@@ -76,23 +76,19 @@ static_assert(LOB_AGENT_STATE_WORDS <= AGW, "exported agent words");
 /* Per-wave LDS layout after the book (int32 word offsets), for A agents (at most 8 new
  * orders per agent per step):
  *   act  8A x 8: new orders of the step (ts, price, qty, oid, tid, time reference, -, -)
- *   perm 8A: shuffled order          lv   A x MAXLV x 4: side, price, desired, resting
- *   seen A x MAXLV: older resting qty seen in the walk      nlv  A: desired levels
+ *   perm 8A: shuffled order
  *   ag   int64 A x AGW: agent state  fl   int64 A x 4: fills of the step
  *   obk  int64 22 + 3A: depth buckets, totals, own stats (shares act's words: the
  *        observation is built after the messages, the new orders before them)
  *   env  int64 8  st  int64 STW */
 struct XL {
-    int act, perm, lv, seen, nlv, ag, fl, obk, env, st, words;
+    int act, perm, ag, fl, obk, env, st, words;
 };
 __host__ __device__ constexpr XL x_layout(int A) {
     XL x{};
     x.act = 0;
     x.perm = x.act + 8 * A * 8;
-    x.lv = x.perm + 8 * A;
-    x.seen = x.lv + A * MAXLV * 4;
-    x.nlv = x.seen + A * MAXLV;
-    x.ag = (x.nlv + A + 1) & ~1;
+    x.ag = (x.perm + 8 * A + 1) & ~1;
     x.fl = x.ag + A * AGW * 2;
     x.obk = x.act;
     x.env = x.fl + A * 4 * 2;
@@ -220,6 +216,10 @@ struct Run {
     int32_t tr_next, tr_room, tr_step0;
     /* counters: lane k holds counter k */
     int64_t ctr;
+    /* the agents' desired levels of the step, in registers: lane MAXLV i + k holds level k
+     * of agent i (side, price, desired and resting quantity, the resting quantity the walk
+     * has seen so far), lane i the level count of agent i */
+    int lv_side, lv_price, lv_d, lv_r, lv_seen, lv_n;
 
     __device__ Run(const KArgs &args, int32_t *lds, int env)
         : a(args), L(lds), lane(lane_id()), capp(uni(args.capp)), e(uni(env)), A(args.n_agents),
@@ -244,7 +244,6 @@ struct Run {
     __device__ __forceinline__ int64_t *X64(int off) { return reinterpret_cast<int64_t *>(X() + off); }
     __device__ __forceinline__ int64_t *AG(int i) { return X64(xl().ag) + i * AGW; }
     __device__ __forceinline__ int64_t *FL(int i) { return X64(xl().fl) + i * 4; }
-    __device__ __forceinline__ int32_t *LV(int ai, int k) { return X() + xl().lv + (ai * MAXLV + k) * 4; }
     __device__ __forceinline__ int64_t *ENV() { return X64(xl().env); }
 
     __device__ __forceinline__ int nsz(int s) const { return s ? n1 : n0; }
@@ -771,26 +770,22 @@ struct Run {
      * touch, see touch_changed) */
     __device__ __forceinline__ void after_message() { seq += 1; }
 
-    /* ---- desired levels of agent ai (LDS, written by lane 0) ---- */
+    /* ---- desired levels of agent ai (registers, lane MAXLV ai + k: level k) ---- */
+    /* the lane of agent ai's level (side, price) among its first nlv, or -1 */
+    __device__ __forceinline__ int find_level(int ai, int nlv, int side, int price) {
+        const uint64_t m = ballot((unsigned)(lane - MAXLV * ai) < (unsigned)nlv && lv_side == side && lv_price == price);
+        return m ? (int)__builtin_ctzll(m) : -1;
+    }
     __device__ __forceinline__ void add_level(int ai, int &nlv, int side, int price, int qty) {
-        int k = 0;
-        for (; k < nlv; ++k)
-            if (uni(LV(ai, k)[0]) == side && uni(LV(ai, k)[1]) == price) break;
-        if (k < nlv) {
-            if (lane == 0) LV(ai, k)[2] += qty;
+        const int l = find_level(ai, nlv, side, price);
+        if (l >= 0) {
+            lv_d += lane == l ? qty : 0;
         } else if (nlv < MAXLV) {
-            if (lane == 0) {
-                int32_t *l = LV(ai, k);
-                l[0] = side; l[1] = price; l[2] = qty; l[3] = 0;
+            if (lane == MAXLV * ai + nlv) {
+                lv_side = side; lv_price = price; lv_d = qty; lv_r = 0; lv_seen = 0;
             }
             nlv += 1;
         }
-        WAVE_SYNC();
-    }
-    __device__ __forceinline__ int find_level(int ai, int nlv, int side, int price) {
-        for (int k = 0; k < nlv; ++k)
-            if (uni(LV(ai, k)[0]) == side && uni(LV(ai, k)[1]) == price) return k;
-        return -1;
     }
 
     /* the agent's resting quantity at each of its desired levels on side S */
@@ -800,11 +795,8 @@ struct Run {
             const int j = find_top<S>(FT, hi, tid);
             if (j < 0) break;
             const int2 pq = US<S>(0, j);
-            const int k = find_level(i, nlv, S, uni(pq.x));
-            if (k >= 0) {
-                if (lane == 0) LV(i, k)[3] += pq.y;
-                WAVE_SYNC();
-            }
+            const int l = find_level(i, nlv, S, uni(pq.x));
+            if (l >= 0) lv_r += lane == l ? uni(pq.y) : 0;
             hi = j - 1;
         }
     }
@@ -914,9 +906,7 @@ struct Run {
             if (act == 1) add_level(i, nlv, 0, ba0, a.dir_q);
             if (act == 2) add_level(i, nlv, 1, bb0, a.dir_q);
         }
-        if (lane == 0) X()[xl().nlv + i] = nlv;
-        if (lane < MAXLV) X()[xl().seen + i * MAXLV + lane] = 0;
-        WAVE_SYNC();
+        if (lane == i) lv_n = nlv;
 
         /* resting quantity of this agent at each desired level (step start) */
         if (nlv > 0) {
@@ -928,9 +918,10 @@ struct Run {
         for (int k = 0; k <= nlv; ++k) {
             int type, side, price, qty;
             if (k < nlv) {
-                const int D = uni(LV(i, k)[2]), R = uni(LV(i, k)[3]);
+                const int l = MAXLV * i + k;
+                const int D = rdlane(lv_d, l), R = rdlane(lv_r, l);
                 if (D <= R) continue;
-                type = T_LIMIT; side = uni(LV(i, k)[0]); price = uni(LV(i, k)[1]); qty = D - R;
+                type = T_LIMIT; side = rdlane(lv_side, l); price = rdlane(lv_price, l); qty = D - R;
             } else {
                 if (mkt <= 0) continue;
                 type = T_MARKET; side = 1; price = 0; qty = (int)mkt;
@@ -1122,15 +1113,13 @@ struct Run {
             if (j < 0) break;
             const int2 pq = US<S>(0, j);
             const int pr = uni(pq.x), qt = uni(pq.y);
-            const int k = find_level(ai, nlv, S, pr);
-            const int D = k >= 0 ? uni(LV(ai, k)[2]) : 0;
+            const int l = find_level(ai, nlv, S, pr);
+            const int D = l >= 0 ? rdlane(lv_d, l) : 0;
             int x = qt; /* quantity to cancel; qt = the whole order */
             if (D > 0) {
-                const int R = uni(LV(ai, k)[3]);
-                int32_t *seen = X() + xl().seen + ai * MAXLV + k;
-                const int older = uni(*seen);
-                if (lane == 0) *seen = older + qt;
-                WAVE_SYNC();
+                const int R = rdlane(lv_r, l);
+                const int older = rdlane(lv_seen, l);
+                lv_seen += lane == l ? qt : 0;
                 x = R > D ? min(max((R - D) - (R - older - qt), 0), qt) : 0;
             }
             if (x > 0) {
@@ -1160,6 +1149,7 @@ struct Run {
         /* step 1 (from the book at step start): every agent's desired levels and new
          * orders, agents in index order */
         int nact = 0;
+        lv_side = 0; lv_price = 0; lv_d = 0; lv_r = 0; lv_seen = 0; lv_n = 0;
         for (int i = 0; i < A; ++i) {
             const int kind = (a.kinds >> (4 * i)) & 15;
             const int nacts = kind_actions(kind);
@@ -1190,7 +1180,7 @@ struct Run {
          * index order, each walking its resting orders on both sides (walk_side). */
         for (int ai = 0; ai < A; ++ai) {
             const int tid = ai + 1;
-            const int nlv = uni(X()[xl().nlv + ai]);
+            const int nlv = rdlane(lv_n, ai);
             walk_side<0>(ai, nlv, tid);
             walk_side<1>(ai, nlv, tid);
         }
@@ -2141,18 +2131,23 @@ int lob_autotune(lob_ctx *c, const lob_msgs *m, int32_t n_steps, const lob_out *
     if (c->classes.size() > 1) {
         int best_b = c->balance;
         float best = 1e30f;
-        for (int b : {0, 800, 840, 880, 920, 960}) {
+        /* the rollout time falls and rises steeply around the best share (a few percent
+         * per 40 permille), so the shares are 20 permille apart; each is run twice and
+         * counts with its faster run */
+        for (int b : {0, 800, 820, 840, 860, 880, 900, 920, 960}) {
             if (rc != LOB_OK) break;
             if ((rc = lob_schedule_balance(c, b)) != LOB_OK || (rc = make_plan(c, m, c->t, n_steps)) != LOB_OK)
                 break;
-            float ms = 0.f;
+            float ms = 1e30f;
             for (int rep = 0; rep < 2 && rc == LOB_OK; ++rep) {
                 restore();
                 (void)hipEventRecord(e0, st);
                 rc = launch_env(c, a, st);
                 (void)hipEventRecord(e1, st);
                 (void)hipEventSynchronize(e1);
-                (void)hipEventElapsedTime(&ms, e0, e1);
+                float r = 0.f;
+                (void)hipEventElapsedTime(&r, e0, e1);
+                ms = std::min(ms, r);
             }
             if (rc == LOB_OK && ms < best) { best = ms; best_b = b; }
         }
