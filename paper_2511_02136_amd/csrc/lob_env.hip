@@ -220,6 +220,11 @@ struct Run {
      * of agent i (side, price, desired and resting quantity, the resting quantity the walk
      * has seen so far), lane i the level count of agent i */
     int lv_side, lv_price, lv_d, lv_r, lv_seen, lv_n;
+    /* the agents' resting orders on side S at step start, best first: lane p holds the
+     * p-th one as 8 x record index + owner's tid (the index kept current through the
+     * cancel walk), and its price and quantity for the resting quantities measured before
+     * the walk; al_n[S] counts them all, the first WAVE are held */
+    int al_jt[2], al_px[2], al_q[2], al_n[2];
 
     __device__ Run(const KArgs &args, int32_t *lds, int env)
         : a(args), L(lds), lane(lane_id()), capp(uni(args.capp)), e(uni(env)), A(args.n_agents),
@@ -654,12 +659,13 @@ struct Run {
         if (S == 1) st_buy += x; else st_sell += x;
         st_last = price;
     }
+    /* returns the index the removed order had, or -1 (no order left the book) */
     template <int S, int MODE>
-    __device__ __forceinline__ void cancel(int qty, int oid) {
+    __device__ __forceinline__ int cancel(int qty, int oid) {
         const int n = nS<S>();
         if (n == 0) {
             count(C_MISS, 1);
-            return;
+            return -1;
         }
         const int rt = (n - 1) >> 6;
         const int j = (rt << 6) + lane;
@@ -681,7 +687,7 @@ struct Run {
                 if (left > 0) {
                     if (lane == 0) RS<S>(k)->y = left;
                     WAVE_SYNC();
-                    return;
+                    return -1;
                 }
             }
             const int4 u = make_int4(shl1(o.x), shl1(o.y), shl1(o.z), shl1(o.w));
@@ -703,12 +709,12 @@ struct Run {
                     refresh_bestS<S>();
                 }
             }
-            return;
+            return k;
         } else {
             k = find_top<S>(FO, (rt << 6) - 1, oid);
             if (k < 0) {
                 count(C_MISS, 1);
-                return;
+                return -1;
             }
             if (MODE != CX_DELETE) {
                 const int4 rk = *RQ<S>(k);
@@ -719,13 +725,14 @@ struct Run {
                 if (left > 0) {
                     if (lane == 0) RS<S>(k)->y = left;
                     WAVE_SYNC();
-                    return;
+                    return -1;
                 }
             }
             remove_below_top<S>(k, n, o, ot);
         }
         /* below the top row: the best order stays */
         nS<S>() = n - 1;
+        return k;
     }
 
     /* ---- one message of the step sequence: m.code says which handler (the operation
@@ -788,16 +795,56 @@ struct Run {
         }
     }
 
-    /* the agent's resting quantity at each of its desired levels on side S */
+    /* every agent's resting orders on side S, best first, into the al_* registers: two
+     * rows of whole records per LDS round trip, a ballot of the agents' tids per row */
+    template <int S> __device__ __forceinline__ void agent_scan() {
+        const int n = nS<S>();
+        int c = 0, ajt = -1, apx = 0, aq = 0;
+        auto take = [&](int r, const int4 &x) {
+            uint64_t m = ballot((r << 6) + lane < n && (unsigned)(x.w - 1) < (unsigned)A);
+            while (m) {
+                const int l = 63 - __builtin_clzll(m);
+                m &= ~(1ull << l);
+                if (c < WAVE) {
+                    const bool me = lane == c;
+                    const int px = rdlane(x.x, l), q = rdlane(x.y, l), tid = rdlane(x.w, l);
+                    ajt = me ? 8 * ((r << 6) + l) + tid : ajt;
+                    apx = me ? px : apx;
+                    aq = me ? q : aq;
+                }
+                c += 1;
+            }
+        };
+        for (int r = (n - 1) >> 6; r >= 0; r -= 2) {
+            const int4 x0 = *RQ<S>(min((r << 6) + lane, n - 1));
+            const int4 x1 = *RQ<S>(max(((r - 1) << 6) + lane, 0));
+            take(r, x0);
+            if (r >= 1) take(r - 1, x1);
+        }
+        al_jt[S] = ajt; al_px[S] = apx; al_q[S] = aq; al_n[S] = c;
+    }
+
+    /* the agent's resting quantity at each of its desired levels on side S: its orders
+     * among the held ones, then (more than WAVE agent orders on the side) a search below
+     * the last held one */
     template <int S> __device__ __forceinline__ void resting_side(int i, int nlv, int tid) {
-        int hi = nS<S>() - 1;
-        for (;;) {
-            const int j = find_top<S>(FT, hi, tid);
-            if (j < 0) break;
-            const int2 pq = US<S>(0, j);
-            const int l = find_level(i, nlv, S, uni(pq.x));
-            if (l >= 0) lv_r += lane == l ? uni(pq.y) : 0;
-            hi = j - 1;
+        uint64_t m = ballot(lane < min(al_n[S], WAVE) && (al_jt[S] & 7) == tid);
+        while (m) {
+            const int p = (int)__builtin_ctzll(m);
+            m &= m - 1;
+            const int l = find_level(i, nlv, S, rdlane(al_px[S], p));
+            if (l >= 0) lv_r += lane == l ? rdlane(al_q[S], p) : 0;
+        }
+        if (al_n[S] > WAVE) {
+            int hi = (rdlane(al_jt[S], WAVE - 1) >> 3) - 1;
+            for (;;) {
+                const int j = find_top<S>(FT, hi, tid);
+                if (j < 0) break;
+                const int2 pq = US<S>(0, j);
+                const int l = find_level(i, nlv, S, uni(pq.x));
+                if (l >= 0) lv_r += lane == l ? uni(pq.y) : 0;
+                hi = j - 1;
+            }
         }
     }
 
@@ -1106,30 +1153,42 @@ struct Run {
      * (best first); an order at a level the agent no longer wants is deleted, at a kept
      * level any excess over the desired quantity comes from its newest orders there.  A
      * cancel at record j moves only records above j, so the walk continues below j. */
+    /* order j of agent ai in the walk: a cancel message (delete, or partial cancel of the
+     * excess) when due; a removal shifts the held indices above it */
+    template <int S> __device__ __forceinline__ void walk_order(int ai, int nlv, int j) {
+        const int4 rj = *RQ<S>(j);
+        const int pr = uni(rj.x), qt = uni(rj.y), oid = uni(rj.z);
+        const int l = find_level(ai, nlv, S, pr);
+        const int D = l >= 0 ? rdlane(lv_d, l) : 0;
+        int x = qt; /* quantity to cancel; qt = the whole order */
+        if (D > 0) {
+            const int R = rdlane(lv_r, l);
+            const int older = rdlane(lv_seen, l);
+            lv_seen += lane == l ? qt : 0;
+            x = R > D ? min(max((R - D) - (R - older - qt), 0), qt) : 0;
+        }
+        if (x > 0) {
+            const int k = D == 0 ? cancel<S, CX_DELETE>(qt, oid) : cancel<S, CX_PARTIAL>(x, oid);
+            after_message();
+            if (k >= 0) al_jt[S] -= (al_jt[S] >> 3) > k ? 8 : 0;
+        }
+    }
     template <int S> __device__ __forceinline__ void walk_side(int ai, int nlv, int tid) {
-        int hi = nS<S>() - 1;
-        for (;;) {
-            const int j = find_top<S>(FT, hi, tid);
-            if (j < 0) break;
-            const int2 pq = US<S>(0, j);
-            const int pr = uni(pq.x), qt = uni(pq.y);
-            const int l = find_level(ai, nlv, S, pr);
-            const int D = l >= 0 ? rdlane(lv_d, l) : 0;
-            int x = qt; /* quantity to cancel; qt = the whole order */
-            if (D > 0) {
-                const int R = rdlane(lv_r, l);
-                const int older = rdlane(lv_seen, l);
-                lv_seen += lane == l ? qt : 0;
-                x = R > D ? min(max((R - D) - (R - older - qt), 0), qt) : 0;
+        uint64_t m = ballot(lane < min(al_n[S], WAVE) && (al_jt[S] & 7) == tid);
+        while (m) {
+            const int p = (int)__builtin_ctzll(m);
+            m &= m - 1;
+            walk_order<S>(ai, nlv, rdlane(al_jt[S], p) >> 3);
+        }
+        if (al_n[S] > WAVE) {
+            /* below the held orders, by search (the held index is current) */
+            int hi = (rdlane(al_jt[S], WAVE - 1) >> 3) - 1;
+            for (;;) {
+                const int j = find_top<S>(FT, hi, tid);
+                if (j < 0) break;
+                walk_order<S>(ai, nlv, j);
+                hi = j - 1;
             }
-            if (x > 0) {
-                /* a cancel message (delete, or partial cancel of x) for this order */
-                const int oid = uni(US<S>(1, j).x);
-                if (D == 0) cancel<S, CX_DELETE>(qt, oid);
-                else cancel<S, CX_PARTIAL>(x, oid);
-                after_message();
-            }
-            hi = j - 1;
         }
     }
 
@@ -1150,6 +1209,10 @@ struct Run {
          * orders, agents in index order */
         int nact = 0;
         lv_side = 0; lv_price = 0; lv_d = 0; lv_r = 0; lv_seen = 0; lv_n = 0;
+        if (A > 0) {
+            agent_scan<0>();
+            agent_scan<1>();
+        }
         for (int i = 0; i < A; ++i) {
             const int kind = (a.kinds >> (4 * i)) & 15;
             const int nacts = kind_actions(kind);

@@ -191,6 +191,50 @@ def test_sweeps_across_rows_and_empty_sides():
 
 
 @pytest.mark.parametrize("mode", ["rollout", "step"])
+def test_more_than_a_row_of_agent_orders(mode):
+    """An agent alone at the best ask, its order there partly filled every step, tops the
+    level up with a new order each step until it rests more than 64 orders (more than the
+    agents' orders a step keeps in registers): its resting quantity is measured and the
+    cancel walk runs over all of them, cancelling the excess from the newest ones when the
+    desired quantity falls, and deleting them all when the level moves away; in the second
+    env a second agent's order rests below them on the same side."""
+    _, DeviceStream = _lob()
+    T, T1 = 110, 89
+    bids = [[990, 5, 1, 0, 1, 0]]
+    asks = [[1000, 1, 2, 0, 1, 0]]
+    snap = hand_book([(bids, asks), (bids, asks)], 200)
+    # every step one market buy of 1: it fills the ask side's first order in priority
+    steps = [[[msg(MARKET, BUY, 0, 1, 100 + t)] for t in range(T)] for _ in range(2)]
+    hs = hand_stream(steps)
+    caps = np.array([200, 200])
+    kw = dict(exec_task=100_000, exec_q0=300, mm_q=7)
+    # exec: one level at the best ask (action 4), at twice the quantity (action 6) for
+    # steps 70-73, the level two ticks up (action 5) at step 90; mm: nothing in env 0,
+    # from step 20 on in env 1 an ask two ticks above the best ask (action 5)
+    acts = np.zeros((T, 2, 2), np.int32)
+    acts[:, 0, :] = 4
+    acts[70:74, 0, :] = 6
+    acts[90, 0, :] = 5
+    acts[20:, 1, 1] = 5
+    o = oracle_for(hs, snap, caps, 200, ("exec", "mm"), T, 17, **kw)
+    ref1 = o.step(hs, n_steps=T1, actions=acts[:T1])
+    b1 = o.books()
+    for e in range(2):
+        n = int(b1["n"][e, 1])
+        assert int((b1["tid"][e, 1, :n] == 1).sum()) > 64
+    ref2 = o.step(hs, n_steps=T - T1, actions=acts[T1:])
+    env = gpu_env(caps, 200, ("exec", "mm"), T, 17, snap, **kw)
+    ds = DeviceStream.from_host(hs)
+    for (t0, n, ref) in ((0, T1, ref1), (T1, T - T1, ref2)):
+        toff = torch.from_numpy(ref["trade_off"]).cuda()
+        a = torch.from_numpy(np.ascontiguousarray(acts[t0:t0 + n])).cuda()
+        got = env.rollout(ds, n, actions=a, trade_off=toff) if mode == "rollout" else run_steps(env, ds, n, a, toff)
+        assert_same_outputs(got, ref, n, what=f"agent orders/{mode}/{t0}")
+    assert_same_books(env.books(), o.books(), what=f"agent orders/{mode}")
+    assert_same_state(env.state(), o.state(), what=f"agent orders/{mode}")
+
+
+@pytest.mark.parametrize("mode", ["rollout", "step"])
 def test_sweeps_of_a_row_or_more_that_stop(mode):
     """Incoming orders that trade against 64 or more resting orders: exactly one row of
     crossing orders and then an order that does not cross; a row and a part; an order
