@@ -1025,28 +1025,37 @@ struct Run {
         const int64_t *O = X64(xl().obk);
         const int64_t mid2 = (int64_t)bb + ba;
         const int64_t strades = uni64(S[2]);
+        /* lane f forms feature f: every value it may need is loaded first (uniform values
+         * and one per-lane read of the book features), then the lane selects its own, so
+         * that no lane waits on a load another lane's feature needs */
+        const int f = lane;
+        const int64_t e3 = uni64(E[3]), e6 = uni64(E[6]), e7 = uni64(E[7]);
+        const int64_t s0 = uni64(S[0]), s1 = uni64(S[1]), s3 = uni64(S[3]);
+        const int64_t ob = O[(f >= 3 && f <= 24) ? f - 3 : 0];
+        int64_t vc = 0; /* the features that do not depend on the agent */
+        vc = f == 0 ? (int64_t)ba - bb : vc;
+        vc = f == 1 ? e7 : vc;
+        vc = f == 2 ? mid2 - e3 : vc;
+        vc = (f >= 3 && f <= 24) ? ob : vc;
+        vc = f == 25 ? (int64_t)n0 : vc;
+        vc = f == 26 ? (int64_t)n1 : vc;
+        vc = f == 27 ? s0 : vc;
+        vc = f == 28 ? s1 : vc;
+        vc = f == 29 ? strades : vc;
+        vc = f == 30 ? (strades > 0 ? 2 * s3 - mid2 : 0) : vc;
+        vc = f == 34 ? (int64_t)a.episode_len - e6 : vc;
         for (int i = 0; i < A; ++i) {
             const int kind = (a.kinds >> (4 * i)) & 15;
             const int64_t *g = AG(i);
-            int64_t v = 0;
-            const int f = lane;
-            if (f >= 3 && f <= 24) v = O[f - 3];
-            else if (f >= 35 && f <= 37) v = O[22 + 3 * i + (f - 35)];
-            else if (f == 0) v = (int64_t)ba - bb;
-            else if (f == 1) v = E[7];
-            else if (f == 2) v = mid2 - E[3];
-            else if (f == 25) v = n0;
-            else if (f == 26) v = n1;
-            else if (f == 27) v = S[0];
-            else if (f == 28) v = S[1];
-            else if (f == 29) v = strades;
-            else if (f == 30) v = strades > 0 ? 2 * S[3] - mid2 : 0;
-            else if (f == 31) v = g[0];
-            else if (f == 32) v = g[1];
-            else if (f == 33) v = exec_kind(kind) ? g[2] : 0;
-            else if (f == 34) v = (int64_t)a.episode_len - E[6];
-            else if (f == 38) v = g[4];
-            else if (f == 39) v = g[5];
+            const int64_t g0 = uni64(g[0]), g1 = uni64(g[1]), g2 = uni64(g[2]), g4 = uni64(g[4]), g5 = uni64(g[5]);
+            const int64_t oa = O[22 + 3 * i + min(max(f - 35, 0), 2)];
+            int64_t v = vc;
+            v = (f >= 35 && f <= 37) ? oa : v;
+            v = f == 31 ? g0 : v;
+            v = f == 32 ? g1 : v;
+            v = f == 33 ? (exec_kind(kind) ? g2 : 0) : v;
+            v = f == 38 ? g4 : v;
+            v = f == 39 ? g5 : v;
             if (f < LOB_OBS_DIM) base[((int64_t)i * a.n_envs + e) * LOB_OBS_DIM + f] = (float)v;
         }
     }
