@@ -280,10 +280,21 @@ struct Run {
         mid_n += mid_f * len;
         mid_at = seq;
     }
+    /* a uniform value kept in vector registers (its arithmetic then issues as VALU) */
+    static __device__ __forceinline__ int64_t vreg64(int64_t x) {
+        int lo = (int)x, hi = (int)(x >> 32);
+        asm volatile("v_mov_b32 %0, %0" : "+v"(lo));
+        asm volatile("v_mov_b32 %0, %0" : "+v"(hi));
+        return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    }
+    static __device__ __forceinline__ int vreg32(int x) {
+        asm volatile("v_mov_b32 %0, %0" : "+v"(x));
+        return x;
+    }
     __device__ __forceinline__ void touch_changed() {
         mid_flush();
         mid_f = min(n0, n1) > 0 ? 1 : 0;
-        mid_c = mid_f ? (int64_t)best0 + best1 : 0;
+        mid_c = vreg64(mid_f ? (int64_t)best0 + best1 : 0);
     }
 
     /* record i of side S (any index; the side's base is uniform) */
@@ -453,6 +464,9 @@ struct Run {
         const int kp = p ^ km(O);
         if (!MARKET && (bestS<O>() ^ km(O)) > kp) return q;
         int no = n_opp, rem = q, ntr = 0, last_price = 0;
+        /* the notional of the fills is needed only for an agent's own fill (replayed
+         * orders have no agent tid) */
+        const bool agg_agent = (unsigned)(agg_tid - 1) < (unsigned)A;
         int64_t notional = 0;
         /* lane 0: the best order, the other lanes the second best (clamped) */
         const int4 bo = *RQ<O>(max(no - 1 - min(lane, 1), 0));
@@ -512,7 +526,8 @@ struct Run {
                 const int px = rdlane(x, l);
                 add_fill(rdlane(r.w, l), S != 0, px, (int64_t)px * rdlane(r.x, l));
             }
-            for (int l = 0; l < nt; ++l) notional += (int64_t)rdlane(x, l) * rdlane(r.x, l);
+            if (agg_agent)
+                for (int l = 0; l < nt; ++l) notional += (int64_t)rdlane(x, l) * rdlane(r.x, l);
             last_price = rdlane(r.x, nt - 1);
             ntr += nt;
             if (kd < kn) {
@@ -532,7 +547,7 @@ struct Run {
             rem -= rdlane((int)inc, nt - 1);
             if (kn < WAVE || no == 0) break;
         }
-        add_fill(agg_tid, S == 0, q - rem, notional);
+        if (agg_agent) add_fill(agg_tid, S == 0, q - rem, notional);
         if (no != n_opp) {
             nS<O>() = no;
             const int l = no_row - no; /* lane of the new best order in rx */
@@ -1204,7 +1219,7 @@ struct Run {
     /* ---- one env-step (Sec. 4 steps 1-5) writing output slot s_idx ---- */
     __device__ __forceinline__ void step(int s_idx) {
         const int N = a.n_envs;
-        mid_sum = 0; mid_n = 0; seq = 0; mid_at = 0;
+        mid_sum = vreg64(0); mid_n = vreg32(0); seq = 0; mid_at = 0;
         touch_changed();
         st_buy = 0; st_sell = 0; st_last = 0;
         tr_step0 = tr_next;
