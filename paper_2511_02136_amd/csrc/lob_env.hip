@@ -20,6 +20,11 @@
  *     order move nothing);
  *   - agent orders and replayed messages run through one loop, 64 messages per chunk
  *     staged with coalesced SoA loads;
+ *   - per step, the agents' desired levels and their resting orders (collected in one
+ *     pass per side) are held in registers, lane-parallel, and their observation
+ *     features are formed one per lane; state that only accumulates (the mid-price run
+ *     sums) is kept in vector registers, so that the CU's one scalar unit, which issues
+ *     most of a message's instructions, carries only what steers control flow;
  *   - envs are grouped by capacity class (books spanning the same number of rows), each
  *     class's launch sized in LDS for its largest capacity; the persistent form keeps
  *     books in LDS for all steps of a rollout and pulls envs from a device work queue,
