@@ -586,7 +586,7 @@ struct Run {
                 const int js = min(max(j - 1, 0), n - 1);
                 const int4 y = *RQ<S>(js);
                 const int yt = *TS<S>(js);
-                cnt = __popcll(better_eq<S>(y.x, p) & lanes_gt(lane, 0) & lanes_le(lane, top));
+                cnt = __popcll(better_eq<S>(y.x, p) & ~1ull & lanes_le(lane, top)); /* lanes 1..top */
                 if (cnt == top) cnt += count_rows<S>(rt - 1, p);
                 const int ins = n - cnt;
                 WAVE_SYNC();
@@ -1242,6 +1242,9 @@ struct Run {
             agent_scan<0>();
             agent_scan<1>();
         }
+        /* random actions: lane i draws agent i's (the counter hash on the vector units) */
+        const uint32_t ua = a.actions_in ? 0u
+                                         : (uint32_t)(hash4(a.seed, DOM_ACTION, (uint64_t)e, (uint64_t)t, (uint64_t)lane) >> 32);
         for (int i = 0; i < A; ++i) {
             const int kind = (a.kinds >> (4 * i)) & 15;
             const int nacts = kind_actions(kind);
@@ -1249,7 +1252,7 @@ struct Run {
             if (a.actions_in) {
                 act = uni(a.actions_in[((int64_t)s_idx * A + i) * N + e]);
             } else {
-                const uint32_t u = (uint32_t)(hash4(a.seed, DOM_ACTION, (uint64_t)e, (uint64_t)t, (uint64_t)i) >> 32);
+                const uint32_t u = (uint32_t)rdlane((int)ua, i);
                 act = (int)(((uint64_t)u * (uint64_t)nacts) >> 32);
             }
             if (a.actions_out && lane == 0) a.actions_out[((int64_t)s_idx * A + i) * N + e] = act;
