@@ -921,6 +921,8 @@ constexpr int GRU_IN_LDS = TI * (XS + HSG);                   /* X and E tiles *
 constexpr int GRU_FWD_LDS = TG * (HSG + 3 * GS);               /* HP, GH, two GI buffers */
 constexpr int GRU_BWD_LDS = TG * (4 * HSG + 4 * GS + 32) + 2 * TG; /* DH, DHO, GH, DGH; two of HP, GI, dO, ST */
 constexpr int GRU_HEAD_LDS = TI * (OS + 4);                    /* outputs, loss terms */
+constexpr int DES = G3 + 4;                                    /* LDS row stride of k_gru_de's DGI tile */
+constexpr int GRU_DE_LDS = TI * DES;
 static_assert(GRU_IN_TH == 512 && GRU_SEQ_TH == 512, "8 waves: 8 column tiles of 128, 24 of 384");
 
 /* E and GI of the 64 samples from s0 = 64 blockIdx.x (the last workgroup may have fewer) */
@@ -1258,12 +1260,18 @@ __global__ void __launch_bounds__(GRU_SEQ_TH) k_gru_bwd(GruSeqArgs a) {
 /* DE = (DGI W_i^T) (1 - E^2) of the 64 samples from s0 = 64 blockIdx.x: column tile
  * `wave` of the four row tiles */
 __global__ void __launch_bounds__(GRU_IN_TH) k_gru_de(GruSeqArgs a) {
+    extern __shared__ float sm[];
+    float *D = sm; /* the 64 samples' DGI rows, read from memory once for all eight waves */
     const int64_t S = (int64_t)a.T * a.m, s0 = (int64_t)blockIdx.x * TI;
     const int rows = (int)min((int64_t)TI, S - s0);
-    const int wave = (int)threadIdx.x >> 6;
+    const int tid = (int)threadIdx.x, wave = tid >> 6;
+    for (int q = tid; q < TI * G3 / 4; q += GRU_IN_TH) {
+        const int r = q / (G3 / 4), c = 4 * (q % (G3 / 4));
+        *(floatx4 *)(D + r * DES + c) = r < rows ? gload4(a.DGI + (s0 + r) * G3 + c) : zero4();
+    }
+    __syncthreads();
     floatx4 acc[4][1] = {{zero4()}, {zero4()}, {zero4()}, {zero4()}};
-    gemm16p<4, 1, GPF>(acc, G3, 0, 16 * wave,
-                       [&](int i, int kb) { return i < rows ? gload4(a.DGI + (s0 + i) * G3 + kb) : zero4(); },
+    gemm16p<4, 1, GPF>(acc, G3, 0, 16 * wave, [&](int i, int kb) { return lds4(D + i * DES + kb); },
                        [&](int kb, int j) { return gload4(a.w.Wi + j * G3 + kb); });
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
@@ -1504,7 +1512,9 @@ bool lds_opt_in() {
             hipFuncSetAttribute(reinterpret_cast<const void *>(k_gru_bwd),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, GRU_BWD_LDS * 4) != hipSuccess ||
             hipFuncSetAttribute(reinterpret_cast<const void *>(k_gru_dw),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, DW_LDS * 4) != hipSuccess)
+                                hipFuncAttributeMaxDynamicSharedMemorySize, DW_LDS * 4) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void *>(k_gru_de),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, GRU_DE_LDS * 4) != hipSuccess)
             return false;
         done = true;
     }
@@ -1681,7 +1691,7 @@ int lob_gru_ppo_fwd_bwd(const float *params, const float *obs, const float *obs_
     hipLaunchKernelGGL(k_gru_fwd, dim3((unsigned)w.ntile), dim3(GRU_SEQ_TH), GRU_FWD_LDS * 4, st, a);
     hipLaunchKernelGGL(k_gru_head, dim3((unsigned)w.nin), dim3(GRU_HEAD_TH), GRU_HEAD_LDS * 4, st, a);
     hipLaunchKernelGGL(k_gru_bwd, dim3((unsigned)w.ntile), dim3(GRU_SEQ_TH), GRU_BWD_LDS * 4, st, a);
-    hipLaunchKernelGGL(k_gru_de, dim3((unsigned)w.nin), dim3(GRU_IN_TH), 0, st, a);
+    hipLaunchKernelGGL(k_gru_de, dim3((unsigned)w.nin), dim3(GRU_IN_TH), GRU_DE_LDS * 4, st, a);
     GruDwArgs d;
     d.obs = obs; d.obs_scale = obs_scale; d.start = start; d.HS = a.HS; d.E = a.E; d.DGI = a.DGI; d.DGH = a.DGH; d.DE = a.DE; d.DO = a.DO;
     d.S = (int64_t)T * m; d.m = m; d.partial = ws + w.part;
