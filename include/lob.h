@@ -339,7 +339,8 @@ int64_t lob_ppo_workspace_bytes(int32_t m);
  * the minibatch of the per-sample total, policy, value and entropy terms (divide by m for
  * the means) and grad [LOB_PPO_PARAMS] = gradient of the mean total loss (device).
  * workspace: device, 16-byte aligned, >= lob_ppo_workspace_bytes(m) (LOB_EINVAL otherwise);
- * params that are not 16-byte aligned are copied into it first (stream-ordered).
+ * params that are not 16-byte aligned are copied into it first, and W2 is written into it
+ * transposed (both stream-ordered, before the fused kernel).
  * Deterministic: 256 workgroups each sum a fixed set of 64-sample tiles in order, and
  * their partials are summed in a fixed order. */
 int lob_ppo_fwd_bwd(const float *params, const float *obs, const float *obs_scale, const int32_t *act,
@@ -352,8 +353,9 @@ int lob_ppo_fwd_bwd(const float *params, const float *obs, const float *obs_scal
  * memory (code under HIP graph capture, tight training loops, harnesses that forbid
  * allocation).  The workspace is a fixed array in device memory that the library holds on
  * every GPU it runs on until the process ends: PPO_SCRATCH = 256 workgroup partials of
- * 78,864 floats, 4 chunk sums of the first reduction level and room for an aligned
- * parameter copy, 82,334,008 bytes (about 82 MB); m is not limited by it, since the
+ * 78,864 floats, 4 chunk sums of the first reduction level, room for an aligned
+ * parameter copy and for W2 transposed (256 x 256 floats), 82,596,168 bytes (about
+ * 83 MB); m is not limited by it, since the
  * partials do not grow with m (LOB_EINVAL if a minibatch ever needed more).  Allocates
  * nothing and calls no allocating routine; the array's device address is resolved once
  * per GPU on the first call there.  Same arguments, results (bit for bit) and errors as

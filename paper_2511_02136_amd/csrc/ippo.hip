@@ -38,6 +38,7 @@ constexpr int PW = NPARAM + 6; /* per-workgroup partial: gradient, the 4 loss su
                                   (a multiple of 4 floats: partials are summed in 16-byte loads) */
 constexpr int PPO_WGS = 256; /* workgroups of the fused PPO kernel */
 constexpr int64_t PARAM_COPY_BYTES = NPARAM * 4 + 16; /* workspace room for an aligned parameter copy */
+constexpr int64_t W2T_BYTES = (int64_t)HID * HID * 4 + 16;  /* workspace room for W2 transposed (aligned) */
 
 constexpr int TR = 64;          /* samples per workgroup tile */
 /* waves per workgroup: four per SIMD (the LDS tile allows one workgroup per CU), so the
@@ -232,10 +233,10 @@ __device__ __forceinline__ float obs_in(const float *__restrict__ obs, const flo
 /* ---- forward of a tile of R samples (R a multiple of 16, at most 64) into LDS: X (the
  * observations times the input scales xs, when given), H1 = tanh(X W1 + b1),
  * H2 = tanh(H1 W2 + b2), O = H2 W3 + b3 (O cols 10..15 zero) ---- */
-template <int R>
+template <int R, bool W2T>
 __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const float *__restrict__ obs,
                                              const float *__restrict__ xs, int rows, float *X, float *H1, float *H2,
-                                             float *O) {
+                                             float *O, const float *__restrict__ w2t) {
     constexpr int MT = R / 16; /* 16-row tiles per wave */
     const int tid = (int)threadIdx.x, wave = tid >> 6;
     for (int i = tid; i < R * XS; i += blockDim.x) {
@@ -276,13 +277,19 @@ __device__ __forceinline__ void forward_tile(const float *__restrict__ P, const 
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int n = 0; n < CT; ++n) acc[m][n] = zero4();
-        gemm16<MT, CT>(acc, HID, 0, CW * wave, [&](int i, int kb) { return lds4(H1 + i * HS + kb); },
-                      [&](int kb, int j) {
-                          floatx4 v;
+        if constexpr (W2T) {
+            /* W2 transposed (w2t[j][k]): a lane's four k values in one 16-byte load */
+            gemm16<MT, CT>(acc, HID, 0, CW * wave, [&](int i, int kb) { return lds4(H1 + i * HS + kb); },
+                          [&](int kb, int j) { return *(const floatx4 *)(w2t + j * HID + kb); });
+        } else {
+            gemm16<MT, CT>(acc, HID, 0, CW * wave, [&](int i, int kb) { return lds4(H1 + i * HS + kb); },
+                          [&](int kb, int j) {
+                              floatx4 v;
 #pragma unroll
-                          for (int t = 0; t < 4; ++t) v[t] = P[O_W2 + (kb + t) * HID + j];
-                          return v;
-                      });
+                              for (int t = 0; t < 4; ++t) v[t] = P[O_W2 + (kb + t) * HID + j];
+                              return v;
+                          });
+        }
 #pragma unroll
         for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -375,7 +382,7 @@ __global__ void __launch_bounds__(NTH) k_policy_forward(FwdArgs a) {
     const int row0 = (int)blockIdx.x * TRP;
     const int rows = min(TRP, a.n - row0);
     const float *P = a.params + (int64_t)ag * NPARAM;
-    forward_tile<TRP>(P, a.obs + ((int64_t)ag * a.n + row0) * IN, a.obs_scale, rows, X, H1, H2, O);
+    forward_tile<TRP, false>(P, a.obs + ((int64_t)ag * a.n + row0) * IN, a.obs_scale, rows, X, H1, H2, O, nullptr);
     const int tid = (int)threadIdx.x;
     if (tid < rows) {
         const uint64_t seed = a.epoch ? a.seed + 0x9E3779B97F4A7C15ULL * a.epoch[0] : a.seed;
@@ -422,7 +429,14 @@ struct PpoArgs {
     int32_t m, n_act;
     float clip, c_v, c_e, scale; /* scale = 1 / m */
     float *partial;              /* [grid][PW]: gradient, then loss sums (total, policy, value, entropy) */
+    const float *w2t;            /* W2 transposed, [256][256] (workspace) */
 };
+
+/* W2 transposed, w2t[j][k] = W2[k][j], for the forward's 16-byte operand loads */
+__global__ void k_w2t(const float *__restrict__ P, float *__restrict__ w2t) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < HID * HID) w2t[(i % HID) * HID + i / HID] = P[O_W2 + i];
+}
 
 /* One sample's clipped-PPO loss terms from its ten outputs z (logits, then the value) and
  * their gradient w.r.t. z, scaled by `scale` (1 / minibatch samples): policy -min(r A,
@@ -485,7 +499,7 @@ __device__ __noinline__ void ppo_tile(const PpoArgs &a, const GLOBAL float *Pg, 
         const int row0 = tile * TR;
         const int rows = min(TR, a.m - row0);
         auto put = [&](int i, float v) { G[i] = first ? v : G[i] + v; };
-        forward_tile<TR>(P, (const float *)obs_g + (int64_t)row0 * IN, a.obs_scale, rows, X, H1, H2, O);
+        forward_tile<TR, true>(P, (const float *)obs_g + (int64_t)row0 * IN, a.obs_scale, rows, X, H1, H2, O, a.w2t);
 
         /* per-sample loss and its gradient w.r.t. the 10 outputs (scaled by 1/m) */
         float lsum[4] = {0.f, 0.f, 0.f, 0.f};
@@ -1549,7 +1563,7 @@ GruWs gru_ws(int32_t T, int32_t m) {
 
 int64_t ppo_workspace_bytes(int32_t m) {
     const int64_t nwg = std::min<int64_t>((m + TR - 1) / TR, PPO_WGS), nch = (nwg + RCH - 1) / RCH;
-    return (nwg + nch) * PW * 4 + PARAM_COPY_BYTES;
+    return (nwg + nch) * PW * 4 + PARAM_COPY_BYTES + W2T_BYTES;
 }
 
 int ppo_launch(const float *params, const float *obs, const float *obs_scale, const int32_t *act, const float *logp_old,
@@ -1562,7 +1576,7 @@ int ppo_launch(const float *params, const float *obs, const float *obs_scale, co
     const int nwg = std::min((m + TR - 1) / TR, PPO_WGS);
     const int nch = (nwg + RCH - 1) / RCH;
     const int64_t part_bytes = (int64_t)(nwg + nch) * PW * 4;
-    if (workspace_bytes < part_bytes + PARAM_COPY_BYTES || ((uintptr_t)workspace & 15)) return LOB_EINVAL;
+    if (workspace_bytes < part_bytes + PARAM_COPY_BYTES + W2T_BYTES || ((uintptr_t)workspace & 15)) return LOB_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     /* the kernel reads W2 in 16-byte loads: parameters that are not 16-byte aligned (a
      * row of a [networks][LOB_PPO_PARAMS] array) are first copied into the workspace */
@@ -1577,7 +1591,10 @@ int ppo_launch(const float *params, const float *obs, const float *obs_scale, co
     a.ret = ret; a.v_old = v_old;
     a.m = m; a.n_act = n_actions; a.clip = clip; a.c_v = c_v; a.c_e = c_e; a.scale = 1.0f / (float)m;
     a.partial = workspace;
+    float *w2t = (float *)(((uintptr_t)workspace + part_bytes + PARAM_COPY_BYTES + 15) & ~(uintptr_t)15);
+    a.w2t = w2t;
     if (!lds_opt_in()) return LOB_EHIP;
+    hipLaunchKernelGGL(k_w2t, dim3((unsigned)(HID * HID / 256)), dim3(256), 0, st, params, w2t);
     hipLaunchKernelGGL(k_ppo_fwd_bwd, dim3((unsigned)nwg), dim3(NTH), LDS_FLOATS * 4, st, a);
     float *sums = workspace + (int64_t)nwg * PW;
     hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((PW / 4 + 255) / 256), (unsigned)nch), dim3(256), 0, st,
@@ -1588,12 +1605,12 @@ int ppo_launch(const float *params, const float *obs, const float *obs_scale, co
 }
 
 /* The fixed scratch of lob_ppo_fwd_bwd_noalloc: the workspace of the largest call (256
- * workgroup partials, the first reduction level's chunk sums and room for an aligned
- * parameter copy), one copy per GPU for the life of the process.  In host code `scratch`
+ * workgroup partials, the first reduction level's chunk sums, room for an aligned
+ * parameter copy and for W2 transposed), one copy per GPU for the life of the process.  In host code `scratch`
  * only names the symbol: its device address on the current GPU comes from
  * hipGetSymbolAddress, taken once per device and kept. */
 constexpr int64_t PPO_SCRATCH_BYTES =
-    ((int64_t)PPO_WGS + (PPO_WGS + RCH - 1) / RCH) * PW * 4 + PARAM_COPY_BYTES;
+    ((int64_t)PPO_WGS + (PPO_WGS + RCH - 1) / RCH) * PW * 4 + PARAM_COPY_BYTES + W2T_BYTES;
 static __device__ __align__(256) float scratch[(PPO_SCRATCH_BYTES + 3) / 4];
 
 constexpr int MAX_DEVICES = 64;

@@ -57,12 +57,13 @@ def test_host_side_checks_of_the_actor_critic():
     (the pointers passed where a check must fail first are never dereferenced), and the
     workspace size of the fused PPO call: 256 workgroup partials at most, plus one partial
     per 64 of them for the first reduction level, of 78,864 floats each (78,858 parameters,
-    4 loss sums, 2 of padding), plus room for an aligned copy of the parameters."""
+    4 loss sums, 2 of padding), plus room for an aligned copy of the parameters and for
+    W2 (256 x 256) transposed."""
     lib = ctypes.CDLL(LIB)
     p, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
     lib.lob_ppo_workspace_bytes.argtypes = [i32]
     lib.lob_ppo_workspace_bytes.restype = ctypes.c_int64
-    pw, copy = 78864 * 4, 78858 * 4 + 16
+    pw, copy = 78864 * 4, 78858 * 4 + 16 + 256 * 256 * 4 + 16
     assert lib.lob_ppo_workspace_bytes(0) == -1 and lib.lob_ppo_workspace_bytes(-3) == -1
     assert lib.lob_ppo_workspace_bytes(1) == (1 + 1) * pw + copy
     assert lib.lob_ppo_workspace_bytes(64 * 100 + 1) == (101 + 2) * pw + copy
