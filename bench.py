@@ -298,7 +298,7 @@ def ippo_bench(reps: int = 3):
             "rollout_ms": roll_ms, "rollout_env_steps_per_s": env_steps / (roll_ms / 1e3),
             "update_ms": upd_ms, "update": "GAE + 4 epochs x 4 minibatches x 2 agents of fused PPO + Adam",
             "ppo_fwd_bwd_call": {"samples": m, "ms": ppo_ms, "flop_per_sample": PPO_FLOP_PER_SAMPLE,
-                                 "launches": "k_ppo_fwd_bwd, k_reduce_chunks, k_reduce_final",
+                                 "launches": "k_w2t, k_ppo_fwd_bwd, k_reduce_chunks, k_reduce_final",
                            "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
                                         "unit": "TFLOP/s", "frac": tflops / FP32_MFMA_PEAK_TFLOPS}}}
 
